@@ -1,0 +1,160 @@
+"""Pins of the oracle's power series, exact solve, spectral radius and
+refinement (Sec. IV, eq. 9-22; convergence condition of Sec. V).
+
+The series is checked against closed forms built from dense matrices with
+numpy/scipy routines (solve, matrix powers, eigenvalues), never by re-typing
+its own recurrence.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import entries, hmatrix, series
+
+
+@pytest.fixture(scope="module")
+def small():
+    """N = 1200 sphere (leaf 32): 64 leaves, far blocks on levels 5 and 6."""
+    prob = W.sphere_problem(1200, math.sqrt(1200 / 1536.0))
+    H = hmatrix.HMatrix(prob, 32, 1.0, 1e-6)
+    assert len(H.far_levels) == 2
+    g = np.random.default_rng(11)
+    b = np.asfortranarray(W.plane_waves(prob.xyz, W.directions(3, 3)))
+    return prob, H, b, g
+
+
+@pytest.fixture(scope="module")
+def small_volume():
+    prob = W.cube_problem(10, 10 / 16)
+    H = hmatrix.HMatrix(prob, 32, 1.0, 1e-6)
+    assert H.far
+    b = W.plane_waves(prob.xyz, W.directions(2, 3))
+    return prob, H, b
+
+
+def _dense_parts(H, level):
+    D = H.dense(level, "D")
+    R = H.dense(level, "R")
+    return D, R
+
+
+def test_single_leaf_is_direct_solve():
+    """N <= leaf size: R is empty and x_K = D^{-1} b = Z^{-1} b for any K."""
+    prob = W.sphere_problem(50, 0.3)
+    H = hmatrix.HMatrix(prob, 64)
+    b = W.plane_waves(prob.xyz, W.Z_HAT)
+    Z = entries.dense(prob)
+    ref = np.linalg.solve(Z, b)
+    for K in (0, 3):
+        assert series.rel_err(series.series(H, b, K), ref) < 1e-13
+
+
+def test_zero_terms_is_block_jacobi(small):
+    """K = 0 gives D x = b with D the leaf self-blocks of the exact Z."""
+    prob, H, b, _ = small
+    x0 = series.series(H, b, 0)
+    Zt = entries.dense(prob)[np.ix_(H.perm, H.perm)]
+    D = np.zeros_like(Zt)
+    for c in H.leaves:
+        sl = slice(c.off, c.off + c.size)
+        D[sl, sl] = Zt[sl, sl]
+    r = D @ H.to_tree(x0) - H.to_tree(b)
+    assert np.linalg.norm(r) <= 1e-13 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("level_pick", ["leaf", "coarsest"])
+@pytest.mark.parametrize("K", [1, 4])
+def test_truncation_identity(small, level_pick, K):
+    """x* - x_K = (-M)^{K+1} x*, M = D^{-1} R_l, with x* = Z_l^{-1} b by a
+    dense solve: holds for any spectral radius."""
+    prob, H, b, _ = small
+    level = -1 if level_pick == "leaf" else min(H.far_levels)
+    D, R = _dense_parts(H, level)
+    M = np.linalg.solve(D, R)
+    xs = np.linalg.solve(D + R, H.to_tree(b))
+    xK = H.to_tree(series.series(H, b, K, level))
+    lhs = xs - xK
+    rhs = np.linalg.matrix_power(-M, K + 1) @ xs
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(xs)
+
+
+def test_truncation_identity_volume(small_volume):
+    prob, H, b = small_volume
+    D, R = _dense_parts(H, -1)
+    M = np.linalg.solve(D, R)
+    xs = np.linalg.solve(D + R, H.to_tree(b))
+    xK = H.to_tree(series.series(H, b, 5))
+    rhs = np.linalg.matrix_power(-M, 6) @ xs
+    assert np.linalg.norm(xs - xK - rhs) <= 1e-11 * np.linalg.norm(xs)
+
+
+def test_series_is_jacobi_iterate(small):
+    """x_K is the K-th block-Jacobi iterate x_k = D^{-1}(b - R x_{k-1}) from
+    x_0 = D^{-1} b (dense LU solves)."""
+    prob, H, b, _ = small
+    D, R = _dense_parts(H, -1)
+    bt = H.to_tree(b)
+    x = np.linalg.solve(D, bt)
+    for _ in range(4):
+        x = np.linalg.solve(D, bt - R @ x)
+    assert np.linalg.norm(x - H.to_tree(series.series(H, b, 4))) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_refinement_passes_extend_the_series(small):
+    """p passes of x += P_K (b - Z_l x) equal the series with (p+1)(K+1) terms."""
+    prob, H, b, _ = small
+    for K, p in ((2, 1), (1, 3)):
+        xr = series.refine(H, b, K, -1, p)
+        xl = series.series(H, b, (p + 1) * (K + 1) - 1, -1)
+        assert series.rel_err(xr, xl) < 1e-12
+
+
+def test_rho_matches_eigenvalues(small):
+    """Power iteration agrees with the largest |eigenvalue| of dense D^{-1} R_l."""
+    prob, H, b, _ = small
+    for level in (-1, min(H.far_levels)):
+        D, R = _dense_parts(H, level)
+        ev = np.max(np.abs(np.linalg.eigvals(np.linalg.solve(D, R))))
+        assert abs(series.rho(H, level, iters=300) - ev) <= 0.03 * ev
+
+
+def test_convergence_when_rho_below_one():
+    """rho < 1: ||x_K - x*|| decays geometrically at rate rho."""
+    prob = W.sphere_problem(512, math.sqrt(512 / 1536.0))
+    H = hmatrix.HMatrix(prob, 64, 1.0, 1e-6)
+    rho = series.rho(H, -1, iters=300)
+    assert rho < 1.0
+    b = W.plane_waves(prob.xyz, W.Z_HAT)
+    xs = series.solve_exact(H, b)
+    errs = [series.rel_err(series.series(H, b, K), xs) for K in range(0, 60, 5)]
+    assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-6
+    rate = (errs[-1] / errs[-3]) ** (1.0 / 10)
+    assert abs(rate - rho) <= 0.05
+
+
+def test_alpha_cancels(small):
+    """A random invertible block-diagonal scaling alpha (eq. 9-11) leaves x_K
+    unchanged."""
+    prob, H, b, g = small
+    alpha = {a: g.standard_normal((c.size, c.size)) + 1j * g.standard_normal((c.size, c.size))
+             + 3 * np.eye(c.size) for a, c in enumerate(H.leaves)}
+    x1 = series.series(H, b, 3, -1)
+    x2 = series.series(H, b, 3, -1, alpha=alpha)
+    assert series.rel_err(x2, x1) < 1e-11
+
+
+def test_gmres_matches_dense_solve(small):
+    prob, H, b, _ = small
+    xd = series.solve_exact(H, b[:, :1], min(H.far_levels))
+    xg = series.solve_gmres(H, b[:, :1], min(H.far_levels))
+    assert series.rel_err(xg, xd) < 1e-11
+
+
+def test_multi_rhs_columns_independent(small):
+    prob, H, b, _ = small
+    X = series.series(H, b, 3)
+    for c in range(b.shape[1]):
+        assert series.rel_err(series.series(H, b[:, c], 3), X[:, c]) < 1e-15
