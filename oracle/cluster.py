@@ -12,7 +12,8 @@ Readings where the paper is silent:
     is not), a pair of two leaves that is not admissible becomes a dense
     near block, anything else recurses into all child pairs (a leaf side
     stays whole);
-  * the level of a block is max(depth(t), depth(s)), root depth 0.
+  * the level of a block is max(depth(t), depth(s)), root depth 0;
+  * a cluster paired with itself is never admissible (it holds the diagonal).
 """
 from __future__ import annotations
 
@@ -91,7 +92,9 @@ def partition(tree: Tree, eta: float) -> Partition:
     near, far = [], []
 
     def rec(t: Cluster, s: Cluster):
-        if admissible(t, s, eta):
+        # a cluster's interaction with itself holds the diagonal and is never
+        # far, even when eq. 7 holds trivially (one point: diam = dist = 0)
+        if t is not s and admissible(t, s, eta):
             far.append((t, s, max(t.depth, s.depth)))
             return
         if t.is_leaf and s.is_leaf:
