@@ -1,0 +1,185 @@
+/*
+ * hmps.h -- C-ABI of libhmps, a multi-level power-series H-matrix solver for
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Negi, Balakrishnan, Rao, "Multi-Level Power Series Solution for
+ * Large Surface and Volume Electric Field Integral Equation" (arXiv
+ * 2307.03968).  The dense system [Z] x = b (Sec. II, eq. 5) is compressed
+ * as an H-matrix Z = Z_N + Z_F (Sec. III, eq. 6): a binary cluster tree, the
+ * admissibility test of eq. 7, dense near blocks and ACA-compressed far
+ * blocks grouped by level (eq. 8).  The solve splits Z_l = D + R_l, D the
+ * leaf self-interaction blocks, R_l the off-diagonal near blocks plus the far
+ * blocks of level >= l, and evaluates the truncated power series of
+ * Sec. IV (eq. 12-13, 20-22):
+ *
+ *     x_K = sum_{k=0..K} (-D^{-1} R_l)^k D^{-1} b .
+ *
+ * Conventions for every call:
+ *   - Return value: HM_OK (0) on success, > 0 a state or warning, < 0 an
+ *     error; hm_last_error() gives a message for the calling thread.
+ *   - Vectors are complex128 (interleaved re, im doubles), column-major
+ *     n x nrhs with leading dimension ld >= n, in ORIGINAL point order.
+ *   - *_dev pointers are device pointers on the current HIP device; a
+ *     hip_stream argument is a hipStream_t (NULL = the null stream).  Device
+ *     calls are stream-ordered and asynchronous unless stated otherwise.
+ *   - The library copies every host input it is given; the caller keeps
+ *     ownership of its buffers.  An hm_matrix_t owns all device memory of
+ *     one geometry until hmat_free.  Calls on one handle are not
+ *     thread-safe (use one handle per stream); server calls are.
+ *   - There is no CPU fallback: a device call without a usable gfx950
+ *     device fails with HM_EHIP.
+ */
+#ifndef HMPS_H
+#define HMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HM_OK         0
+#define HM_ENOTREADY  1   /* ps_poll: the request has not finished          */
+#define HM_EDIVERGED  2   /* a result was written but the series grew       */
+                          /* (||y_K|| > ||y_0||) or went non-finite          */
+#define HM_EINVAL    (-1) /* bad argument                                    */
+#define HM_ENOMEM    (-2) /* device allocation failed or over the budget     */
+#define HM_EHIP      (-3) /* HIP runtime error (no device, launch failure)   */
+#define HM_EBUSY     (-4) /* no server slot free; retry                      */
+#define HM_ESTATE    (-5) /* handle not in a state that allows this call     */
+
+/* ---- enums --------------------------------------------------------------- */
+enum { HM_SURFACE = 0, HM_VOLUME = 1 };
+/* HM_F64: every product in FP64.  HM_F32_APPLY: near and far products read
+ * FP32 copies of the blocks (FP64 vectors and accumulation); leaf LU,
+ * D^{-1}, residuals and refinement stay FP64. */
+enum { HM_F64 = 0, HM_F32_APPLY = 1 };
+/* PS_SERIES: return x_K.  PS_REFINE: x <- x + P_K(b - Z_l x) passes (P_K is
+ * the K-term series operator, residual in FP64) until the correction is
+ * below refine_tol relative to x; the fixed point is Z_l^{-1} b and the
+ * per-pass error factor is rho(D^{-1} R_l)^{K+1}. */
+enum { PS_SERIES = 0, PS_REFINE = 1 };
+
+#define HM_BUILD_HOST_ONLY 0x1u /* build tree, partition and blocks on the host
+                                   only: no device memory, for hmat_export /
+                                   hmat_info; device calls return HM_ESTATE */
+#define HM_BUILD_NO_F32    0x2u /* do not keep FP32 block copies */
+#define HM_BUILD_KEEP_HOST 0x4u /* keep the host copy of the blocks after the
+                                   upload so that hmat_export works on a
+                                   device-built handle */
+
+/* ---- problem and options -------------------------------------------------- */
+/* Entries of Z (synthetic point-kernel stand-in for the MoM matrix of eq. 5,
+ * one unknown per point, e^{-jkR} convention):
+ *   surface  Z_ij = h^2 e^{-jkR}/(4 pi R)            i != j,  Z_ii = 2h(1 + 0.1j)
+ *   volume   Z_ij = k^2 chi_j h^3 e^{-jkR}/(4 pi R)  i != j,  Z_ii = 1/chi_i + 0.5
+ * Coincident points (R < 1e-12) are rejected with HM_EINVAL. */
+typedef struct {
+  int64_t n;          /* number of unknowns, >= 1                         */
+  const double* xyz;  /* host, n x 3 row-major, wavelengths; copied        */
+  int32_t kind;       /* HM_SURFACE or HM_VOLUME                           */
+  double k;           /* wavenumber                                        */
+  double h;           /* spacing (surface) or cell edge (volume)           */
+  const double* chi;  /* host, n contrasts (HM_VOLUME), else NULL; copied  */
+} hm_problem;
+
+/* Cluster tree (Sec. III): split while a cluster has more than leaf_max
+ * points, along the longest bounding-box axis at the median (ties by
+ * original index).  Admissibility eq. 7 with eta.  Far blocks: ACA with
+ * partial pivoting plus recompression to aca_tol, rank <= max_rank (0 = no
+ * cap); only the block with the smaller row offset is compressed and its
+ * mirror is the transpose (half H-matrix, Sec. III). */
+typedef struct {
+  int32_t leaf_max;     /* >= 1 (<= 256)                                    */
+  double eta;           /* admissibility parameter, the paper uses 1.0      */
+  double aca_tol;       /* relative ACA / recompression tolerance, > 0      */
+  int32_t max_rank;     /* 0 = min(m, n)                                    */
+  uint32_t flags;       /* HM_BUILD_*                                       */
+  int32_t num_threads;  /* host threads for the build, 0 = all             */
+} hm_build_opts;
+
+typedef struct {
+  int32_t K;            /* highest power of the series (K + 1 terms), >= 0 */
+  int32_t level;        /* far blocks of level >= level are used; -1 = leaf
+                           level only (the paper's runs); levels below the
+                           coarsest far level act as the coarsest          */
+  int32_t precision;    /* HM_F64 or HM_F32_APPLY                           */
+  int32_t kind;         /* PS_SERIES or PS_REFINE                           */
+  int32_t max_passes;   /* PS_REFINE: pass limit                            */
+  double refine_tol;    /* PS_REFINE: stop when ||d|| <= tol ||x|| per RHS   */
+} ps_opts;
+
+/* Per right-hand side statistics.  Filling them synchronises the stream. */
+typedef struct {
+  int32_t passes;       /* refinement passes done (0 for PS_SERIES)         */
+  int32_t diverged;     /* 1 if growth > 1 or non-finite values             */
+  double resid_rel;     /* PS_REFINE: last ||d|| / ||x||; else 0           */
+  double growth;        /* ||y_K|| / ||y_0|| of the (last) series           */
+  double t_ms;          /* wall time of the whole call (same for all RHS)   */
+} ps_stats;
+
+#define HM_MAX_LEVELS 32
+typedef struct {
+  int64_t n;
+  int32_t leaf_level;               /* depth L of the deepest leaf           */
+  int32_t num_leaves;
+  int32_t max_leaf;                 /* largest leaf size                     */
+  int32_t min_far_level;            /* coarsest level holding far blocks, or -1 */
+  int64_t near_blocks;              /* including the diagonal blocks         */
+  int64_t near_offdiag_entries;     /* sum m n over off-diagonal near blocks */
+  int64_t diag_entries;             /* sum m^2 over leaves                   */
+  int64_t far_blocks[HM_MAX_LEVELS];   /* per level, both orientations      */
+  int64_t far_rank_sum[HM_MAX_LEVELS];
+  int64_t far_entries[HM_MAX_LEVELS];  /* sum r (m + n)                      */
+  int64_t device_bytes;             /* device memory held by the handle     */
+  double build_ms;                  /* host build + upload + device LU       */
+} hm_info;
+
+typedef struct hm_matrix* hm_matrix_t;
+
+/* ---- H-matrix ------------------------------------------------------------- */
+
+/* Build the H-matrix of `prob` (Sec. III): tree, partition, near fill, ACA
+ * with recompression on the host; upload; leaf LU with partial pivoting
+ * (eq. 12's near-field inverse) and D^{-1} on the device.  Synchronises
+ * `hip_stream` before returning.  *out is set only on success. */
+int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
+               hm_matrix_t* out);
+
+/* Structure statistics (host only, no device access). */
+int hmat_info(hm_matrix_t h, hm_info* out);
+
+/* y = Z_l x (eq. 6 restricted to far levels >= level), including D, for
+ * nrhs right-hand sides.  precision HM_F32_APPLY reads the FP32 block
+ * copies.  x_dev and y_dev must not overlap. */
+int hmat_apply(hm_matrix_t h, int32_t level, int32_t precision, const void* x_dev,
+               int64_t ldx, void* y_dev, int64_t ldy, int32_t nrhs, void* hip_stream);
+
+/* Power-series solve (Sec. IV).  b_dev and x_dev must not overlap.  per_rhs
+ * (host, nrhs entries) may be NULL; when given, the call synchronises and
+ * fills it.  Returns HM_EDIVERGED (> 0) when stats were requested and some
+ * right-hand side grew; x is still written. */
+int ps_solve(hm_matrix_t h, const ps_opts* opts, const void* b_dev, int64_t ldb, void* x_dev,
+             int64_t ldx, int32_t nrhs, ps_stats* per_rhs, void* hip_stream);
+
+/* Write the host-side H-matrix (permutation, blocks, factors) to `path` as
+ * (needs HM_BUILD_HOST_ONLY or HM_BUILD_KEEP_HOST, else HM_ESTATE)
+ * a sequence of named arrays: u32 name length, name bytes, u32 dtype code
+ * (1 int32, 2 int64, 3 float64, 4 complex128), u32 ndim, u64 shape[ndim],
+ * raw little-endian data.  For checking the build against an independent
+ * implementation. */
+int hmat_export(hm_matrix_t h, const char* path);
+
+/* Release the handle and all its device memory (synchronises the device). */
+int hmat_free(hm_matrix_t h);
+
+/* ---- errors ----------------------------------------------------------------- */
+const char* hm_strerror(int status);
+const char* hm_last_error(void);   /* thread-local detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HMPS_H */

@@ -1,0 +1,109 @@
+// Internal types of libhmps shared by the host build, the device packer and
+// the solver driver.  Not part of the C-ABI.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/hmps.h"
+
+namespace hm {
+
+using cplx = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+struct Error {
+  int code;
+  std::string msg;
+};
+
+// ---------------------------------------------------------------- problem
+struct Problem {
+  int64_t n = 0;
+  int kind = HM_SURFACE;
+  double k = 0, h = 0;
+  std::vector<double> xyz;  // n x 3
+  std::vector<double> chi;  // n (volume)
+};
+
+// Entries of Z in original indices (see include/hmps.h for the formulas).
+cplx entry(const Problem& p, int64_t i, int64_t j);
+// Symmetric kernel part for i != j: Z_ij (surface) or G_ij (volume).
+cplx kernel(const Problem& p, int64_t i, int64_t j);
+
+// ---------------------------------------------------------------- tree
+struct Cluster {
+  int32_t off, size, depth;
+  int32_t child[2];  // -1 for a leaf
+  double lo[3], hi[3];
+  bool leaf() const { return child[0] < 0; }
+};
+
+struct Tree {
+  std::vector<int64_t> perm;      // tree position -> original index
+  std::vector<Cluster> nodes;     // nodes[0] = root
+  std::vector<int32_t> leaves;    // node ids in tree order
+  std::vector<int32_t> leaf_of;   // tree position -> leaf index
+  int32_t depth = 0;              // deepest leaf depth
+};
+
+Tree build_tree(const Problem& p, int leaf_max);
+
+struct BlockPair {
+  int32_t t, s;    // node ids
+  int32_t level;   // max(depth t, depth s)
+};
+
+void build_partition(const Tree& tr, double eta, std::vector<BlockPair>& near,
+                     std::vector<BlockPair>& far);
+
+// ---------------------------------------------------------------- blocks
+// Far block with A ~ U V^T (U m x r, V n x r, both column-major) on the
+// symmetric kernel part.  For the volume case the contrast of the source
+// points multiplies V's rows when the block is packed for the device.
+struct LowRank {
+  int32_t m = 0, n = 0, r = 0;
+  std::vector<cplx> U, V;
+};
+
+// ACA with partial pivoting followed by recompression (rules in aca.cpp).
+LowRank compress_block(const Problem& p, const int64_t* rows, int32_t m, const int64_t* cols,
+                       int32_t n, double eps, int32_t max_rank);
+
+struct FarBlock {
+  int32_t t_off, m, s_off, n, level;
+  int32_t src;       // index into the compressed list
+  bool transposed;   // block (s,t) stored as the transpose of (t,s)
+};
+
+struct NearBlock {
+  int32_t t_leaf, s_leaf;
+  int64_t data;      // offset into HostH::near_data (column-major m x n)
+};
+
+// Host-side H-matrix in tree order.
+struct HostH {
+  Problem prob;
+  Tree tree;
+  int leaf_max = 0;
+  double eta = 1, tol = 1e-4;
+  std::vector<int32_t> leaf_off, leaf_size;      // per leaf
+  std::vector<NearBlock> near;                   // incl. diagonal, sorted by (t, s)
+  std::vector<cplx> near_data;
+  std::vector<LowRank> lowrank;                  // compressed (t before s) blocks
+  std::vector<FarBlock> far;                     // both orientations
+  std::vector<double> chi_tree;                  // volume: chi in tree order
+  int32_t min_far_level = -1;
+  int32_t max_leaf = 0;
+};
+
+int build_host(const Problem& p, const hm_build_opts& o, HostH& out);
+
+// Export helper (binary named arrays).
+int export_host(const HostH& H, const char* path, const std::vector<cplx>* lu_host,
+                const std::vector<int32_t>* piv_host);
+
+}  // namespace hm

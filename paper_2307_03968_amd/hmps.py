@@ -1,0 +1,222 @@
+"""ctypes binding of libhmps (include/hmps.h).
+
+Argument marshalling only: every step of the build's device part and of the
+solve runs in the library.  Device vectors are torch complex128 CUDA tensors;
+the binding passes their data pointers and the current torch stream.
+
+Layout: the C-ABI takes column-major n x nrhs arrays.  A torch tensor of
+shape (nrhs, n), contiguous, is exactly that; the helpers below accept
+(n,) or (n, nrhs) tensors and return (n,) or (n, nrhs) views.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhmps.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "hmps.h")
+
+HM_OK, HM_ENOTREADY, HM_EDIVERGED = 0, 1, 2
+HM_EINVAL, HM_ENOMEM, HM_EHIP, HM_EBUSY, HM_ESTATE = -1, -2, -3, -4, -5
+HM_SURFACE, HM_VOLUME = 0, 1
+HM_F64, HM_F32_APPLY = 0, 1
+PS_SERIES, PS_REFINE = 0, 1
+HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST = 0x1, 0x2, 0x4
+HM_MAX_LEVELS = 32
+
+
+class hm_problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("kind", C.c_int32),
+                ("k", C.c_double), ("h", C.c_double), ("chi", C.POINTER(C.c_double))]
+
+
+class hm_build_opts(C.Structure):
+    _fields_ = [("leaf_max", C.c_int32), ("eta", C.c_double), ("aca_tol", C.c_double),
+                ("max_rank", C.c_int32), ("flags", C.c_uint32), ("num_threads", C.c_int32)]
+
+
+class ps_opts(C.Structure):
+    _fields_ = [("K", C.c_int32), ("level", C.c_int32), ("precision", C.c_int32),
+                ("kind", C.c_int32), ("max_passes", C.c_int32), ("refine_tol", C.c_double)]
+
+
+class ps_stats(C.Structure):
+    _fields_ = [("passes", C.c_int32), ("diverged", C.c_int32), ("resid_rel", C.c_double),
+                ("growth", C.c_double), ("t_ms", C.c_double)]
+
+
+class hm_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("leaf_level", C.c_int32), ("num_leaves", C.c_int32),
+                ("max_leaf", C.c_int32), ("min_far_level", C.c_int32),
+                ("near_blocks", C.c_int64), ("near_offdiag_entries", C.c_int64),
+                ("diag_entries", C.c_int64),
+                ("far_blocks", C.c_int64 * HM_MAX_LEVELS),
+                ("far_rank_sum", C.c_int64 * HM_MAX_LEVELS),
+                ("far_entries", C.c_int64 * HM_MAX_LEVELS),
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+
+
+class HmpsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {_lib().hm_strerror(status).decode()} ({status}): "
+                         f"{_lib().hm_last_error().decode()}")
+        self.status = status
+
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libhmps is not built ({LIB_PATH} missing); run "
+                              "`python -m paper_2307_03968_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        lib.hmat_build.argtypes = [C.POINTER(hm_problem), C.POINTER(hm_build_opts), vp, C.POINTER(vp)]
+        lib.hmat_info.argtypes = [vp, C.POINTER(hm_info)]
+        lib.hmat_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, vp]
+        lib.ps_solve.argtypes = [vp, C.POINTER(ps_opts), vp, i64, vp, i64, i32, C.POINTER(ps_stats), vp]
+        lib.hmat_export.argtypes = [vp, C.c_char_p]
+        lib.hmat_free.argtypes = [vp]
+        lib.hm_strerror.argtypes = [C.c_int]
+        lib.hm_strerror.restype = C.c_char_p
+        lib.hm_last_error.restype = C.c_char_p
+        for f in ("hmat_build", "hmat_info", "hmat_apply", "ps_solve", "hmat_export", "hmat_free"):
+            getattr(lib, f).restype = C.c_int
+        _LIB = lib
+    return _LIB
+
+
+def header_functions():
+    """Names of the functions include/hmps.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def _check(status: int, what: str, allow=(HM_OK,)):
+    if status not in allow:
+        raise HmpsError(status, what)
+    return status
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _as_cols(t):
+    """(n,) or (n, nrhs) complex128 CUDA tensor -> (nrhs, n) contiguous."""
+    import torch
+    if t.dtype != torch.complex128 or not t.is_cuda:
+        raise TypeError("expected a complex128 CUDA tensor")
+    if t.dim() == 1:
+        return t.reshape(1, -1).contiguous()
+    return t.t().contiguous()
+
+
+class HMatrix:
+    """Owning wrapper of an hm_matrix_t."""
+
+    def __init__(self, prob, leaf_max: int, eta: float = 1.0, aca_tol: float = 1e-4,
+                 max_rank: int = 0, flags: int = 0, num_threads: int = 0, stream=None):
+        lib = _lib()
+        xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
+        chi = None if prob.chi is None else np.ascontiguousarray(prob.chi, dtype=np.float64)
+        p = hm_problem(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), int(prob.kind),
+                       float(prob.k), float(prob.h),
+                       chi.ctypes.data_as(C.POINTER(C.c_double)) if chi is not None else None)
+        o = hm_build_opts(int(leaf_max), float(eta), float(aca_tol), int(max_rank), int(flags),
+                          int(num_threads))
+        self.host_only = bool(flags & HM_BUILD_HOST_ONLY)
+        st = C.c_void_p(None) if self.host_only else _stream(stream)
+        h = C.c_void_p()
+        _check(lib.hmat_build(C.byref(p), C.byref(o), st, C.byref(h)), "hmat_build")
+        self._h = h
+        self.n = int(xyz.shape[0])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value is not None:
+            _lib().hmat_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        i = hm_info()
+        _check(_lib().hmat_info(self._h, C.byref(i)), "hmat_info")
+        d = {k: getattr(i, k) for k, _ in hm_info._fields_ if not k.startswith("far_")}
+        d["far"] = {lev: {"blocks": i.far_blocks[lev], "rank_sum": i.far_rank_sum[lev],
+                          "entries": i.far_entries[lev]}
+                    for lev in range(HM_MAX_LEVELS) if i.far_blocks[lev]}
+        return d
+
+    def export(self, path: str) -> None:
+        _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")
+
+    def apply(self, x, level: int = -1, precision: int = HM_F64, out=None, stream=None):
+        """y = Z_level x on the device (original point order)."""
+        import torch
+        xc = _as_cols(x)
+        nrhs = xc.shape[0]
+        yc = torch.empty_like(xc) if out is None else out
+        _check(_lib().hmat_apply(self._h, level, precision, C.c_void_p(xc.data_ptr()), self.n,
+                                 C.c_void_p(yc.data_ptr()), self.n, nrhs, _stream(stream)),
+               "hmat_apply")
+        return yc.reshape(-1) if x.dim() == 1 else yc.t()
+
+    def solve(self, b, K: int, level: int = -1, precision: int = HM_F64, kind: int = PS_SERIES,
+              max_passes: int = 0, refine_tol: float = 1e-9, stats: bool = False, out=None,
+              stream=None):
+        """Power-series solve; returns x (and per-RHS stats when asked)."""
+        import torch
+        bc = _as_cols(b)
+        nrhs = bc.shape[0]
+        xc = torch.empty_like(bc) if out is None else out
+        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol))
+        st_arr = (ps_stats * nrhs)() if stats else None
+        status = _lib().ps_solve(self._h, C.byref(o), C.c_void_p(bc.data_ptr()), self.n,
+                                 C.c_void_p(xc.data_ptr()), self.n, nrhs,
+                                 st_arr if stats else None, _stream(stream))
+        _check(status, "ps_solve", allow=(HM_OK, HM_EDIVERGED))
+        x = xc.reshape(-1) if b.dim() == 1 else xc.t()
+        if stats:
+            return x, [{k: getattr(s, k) for k, _ in ps_stats._fields_} for s in st_arr]
+        return x
+
+
+_DT = {1: np.int32, 2: np.int64, 3: np.float64, 4: np.complex128}
+
+
+def read_export(path: str) -> Dict[str, np.ndarray]:
+    """Read the named-array file written by hmat_export."""
+    out = {}
+    with open(path, "rb") as f:
+        while True:
+            hdr = f.read(4)
+            if not hdr:
+                break
+            nl = int(np.frombuffer(hdr, np.uint32)[0])
+            name = f.read(nl).decode()
+            dt, nd = np.frombuffer(f.read(8), np.uint32)
+            shape = tuple(int(s) for s in np.frombuffer(f.read(8 * int(nd)), np.uint64)) if nd else ()
+            dtype = np.dtype(_DT[int(dt)])
+            cnt = int(np.prod(shape)) if shape else 1
+            out[name] = np.frombuffer(f.read(cnt * dtype.itemsize), dtype).reshape(shape)
+    return out

@@ -1,0 +1,144 @@
+"""CPU tests of libhmps: the C-ABI loads and exports what include/hmps.h
+declares, argument errors are reported, and the library's host build of the
+H-matrix (tree, partition, near fill, ACA + recompression, half H-matrix)
+agrees with the independent FP64 oracle (no device is used).
+"""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hmatrix
+from paper_2307_03968_amd import hmps
+
+HOST = hmps.HM_BUILD_HOST_ONLY
+
+
+def test_library_exports_header_symbols():
+    lib = hmps._lib()
+    names = hmps.header_functions()
+    assert {"hmat_build", "hmat_apply", "ps_solve", "hmat_export", "hmat_free"} <= set(names)
+    for f in names:
+        assert hasattr(lib, f), f
+
+
+def _lib_dense(E, n):
+    """Dense H (tree order) from an export, every far level included."""
+    A = np.zeros((n, n), np.complex128)
+    lo, ls = E["leaf_off"], E["leaf_size"]
+    for t, s, off in E["near"]:
+        m, k = ls[t], ls[s]
+        A[lo[t]:lo[t] + m, lo[s]:lo[s] + k] = E["near_data"][off:off + m * k].reshape(k, m).T
+    chi = E.get("chi_tree")
+    for t_off, m, s_off, k, lev, r, off in E["far"]:
+        U = E["far_uv"][off:off + m * r].reshape(r, m).T
+        V = E["far_uv"][off + m * r:off + m * r + k * r].reshape(r, k).T
+        B = U @ V.T
+        if chi is not None:
+            B = B * chi[s_off:s_off + k][None, :]
+        A[t_off:t_off + m, s_off:s_off + k] = B
+    return A
+
+
+CASES = {
+    "sphere_1536": lambda: (W.sphere_small().problem, 64, 1e-4),
+    "sphere_1000_leaf40": lambda: (W.sphere_problem(1000, math.sqrt(1000 / 1536)), 40, 1e-4),
+    "cube_1000_leaf32": lambda: (W.cube_problem(10, 10 / 16), 32, 1e-5),
+    "cube_1728_leaf40": lambda: (W.cube_problem(12, 12 / 16), 40, 1e-5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_build_matches_oracle(case, tmp_path):
+    """Same permutation, same block partition, near blocks to rounding of the
+    entries, far approximants and the whole H-matvec to 1e-12 relative."""
+    prob, leaf, tol = CASES[case]()
+    h = hmps.HMatrix(prob, leaf, 1.0, tol, flags=HOST)
+    path = str(tmp_path / "h.bin")
+    h.export(path)
+    E = hmps.read_export(path)
+    H = hmatrix.HMatrix(prob, leaf, 1.0, tol)
+    assert np.array_equal(E["perm"], H.perm)
+    assert np.array_equal(E["leaf_size"], [c.size for c in H.leaves])
+    lib_near = {(int(t), int(s)) for t, s, _ in E["near"]}
+    assert lib_near == {(b.t, b.s) for b in H.near}
+    lib_far = {tuple(int(v) for v in row[:5]): int(row[5]) for row in E["far"]}
+    or_far = {(b.t_off, b.m, b.s_off, b.n, b.level): b.U.shape[1] for b in H.far}
+    assert set(lib_far) == set(or_far)
+    # ranks: the truncation rule decides the same rank unless a singular
+    # value sits at the threshold to rounding
+    same_rank = sum(lib_far[k] == or_far[k] for k in lib_far)
+    assert same_rank >= len(lib_far) - max(1, len(lib_far) // 500)
+    A_lib = _lib_dense(E, prob.n)
+    lev = min(H.far_levels) if H.far_levels else -1
+    A_or = H.dense(lev)
+    assert np.linalg.norm(A_lib - A_or) <= 1e-12 * np.linalg.norm(A_or)
+    g = np.random.default_rng(5)
+    x = g.standard_normal(prob.n) + 1j * g.standard_normal(prob.n)
+    assert np.linalg.norm(A_lib @ x - A_or @ x) <= 1e-12 * np.linalg.norm(A_or @ x)
+    info = h.info()
+    assert info["num_leaves"] == len(H.leaves) and info["leaf_level"] == H.L
+    assert info["near_blocks"] == len(H.near)
+    h.close()
+
+
+def test_info_counts_match_oracle_stats():
+    prob = W.sphere_small().problem
+    h = hmps.HMatrix(prob, 64, 1.0, 1e-4, flags=HOST)
+    st = hmatrix.HMatrix(prob, 64, 1.0, 1e-4).stats()
+    info = h.info()
+    assert info["near_offdiag_entries"] == st["near_offdiag_entries"]
+    assert info["diag_entries"] == st["diag_entries"]
+    for lev, d in st["far"].items():
+        assert info["far"][lev]["blocks"] == d["blocks"]
+
+
+def _raw_build(n=10, xyz=None, kind=0, chi=None, leaf=8, eta=1.0, tol=1e-4, k=2 * math.pi, hh=0.1):
+    lib = hmps._lib()
+    xyz = np.ascontiguousarray(W.sphere_points(max(n, 1), 0.5) if xyz is None else xyz)
+    p = hmps.hm_problem(n, xyz.ctypes.data_as(C.POINTER(C.c_double)), kind, k, hh,
+                        None if chi is None else chi.ctypes.data_as(C.POINTER(C.c_double)))
+    o = hmps.hm_build_opts(leaf, eta, tol, 0, HOST, 0)
+    h = C.c_void_p()
+    st = lib.hmat_build(C.byref(p), C.byref(o), None, C.byref(h))
+    if st == hmps.HM_OK:
+        lib.hmat_free(h)
+    return st
+
+
+def test_invalid_arguments_rejected():
+    assert _raw_build(n=0) == hmps.HM_EINVAL
+    assert _raw_build(leaf=0) == hmps.HM_EINVAL
+    assert _raw_build(leaf=300) == hmps.HM_EINVAL
+    assert _raw_build(kind=1) == hmps.HM_EINVAL          # volume without chi
+    assert _raw_build(kind=7) == hmps.HM_EINVAL
+    assert _raw_build(tol=0.0) == hmps.HM_EINVAL
+    assert _raw_build(eta=-1.0) == hmps.HM_EINVAL
+    xyz = W.sphere_points(10, 0.5)
+    xyz[3] = xyz[4]
+    assert _raw_build(xyz=xyz) == hmps.HM_EINVAL         # coincident points
+    xyz = W.sphere_points(10, 0.5)
+    xyz[2, 1] = np.nan
+    assert _raw_build(xyz=xyz) == hmps.HM_EINVAL
+    assert _raw_build() == hmps.HM_OK
+    assert b"coincident" not in hmps._lib().hm_strerror(hmps.HM_EINVAL)
+
+
+def test_device_calls_on_host_only_handle():
+    """A host-only handle refuses device work with HM_ESTATE (no device touched)."""
+    h = hmps.HMatrix(W.sphere_problem(100, 0.5), 32, flags=HOST)
+    lib = hmps._lib()
+    o = hmps.ps_opts(2, -1, 0, 0, 0, 1e-9)
+    assert lib.ps_solve(h.handle, C.byref(o), None, 100, None, 100, 1, None, None) == hmps.HM_ESTATE
+    assert lib.hmat_apply(h.handle, -1, 0, None, 100, None, 100, 1, None) == hmps.HM_ESTATE
+    h.close()
+
+
+def test_single_point_and_single_leaf():
+    for n in (1, 5, 64):
+        h = hmps.HMatrix(W.sphere_problem(n, 0.5), 64, flags=HOST)
+        info = h.info()
+        assert info["num_leaves"] == 1 and info["min_far_level"] == -1
+        h.close()
