@@ -135,7 +135,31 @@ typedef struct {
   int64_t far_entries[HM_MAX_LEVELS];  /* sum r (m + n)                      */
   int64_t device_bytes;             /* device memory held by the handle     */
   double build_ms;                  /* host build + upload + device LU       */
+  /* Entries (complex elements) a product at far level l reads, by level;
+   * zero for levels without far blocks when far blocks exist elsewhere:
+   *   series_entries  D^{-1}-premultiplied near and far columns (one term)
+   *   apply_entries   D, near and far columns of Z_l (one H-matvec)
+   *   stageA_entries  W_b of the far blocks of level >= l
+   *   coeffs          stage-A coefficients of the far blocks of level >= l */
+  int64_t series_entries[HM_MAX_LEVELS];
+  int64_t apply_entries[HM_MAX_LEVELS];
+  int64_t stageA_entries[HM_MAX_LEVELS];
+  int64_t coeffs[HM_MAX_LEVELS];
 } hm_info;
+
+/* Kernel classes timed by hm_profile_enable. */
+enum {
+  HM_K_STAGEA = 0,        /* t_b = W_b y_s                                  */
+  HM_K_PANEL_SERIES = 1,  /* D^{-1}-premultiplied near + far columns        */
+  HM_K_PANEL_APPLY = 2,   /* H-matvec panels (residual, hmat_apply)         */
+  HM_K_PANEL_DINV = 3,    /* y_0 = D^{-1} b                                 */
+  HM_K_EPILOGUE = 4,      /* partial-sum reduction and term update          */
+  HM_K_COUNT = 5
+};
+typedef struct {
+  int64_t launches;
+  double total_ms;        /* sum of per-launch durations from HIP events    */
+} hm_kernel_time;
 
 typedef struct hm_matrix* hm_matrix_t;
 
@@ -171,6 +195,14 @@ int ps_solve(hm_matrix_t h, const ps_opts* opts, const void* b_dev, int64_t ldb,
  * raw little-endian data.  For checking the build against an independent
  * implementation. */
 int hmat_export(hm_matrix_t h, const char* path);
+
+/* Per-kernel timing for measurement: while enabled, every launch of the
+ * classes above is bracketed by HIP events recorded on the launch stream.
+ * Enabling (or disabling) resets the counters. */
+int hm_profile_enable(hm_matrix_t h, int32_t enable);
+/* Synchronise the recorded events and return launches and summed durations
+ * per class (out has HM_K_COUNT entries). */
+int hm_profile_read(hm_matrix_t h, hm_kernel_time* out);
 
 /* Release the handle and all its device memory (synchronises the device). */
 int hmat_free(hm_matrix_t h);

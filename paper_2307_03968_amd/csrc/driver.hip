@@ -81,7 +81,7 @@ struct hm_matrix {
   float2* W32 = nullptr;
   hm::StageABlock* blk = nullptr;
   std::vector<int> nA;          // per level index: active far blocks (prefix)
-  std::vector<int64_t> bytes_R, bytes_M, bytes_W;  // per level index, FP64 element counts
+  std::vector<int64_t> bytes_R, bytes_M, bytes_W, ncoef;  // per level index, element counts
   // work lists
   std::vector<hm::WorkList> wl_apply, wl_series;
   hm::WorkList wl_dinv;
@@ -93,8 +93,15 @@ struct hm_matrix {
   double *nscratch = nullptr, *norms = nullptr;
   double* norms_host = nullptr;  // pinned
   std::vector<void*> ws_allocs;
+  // per-kernel timing
+  bool prof = false;
+  struct ProfRec { int cls; hipEvent_t e0, e1; };
+  std::vector<ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
 
   ~hm_matrix() {
+    for (auto& r : prof_recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
+    for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : ws_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
     if (norms_host) (void)hipHostFree(norms_host);
@@ -228,6 +235,37 @@ EpilogueArgs epi(const hm_matrix* h, const WorkList& wl, int64_t ldp) {
 
 #define LCHK(x) HIPCHK(x)
 
+hipEvent_t pool_event(hm_matrix* h) {
+  if (!h->ev_pool.empty()) {
+    hipEvent_t e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one kernel launch with events when profiling is on.
+struct ProfScope {
+  hm_matrix* h;
+  int cls;
+  hipStream_t st;
+  hipEvent_t e0 = nullptr;
+  ProfScope(hm_matrix* h_, int cls_, hipStream_t st_) : h(h_), cls(cls_), st(st_) {
+    if (h->prof && (e0 = pool_event(h)) != nullptr) (void)hipEventRecord(e0, st);
+  }
+  void done() {
+    if (!e0) return;
+    hipEvent_t e1 = pool_event(h);
+    if (!e1) { h->ev_pool.push_back(e0); e0 = nullptr; return; }
+    (void)hipEventRecord(e1, st);
+    h->prof_recs.push_back({cls, e0, e1});
+    e0 = nullptr;
+  }
+  ~ProfScope() { if (e0) h->ev_pool.push_back(e0); }
+};
+
 // x_out = P_K rhs (tree order, ld N), as the power series of Sec. IV.
 // y_0 = D^{-1} rhs; y_k = -(D^{-1} R_l) y_{k-1}; x = sum y_k.
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, double2* x_out,
@@ -235,22 +273,38 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, doubl
   const int64_t N = h->N, ldin = h->N + h->T, ldp = h->partial_rows;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
-  LCHK(launch_panel(false, h->max_m, dinv_set(h), h->wl_dinv.items, h->wl_dinv.n, rhs, N, nrhs,
-                    h->partial, ldp, st));
+  {
+    ProfScope ps(h, HM_K_PANEL_DINV, st);
+    LCHK(launch_panel(false, h->max_m, dinv_set(h), h->wl_dinv.items, h->wl_dinv.n, rhs, N, nrhs,
+                      h->partial, ldp, st));
+    ps.done();
+  }
   EpilogueArgs e = epi(h, h->wl_dinv, ldp);
   e.yout = y_cur;
   e.ldy = ldin;
   e.xacc = x_out;
   e.ldxa = N;
   e.accumulate = 0;
-  LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
+  {
+    ProfScope ps(h, HM_K_EPILOGUE, st);
+    LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
+    ps.done();
+  }
   if (want_norms) LCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch, h->norms, st));
   const WorkList& wl = h->wl_series[li];
   const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
   for (int k = 1; k <= K; ++k) {
-    LCHK(launch_stageA(f32, W, h->blk, h->nA[li], y_cur, ldin, N, nrhs, st));
-    LCHK(launch_panel(f32, h->max_m, series_set(h, f32), wl.items, wl.n, y_cur, ldin, nrhs,
-                      h->partial, ldp, st));
+    {
+      ProfScope ps(h, HM_K_STAGEA, st);
+      LCHK(launch_stageA(f32, W, h->blk, h->nA[li], y_cur, ldin, N, nrhs, st));
+      ps.done();
+    }
+    {
+      ProfScope ps(h, HM_K_PANEL_SERIES, st);
+      LCHK(launch_panel(f32, h->max_m, series_set(h, f32), wl.items, wl.n, y_cur, ldin, nrhs,
+                        h->partial, ldp, st));
+      ps.done();
+    }
     EpilogueArgs t = epi(h, wl, ldp);
     t.alpha = -1.0;
     t.yout = y_nxt;
@@ -258,7 +312,11 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, doubl
     t.xacc = x_out;
     t.ldxa = N;
     t.accumulate = 1;
-    LCHK(launch_epilogue(t, h->nl, h->max_m, nrhs, st));
+    {
+      ProfScope ps(h, HM_K_EPILOGUE, st);
+      LCHK(launch_epilogue(t, h->nl, h->max_m, nrhs, st));
+      ps.done();
+    }
     std::swap(y_cur, y_nxt);
   }
   if (want_norms)
@@ -272,10 +330,18 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
                const double2* v, double2* out, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T, ldp = h->partial_rows;
   const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
-  LCHK(launch_stageA(f32, W, h->blk, h->nA[li], h->xin0, ldin, N, nrhs, st));
+  {
+    ProfScope ps(h, HM_K_STAGEA, st);
+    LCHK(launch_stageA(f32, W, h->blk, h->nA[li], h->xin0, ldin, N, nrhs, st));
+    ps.done();
+  }
   const WorkList& wl = h->wl_apply[li];
-  LCHK(launch_panel(f32, h->max_m, apply_set(h, f32), wl.items, wl.n, h->xin0, ldin, nrhs,
-                    h->partial, ldp, st));
+  {
+    ProfScope ps(h, HM_K_PANEL_APPLY, st);
+    LCHK(launch_panel(f32, h->max_m, apply_set(h, f32), wl.items, wl.n, h->xin0, ldin, nrhs,
+                      h->partial, ldp, st));
+    ps.done();
+  }
   EpilogueArgs e = epi(h, wl, ldp);
   e.alpha = alpha;
   e.beta = beta;
@@ -283,7 +349,11 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
   e.ldv = N;
   e.yout = out;
   e.ldy = N;
-  LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
+  {
+    ProfScope ps(h, HM_K_EPILOGUE, st);
+    LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
+    ps.done();
+  }
   return HM_OK;
 }
 
@@ -505,8 +575,9 @@ int build_device(hm_matrix* h, hipStream_t st) {
   h->bytes_R.assign(h->nlev, 0);
   h->bytes_M.assign(h->nlev, 0);
   h->bytes_W.assign(h->nlev, 0);
+  h->ncoef.assign(h->nlev, 0);
   for (int li = 0; li < h->nlev; ++li) {
-    int64_t eR = 0, eM = 0, eW = 0;
+    int64_t eR = 0, eM = 0, eW = 0, nc = 0;
     for (int a = 0; a < nl; ++a) {
       last[a] = H.leaf_size[a] + near_cols[a] + far_end[li][a];
       eR += (int64_t)H.leaf_size[a] * last[a];
@@ -517,7 +588,11 @@ int build_device(hm_matrix* h, hipStream_t st) {
       eM += (int64_t)H.leaf_size[a] * last[a];
     }
     STCHK(make_worklist(h, zero, last, h->wl_series[li], st));
-    for (int b = 0; b < h->nA[li]; ++b) eW += (int64_t)blk[b].r * blk[b].n;
+    for (int b = 0; b < h->nA[li]; ++b) {
+      eW += (int64_t)blk[b].r * blk[b].n;
+      nc += blk[b].r;
+    }
+    h->ncoef[li] = nc;
     h->bytes_R[li] = eR;
     h->bytes_M[li] = eM;
     h->bytes_W[li] = eW;
@@ -571,6 +646,14 @@ void fill_info(const hm_matrix* h, hm_info* out) {
   }
   out->device_bytes = h->bytes;
   out->build_ms = h->build_ms;
+  for (int li = 0; li < (int)h->bytes_M.size(); ++li) {
+    const int lev = (h->lmin < 0) ? h->L : h->lmin + li;
+    if (lev < 0 || lev >= HM_MAX_LEVELS) continue;
+    out->series_entries[lev] = h->bytes_M[li];
+    out->apply_entries[lev] = h->bytes_R[li];
+    out->stageA_entries[lev] = h->bytes_W[li];
+    out->coeffs[lev] = h->ncoef[li];
+  }
 }
 
 }  // namespace
@@ -781,6 +864,30 @@ int hmat_export(hm_matrix_t h, const char* path) {
   HIPCHK(hipMemcpy(lu.data(), h->LU, sizeof(cplx) * dtot, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(piv.data(), h->piv, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost));
   return export_host(h->H, path, &lu, &piv);
+}
+
+int hm_profile_enable(hm_matrix_t h, int32_t enable) {
+  if (!h) { set_error("null handle"); return HM_EINVAL; }
+  if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
+  HIPCHK(hipSetDevice(h->device));
+  HIPCHK(hipDeviceSynchronize());
+  for (auto& r : h->prof_recs) { h->ev_pool.push_back(r.e0); h->ev_pool.push_back(r.e1); }
+  h->prof_recs.clear();
+  h->prof = enable != 0;
+  return HM_OK;
+}
+
+int hm_profile_read(hm_matrix_t h, hm_kernel_time* out) {
+  if (!h || !out) { set_error("null argument"); return HM_EINVAL; }
+  for (int c = 0; c < HM_K_COUNT; ++c) out[c] = hm_kernel_time{0, 0.0};
+  for (auto& r : h->prof_recs) {
+    HIPCHK(hipEventSynchronize(r.e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, r.e0, r.e1));
+    out[r.cls].launches += 1;
+    out[r.cls].total_ms += ms;
+  }
+  return HM_OK;
 }
 
 int hmat_free(hm_matrix_t h) {

@@ -58,7 +58,18 @@ class hm_info(C.Structure):
                 ("far_blocks", C.c_int64 * HM_MAX_LEVELS),
                 ("far_rank_sum", C.c_int64 * HM_MAX_LEVELS),
                 ("far_entries", C.c_int64 * HM_MAX_LEVELS),
-                ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+                ("device_bytes", C.c_int64), ("build_ms", C.c_double),
+                ("series_entries", C.c_int64 * HM_MAX_LEVELS),
+                ("apply_entries", C.c_int64 * HM_MAX_LEVELS),
+                ("stageA_entries", C.c_int64 * HM_MAX_LEVELS),
+                ("coeffs", C.c_int64 * HM_MAX_LEVELS)]
+
+
+HM_K_STAGEA, HM_K_PANEL_SERIES, HM_K_PANEL_APPLY, HM_K_PANEL_DINV, HM_K_EPILOGUE, HM_K_COUNT = range(6)
+
+
+class hm_kernel_time(C.Structure):
+    _fields_ = [("launches", C.c_int64), ("total_ms", C.c_double)]
 
 
 class HmpsError(RuntimeError):
@@ -85,10 +96,13 @@ def _lib():
         lib.ps_solve.argtypes = [vp, C.POINTER(ps_opts), vp, i64, vp, i64, i32, C.POINTER(ps_stats), vp]
         lib.hmat_export.argtypes = [vp, C.c_char_p]
         lib.hmat_free.argtypes = [vp]
+        lib.hm_profile_enable.argtypes = [vp, i32]
+        lib.hm_profile_read.argtypes = [vp, C.POINTER(hm_kernel_time)]
         lib.hm_strerror.argtypes = [C.c_int]
         lib.hm_strerror.restype = C.c_char_p
         lib.hm_last_error.restype = C.c_char_p
-        for f in ("hmat_build", "hmat_info", "hmat_apply", "ps_solve", "hmat_export", "hmat_free"):
+        for f in ("hmat_build", "hmat_info", "hmat_apply", "ps_solve", "hmat_export", "hmat_free",
+                  "hm_profile_enable", "hm_profile_read"):
             getattr(lib, f).restype = C.c_int
         _LIB = lib
     return _LIB
@@ -161,7 +175,10 @@ class HMatrix:
     def info(self) -> dict:
         i = hm_info()
         _check(_lib().hmat_info(self._h, C.byref(i)), "hmat_info")
-        d = {k: getattr(i, k) for k, _ in hm_info._fields_ if not k.startswith("far_")}
+        per_level = ("far_", "series_entries", "apply_entries", "stageA_entries", "coeffs")
+        d = {k: getattr(i, k) for k, _ in hm_info._fields_ if not k.startswith(per_level)}
+        for k in per_level[1:]:
+            d[k] = list(getattr(i, k))
         d["far"] = {lev: {"blocks": i.far_blocks[lev], "rank_sum": i.far_rank_sum[lev],
                           "entries": i.far_entries[lev]}
                     for lev in range(HM_MAX_LEVELS) if i.far_blocks[lev]}
