@@ -149,12 +149,14 @@ typedef struct {
 
 /* Kernel classes timed by hm_profile_enable. */
 enum {
-  HM_K_STAGEA = 0,        /* t_b = W_b y_s                                  */
-  HM_K_PANEL_SERIES = 1,  /* D^{-1}-premultiplied near + far columns        */
-  HM_K_PANEL_APPLY = 2,   /* H-matvec panels (residual, hmat_apply)         */
-  HM_K_PANEL_DINV = 3,    /* y_0 = D^{-1} b                                 */
-  HM_K_EPILOGUE = 4,      /* partial-sum reduction and term update          */
-  HM_K_COUNT = 5
+  HM_K_STAGEA = 0,       /* t_b = W_b y_s for far blocks whose row cluster
+                            spans several leaves (levels above the leaf level) */
+  HM_K_TERM_SERIES = 1,  /* one power-series term: D^{-1}-premultiplied near
+                            and far products, in-row low-rank blocks, y and x
+                            update (one launch per term)                      */
+  HM_K_TERM_APPLY = 2,   /* one H-matvec (hmat_apply, refinement residual)   */
+  HM_K_TERM_DINV = 3,    /* y_0 = D^{-1} b                                    */
+  HM_K_COUNT = 4
 };
 typedef struct {
   int64_t launches;

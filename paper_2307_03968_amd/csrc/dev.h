@@ -1,17 +1,23 @@
 // Device-side data layout and kernel launchers of libhmps (internal).
 //
-// Layout in HBM (all tree order):
-//   * a "panel" per leaf row a: column-major m_a x C_a, complex, ld = m_a.
-//     The apply panel holds [D_a | near blocks (a, s != a) | far slices]; the
-//     series panel holds D_a^{-1} times the same columns without D_a.  Far
-//     slices are the rows of the leaf inside U_b (m_b x r_b) of every far
-//     block b whose row cluster contains the leaf, ordered finest level
-//     first, so the blocks of level >= l are a prefix of the far columns.
-//   * every panel column has a source index into the combined input vector
-//     [y (N) | t (T)] of one right-hand side, where t holds the stage-A
-//     coefficients t_b = W_b y_s of all far blocks (T = sum of ranks).
-//   * W_b (r_b x n_b, row-major), finest level first, with the contrast of
-//     the source points folded in for the volume case.
+// Layout in HBM (all tree order, complex elements, column-major):
+//   * a "panel" per leaf row a with leading dimension ld_a = m_a rounded up
+//     to even (zero pad row when m_a is odd, so FP32 panels can be read two
+//     rows per 16-byte load).  The apply panel holds
+//       [D_a | near blocks (a, s != a) | in-row far | global far]
+//     and the series panel D_a^{-1} times the same columns without D_a; the
+//     D^{-1} panel holds D_a^{-1}.
+//   * a far block is "in-row" when its row cluster is a single leaf (every
+//     leaf-level block is).  Its panel columns are U_b (m_a x r_b) and its W_b
+//     (r_b x n_b) is a block of rows of the leaf's W stack, so one workgroup
+//     forms t_b = W_b y_s and applies U_b t_b without a separate pass.
+//     Other far blocks are "global": U_b is sliced into the panels of the
+//     leaves of its row cluster and t_b comes from a separate stage-A pass
+//     grouped by source cluster (W_g column-major, even leading dimension),
+//     written into the t part of the combined input vector [y (N) | t (T)].
+//   * far columns (and W stack rows) are ordered finest level first, so the
+//     blocks of level >= l are a prefix of the in-row and of the global part.
+//   * every dense panel column has a source index into [y | t].
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,58 +26,106 @@
 
 namespace hm {
 
-struct WorkItem {      // one workgroup of the panel product
-  int32_t leaf;
-  int32_t c0, c1;      // panel column range [c0, c1)
-  int32_t prow;        // first row of its partial sums in the partial buffer
-};
+inline int even_ld(int m) { return m + (m & 1); }
 
 struct PanelSet {
-  const void* data;          // double2 or float2 elements
-  const int64_t* panel_off;  // per leaf: element offset of the panel
+  const void* data;          // double2 (FP64) or float2 pairs (FP32) elements
+  const int64_t* panel_off;  // per leaf: complex-element offset of the panel
   const int32_t* src;        // per panel column: row in the input vector
   const int64_t* col_off;    // per leaf: index of its first column in src
-  const int32_t* leaf_m;     // per leaf: rows
+  const int32_t* leaf_m;     // per leaf: rows (ld = m rounded up to even)
 };
 
-struct StageABlock {
-  int32_t s_off, n, r, tb_off;  // source range, rank, coefficient offset in t
-  int64_t w_off;                // element offset of W_b
+// One piece of the work of a term kernel.  The pieces of all leaves are
+// split evenly over a fixed number of persistent workgroups (one resident
+// round), each workgroup taking a contiguous run of pieces.
+//  kind 0: panel columns [c0, c1) against the input vector through src.
+//  kind 1: in-row low-rank rows [r0, r1) of the leaf's W stack (at most
+//          kInRowTile): first t = W_stack[r0:r1, :] y (each row has its own
+//          source range), then the panel columns c0 .. c0 + (r1 - r0) against t.
+struct TermItem {
+  int32_t leaf, kind;
+  int32_t c0, c1;
+  int32_t r0, r1;
+  int32_t prow;              // first row of its partial sums
+  int32_t pad;
 };
 
-struct EpilogueArgs {
+struct InRow {               // per-leaf W stacks of the in-row far blocks
+  const void* W;             // double2 or float2 elements
+  const int64_t* off;        // per leaf: complex-element offset of the stack
+  const int32_t* ld;         // per leaf: leading dimension (even)
+  const int32_t* ncol;       // per leaf: columns (largest source size)
+  const int32_t* row0;       // per leaf: first row in soff / n
+  const int32_t* soff;       // per stack row: source offset (tree order)
+  const int32_t* n;          // per stack row: source size
+};
+
+struct Group {                // stage-A group (one source cluster)
+  int32_t s_off, n;           // source points [s_off, s_off + n)
+  int32_t t0, ld;             // first coefficient in t, leading dimension of W_g
+  int64_t w_off;              // complex-element offset of W_g
+};
+
+struct GroupItem {            // one workgroup of a group product
+  int32_t group;
+  int32_t row0, rows;         // row tile start and active rows of the group
+  int32_t pad;
+};
+
+struct TermArgs {
+  PanelSet ps;
+  InRow ir;
+  const TermItem* items;     // pieces, grouped by workgroup
+  const int32_t* wptr;       // per workgroup: first piece (count + 1 entries)
+  const int32_t* lptr;       // per leaf: first entry in lprow (nleaves + 1)
+  const int32_t* lprow;      // partial rows of each leaf's pieces, fixed order
   const int32_t* leaf_off;
-  const int32_t* leaf_m;
-  const int32_t* item_ptr;   // per leaf: first work item (items sorted by leaf)
-  const WorkItem* items;
-  const double2* partial;
+  const double2* xin;        // [y | t] input, column stride ldx
+  int64_t ldx;
+  const int64_t* in_perm;    // non-null: kind-0 inputs read xin[in_perm[src]]
+  double2* partial;
   int64_t ldp;
-  double alpha;              // y = alpha * z + beta * v
-  double beta;
-  const double2* v;          // may be null
+  int32_t* counters;         // per (leaf, rhs tile); zero between launches
+  // epilogue of leaf a, run by its last workgroup: y = alpha z + beta v
+  double alpha, beta;
+  const double2* v;          // may be null (tree order, ld ldv)
   int64_t ldv;
-  double2* yout;             // may be null
+  double2* yout;             // may be null (tree order, ld ldy)
   int64_t ldy;
-  double2* xacc;             // may be null
+  double2* xacc;             // may be null: x = y or x += y (tree order)
   int64_t ldxa;
-  int accumulate;            // xacc += y (1) or xacc = y (0)
+  int accumulate;
+  double2* out;              // may be null: out[out_perm[q]] = new x (or y)
+  int64_t ldo;
+  const int64_t* out_perm;
 };
+
+constexpr int kInRowTile = 128;  // stack rows per kind-1 item
+constexpr int kGroupTile = 128;  // rows per stage-A group item
 
 // ---- launchers (return hipError_t of the launch) ---------------------------
 hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm, double2* out,
                              int64_t ldo, int64_t n, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, double2* x,
                               int64_t ldx, int64_t n, int nrhs, hipStream_t st);
-hipError_t launch_panel(bool f32, int max_m, const PanelSet& ps, const WorkItem* items, int nitems,
-                        const double2* xin, int64_t ldx, int nrhs, double2* partial, int64_t ldp,
-                        hipStream_t st);
-hipError_t launch_stageA(bool f32, const void* W, const StageABlock* blk, int nblk, double2* xin,
-                         int64_t ldx, int64_t N, int nrhs, hipStream_t st);
-hipError_t launch_epilogue(const EpilogueArgs& e, int nleaves, int max_m, int nrhs, hipStream_t st);
+// nwg persistent workgroups; grid.y covers the right-hand sides
+hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
+                       hipStream_t st);
+// workgroups of the 1-RHS term kernel that fit on one CU at once
+int term_occupancy(bool f32, int max_m);
+// number of right-hand sides one term workgroup handles for nrhs
+int term_rhs_tile(int nrhs);
+// t rows of the listed group tiles: xin[N + t0 + row] = W_g xin[s_off ...]
+hipError_t launch_stageA(bool f32, const void* W, const Group* groups, const GroupItem* items,
+                         int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs,
+                         hipStream_t st);
 hipError_t launch_getrf(double2* A, const int64_t* off, const int32_t* m, int32_t* piv,
                         const int64_t* piv_off, int nblk, int* info, hipStream_t st);
+// D^{-1} into panels of even leading dimension at dinv_off
 hipError_t launch_getri(const double2* LU, const int64_t* off, const int32_t* m, const int32_t* piv,
-                        const int64_t* piv_off, double2* Ainv, int nblk, hipStream_t st);
+                        const int64_t* piv_off, double2* Ainv, const int64_t* dinv_off, int nblk,
+                        hipStream_t st);
 // M panel columns c of leaf a = Dinv_a * (apply panel column m_a + c)
 hipError_t launch_premul(const double2* Dinv, const int64_t* dinv_off, const double2* P,
                          const int64_t* p_off, const int32_t* leaf_m, const int32_t* ncols_m,

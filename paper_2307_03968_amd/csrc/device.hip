@@ -1,12 +1,18 @@
 // HIP kernels of libhmps for gfx950 (CDNA4, wave64).
 //
-// Hot loop of the power series (Sec. IV, eq. 12-13 and 20-22), one term:
-//   stage A   t_b = W_b y_s for every far block of level >= l   (k_stageA)
-//   panel     z_a = sum over the leaf's series panel columns     (k_panel)
-//             = D_a^{-1} (R_l y)_a, split over several workgroups per leaf
-//   epilogue  y_a = -z_a, x_a += y_a                              (k_epilogue)
-// The 1-RHS products are HBM-bound GEMVs (0.5 flop/B in FP64), so they stay
-// on the vector ALUs with wide coalesced loads; no MFMA.
+// Hot loop of the power series (Sec. IV, eq. 12-13 and 20-22): one launch
+// of k_term per term.  Its workgroups cover a leaf's series panel
+// D_a^{-1} [near | far] in column ranges, and the leaf's in-row low-rank
+// blocks (t = W y in LDS, then D_a^{-1} U t); each writes partial sums, and
+// the last workgroup of the leaf to finish (a device-scope counter) reduces
+// them in a fixed order into y_a = -z_a and updates x_a.  Far blocks whose
+// row cluster spans several leaves need t = W y first (k_stageA), one
+// launch before k_term, only when levels above the leaf level are used.
+// One-RHS products are HBM-bound GEMVs (0.5 flop/B in FP64, 1 in FP32), so
+// they run on the vector ALUs: each lane owns one row (FP64) or two rows
+// (FP32) of a column-major panel and every load is 16 bytes, so a wave
+// reads 1 KiB of contiguous panel per instruction; UNR columns are loaded
+// before they are used so that enough bytes are in flight per CU.
 #include <hip/hip_runtime.h>
 
 #include "dev.h"
@@ -19,8 +25,6 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
 __device__ __forceinline__ double2 zero2() { return make_double2(0.0, 0.0); }
-__device__ __forceinline__ double2 widen(double2 a) { return a; }
-__device__ __forceinline__ double2 widen(float2 a) { return make_double2((double)a.x, (double)a.y); }
 
 // acc += a * x (complex)
 __device__ __forceinline__ void cmac(double2& acc, double2 a, double2 x) {
@@ -34,22 +38,130 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
-template <typename TM>
-__device__ __forceinline__ TM zero_elem();
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+// E = complex rows per 16-byte lane load: 1 for FP64 (double2), 2 for FP32
+// (float4 = two consecutive complex64 of one column).  Block data is read
+// once per term and does not fit in the caches, so it is loaded with the
+// non-temporal hint (streaming loads measured ~13% faster on gfx950).
+template <int E>
+struct Elem;
 template <>
-__device__ __forceinline__ double2 zero_elem<double2>() { return make_double2(0.0, 0.0); }
+struct Elem<1> {
+  using T = double2;
+  __device__ static __forceinline__ T zero() { return make_double2(0.0, 0.0); }
+  __device__ static __forceinline__ T load(const void* base, int64_t idx) {
+    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(base) + idx);
+    return make_double2(v.x, v.y);
+  }
+  __device__ static __forceinline__ double2 get(const T& a, int) { return a; }
+  __device__ static __forceinline__ const void* offset(const void* base, int64_t n) {
+    return reinterpret_cast<const double2*>(base) + n;
+  }
+};
 template <>
-__device__ __forceinline__ float2 zero_elem<float2>() { return make_float2(0.f, 0.f); }
+struct Elem<2> {
+  using T = float4;
+  __device__ static __forceinline__ T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  __device__ static __forceinline__ T load(const void* base, int64_t idx) {  // idx even
+    const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4*>(base) + (idx >> 1));
+    return make_float4(v.x, v.y, v.z, v.w);
+  }
+  __device__ static __forceinline__ double2 get(const T& a, int e) {
+    return e == 0 ? make_double2((double)a.x, (double)a.y) : make_double2((double)a.z, (double)a.w);
+  }
+  __device__ static __forceinline__ const void* offset(const void* base, int64_t n) {
+    return reinterpret_cast<const float2*>(base) + n;
+  }
+};
+
+// Lane l of wave w accumulates rows row0 + (g*64 + l)*E + e (g < G, e < E)
+// of the column-major matrix P (leading dimension ld >= rows) against the
+// input X(c, r), over columns c0 + w + kWaves*k < c1.  Loads are issued
+// without branches: the row index is clamped into the column (lanes past
+// `rows` re-read a valid element whose sum is never stored) and columns past
+// c1 re-read column c1 - 1 with a zero input.
+template <int E, int G, int NR, int UNR, typename XF>
+__device__ __forceinline__ void tall_gemv(const void* __restrict__ P, int64_t ld, int rows,
+                                          int row0, int c0, int c1, int w, int lane, const XF& X,
+                                          double2 (&acc)[G][E][NR]) {
+  using T = typename Elem<E>::T;
+  (void)rows;
+  int64_t ri[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) ri[g] = min<int64_t>(row0 + (g * 64 + lane) * E, ld - E);
+  for (int c = c0 + w; c < c1; c += kWaves * UNR) {
+    T a[UNR][G];
+    double2 xv[UNR][NR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int cc = c + kWaves * u;
+      const bool ok = cc < c1;
+      const int64_t col = (int64_t)(ok ? cc : c1 - 1) * ld;
+#pragma unroll
+      for (int g = 0; g < G; ++g) a[u][g] = Elem<E>::load(P, ri[g] + col);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const double2 v = X(ok ? cc : c1 - 1, r);
+        xv[u][r] = ok ? v : zero2();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cmac(acc[g][e][r], Elem<E>::get(a[u][g], e), xv[u][r]);
+  }
+}
+
+// Sum acc over the waves of the workgroup into wave 0 (through LDS).
+template <int E, int G, int NR>
+__device__ __forceinline__ void reduce_waves(double2 (&acc)[G][E][NR], int w, int lane,
+                                             double2* red) {
+  constexpr int S = G * E * NR;
+  if (w > 0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          red[((w - 1) * S + (g * E + e) * NR + r) * 64 + lane] = acc[g][e][r];
+  }
+  __syncthreads();
+  if (w == 0) {
+#pragma unroll
+    for (int v = 0; v < kWaves - 1; ++v)
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const double2 o = red[(v * S + (g * E + e) * NR + r) * 64 + lane];
+            acc[g][e][r].x += o.x;
+            acc[g][e][r].y += o.y;
+          }
+  }
+}
+
+template <int E, int G, int NR>
+__device__ __forceinline__ void zero_acc(double2 (&acc)[G][E][NR]) {
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) acc[g][e][r] = zero2();
+}
 
 // ---------------------------------------------------------------- permute
 __global__ void k_permute_in(const double2* __restrict__ b, int64_t ldb,
@@ -68,174 +180,285 @@ __global__ void k_permute_out(const double2* __restrict__ in, int64_t ldi,
   if (q < n) x[perm[q] + c * ldx] = in[q + c * ldi];
 }
 
-// ---------------------------------------------------------------- panel GEMV
-// One workgroup = one work item (leaf row, column range).  Lane l of every
-// wave owns rows l, l+64, ... of the leaf; the four waves take interleaved
-// columns so that a workgroup streams consecutive panel columns; UNR columns
-// per wave are loaded before they are used to keep enough bytes in flight.
-template <typename TM, int RPL, int NR, int UNR>
-__global__ __launch_bounds__(kThreads) void k_panel(PanelSet ps, const WorkItem* __restrict__ items,
-                                                    const double2* __restrict__ xin, int64_t ldx,
-                                                    int nrhs, double2* __restrict__ partial,
-                                                    int64_t ldp) {
-  const WorkItem it = items[blockIdx.x];
-  const int m = ps.leaf_m[it.leaf];
-  const TM* __restrict__ P = reinterpret_cast<const TM*>(ps.data) + ps.panel_off[it.leaf];
-  const int32_t* __restrict__ src = ps.src + ps.col_off[it.leaf];
-  const int rhs0 = blockIdx.y * NR;
-  const int w = wave_id();
-  const int lane = threadIdx.x & 63;
-
-  double2 acc[RPL][NR];
+// ---------------------------------------------------------------- term
+// In-row low-rank rows: lane l of wave w owns stack rows r0 + (g*64 + l)*E + e
+// (each with its own source range) and accumulates W[row, j] y[soff + j] over
+// the columns j = w + kWaves*k < ncol.
+template <int E, int GW, int NR, int UNR>
+__device__ __forceinline__ void inrow_t(const void* __restrict__ Wa, int64_t wld, int ncol,
+                                        int r0, int r1, const int32_t* __restrict__ soff_a,
+                                        const int32_t* __restrict__ n_a,
+                                        const double2* __restrict__ xin, int64_t ldx, int rhs0,
+                                        int nrhs, int w, int lane, double2 (&acc)[GW][E][NR]) {
+  using T = typename Elem<E>::T;
+  int so[GW][E], nn[GW][E];
+  int64_t ri[GW];
 #pragma unroll
-  for (int q = 0; q < RPL; ++q)
+  for (int g = 0; g < GW; ++g) {
+    ri[g] = min<int64_t>(r0 + (g * 64 + lane) * E, wld - E);
 #pragma unroll
-    for (int r = 0; r < NR; ++r) acc[q][r] = zero2();
-
-  for (int c = it.c0 + w; c < it.c1; c += kWaves * UNR) {
-    TM a[UNR][RPL];
-    double2 xv[UNR][NR];
+    for (int e = 0; e < E; ++e) {
+      const int row = r0 + (g * 64 + lane) * E + e;
+      so[g][e] = row < r1 ? soff_a[row] : 0;
+      nn[g][e] = row < r1 ? n_a[row] : 0;
+    }
+  }
+  for (int c = w; c < ncol; c += kWaves * UNR) {
+    T wv[UNR][GW];
+    double2 yv[UNR][GW][E][NR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int cc = c + kWaves * u;
-      const bool ok = cc < it.c1;
-      const int64_t s = ok ? (int64_t)src[cc] : 0;
+      const int64_t col = (int64_t)(cc < ncol ? cc : ncol - 1) * wld;
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        xv[u][r] = (ok && rhs0 + r < nrhs) ? xin[s + (int64_t)(rhs0 + r) * ldx] : zero2();
+      for (int g = 0; g < GW; ++g) {
+        wv[u][g] = Elem<E>::load(Wa, ri[g] + col);
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        const int i = lane + 64 * q;
-        a[u][q] = (ok && i < m) ? P[i + (int64_t)cc * m] : zero_elem<TM>();
+        for (int e = 0; e < E; ++e) {
+          const bool ok = cc < nn[g][e];
+          const int64_t yi = so[g][e] + (ok ? cc : 0);
+#pragma unroll
+          for (int r = 0; r < NR; ++r) {
+            const int rr = rhs0 + r < nrhs ? rhs0 + r : rhs0;
+            const double2 v = xin[yi + (int64_t)rr * ldx];
+            yv[u][g][e][r] = (ok && rhs0 + r < nrhs) ? v : zero2();
+          }
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u)
 #pragma unroll
-      for (int q = 0; q < RPL; ++q)
+      for (int g = 0; g < GW; ++g)
 #pragma unroll
-        for (int r = 0; r < NR; ++r) cmac(acc[q][r], widen(a[u][q]), xv[u][r]);
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cmac(acc[g][e][r], Elem<E>::get(wv[u][g], e), yv[u][g][e][r]);
   }
+}
 
-  __shared__ double2 red[kWaves - 1][RPL][NR][64];
-  if (w > 0) {
+template <int E, int G, int NR>
+constexpr int term_red_slots() {
+  return (G > kInRowTile / (64 * E) ? G : kInRowTile / (64 * E)) * E * NR;
+}
+
+// Epilogue of leaf a for the RHS tile [rhs0, rhs0 + NR): z = sum of the
+// leaf's partial sums in a fixed order, y = alpha z + beta v, y and x stores.
+template <int NR>
+__device__ void term_epilogue(const TermArgs& A, int a, int rhs0, int nrhs, int* s_prow) {
+  constexpr int KE = (256 * NR + kThreads - 1) / kThreads;
+  const int m = A.ps.leaf_m[a];
+  const int64_t off = A.leaf_off[a];
+  const int q0a = A.lptr[a], q1a = A.lptr[a + 1];
+  double2 zacc[KE];
 #pragma unroll
-    for (int q = 0; q < RPL; ++q)
+  for (int k = 0; k < KE; ++k) zacc[k] = zero2();
+  for (int q0 = q0a; q0 < q1a; q0 += kThreads) {
+    const int nq = min(kThreads, q1a - q0);
+    __syncthreads();
+    if ((int)threadIdx.x < nq) s_prow[threadIdx.x] = A.lprow[q0 + threadIdx.x];
+    __syncthreads();
 #pragma unroll
-      for (int r = 0; r < NR; ++r) red[w - 1][q][r][lane] = acc[q][r];
-  }
-  __syncthreads();
-  if (w == 0) {
+    for (int k = 0; k < KE; ++k) {
+      const int idx = threadIdx.x + k * kThreads;
+      if (idx >= m * NR) break;
+      const int i = idx % m;
+      const int c = rhs0 + idx / m;
+      if (c >= nrhs) continue;
+      const double* pc = reinterpret_cast<const double*>(A.partial + i + (int64_t)c * A.ldp);
+      // fixed order, so results do not depend on timing; loads issued in
+      // batches of 8 so that they are in flight together
+      for (int p = 0; p < nq; p += 8) {
+        double vr[8], vi[8];
 #pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-      const int i = lane + 64 * q;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double2 s = acc[q][r];
-#pragma unroll
-        for (int v = 0; v < kWaves - 1; ++v) {
-          s.x += red[v][q][r][lane].x;
-          s.y += red[v][q][r][lane].y;
+        for (int u = 0; u < 8; ++u) {
+          if (p + u < nq) {
+            const double* q = pc + 2 * (int64_t)s_prow[p + u];
+            vr[u] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            vi[u] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            vr[u] = 0.0;
+            vi[u] = 0.0;
+          }
         }
-        if (i < m && rhs0 + r < nrhs) partial[it.prow + i + (int64_t)(rhs0 + r) * ldp] = s;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          zacc[k].x += vr[u];
+          zacc[k].y += vi[u];
+        }
       }
     }
+  }
+#pragma unroll
+  for (int k = 0; k < KE; ++k) {
+    const int idx = threadIdx.x + k * kThreads;
+    if (idx >= m * NR) break;
+    const int i = idx % m;
+    const int c = rhs0 + idx / m;
+    if (c >= nrhs) continue;
+    const double2 z = zacc[k];
+    double2 y = make_double2(A.alpha * z.x, A.alpha * z.y);
+    if (A.v) {
+      const double2 v = A.v[off + i + (int64_t)c * A.ldv];
+      y.x = fma(A.beta, v.x, y.x);
+      y.y = fma(A.beta, v.y, y.y);
+    }
+    if (A.yout) A.yout[off + i + (int64_t)c * A.ldy] = y;
+    double2 res = y;
+    if (A.xacc) {
+      const int64_t q = off + i + (int64_t)c * A.ldxa;
+      if (A.accumulate) {
+        const double2 o = A.xacc[q];
+        res.x += o.x;
+        res.y += o.y;
+      }
+      A.xacc[q] = res;
+    }
+    if (A.out) A.out[A.out_perm[off + i] + (int64_t)c * A.ldo] = res;
+  }
+}
+
+// Persistent workgroup: processes its run of pieces; after each piece it
+// publishes the partial sums and counts the piece for its leaf; the
+// workgroup that completes a leaf runs the leaf's epilogue.
+template <int E, int G, int NR, int UNR>
+__global__ __launch_bounds__(kThreads) void k_term(TermArgs A, int nrhs) {
+  constexpr int GW = kInRowTile / (64 * E);
+  const int rhs0 = blockIdx.y * NR;
+  const int w = wave_id();
+  const int lane = threadIdx.x & 63;
+  __shared__ double2 red[(kWaves - 1) * term_red_slots<E, G, NR>() * 64];
+  constexpr int kXChunk = 1024 / NR;
+  __shared__ double2 tbuf[NR][kInRowTile];
+  __shared__ double2 xs[NR][kXChunk];
+  __shared__ int s_prow[kThreads];
+  __shared__ int s_last;
+  const int pe = A.wptr[blockIdx.x + 1];
+  for (int p = A.wptr[blockIdx.x]; p < pe; ++p) {
+    const TermItem it = A.items[p];
+    const int a = it.leaf;
+    const int m = A.ps.leaf_m[a];
+    const int64_t ld = m + (m & 1);
+    const void* P = Elem<E>::offset(A.ps.data, A.ps.panel_off[a]);
+    const int32_t* __restrict__ src = A.ps.src + A.ps.col_off[a];
+    double2 acc[G][E][NR];
+    zero_acc(acc);
+    if (it.kind == 0) {
+      // the piece's input values go to LDS first (chunks of kXChunk columns),
+      // so the streaming loop reads them as LDS broadcasts
+      for (int cb = it.c0; cb < it.c1; cb += kXChunk) {
+        const int nc = min(kXChunk, it.c1 - cb);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nc * NR; t += kThreads) {
+          const int k = t % nc;
+          const int r = t / nc;
+          int64_t sidx = src[cb + k];
+          if (A.in_perm) sidx = A.in_perm[sidx];
+          xs[r][k] = (rhs0 + r < nrhs) ? A.xin[sidx + (int64_t)(rhs0 + r) * A.ldx] : zero2();
+        }
+        __syncthreads();
+        auto X = [&](int c, int r) -> double2 { return xs[r][c - cb]; };
+        tall_gemv<E, G, NR, UNR>(P, ld, m, 0, cb, cb + nc, w, lane, X, acc);
+      }
+    } else {
+      double2 tacc[GW][E][NR];
+      zero_acc(tacc);
+      const int rb = A.ir.row0[a];
+      inrow_t<E, GW, NR, 4>(Elem<E>::offset(A.ir.W, A.ir.off[a]), A.ir.ld[a], A.ir.ncol[a],
+                            it.r0, it.r1, A.ir.soff + rb, A.ir.n + rb, A.xin, A.ldx, rhs0, nrhs,
+                            w, lane, tacc);
+      reduce_waves(tacc, w, lane, red);
+      if (w == 0) {
+#pragma unroll
+        for (int g = 0; g < GW; ++g)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int k = (g * 64 + lane) * E + e;
+#pragma unroll
+            for (int r = 0; r < NR; ++r)
+              if (k < kInRowTile) tbuf[r][k] = tacc[g][e][r];
+          }
+      }
+      __syncthreads();
+      auto X = [&](int c, int r) -> double2 { return tbuf[r][c - it.c0]; };
+      tall_gemv<E, G, NR, UNR>(P, ld, m, 0, it.c0, it.c0 + (it.r1 - it.r0), w, lane, X, acc);
+    }
+    reduce_waves(acc, w, lane, red);
+    // Partial sums are published with device-coherent (agent-scope) stores
+    // and read back with device-coherent loads, so no writeback/invalidate
+    // of the whole L2 is needed; the stores are complete (s_waitcnt) before
+    // the workgroup's barrier and its counter increment.
+    if (w == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = (g * 64 + lane) * E + e;
+#pragma unroll
+          for (int r = 0; r < NR; ++r)
+            if (i < m && rhs0 + r < nrhs) {
+              double* q = reinterpret_cast<double*>(A.partial + it.prow + i +
+                                                    (int64_t)(rhs0 + r) * A.ldp);
+              __hip_atomic_store(q, acc[g][e][r].x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              __hip_atomic_store(q + 1, acc[g][e][r].y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    int32_t* cnt = A.counters + (int64_t)a * gridDim.y + blockIdx.y;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_last = (old == A.lptr[a + 1] - A.lptr[a] - 1);
+    }
+    __syncthreads();
+    if (s_last) {
+      term_epilogue<NR>(A, a, rhs0, nrhs, s_prow);
+      if (threadIdx.x == 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------- stage A
-// One wave per far block: t_b = W_b y_s.  Lanes stride over the n source
-// points (coalesced along the rows of W_b), QC coefficient rows at a time,
-// then a butterfly reduction across the wave.
-template <typename TM, int NR, int QC>
-__global__ __launch_bounds__(kThreads) void k_stageA(const TM* __restrict__ W,
-                                                     const StageABlock* __restrict__ blk, int nblk,
+// One workgroup = one row tile of a source group: t rows = W_g y_s.
+template <int E, int G, int NR, int UNR>
+__global__ __launch_bounds__(kThreads) void k_stageA(const void* __restrict__ W,
+                                                     const Group* __restrict__ groups,
+                                                     const GroupItem* __restrict__ items,
                                                      double2* __restrict__ xin, int64_t ldx,
                                                      int64_t N, int nrhs) {
+  const GroupItem it = items[blockIdx.x];
+  const Group g = groups[it.group];
+  const void* Wg = Elem<E>::offset(W, g.w_off);
+  const int rhs0 = blockIdx.y * NR;
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
-  const int b = blockIdx.x * kWaves + w;
-  if (b >= nblk) return;  // whole wave leaves; no barrier in this kernel
-  const StageABlock f = blk[b];
-  const TM* __restrict__ Wb = W + f.w_off;
-  const int rhs0 = blockIdx.y * NR;
-  for (int q0 = 0; q0 < f.r; q0 += QC) {
-    double2 acc[QC][NR];
+  auto X = [&](int c, int r) -> double2 {
+    return (rhs0 + r < nrhs) ? xin[g.s_off + c + (int64_t)(rhs0 + r) * ldx] : zero2();
+  };
+  double2 acc[G][E][NR];
+  zero_acc(acc);
+  tall_gemv<E, G, NR, UNR>(Wg, g.ld, it.rows, it.row0, 0, g.n, w, lane, X, acc);
+  __shared__ double2 red[(kWaves - 1) * G * E * NR * 64];
+  reduce_waves(acc, w, lane, red);
+  if (w == 0) {
 #pragma unroll
-    for (int qq = 0; qq < QC; ++qq)
+    for (int gg = 0; gg < G; ++gg)
 #pragma unroll
-      for (int r = 0; r < NR; ++r) acc[qq][r] = zero2();
-    for (int j = lane; j < f.n; j += 64) {
-      double2 yv[NR];
-#pragma unroll
-      for (int r = 0; r < NR; ++r)
-        yv[r] = (rhs0 + r < nrhs) ? xin[f.s_off + j + (int64_t)(rhs0 + r) * ldx] : zero2();
-#pragma unroll
-      for (int qq = 0; qq < QC; ++qq) {
-        if (q0 + qq < f.r) {
-          const double2 wv = widen(Wb[(int64_t)(q0 + qq) * f.n + j]);
-#pragma unroll
-          for (int r = 0; r < NR; ++r) cmac(acc[qq][r], wv, yv[r]);
-        }
-      }
-    }
-#pragma unroll
-    for (int qq = 0; qq < QC; ++qq)
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        acc[qq][r].x = wave_sum(acc[qq][r].x);
-        acc[qq][r].y = wave_sum(acc[qq][r].y);
-      }
-    if (lane == 0) {
-#pragma unroll
-      for (int qq = 0; qq < QC; ++qq)
+      for (int e = 0; e < E; ++e) {
+        const int row = it.row0 + (gg * 64 + lane) * E + e;
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-          if (q0 + qq < f.r && rhs0 + r < nrhs)
-            xin[N + f.tb_off + q0 + qq + (int64_t)(rhs0 + r) * ldx] = acc[qq][r];
-    }
-  }
-}
-
-// ---------------------------------------------------------------- epilogue
-// Per leaf: z = sum of the partial sums of its work items (fixed order),
-// y = alpha z + beta v; optionally store y and add it to (or store it in) x.
-__global__ __launch_bounds__(kThreads) void k_epilogue(EpilogueArgs e, int nrhs) {
-  const int a = blockIdx.x;
-  const int m = e.leaf_m[a];
-  const int64_t off = e.leaf_off[a];
-  const int p0 = e.item_ptr[a], p1 = e.item_ptr[a + 1];
-  for (int c = blockIdx.y; c < nrhs; c += gridDim.y) {
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      double2 z = zero2();
-      for (int p = p0; p < p1; ++p) {
-        const double2 v = e.partial[e.items[p].prow + i + (int64_t)c * e.ldp];
-        z.x += v.x;
-        z.y += v.y;
+          if (row < it.rows && rhs0 + r < nrhs)
+            xin[N + g.t0 + row + (int64_t)(rhs0 + r) * ldx] = acc[gg][e][r];
       }
-      double2 y = make_double2(e.alpha * z.x, e.alpha * z.y);
-      if (e.v) {
-        const double2 v = e.v[off + i + (int64_t)c * e.ldv];
-        y.x = fma(e.beta, v.x, y.x);
-        y.y = fma(e.beta, v.y, y.y);
-      }
-      if (e.yout) e.yout[off + i + (int64_t)c * e.ldy] = y;
-      if (e.xacc) {
-        const int64_t idx = off + i + (int64_t)c * e.ldxa;
-        if (e.accumulate) {
-          const double2 x = e.xacc[idx];
-          y.x += x.x;
-          y.y += x.y;
-        }
-        e.xacc[idx] = y;
-      }
-    }
   }
 }
 
 // ---------------------------------------------------------------- leaf LU
 // Right-looking LU with partial pivoting of one leaf self-block per
-// workgroup, in place (column-major).  Build-time only; works from L2.
+// workgroup, in place (column-major, ld = m).  Build-time only.
 __global__ __launch_bounds__(kThreads) void k_getrf(double2* __restrict__ A,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ mm,
@@ -308,21 +531,24 @@ __global__ __launch_bounds__(kThreads) void k_getrf(double2* __restrict__ A,
   }
 }
 
-// Inverse from the LU factors: column j of D^{-1} solves L U x = P e_j.
-// One thread per column, working on its own column in the output.
+// D^{-1} from the LU factors: column j solves L U x = P e_j.  One thread
+// per column works on its own column of the output (ld = m rounded up to
+// even; the pad row is set to zero).
 __global__ __launch_bounds__(kThreads) void k_getri(const double2* __restrict__ LU,
                                                     const int64_t* __restrict__ off,
                                                     const int32_t* __restrict__ mm,
                                                     const int32_t* __restrict__ piv,
                                                     const int64_t* __restrict__ poff,
-                                                    double2* __restrict__ Ainv) {
+                                                    double2* __restrict__ Ainv,
+                                                    const int64_t* __restrict__ ioff) {
   const int b = blockIdx.x;
   const int m = mm[b];
+  const int ld = m + (m & 1);
   const double2* a = LU + off[b];
   const int32_t* pv = piv + poff[b];
   for (int j = threadIdx.x; j < m; j += blockDim.x) {
-    double2* x = Ainv + off[b] + (int64_t)j * m;
-    for (int i = 0; i < m; ++i) x[i] = zero2();
+    double2* x = Ainv + ioff[b] + (int64_t)j * ld;
+    for (int i = 0; i < ld; ++i) x[i] = zero2();
     x[j] = make_double2(1.0, 0.0);
     for (int k = 0; k < m; ++k) {
       const int p = pv[k];
@@ -359,7 +585,7 @@ __global__ __launch_bounds__(kThreads) void k_getri(const double2* __restrict__ 
   }
 }
 
-// M panel tile: 32 columns c0.. of leaf a, M[:, c] = Dinv_a * P_a[:, m_a + c].
+// Series panel tile: 32 columns c0.. of leaf a, M[:, c] = Dinv_a P_a[:, m_a + c].
 // Lane l owns rows l, l+64, ...; wave w owns columns w, w+4, ... of the tile.
 template <int RPL>
 __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__ Dinv,
@@ -371,15 +597,16 @@ __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__
                                                      double2* __restrict__ M,
                                                      const int64_t* __restrict__ m_off,
                                                      const int32_t* __restrict__ tiles) {
-  constexpr int TC = 8;  // columns per wave
+  constexpr int TC = kPremulCols / kWaves;  // columns per wave
   const int a = tiles[2 * blockIdx.x];
   const int c0 = tiles[2 * blockIdx.x + 1];
   const int m = leaf_m[a];
+  const int64_t ld = m + (m & 1);
   const int nc = ncols_m[a];
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
   const double2* Di = Dinv + dinv_off[a];
-  const double2* Pa = P + p_off[a] + (int64_t)m * m;  // skip the D_a columns
+  const double2* Pa = P + p_off[a] + ld * m;  // skip the D_a columns
   double2* Ma = M + m_off[a];
   double2 acc[RPL][TC];
 #pragma unroll
@@ -391,12 +618,12 @@ __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = lane + 64 * q;
-      d[q] = (i < m) ? Di[i + (int64_t)l * m] : zero2();
+      d[q] = (i < m) ? Di[i + (int64_t)l * ld] : zero2();
     }
 #pragma unroll
     for (int u = 0; u < TC; ++u) {
       const int c = c0 + w + kWaves * u;
-      const double2 pv = (c < nc) ? Pa[l + (int64_t)c * m] : zero2();
+      const double2 pv = (c < nc) ? Pa[l + (int64_t)c * ld] : zero2();
 #pragma unroll
       for (int q = 0; q < RPL; ++q) cmac(acc[q][u], d[q], pv);
     }
@@ -408,7 +635,7 @@ __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
       const int i = lane + 64 * q;
-      if (i < m) Ma[i + (int64_t)c * m] = acc[q][u];
+      if (i < m) Ma[i + (int64_t)c * ld] = acc[q][u];
     }
   }
 }
@@ -467,6 +694,9 @@ __global__ void k_axpy(double alpha, const double2* __restrict__ x, int64_t ldx,
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
+// NR (right-hand sides per workgroup) for nrhs; grid.y = ceil(nrhs / NR)
+inline int pick_nr(int nrhs) { return nrhs == 1 ? 1 : (nrhs == 2 ? 2 : 4); }
+
 }  // namespace
 
 // ============================================================== launchers
@@ -484,75 +714,81 @@ hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* per
   return hipGetLastError();
 }
 
-template <typename TM, int RPL>
-static hipError_t panel_rpl(const PanelSet& ps, const WorkItem* items, int nitems,
-                            const double2* xin, int64_t ldx, int nrhs, double2* partial,
-                            int64_t ldp, hipStream_t st) {
-  constexpr int UNR = sizeof(TM) == 16 ? 8 : 16;
-  if (nrhs == 1) {
-    hipLaunchKernelGGL((k_panel<TM, RPL, 1, UNR>), dim3(nitems, 1), dim3(kThreads), 0, st, ps,
-                       items, xin, ldx, nrhs, partial, ldp);
-  } else if (nrhs == 2) {
-    hipLaunchKernelGGL((k_panel<TM, RPL, 2, UNR / 2>), dim3(nitems, 1), dim3(kThreads), 0, st,
-                       ps, items, xin, ldx, nrhs, partial, ldp);
-  } else {
-    hipLaunchKernelGGL((k_panel<TM, RPL, 4, UNR / 4>), dim3(nitems, (nrhs + 3) / 4),
-                       dim3(kThreads), 0, st, ps, items, xin, ldx, nrhs, partial, ldp);
-  }
+int term_rhs_tile(int nrhs) { return pick_nr(nrhs); }
+
+template <int E, int G>
+static hipError_t term_eg(const TermArgs& a, int nwg, int nrhs, hipStream_t st) {
+  const int nr = pick_nr(nrhs);
+  const dim3 grid(nwg, (nrhs + nr - 1) / nr);
+  if (nr == 1)
+    hipLaunchKernelGGL((k_term<E, G, 1, 8>), grid, dim3(kThreads), 0, st, a, nrhs);
+  else if (nr == 2)
+    hipLaunchKernelGGL((k_term<E, G, 2, 4>), grid, dim3(kThreads), 0, st, a, nrhs);
+  else
+    hipLaunchKernelGGL((k_term<E, G, 4, 2>), grid, dim3(kThreads), 0, st, a, nrhs);
   return hipGetLastError();
 }
 
-hipError_t launch_panel(bool f32, int max_m, const PanelSet& ps, const WorkItem* items, int nitems,
-                        const double2* xin, int64_t ldx, int nrhs, double2* partial, int64_t ldp,
-                        hipStream_t st) {
-  if (nitems <= 0 || nrhs <= 0) return hipSuccess;
+hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
+                       hipStream_t st) {
+  if (nwg <= 0 || nrhs <= 0) return hipSuccess;
   if (max_m > 256) return hipErrorInvalidValue;
-  const int rpl = (max_m + 63) / 64;
-#define HM_PANEL_CASE(R)                                                                        \
-  case R:                                                                                      \
-    return f32 ? panel_rpl<float2, R>(ps, items, nitems, xin, ldx, nrhs, partial, ldp, st)     \
-               : panel_rpl<double2, R>(ps, items, nitems, xin, ldx, nrhs, partial, ldp, st);
-  switch (rpl) {
-    HM_PANEL_CASE(1)
-    HM_PANEL_CASE(2)
-    HM_PANEL_CASE(3)
-    HM_PANEL_CASE(4)
-    default:
-      return hipErrorInvalidValue;
+  if (f32) {
+    if (max_m <= 128) return term_eg<2, 1>(a, nwg, nrhs, st);
+    return term_eg<2, 2>(a, nwg, nrhs, st);
   }
-#undef HM_PANEL_CASE
+  switch ((max_m + 63) / 64) {
+    case 1: return term_eg<1, 1>(a, nwg, nrhs, st);
+    case 2: return term_eg<1, 2>(a, nwg, nrhs, st);
+    case 3: return term_eg<1, 3>(a, nwg, nrhs, st);
+    default: return term_eg<1, 4>(a, nwg, nrhs, st);
+  }
 }
 
-hipError_t launch_stageA(bool f32, const void* W, const StageABlock* blk, int nblk, double2* xin,
-                         int64_t ldx, int64_t N, int nrhs, hipStream_t st) {
-  if (nblk <= 0 || nrhs <= 0) return hipSuccess;
-  const unsigned gx = blocks_for(nblk, kWaves);
-  if (nrhs == 1) {
-    if (f32)
-      hipLaunchKernelGGL((k_stageA<float2, 1, 8>), dim3(gx, 1), dim3(kThreads), 0, st,
-                         (const float2*)W, blk, nblk, xin, ldx, N, nrhs);
-    else
-      hipLaunchKernelGGL((k_stageA<double2, 1, 8>), dim3(gx, 1), dim3(kThreads), 0, st,
-                         (const double2*)W, blk, nblk, xin, ldx, N, nrhs);
-  } else {
-    const unsigned gy = (unsigned)((nrhs + 3) / 4);
-    if (f32)
-      hipLaunchKernelGGL((k_stageA<float2, 4, 4>), dim3(gx, gy), dim3(kThreads), 0, st,
-                         (const float2*)W, blk, nblk, xin, ldx, N, nrhs);
-    else
-      hipLaunchKernelGGL((k_stageA<double2, 4, 4>), dim3(gx, gy), dim3(kThreads), 0, st,
-                         (const double2*)W, blk, nblk, xin, ldx, N, nrhs);
+template <int E, int G>
+static int occ_eg() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_term<E, G, 1, 8>, kThreads, 0) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+int term_occupancy(bool f32, int max_m) {
+  if (f32) return max_m <= 128 ? occ_eg<2, 1>() : occ_eg<2, 2>();
+  switch ((max_m + 63) / 64) {
+    case 1: return occ_eg<1, 1>();
+    case 2: return occ_eg<1, 2>();
+    case 3: return occ_eg<1, 3>();
+    default: return occ_eg<1, 4>();
   }
+}
+
+// group tiles are kGroupTile = 128 rows: G = 2 for FP64, 1 for FP32
+template <int E>
+static hipError_t stageA_e(const void* W, const Group* groups, const GroupItem* items, int nitems,
+                           double2* xin, int64_t ldx, int64_t N, int nrhs, hipStream_t st) {
+  constexpr int G = kGroupTile / (64 * E);
+  const int nr = pick_nr(nrhs);
+  const dim3 grid(nitems, (nrhs + nr - 1) / nr);
+  if (nr == 1)
+    hipLaunchKernelGGL((k_stageA<E, G, 1, 4>), grid, dim3(kThreads), 0, st, W, groups, items,
+                       xin, ldx, N, nrhs);
+  else if (nr == 2)
+    hipLaunchKernelGGL((k_stageA<E, G, 2, 2>), grid, dim3(kThreads), 0, st, W, groups, items,
+                       xin, ldx, N, nrhs);
+  else
+    hipLaunchKernelGGL((k_stageA<E, G, 4, 1>), grid, dim3(kThreads), 0, st, W, groups, items,
+                       xin, ldx, N, nrhs);
   return hipGetLastError();
 }
 
-hipError_t launch_epilogue(const EpilogueArgs& e, int nleaves, int max_m, int nrhs,
-                           hipStream_t st) {
-  if (nleaves <= 0 || nrhs <= 0) return hipSuccess;
-  (void)max_m;
-  const unsigned gy = (unsigned)(nrhs < 64 ? nrhs : 64);
-  hipLaunchKernelGGL(k_epilogue, dim3(nleaves, gy), dim3(kThreads), 0, st, e, nrhs);
-  return hipGetLastError();
+hipError_t launch_stageA(bool f32, const void* W, const Group* groups, const GroupItem* items,
+                         int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs,
+                         hipStream_t st) {
+  if (nitems <= 0 || nrhs <= 0) return hipSuccess;
+  return f32 ? stageA_e<2>(W, groups, items, nitems, xin, ldx, N, nrhs, st)
+             : stageA_e<1>(W, groups, items, nitems, xin, ldx, N, nrhs, st);
 }
 
 hipError_t launch_getrf(double2* A, const int64_t* off, const int32_t* m, int32_t* piv,
@@ -563,10 +799,11 @@ hipError_t launch_getrf(double2* A, const int64_t* off, const int32_t* m, int32_
 }
 
 hipError_t launch_getri(const double2* LU, const int64_t* off, const int32_t* m,
-                        const int32_t* piv, const int64_t* piv_off, double2* Ainv, int nblk,
-                        hipStream_t st) {
+                        const int32_t* piv, const int64_t* piv_off, double2* Ainv,
+                        const int64_t* dinv_off, int nblk, hipStream_t st) {
   if (nblk <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_getri, dim3(nblk), dim3(kThreads), 0, st, LU, off, m, piv, piv_off, Ainv);
+  hipLaunchKernelGGL(k_getri, dim3(nblk), dim3(kThreads), 0, st, LU, off, m, piv, piv_off, Ainv,
+                     dinv_off);
   return hipGetLastError();
 }
 
@@ -575,13 +812,12 @@ hipError_t launch_premul(const double2* Dinv, const int64_t* dinv_off, const dou
                          double2* M, const int64_t* m_off, const int32_t* tiles, int ntiles,
                          int max_m, hipStream_t st) {
   if (ntiles <= 0) return hipSuccess;
-  const int rpl = (max_m + 63) / 64;
 #define HM_PREMUL_CASE(R)                                                                      \
   case R:                                                                                     \
     hipLaunchKernelGGL(k_premul<R>, dim3(ntiles), dim3(kThreads), 0, st, Dinv, dinv_off, P,   \
                        p_off, leaf_m, ncols_m, M, m_off, tiles);                              \
     break;
-  switch (rpl) {
+  switch ((max_m + 63) / 64) {
     HM_PREMUL_CASE(1)
     HM_PREMUL_CASE(2)
     HM_PREMUL_CASE(3)

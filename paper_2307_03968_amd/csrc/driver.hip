@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -35,11 +36,19 @@ void set_error(const std::string& msg) { g_err = msg; }
     if (s_ != HM_OK) return s_;  \
   } while (0)
 
-struct WorkList {
-  WorkItem* items = nullptr;   // device
-  int32_t* ptr = nullptr;      // device, nleaves + 1
-  int n = 0;
+struct TermList {
+  TermItem* items = nullptr;   // device: pieces grouped by workgroup
+  int32_t* wptr = nullptr;     // device: nwg + 1
+  int32_t* lptr = nullptr;     // device: nleaves + 1
+  int32_t* lprow = nullptr;    // device: partial rows of each leaf's pieces
+  int nwg = 0;                 // persistent workgroups
+  int npieces = 0;
   int64_t rows = 0;            // partial rows
+};
+
+struct GroupList {
+  GroupItem* items = nullptr;  // device
+  int n = 0;
 };
 
 }  // namespace hm
@@ -60,7 +69,7 @@ struct hm_matrix {
   int64_t* perm = nullptr;
   int32_t* leaf_off = nullptr;
   int32_t* leaf_m = nullptr;
-  // apply panels [D | near | far], series panels D^{-1}[near | far]
+  // apply panels [D | near | far], series panels D^{-1}[near | far], D^{-1}
   double2* R64 = nullptr;
   float2* R32 = nullptr;
   int64_t* R_off = nullptr;
@@ -70,22 +79,30 @@ struct hm_matrix {
   float2* M32 = nullptr;
   int64_t* M_off = nullptr;
   int64_t* M_col = nullptr;
-  // D blocks, LU, inverse
-  double2* LU = nullptr;
-  double2* Dinv = nullptr;
-  int64_t* D_off = nullptr;
+  double2* LU = nullptr;      // m x m per leaf (ld m)
+  int64_t* LU_off = nullptr;
+  double2* Dinv = nullptr;    // ld even(m) per leaf
+  int64_t* Dinv_off = nullptr;
   int32_t* piv = nullptr;
   int64_t* piv_off = nullptr;
-  // stage A
+  // stage A groups (global far blocks)
   double2* W64 = nullptr;
   float2* W32 = nullptr;
-  hm::StageABlock* blk = nullptr;
-  std::vector<int> nA;          // per level index: active far blocks (prefix)
-  std::vector<int64_t> bytes_R, bytes_M, bytes_W, ncoef;  // per level index, element counts
-  // work lists
-  std::vector<hm::WorkList> wl_apply, wl_series;
-  hm::WorkList wl_dinv;
+  hm::Group* groups = nullptr;
+  // in-row W stacks
+  double2* IR64 = nullptr;
+  float2* IR32 = nullptr;
+  int64_t* ir_off = nullptr;
+  int32_t *ir_ld = nullptr, *ir_ncol = nullptr, *ir_row0 = nullptr, *ir_soff = nullptr,
+          *ir_n = nullptr;
+  // per level index
+  std::vector<hm::TermList> tl_apply, tl_series;
+  std::vector<hm::GroupList> sa;
+  std::vector<int64_t> ent_R, ent_M, ent_W, ncoef;
+  hm::TermList tl_dinv;
   int64_t partial_rows = 0;
+  int term_wgs = 1024;          // persistent workgroups of a term kernel
+  int32_t* counters = nullptr;  // workspace
   // workspace
   int ws_nrhs = 0;
   double2 *xin0 = nullptr, *xin1 = nullptr, *xt = nullptr, *bt = nullptr, *rt = nullptr,
@@ -147,33 +164,103 @@ int level_index(const hm_matrix* h, int level, int* li) {
   return HM_OK;
 }
 
-// Split each leaf's active columns into work items.  `first` and `last`
-// give the active column range of leaf a; target ~2048 items.
-int make_worklist(hm_matrix* h, const std::vector<int64_t>& first, const std::vector<int64_t>& last,
-                  WorkList& wl, hipStream_t st) {
+// Pieces of one term kernel, split evenly over h->term_wgs persistent
+// workgroups.  Per leaf a, in order: dense column ranges dense[a] (pairs
+// [begin, end), cost m per column), then in-row stack rows [0, inrow_rows[a])
+// (cost W row + U column per row) whose panel columns start at inrow_col[a].
+// Each unit of work goes to the workgroup whose share its cost start falls
+// in; runs of units of one segment within one workgroup form a piece (in-row
+// pieces at most kInRowTile rows).
+int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t, int64_t>>>& dense,
+                  const std::vector<int64_t>& inrow_rows, const std::vector<int64_t>& inrow_col,
+                  const std::vector<int32_t>& inrow_ncol, TermList& tl, hipStream_t st) {
+  struct Seg { int leaf, kind; int64_t u0, u1, col0, cost; };
+  std::vector<Seg> segs;
   int64_t total = 0;
-  for (int a = 0; a < h->nl; ++a) total += last[a] - first[a];
-  const int64_t target = 2048;
-  int64_t chunk = std::max<int64_t>(64, (total + target - 1) / target);
-  chunk = (chunk + 31) / 32 * 32;
-  std::vector<WorkItem> items;
-  std::vector<int32_t> ptr(h->nl + 1, 0);
-  int64_t rows = 0;
   for (int a = 0; a < h->nl; ++a) {
-    ptr[a] = (int32_t)items.size();
-    const int m = h->H.leaf_size[a];
-    for (int64_t c = first[a]; c < last[a]; c += chunk) {
-      items.push_back({a, (int32_t)c, (int32_t)std::min(last[a], c + chunk), (int32_t)rows});
-      rows += m;
-    }
+    const int64_t m = h->H.leaf_size[a];
+    const size_t first = segs.size();
+    for (auto& r : dense[a])
+      if (r.second > r.first) segs.push_back({a, 0, r.first, r.second, 0, m});
+    if (inrow_rows[a] > 0)
+      segs.push_back({a, 1, 0, inrow_rows[a], inrow_col[a], (int64_t)inrow_ncol[a] + m});
+    if (segs.size() == first) segs.push_back({a, 0, 0, 0, 0, 0});  // epilogue only
+    for (size_t k = first; k < segs.size(); ++k) total += (segs[k].u1 - segs[k].u0) * segs[k].cost;
   }
-  ptr[h->nl] = (int32_t)items.size();
-  wl.n = (int)items.size();
-  wl.rows = rows;
-  STCHK(upload(h, &wl.items, items, st));
-  STCHK(upload(h, &wl.ptr, ptr, st));
+  const int G = std::max(1, h->term_wgs);
+  std::vector<TermItem> items;
+  std::vector<int32_t> wg_of;
+  int64_t rows = 0, done = 0;
+  auto wg_at = [&](int64_t cost) {
+    return total > 0 ? (int)std::min<int64_t>(G - 1, (cost * G) / total) : 0;
+  };
+  for (const Seg& sg : segs) {
+    const int m = h->H.leaf_size[sg.leaf];
+    int64_t u = sg.u0;
+    do {
+      const int g = wg_at(done);
+      // units of this segment that start before the next workgroup boundary
+      int64_t k = sg.u1 - u;
+      if (g < G - 1 && sg.cost > 0) {
+        const int64_t bound = ((int64_t)(g + 1) * total + G - 1) / G;
+        k = std::min(k, std::max<int64_t>(1, (bound - done + sg.cost - 1) / sg.cost));
+      }
+      if (sg.kind == 1) {
+        // FP32 stacks are read two rows per load from an even row: keep
+        // every in-row piece start even (kInRowTile is even)
+        k = std::min<int64_t>(k, kInRowTile);
+        if ((k & 1) && u + k < sg.u1) ++k;
+      }
+      TermItem it{sg.leaf, sg.kind, 0, 0, 0, 0, (int32_t)rows, 0};
+      if (sg.kind == 0) {
+        it.c0 = (int32_t)u;
+        it.c1 = (int32_t)(u + k);
+      } else {
+        it.r0 = (int32_t)u;
+        it.r1 = (int32_t)(u + k);
+        it.c0 = (int32_t)(sg.col0 + u);
+        it.c1 = (int32_t)(sg.col0 + u + k);
+      }
+      items.push_back(it);
+      wg_of.push_back(g);
+      rows += m;
+      done += k * sg.cost;
+      u += k;
+    } while (u < sg.u1);
+  }
+  for (const TermItem& it : items)
+    if (it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > kInRowTile)) {
+      set_error("internal: bad in-row piece");
+      return HM_EINVAL;
+    }
+  // group pieces by workgroup (stable: pieces of one workgroup keep their order)
+  std::vector<int32_t> wptr(G + 1, 0);
+  for (int g : wg_of) wptr[g + 1]++;
+  for (int g = 0; g < G; ++g) wptr[g + 1] += wptr[g];
+  std::vector<TermItem> by_wg(items.size());
+  std::vector<int32_t> fill(wptr.begin(), wptr.end() - 1);
+  for (size_t q = 0; q < items.size(); ++q) by_wg[fill[wg_of[q]]++] = items[q];
+  // per leaf: the partial rows of its pieces, in piece order
+  std::vector<int32_t> lptr(h->nl + 1, 0), lprow;
+  for (auto& it : items) lptr[it.leaf + 1]++;
+  for (int a = 0; a < h->nl; ++a) lptr[a + 1] += lptr[a];
+  lprow.assign(items.size(), 0);
+  std::vector<int32_t> lf(lptr.begin(), lptr.end() - 1);
+  for (auto& it : items) lprow[lf[it.leaf]++] = it.prow;
+  tl.nwg = G;
+  tl.npieces = (int)items.size();
+  tl.rows = rows;
+  STCHK(upload(h, &tl.items, by_wg, st));
+  STCHK(upload(h, &tl.wptr, wptr, st));
+  STCHK(upload(h, &tl.lptr, lptr, st));
+  STCHK(upload(h, &tl.lprow, lprow, st));
   h->partial_rows = std::max(h->partial_rows, rows);
   return HM_OK;
+}
+
+int upload_groups(hm_matrix* h, const std::vector<GroupItem>& v, GroupList& gl, hipStream_t st) {
+  gl.n = (int)v.size();
+  return upload(h, &gl.items, v, st);
 }
 
 int ensure_workspace(hm_matrix* h, int nrhs) {
@@ -201,6 +288,8 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   STCHK(al((void**)&h->partial, sizeof(double2) * h->partial_rows * nrhs));
   STCHK(al((void**)&h->nscratch, sizeof(double) * kNormBlocks * nrhs * 2));
   STCHK(al((void**)&h->norms, sizeof(double) * nrhs * 2));
+  STCHK(al((void**)&h->counters, sizeof(int32_t) * h->nl * nrhs));
+  HIPCHK(hipMemset(h->counters, 0, sizeof(int32_t) * h->nl * nrhs));
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   h->norms_host = nullptr;
   HIPCHK(hipHostMalloc((void**)&h->norms_host, sizeof(double) * nrhs * 2, hipHostMallocDefault));
@@ -217,23 +306,29 @@ PanelSet series_set(const hm_matrix* h, bool f32) {
                   h->leaf_m};
 }
 PanelSet dinv_set(const hm_matrix* h) {
-  return PanelSet{(const void*)h->Dinv, h->D_off, h->src, h->R_col, h->leaf_m};
+  return PanelSet{(const void*)h->Dinv, h->Dinv_off, h->src, h->R_col, h->leaf_m};
 }
 
-EpilogueArgs epi(const hm_matrix* h, const WorkList& wl, int64_t ldp) {
-  EpilogueArgs e{};
-  e.leaf_off = h->leaf_off;
-  e.leaf_m = h->leaf_m;
-  e.item_ptr = wl.ptr;
-  e.items = wl.items;
-  e.partial = h->partial;
-  e.ldp = ldp;
-  e.alpha = 1.0;
-  e.beta = 0.0;
-  return e;
+TermArgs term_args(const hm_matrix* h, const PanelSet& ps, const TermList& tl, bool f32,
+                   const double2* xin, int64_t ldx) {
+  TermArgs t{};
+  t.ps = ps;
+  t.ir = InRow{f32 ? (const void*)h->IR32 : (const void*)h->IR64, h->ir_off, h->ir_ld,
+               h->ir_ncol, h->ir_row0, h->ir_soff, h->ir_n};
+  t.items = tl.items;
+  t.wptr = tl.wptr;
+  t.lptr = tl.lptr;
+  t.lprow = tl.lprow;
+  t.leaf_off = h->leaf_off;
+  t.xin = xin;
+  t.ldx = ldx;
+  t.partial = h->partial;
+  t.ldp = h->partial_rows;
+  t.counters = h->counters;
+  t.alpha = 1.0;
+  t.beta = 0.0;
+  return t;
 }
-
-#define LCHK(x) HIPCHK(x)
 
 hipEvent_t pool_event(hm_matrix* h) {
   if (!h->ev_pool.empty()) {
@@ -266,94 +361,77 @@ struct ProfScope {
   ~ProfScope() { if (e0) h->ev_pool.push_back(e0); }
 };
 
-// x_out = P_K rhs (tree order, ld N), as the power series of Sec. IV.
-// y_0 = D^{-1} rhs; y_k = -(D^{-1} R_l) y_{k-1}; x = sum y_k.
-int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, double2* x_out,
-                int nrhs, bool want_norms, hipStream_t st) {
-  const int64_t N = h->N, ldin = h->N + h->T, ldp = h->partial_rows;
+#define TIMED(cls, call)                 \
+  do {                                   \
+    ProfScope ps_(h, cls, st);           \
+    HIPCHK(call);                        \
+    ps_.done();                          \
+  } while (0)
+
+// Power series of Sec. IV: y_0 = D^{-1} rhs, y_k = -(D^{-1} R_l) y_{k-1},
+// x = sum y_k, accumulated in tree order in x_tree (ld N).  rhs is read in
+// tree order (ld N), or in original order through the permutation when
+// rhs_perm is set (ld ldr).  When out is set the final x is also written
+// there in original order (ld ldo).
+int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
+                bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
+                bool want_norms, hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
-  {
-    ProfScope ps(h, HM_K_PANEL_DINV, st);
-    LCHK(launch_panel(false, h->max_m, dinv_set(h), h->wl_dinv.items, h->wl_dinv.n, rhs, N, nrhs,
-                      h->partial, ldp, st));
-    ps.done();
-  }
-  EpilogueArgs e = epi(h, h->wl_dinv, ldp);
-  e.yout = y_cur;
-  e.ldy = ldin;
-  e.xacc = x_out;
-  e.ldxa = N;
-  e.accumulate = 0;
-  {
-    ProfScope ps(h, HM_K_EPILOGUE, st);
-    LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
-    ps.done();
-  }
-  if (want_norms) LCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch, h->norms, st));
-  const WorkList& wl = h->wl_series[li];
   const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
+  {
+    TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, rhs, ldr);
+    t.in_perm = rhs_perm ? h->perm : nullptr;
+    t.yout = y_cur;
+    t.ldy = ldin;
+    t.xacc = x_tree;
+    t.ldxa = N;
+    t.accumulate = 0;
+    if (K == 0 && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+    TIMED(HM_K_TERM_DINV, launch_term(false, h->max_m, t, h->tl_dinv.nwg, nrhs, st));
+  }
+  if (want_norms) HIPCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch, h->norms, st));
+  const TermList& tl = h->tl_series[li];
+  const GroupList& sa = h->sa[li];
   for (int k = 1; k <= K; ++k) {
-    {
-      ProfScope ps(h, HM_K_STAGEA, st);
-      LCHK(launch_stageA(f32, W, h->blk, h->nA[li], y_cur, ldin, N, nrhs, st));
-      ps.done();
-    }
-    {
-      ProfScope ps(h, HM_K_PANEL_SERIES, st);
-      LCHK(launch_panel(f32, h->max_m, series_set(h, f32), wl.items, wl.n, y_cur, ldin, nrhs,
-                        h->partial, ldp, st));
-      ps.done();
-    }
-    EpilogueArgs t = epi(h, wl, ldp);
+    if (sa.n > 0)
+      TIMED(HM_K_STAGEA, launch_stageA(f32, W, h->groups, sa.items, sa.n, y_cur, ldin, N, nrhs, st));
+    TermArgs t = term_args(h, series_set(h, f32), tl, f32, y_cur, ldin);
     t.alpha = -1.0;
     t.yout = y_nxt;
     t.ldy = ldin;
-    t.xacc = x_out;
+    t.xacc = x_tree;
     t.ldxa = N;
     t.accumulate = 1;
-    {
-      ProfScope ps(h, HM_K_EPILOGUE, st);
-      LCHK(launch_epilogue(t, h->nl, h->max_m, nrhs, st));
-      ps.done();
-    }
+    if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+    TIMED(HM_K_TERM_SERIES, launch_term(f32, h->max_m, t, tl.nwg, nrhs, st));
     std::swap(y_cur, y_nxt);
   }
   if (want_norms)
-    LCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
+    HIPCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
   return HM_OK;
 }
 
-// out = alpha * Z_l x + beta * v (tree order, ld N); x_tree is read from
-// xin0 (whose t part stage A fills).
+// alpha * Z_l x + beta * v (v tree order, ld N) from x in xin0 (tree order),
+// into out_tree (tree order, ld N) and/or out (original order, ld ldo).
 int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double beta,
-               const double2* v, double2* out, hipStream_t st) {
-  const int64_t N = h->N, ldin = h->N + h->T, ldp = h->partial_rows;
+               const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T;
   const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
-  {
-    ProfScope ps(h, HM_K_STAGEA, st);
-    LCHK(launch_stageA(f32, W, h->blk, h->nA[li], h->xin0, ldin, N, nrhs, st));
-    ps.done();
-  }
-  const WorkList& wl = h->wl_apply[li];
-  {
-    ProfScope ps(h, HM_K_PANEL_APPLY, st);
-    LCHK(launch_panel(f32, h->max_m, apply_set(h, f32), wl.items, wl.n, h->xin0, ldin, nrhs,
-                      h->partial, ldp, st));
-    ps.done();
-  }
-  EpilogueArgs e = epi(h, wl, ldp);
-  e.alpha = alpha;
-  e.beta = beta;
-  e.v = v;
-  e.ldv = N;
-  e.yout = out;
-  e.ldy = N;
-  {
-    ProfScope ps(h, HM_K_EPILOGUE, st);
-    LCHK(launch_epilogue(e, h->nl, h->max_m, nrhs, st));
-    ps.done();
-  }
+  const GroupList& sa = h->sa[li];
+  if (sa.n > 0)
+    TIMED(HM_K_STAGEA, launch_stageA(f32, W, h->groups, sa.items, sa.n, h->xin0, ldin, N, nrhs, st));
+  const TermList& tl = h->tl_apply[li];
+  TermArgs t = term_args(h, apply_set(h, f32), tl, f32, h->xin0, ldin);
+  t.alpha = alpha;
+  t.beta = beta;
+  t.v = v;
+  t.ldv = N;
+  t.yout = out_tree;
+  t.ldy = N;
+  if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+  TIMED(HM_K_TERM_APPLY, launch_term(f32, h->max_m, t, tl.nwg, nrhs, st));
   return HM_OK;
 }
 
@@ -371,91 +449,179 @@ int build_device(hm_matrix* h, hipStream_t st) {
   const HostH& H = h->H;
   const int nl = h->nl;
   const int64_t N = h->N;
-  // far blocks in device order (already finest first)
   const int nfar = (int)H.far.size();
-  std::vector<int32_t> tb(nfar);
-  int64_t T = 0;
+  h->nlev = (h->lmin < 0) ? 1 : (h->L - h->lmin + 1);
+  auto lev_of = [&](int li) { return (h->lmin < 0) ? h->L + 1 : h->lmin + li; };
+  auto rank = [&](int b) { return H.lowrank[H.far[b].src].r; };
+  const double* chi = H.chi_tree.empty() ? nullptr : H.chi_tree.data();
+  // W_b[q, j] = V[j, q] chi_s[j] of the stored orientation (n x r)
+  auto wval = [&](int b, int q, int j) -> double2 {
+    const FarBlock& fb = H.far[b];
+    const LowRank& lr = H.lowrank[fb.src];
+    const std::vector<cplx>& V = fb.transposed ? lr.U : lr.V;
+    cplx v = V[j + (size_t)q * fb.n];
+    if (chi) v *= chi[fb.s_off + j];
+    return make_double2(v.real(), v.imag());
+  };
+
+  // ---- classify far blocks: in-row (row cluster = one leaf) or global
+  std::vector<int> row_leaf(nfar, -1);
   for (int b = 0; b < nfar; ++b) {
-    tb[b] = (int32_t)T;
-    T += H.lowrank[H.far[b].src].r;
+    const int a = H.tree.leaf_of[H.far[b].t_off];
+    if (H.leaf_off[a] == H.far[b].t_off && H.leaf_size[a] == H.far[b].m) row_leaf[b] = a;
   }
-  h->T = T;
-  // far slices per leaf, in device order
-  std::vector<std::vector<std::pair<int, int>>> slices(nl);  // (block, row offset in block)
-  {
-    // leaf covering tree position: leaf_of
-    for (int b = 0; b < nfar; ++b) {
-      const FarBlock& fb = H.far[b];
-      int a = H.tree.leaf_of[fb.t_off];
-      while (a < nl && H.leaf_off[a] < fb.t_off + fb.m) {
-        slices[a].push_back({b, H.leaf_off[a] - fb.t_off});
-        ++a;
+
+  // ---- stage-A groups over global blocks: by source cluster, finest first
+  std::map<std::pair<int32_t, int32_t>, int> gkey;  // (s_off, n) -> group
+  for (int b = 0; b < nfar; ++b)
+    if (row_leaf[b] < 0) gkey.emplace(std::make_pair(H.far[b].s_off, H.far[b].n), 0);
+  int ng = 0;
+  for (auto& kv : gkey) kv.second = ng++;
+  std::vector<std::vector<int>> gblocks(ng);
+  for (int b = 0; b < nfar; ++b)
+    if (row_leaf[b] < 0) gblocks[gkey[{H.far[b].s_off, H.far[b].n}]].push_back(b);
+  std::vector<Group> groups(ng);
+  std::vector<int32_t> tb(nfar, -1);
+  std::vector<std::vector<int32_t>> grows(ng, std::vector<int32_t>(h->nlev, 0));
+  int64_t T = 0, wtot = 0;
+  for (auto& kv : gkey) {
+    const int g = kv.second;
+    auto& bl = gblocks[g];
+    std::sort(bl.begin(), bl.end(), [&](int x, int y) {
+      if (H.far[x].level != H.far[y].level) return H.far[x].level > H.far[y].level;
+      return H.far[x].t_off < H.far[y].t_off;
+    });
+    int32_t R = 0;
+    for (int b : bl) {
+      tb[b] = (int32_t)(T + R);
+      R += rank(b);
+    }
+    groups[g] = Group{kv.first.first, kv.first.second, (int32_t)T, even_ld(R), wtot};
+    T += R;
+    wtot += (int64_t)even_ld(R) * kv.first.second;
+    for (int li = 0; li < h->nlev; ++li) {
+      int32_t rr = 0;
+      for (int b : bl) {
+        if (H.far[b].level < lev_of(li)) break;
+        rr += rank(b);
       }
+      grows[g][li] = rr;
     }
   }
-  // levels
-  h->nlev = (h->lmin < 0) ? 1 : (h->L - h->lmin + 1);
-  std::vector<std::vector<int64_t>> far_end(h->nlev, std::vector<int64_t>(nl, 0));
-  std::vector<int64_t> near_cols(nl, 0), ncols(nl, 0);
+  h->T = T;
+  std::vector<double2> W((size_t)std::max<int64_t>(wtot, 1), make_double2(0.0, 0.0));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = groups[g];
+    int32_t row = 0;
+    for (int b : gblocks[g])
+      for (int q = 0; q < rank(b); ++q, ++row)
+        for (int j = 0; j < G.n; ++j) W[G.w_off + row + (int64_t)j * G.ld] = wval(b, q, j);
+  }
+
+  // ---- per leaf: in-row blocks (finest first) and global slices (finest first)
+  std::vector<std::vector<int>> inrow(nl);
+  std::vector<std::vector<std::pair<int, int>>> gslices(nl);  // (block, row offset in block)
+  for (int b = 0; b < nfar; ++b) {  // H.far is sorted finest level first
+    const FarBlock& fb = H.far[b];
+    if (row_leaf[b] >= 0) {
+      inrow[row_leaf[b]].push_back(b);
+      continue;
+    }
+    for (int a = H.tree.leaf_of[fb.t_off]; a < nl && H.leaf_off[a] < fb.t_off + fb.m; ++a)
+      gslices[a].push_back({b, H.leaf_off[a] - fb.t_off});
+  }
+  std::vector<int64_t> near_cols(nl, 0), ir_cols(nl, 0), gl_cols(nl, 0), ncols(nl, 0);
+  std::vector<std::vector<int64_t>> ir_end(h->nlev, std::vector<int64_t>(nl, 0));
+  std::vector<std::vector<int64_t>> gl_end(h->nlev, std::vector<int64_t>(nl, 0));
   std::vector<std::vector<int>> near_of(nl);
+  std::vector<int> diag_of(nl, -1);
   for (int q = 0; q < (int)H.near.size(); ++q) {
     const NearBlock& nb = H.near[q];
     if (nb.t_leaf != nb.s_leaf) {
       near_of[nb.t_leaf].push_back(q);
       near_cols[nb.t_leaf] += H.leaf_size[nb.s_leaf];
+    } else {
+      diag_of[nb.t_leaf] = q;
     }
   }
-  std::vector<int> diag_of(nl, -1);
-  for (int q = 0; q < (int)H.near.size(); ++q)
-    if (H.near[q].t_leaf == H.near[q].s_leaf) diag_of[H.near[q].t_leaf] = q;
   for (int a = 0; a < nl; ++a) {
     if (diag_of[a] < 0) { set_error("internal: missing diagonal block"); return HM_EINVAL; }
-    int64_t fc = 0;
-    for (auto& sl : slices[a]) fc += H.lowrank[H.far[sl.first].src].r;
-    ncols[a] = H.leaf_size[a] + near_cols[a] + fc;
+    for (int b : inrow[a]) ir_cols[a] += rank(b);
+    for (auto& sl : gslices[a]) gl_cols[a] += rank(sl.first);
+    ncols[a] = H.leaf_size[a] + near_cols[a] + ir_cols[a] + gl_cols[a];
     for (int li = 0; li < h->nlev; ++li) {
-      const int lev = (h->lmin < 0) ? h->L + 1 : h->lmin + li;
       int64_t e = 0;
-      for (auto& sl : slices[a]) {
-        const FarBlock& fb = H.far[sl.first];
-        if (fb.level < lev) break;
-        e += H.lowrank[fb.src].r;
+      for (int b : inrow[a]) {
+        if (H.far[b].level < lev_of(li)) break;
+        e += rank(b);
       }
-      far_end[li][a] = e;
+      ir_end[li][a] = e;
+      e = 0;
+      for (auto& sl : gslices[a]) {
+        if (H.far[sl.first].level < lev_of(li)) break;
+        e += rank(sl.first);
+      }
+      gl_end[li][a] = e;
     }
   }
-  // stage-A prefix counts per level
-  h->nA.assign(h->nlev, 0);
-  for (int li = 0; li < h->nlev; ++li) {
-    const int lev = (h->lmin < 0) ? h->L + 1 : h->lmin + li;
-    int c = 0;
-    while (c < nfar && H.far[c].level >= lev) ++c;
-    h->nA[li] = c;
-  }
-  // ---- host panels, sources
-  std::vector<int64_t> R_off(nl), R_col(nl), M_off(nl), M_col(nl), D_off(nl), piv_off(nl);
-  int64_t rtot = 0, ctot = 0, mtot = 0, dtot = 0, ptot = 0;
+
+  // ---- in-row W stacks: rows = (block, q) in in-row order, columns = source
+  std::vector<int64_t> ir_off(nl);
+  std::vector<int32_t> ir_ld(nl), ir_ncol(nl), ir_row0(nl);
+  int64_t irtot = 0, irrows = 0;
   for (int a = 0; a < nl; ++a) {
-    const int m = H.leaf_size[a];
+    int nmax = 0;
+    for (int b : inrow[a]) nmax = std::max(nmax, H.far[b].n);
+    ir_off[a] = irtot;
+    ir_ld[a] = even_ld((int)ir_cols[a]);
+    ir_ncol[a] = nmax;
+    ir_row0[a] = (int32_t)irrows;
+    irtot += (int64_t)ir_ld[a] * nmax;
+    irrows += ir_cols[a];
+  }
+  std::vector<double2> IR((size_t)std::max<int64_t>(irtot, 1), make_double2(0.0, 0.0));
+  std::vector<int32_t> ir_soff((size_t)std::max<int64_t>(irrows, 1)), ir_n((size_t)std::max<int64_t>(irrows, 1));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int a = 0; a < nl; ++a) {
+    int32_t row = 0;
+    for (int b : inrow[a]) {
+      const FarBlock& fb = H.far[b];
+      for (int q = 0; q < rank(b); ++q, ++row) {
+        ir_soff[ir_row0[a] + row] = fb.s_off;
+        ir_n[ir_row0[a] + row] = fb.n;
+        for (int j = 0; j < fb.n; ++j) IR[ir_off[a] + row + (int64_t)j * ir_ld[a]] = wval(b, q, j);
+      }
+    }
+  }
+
+  // ---- panels (ld = even(m)): [D | near | in-row U | global U slices]
+  std::vector<int64_t> R_off(nl), R_col(nl), M_off(nl), M_col(nl), LU_off(nl), Dinv_off(nl),
+      piv_off(nl);
+  int64_t rtot = 0, ctot = 0, mtot = 0, lutot = 0, ditot = 0, ptot = 0;
+  for (int a = 0; a < nl; ++a) {
+    const int m = H.leaf_size[a], ld = even_ld(m);
     R_off[a] = rtot;
-    rtot += (int64_t)m * ncols[a];
+    rtot += (int64_t)ld * ncols[a];
     R_col[a] = ctot;
     M_col[a] = ctot + m;
     ctot += ncols[a];
     M_off[a] = mtot;
-    mtot += (int64_t)m * (ncols[a] - m);
-    D_off[a] = dtot;
-    dtot += (int64_t)m * m;
+    mtot += (int64_t)ld * (ncols[a] - m);
+    LU_off[a] = lutot;
+    lutot += (int64_t)m * m;
+    Dinv_off[a] = ditot;
+    ditot += (int64_t)ld * m;
     piv_off[a] = ptot;
     ptot += m;
   }
-  std::vector<double2> R((size_t)rtot);
-  std::vector<int32_t> src((size_t)ctot);
-  std::vector<double2> D((size_t)dtot);
-  const double* chi = H.chi_tree.empty() ? nullptr : H.chi_tree.data();
+  std::vector<double2> R((size_t)std::max<int64_t>(rtot, 1), make_double2(0.0, 0.0));
+  std::vector<int32_t> src((size_t)std::max<int64_t>(ctot, 1));
+  std::vector<double2> D((size_t)lutot);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
     const int m = H.leaf_size[a];
+    const int64_t ld = even_ld(m);
     double2* P = R.data() + R_off[a];
     int32_t* S = src.data() + R_col[a];
     int64_t c = 0;
@@ -466,52 +632,32 @@ int build_device(hm_matrix* h, hipStream_t st) {
         S[c] = H.leaf_off[nb.s_leaf] + j;
         for (int i = 0; i < m; ++i) {
           const cplx v = z[i + (size_t)j * m];
-          P[i + c * m] = make_double2(v.real(), v.imag());
+          P[i + c * ld] = make_double2(v.real(), v.imag());
+        }
+      }
+    };
+    auto put_u = [&](int b, int row_in_block, int32_t src_base) {
+      const FarBlock& fb = H.far[b];
+      const LowRank& lr = H.lowrank[fb.src];
+      const std::vector<cplx>& U = fb.transposed ? lr.V : lr.U;  // m_b x r
+      for (int q = 0; q < lr.r; ++q, ++c) {
+        S[c] = src_base < 0 ? 0 : (int32_t)(src_base + q);
+        for (int i = 0; i < m; ++i) {
+          const cplx v = U[row_in_block + i + (size_t)q * fb.m];
+          P[i + c * ld] = make_double2(v.real(), v.imag());
         }
       }
     };
     put_block(H.near[diag_of[a]]);
     {
       const cplx* z = H.near_data.data() + H.near[diag_of[a]].data;
-      for (int64_t e = 0; e < (int64_t)m * m; ++e) D[D_off[a] + e] = make_double2(z[e].real(), z[e].imag());
+      for (int64_t e = 0; e < (int64_t)m * m; ++e) D[LU_off[a] + e] = make_double2(z[e].real(), z[e].imag());
     }
     for (int q : near_of[a]) put_block(H.near[q]);
-    for (auto& sl : slices[a]) {
-      const FarBlock& fb = H.far[sl.first];
-      const LowRank& lr = H.lowrank[fb.src];
-      const std::vector<cplx>& U = fb.transposed ? lr.V : lr.U;  // m_b x r
-      for (int q = 0; q < lr.r; ++q, ++c) {
-        S[c] = (int32_t)(N + tb[sl.first] + q);
-        for (int i = 0; i < m; ++i) {
-          const cplx v = U[sl.second + i + (size_t)q * fb.m];
-          P[i + c * m] = make_double2(v.real(), v.imag());
-        }
-      }
-    }
+    for (int b : inrow[a]) put_u(b, 0, -1);          // read from LDS, no source
+    for (auto& sl : gslices[a]) put_u(sl.first, sl.second, (int32_t)(N + tb[sl.first]));
   }
-  // stage A: W_b = V^T diag(chi_s) row-major r x n
-  std::vector<StageABlock> blk(nfar);
-  int64_t wtot = 0;
-  for (int b = 0; b < nfar; ++b) {
-    const FarBlock& fb = H.far[b];
-    const int r = H.lowrank[fb.src].r;
-    blk[b] = StageABlock{fb.s_off, fb.n, r, tb[b], wtot};
-    wtot += (int64_t)r * fb.n;
-  }
-  std::vector<double2> W((size_t)wtot);
-#pragma omp parallel for schedule(dynamic, 16)
-  for (int b = 0; b < nfar; ++b) {
-    const FarBlock& fb = H.far[b];
-    const LowRank& lr = H.lowrank[fb.src];
-    const std::vector<cplx>& V = fb.transposed ? lr.U : lr.V;  // n_b x r
-    double2* w = W.data() + blk[b].w_off;
-    for (int q = 0; q < lr.r; ++q)
-      for (int j = 0; j < fb.n; ++j) {
-        cplx v = V[j + (size_t)q * fb.n];
-        if (chi) v *= chi[fb.s_off + j];
-        w[(int64_t)q * fb.n + j] = make_double2(v.real(), v.imag());
-      }
-  }
+
   // ---- upload
   std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
   STCHK(upload(h, &h->perm, H.tree.perm, st));
@@ -524,22 +670,33 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->R_col, R_col, st));
   STCHK(upload(h, &h->M_off, M_off, st));
   STCHK(upload(h, &h->M_col, M_col, st));
-  STCHK(upload(h, &h->D_off, D_off, st));
+  STCHK(upload(h, &h->LU_off, LU_off, st));
+  STCHK(upload(h, &h->Dinv_off, Dinv_off, st));
   STCHK(upload(h, &h->piv_off, piv_off, st));
   STCHK(upload(h, &h->LU, D, st));
   std::vector<double2>().swap(D);
   STCHK(upload(h, &h->W64, W, st));
   std::vector<double2>().swap(W);
-  STCHK(upload(h, &h->blk, blk, st));
-  STCHK(dalloc(h, (void**)&h->Dinv, sizeof(double2) * dtot));
+  STCHK(upload(h, &h->groups, groups, st));
+  STCHK(upload(h, &h->IR64, IR, st));
+  std::vector<double2>().swap(IR);
+  STCHK(upload(h, &h->ir_off, ir_off, st));
+  STCHK(upload(h, &h->ir_ld, ir_ld, st));
+  STCHK(upload(h, &h->ir_ncol, ir_ncol, st));
+  STCHK(upload(h, &h->ir_row0, ir_row0, st));
+  STCHK(upload(h, &h->ir_soff, ir_soff, st));
+  STCHK(upload(h, &h->ir_n, ir_n, st));
+  STCHK(dalloc(h, (void**)&h->Dinv, sizeof(double2) * std::max<int64_t>(ditot, 1)));
   STCHK(dalloc(h, (void**)&h->piv, sizeof(int32_t) * ptot));
   STCHK(dalloc(h, (void**)&h->M64, sizeof(double2) * std::max<int64_t>(mtot, 1)));
+  HIPCHK(hipMemsetAsync(h->M64, 0, sizeof(double2) * std::max<int64_t>(mtot, 1), st));
+
   // ---- leaf LU with partial pivoting, then D^{-1} (eq. 12's near inverse)
   int* info = nullptr;
   STCHK(dalloc(h, (void**)&info, sizeof(int) * nl));
   HIPCHK(hipMemsetAsync(info, 0, sizeof(int) * nl, st));
-  LCHK(launch_getrf(h->LU, h->D_off, h->leaf_m, h->piv, h->piv_off, nl, info, st));
-  LCHK(launch_getri(h->LU, h->D_off, h->leaf_m, h->piv, h->piv_off, h->Dinv, nl, st));
+  HIPCHK(launch_getrf(h->LU, h->LU_off, h->leaf_m, h->piv, h->piv_off, nl, info, st));
+  HIPCHK(launch_getri(h->LU, h->LU_off, h->leaf_m, h->piv, h->piv_off, h->Dinv, h->Dinv_off, nl, st));
   std::vector<int> info_h(nl);
   HIPCHK(hipMemcpyAsync(info_h.data(), info, sizeof(int) * nl, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -548,7 +705,8 @@ int build_device(hm_matrix* h, hipStream_t st) {
       set_error("leaf block " + std::to_string(a) + " is singular");
       return HM_EINVAL;
     }
-  // ---- series panels M_a = D_a^{-1} [near | far] columns
+
+  // ---- series panels M_a = D_a^{-1} [near | in-row U | global U] columns
   std::vector<int32_t> tiles, ncm(nl);
   for (int a = 0; a < nl; ++a) {
     ncm[a] = (int32_t)(ncols[a] - H.leaf_size[a]);
@@ -557,48 +715,81 @@ int build_device(hm_matrix* h, hipStream_t st) {
   int32_t *d_tiles = nullptr, *d_ncm = nullptr;
   STCHK(upload(h, &d_tiles, tiles, st));
   STCHK(upload(h, &d_ncm, ncm, st));
-  LCHK(launch_premul(h->Dinv, h->D_off, h->R64, h->R_off, h->leaf_m, d_ncm, h->M64, h->M_off,
-                     d_tiles, (int)(tiles.size() / 2), h->max_m, st));
-  // ---- FP32 copies
+  HIPCHK(launch_premul(h->Dinv, h->Dinv_off, h->R64, h->R_off, h->leaf_m, d_ncm, h->M64, h->M_off,
+                       d_tiles, (int)(tiles.size() / 2), h->max_m, st));
+
+  // ---- FP32 copies (same layout, pad rows stay zero)
   if (h->has_f32) {
-    STCHK(dalloc(h, (void**)&h->R32, sizeof(float2) * rtot));
+    STCHK(dalloc(h, (void**)&h->R32, sizeof(float2) * std::max<int64_t>(rtot, 1)));
     STCHK(dalloc(h, (void**)&h->M32, sizeof(float2) * std::max<int64_t>(mtot, 1)));
     STCHK(dalloc(h, (void**)&h->W32, sizeof(float2) * std::max<int64_t>(wtot, 1)));
-    LCHK(launch_cast(h->R64, h->R32, rtot, st));
-    LCHK(launch_cast(h->M64, h->M32, mtot, st));
-    LCHK(launch_cast(h->W64, h->W32, wtot, st));
+    STCHK(dalloc(h, (void**)&h->IR32, sizeof(float2) * std::max<int64_t>(irtot, 1)));
+    HIPCHK(launch_cast(h->R64, h->R32, rtot, st));
+    HIPCHK(launch_cast(h->M64, h->M32, mtot, st));
+    HIPCHK(launch_cast(h->W64, h->W32, wtot, st));
+    HIPCHK(launch_cast(h->IR64, h->IR32, irtot, st));
   }
-  // ---- work lists
-  std::vector<int64_t> zero(nl, 0), last(nl);
-  h->wl_apply.assign(h->nlev, WorkList());
-  h->wl_series.assign(h->nlev, WorkList());
-  h->bytes_R.assign(h->nlev, 0);
-  h->bytes_M.assign(h->nlev, 0);
-  h->bytes_W.assign(h->nlev, 0);
+
+  // ---- work lists per level: one resident round of persistent workgroups
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->device));
+    const int occ = std::min(term_occupancy(false, h->max_m), term_occupancy(true, h->max_m));
+    h->term_wgs = std::max(1, prop.multiProcessorCount * occ);
+  }
+  h->tl_apply.assign(h->nlev, TermList());
+  h->tl_series.assign(h->nlev, TermList());
+  h->sa.assign(h->nlev, GroupList());
+  h->ent_R.assign(h->nlev, 0);
+  h->ent_M.assign(h->nlev, 0);
+  h->ent_W.assign(h->nlev, 0);
   h->ncoef.assign(h->nlev, 0);
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
+  std::vector<int64_t> irr(nl), irc(nl);
   for (int li = 0; li < h->nlev; ++li) {
     int64_t eR = 0, eM = 0, eW = 0, nc = 0;
-    for (int a = 0; a < nl; ++a) {
-      last[a] = H.leaf_size[a] + near_cols[a] + far_end[li][a];
-      eR += (int64_t)H.leaf_size[a] * last[a];
+    for (int pass = 0; pass < 2; ++pass) {  // 0: apply panels, 1: series panels
+      for (int a = 0; a < nl; ++a) {
+        const int64_t m = H.leaf_size[a];
+        const int64_t base = pass == 0 ? 0 : -m;  // series panels have no D columns
+        const int64_t gstart = base + m + near_cols[a] + ir_cols[a];
+        dense[a].clear();
+        dense[a].push_back({0, base + m + near_cols[a]});
+        if (gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + gl_end[li][a]});
+        irr[a] = ir_end[li][a];
+        irc[a] = base + m + near_cols[a];
+        const int64_t cols = (base + m + near_cols[a]) + ir_end[li][a] + gl_end[li][a];
+        (pass == 0 ? eR : eM) += m * cols;
+      }
+      STCHK(make_termlist(h, dense, irr, irc, ir_ncol, pass == 0 ? h->tl_apply[li] : h->tl_series[li], st));
     }
-    STCHK(make_worklist(h, zero, last, h->wl_apply[li], st));
-    for (int a = 0; a < nl; ++a) {
-      last[a] = near_cols[a] + far_end[li][a];
-      eM += (int64_t)H.leaf_size[a] * last[a];
+    std::vector<GroupItem> items;
+    for (int g = 0; g < ng; ++g) {
+      const int rows = grows[g][li];
+      eW += (int64_t)rows * groups[g].n;
+      nc += rows;
+      for (int r0 = 0; r0 < rows; r0 += kGroupTile) items.push_back({g, r0, rows, 0});
     }
-    STCHK(make_worklist(h, zero, last, h->wl_series[li], st));
-    for (int b = 0; b < h->nA[li]; ++b) {
-      eW += (int64_t)blk[b].r * blk[b].n;
-      nc += blk[b].r;
-    }
+    for (int a = 0; a < nl; ++a)
+      for (int b : inrow[a]) {
+        if (H.far[b].level < lev_of(li)) break;
+        eW += (int64_t)rank(b) * H.far[b].n;
+        nc += rank(b);
+      }
+    STCHK(upload_groups(h, items, h->sa[li], st));
+    h->ent_R[li] = eR;
+    h->ent_M[li] = eM;
+    h->ent_W[li] = eW;
     h->ncoef[li] = nc;
-    h->bytes_R[li] = eR;
-    h->bytes_M[li] = eM;
-    h->bytes_W[li] = eW;
   }
-  for (int a = 0; a < nl; ++a) last[a] = H.leaf_size[a];
-  STCHK(make_worklist(h, zero, last, h->wl_dinv, st));
+  {
+    std::vector<int64_t> zero(nl, 0);
+    for (int a = 0; a < nl; ++a) {
+      dense[a].clear();
+      dense[a].push_back({0, H.leaf_size[a]});
+    }
+    STCHK(make_termlist(h, dense, zero, zero, ir_ncol, h->tl_dinv, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   return HM_OK;
 }
@@ -606,7 +797,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
 int validate_problem(const hm_problem* p, const hm_build_opts* o) {
   if (!p || !o) { set_error("null problem or options"); return HM_EINVAL; }
   if (p->n < 1 || !p->xyz) { set_error("n must be >= 1 and xyz non-null"); return HM_EINVAL; }
-  if (p->n > (int64_t)1 << 30) { set_error("n too large"); return HM_EINVAL; }
+  if (p->n > (int64_t)1 << 28) { set_error("n too large"); return HM_EINVAL; }
   if (p->kind != HM_SURFACE && p->kind != HM_VOLUME) { set_error("bad kind"); return HM_EINVAL; }
   if (p->kind == HM_VOLUME && !p->chi) { set_error("volume problem needs chi"); return HM_EINVAL; }
   if (!(p->k > 0) || !(p->h > 0)) { set_error("k and h must be > 0"); return HM_EINVAL; }
@@ -639,19 +830,19 @@ void fill_info(const hm_matrix* h, hm_info* out) {
   }
   for (const auto& fb : H.far) {
     if (fb.level < 0 || fb.level >= HM_MAX_LEVELS) continue;
-    const int r = H.lowrank.empty() ? 0 : H.lowrank[fb.src].r;
+    const int r = H.lowrank[fb.src].r;
     out->far_blocks[fb.level] += 1;
     out->far_rank_sum[fb.level] += r;
     out->far_entries[fb.level] += (int64_t)r * (fb.m + fb.n);
   }
   out->device_bytes = h->bytes;
   out->build_ms = h->build_ms;
-  for (int li = 0; li < (int)h->bytes_M.size(); ++li) {
+  for (int li = 0; li < (int)h->ent_M.size(); ++li) {
     const int lev = (h->lmin < 0) ? h->L : h->lmin + li;
     if (lev < 0 || lev >= HM_MAX_LEVELS) continue;
-    out->series_entries[lev] = h->bytes_M[li];
-    out->apply_entries[lev] = h->bytes_R[li];
-    out->stageA_entries[lev] = h->bytes_W[li];
+    out->series_entries[lev] = h->ent_M[li];
+    out->apply_entries[lev] = h->ent_R[li];
+    out->stageA_entries[lev] = h->ent_W[li];
     out->coeffs[lev] = h->ncoef[li];
   }
 }
@@ -748,9 +939,8 @@ int hmat_apply(hm_matrix_t h, int32_t level, int32_t precision, const void* x_de
   STCHK(ensure_workspace(h, nrhs));
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t ldin = h->N + h->T;
-  LCHK(launch_permute_in((const double2*)x_dev, ldx, h->perm, h->xin0, ldin, h->N, nrhs, st));
-  STCHK(apply_core(h, li, f32, nrhs, 1.0, 0.0, nullptr, h->bt, st));
-  LCHK(launch_permute_out(h->bt, h->N, h->perm, (double2*)y_dev, ldy, h->N, nrhs, st));
+  HIPCHK(launch_permute_in((const double2*)x_dev, ldx, h->perm, h->xin0, ldin, h->N, nrhs, st));
+  STCHK(apply_core(h, li, f32, nrhs, 1.0, 0.0, nullptr, nullptr, (double2*)y_dev, ldy, st));
   return HM_OK;
 }
 
@@ -785,8 +975,14 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
   }
-  LCHK(launch_permute_in((const double2*)b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
-  STCHK(series_core(h, li, f32, o->K, h->bt, h->xt, nrhs, want, st));
+  const bool refine = o->kind == PS_REFINE;
+  if (refine) {
+    HIPCHK(launch_permute_in((const double2*)b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
+    STCHK(series_core(h, li, f32, o->K, h->bt, N, false, h->xt, nullptr, 0, nrhs, want, st));
+  } else {
+    STCHK(series_core(h, li, f32, o->K, (const double2*)b_dev, ldb, true, h->xt, (double2*)x_dev,
+                      ldx, nrhs, want, st));
+  }
   std::vector<double> growth(nrhs, 0.0), resid(nrhs, 0.0);
   std::vector<int> passes(nrhs, 0), done(nrhs, 0);
   auto read_norms = [&]() -> int {
@@ -804,13 +1000,13 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   if (o->kind == PS_REFINE) {
     for (int pass = 1; pass <= o->max_passes; ++pass) {
       // r = b - Z_l x in FP64 (all blocks including D)
-      LCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
-      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, st));
+      HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, nullptr, 0, st));
       // d = P_K r, x += d
-      STCHK(series_core(h, li, f32, o->K, h->rt, h->dt, nrhs, false, st));
-      LCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
-      LCHK(launch_norm2(h->dt, N, N, nrhs, h->nscratch, h->norms, st));
-      LCHK(launch_norm2(h->xt, N, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
+      STCHK(series_core(h, li, f32, o->K, h->rt, N, false, h->dt, nullptr, 0, nrhs, false, st));
+      HIPCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
+      HIPCHK(launch_norm2(h->dt, N, N, nrhs, h->nscratch, h->norms, st));
+      HIPCHK(launch_norm2(h->xt, N, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
       STCHK(read_norms());
       bool all = true;
       for (int c = 0; c < nrhs; ++c) {
@@ -826,7 +1022,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
       if (all) break;
     }
   }
-  LCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
+  if (refine) HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
   int status = HM_OK;
   if (per_rhs) {
     HIPCHK(hipEventRecord(ev1, st));
@@ -854,7 +1050,6 @@ int hmat_export(hm_matrix_t h, const char* path) {
   if (!h || !path) { set_error("null argument"); return HM_EINVAL; }
   if (!h->host_kept) { set_error("host blocks were released (build with HM_BUILD_KEEP_HOST)"); return HM_ESTATE; }
   if (h->host_only) return export_host(h->H, path, nullptr, nullptr);
-  // add the device LU factors
   HIPCHK(hipSetDevice(h->device));
   int64_t dtot = 0;
   for (int a = 0; a < h->nl; ++a) dtot += (int64_t)h->H.leaf_size[a] * h->H.leaf_size[a];

@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hmps.h"
+#include "hmps.h"
 
 namespace hm {
 

@@ -65,7 +65,7 @@ class hm_info(C.Structure):
                 ("coeffs", C.c_int64 * HM_MAX_LEVELS)]
 
 
-HM_K_STAGEA, HM_K_PANEL_SERIES, HM_K_PANEL_APPLY, HM_K_PANEL_DINV, HM_K_EPILOGUE, HM_K_COUNT = range(6)
+HM_K_STAGEA, HM_K_TERM_SERIES, HM_K_TERM_APPLY, HM_K_TERM_DINV, HM_K_COUNT = range(5)
 
 
 class hm_kernel_time(C.Structure):

@@ -71,6 +71,25 @@ def ragged():
     return Case("sphere_1000_leaf40", W.sphere_problem(1000, math.sqrt(1000 / 1536)), 40, 1e-4, 7)
 
 
+@pytest.fixture(scope="module")
+def ragged_depth():
+    """Leaves at depths 5 and 6 (sizes 68 and 34/35); far blocks on levels 5
+    and 6, some of them with a one-leaf row cluster at level 5."""
+    return Case("sphere_2200_leaf68", W.sphere_problem(2200, math.sqrt(2200 / 1536)), 68, 1e-4, 3)
+
+
+def test_series_ragged_depths_each_level(ragged_depth):
+    c = ragged_depth
+    for lev in [-1] + list(reversed(c.H.far_levels)):
+        for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+            _say(f"series {c.name} level={lev} precision={prec}")
+            x = _host(c.h.solve(_dev(c.b), K=3, level=lev, precision=prec))
+            assert series.rel_err(x, series.series(c.H, c.b, 3, lev)) <= tol, (lev, prec)
+        _say(f"hmat_apply {c.name} level={lev}")
+        y = _host(c.h.apply(_dev(c.b), level=lev))
+        assert series.rel_err(y, series.apply_Z(c.H, c.b, lev)) <= 1e-12
+
+
 def test_series_f64_sphere(sphere):
     _say("series f64 sphere_1536 K=4 leaf level")
     x = _host(sphere.h.solve(_dev(sphere.b), K=4))

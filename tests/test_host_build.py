@@ -47,6 +47,8 @@ CASES = {
     "sphere_1000_leaf40": lambda: (W.sphere_problem(1000, math.sqrt(1000 / 1536)), 40, 1e-4),
     "cube_1000_leaf32": lambda: (W.cube_problem(10, 10 / 16), 32, 1e-5),
     "cube_1728_leaf40": lambda: (W.cube_problem(12, 12 / 16), 40, 1e-5),
+    # leaves at depths 5 and 6 (sizes 68 and 34/35), far blocks on levels 5, 6
+    "sphere_2200_leaf68_ragged": lambda: (W.sphere_problem(2200, math.sqrt(2200 / 1536)), 68, 1e-4),
 }
 
 
