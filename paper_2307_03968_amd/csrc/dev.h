@@ -101,7 +101,7 @@ struct TermArgs {
   const int64_t* out_perm;
 };
 
-constexpr int kInRowTile = 128;  // stack rows per kind-1 item
+constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)
 constexpr int kGroupTile = 128;  // rows per stage-A group item
 
 // ---- launchers (return hipError_t of the launch) ---------------------------

@@ -55,7 +55,7 @@ template <>
 struct Elem<1> {
   using T = double2;
   __device__ static __forceinline__ T zero() { return make_double2(0.0, 0.0); }
-  __device__ static __forceinline__ T load(const void* base, int64_t idx) {
+  __device__ static __forceinline__ T load(const void* base, uint32_t idx) {
     const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(base) + idx);
     return make_double2(v.x, v.y);
   }
@@ -68,7 +68,7 @@ template <>
 struct Elem<2> {
   using T = float4;
   __device__ static __forceinline__ T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
-  __device__ static __forceinline__ T load(const void* base, int64_t idx) {  // idx even
+  __device__ static __forceinline__ T load(const void* base, uint32_t idx) {  // idx even
     const fvec4 v = __builtin_nontemporal_load(reinterpret_cast<const fvec4*>(base) + (idx >> 1));
     return make_float4(v.x, v.y, v.z, v.w);
   }
@@ -92,9 +92,11 @@ __device__ __forceinline__ void tall_gemv(const void* __restrict__ P, int64_t ld
                                           double2 (&acc)[G][E][NR]) {
   using T = typename Elem<E>::T;
   (void)rows;
-  int64_t ri[G];
+  // element offsets within one panel fit in 32 bits (checked at build time)
+  uint32_t ri[G];
 #pragma unroll
-  for (int g = 0; g < G; ++g) ri[g] = min<int64_t>(row0 + (g * 64 + lane) * E, ld - E);
+  for (int g = 0; g < G; ++g) ri[g] = (uint32_t)min<int64_t>(row0 + (g * 64 + lane) * E, ld - E);
+  const uint32_t ld32 = (uint32_t)ld;
   for (int c = c0 + w; c < c1; c += kWaves * UNR) {
     T a[UNR][G];
     double2 xv[UNR][NR];
@@ -102,7 +104,7 @@ __device__ __forceinline__ void tall_gemv(const void* __restrict__ P, int64_t ld
     for (int u = 0; u < UNR; ++u) {
       const int cc = c + kWaves * u;
       const bool ok = cc < c1;
-      const int64_t col = (int64_t)(ok ? cc : c1 - 1) * ld;
+      const uint32_t col = (uint32_t)(ok ? cc : c1 - 1) * ld32;
 #pragma unroll
       for (int g = 0; g < G; ++g) a[u][g] = Elem<E>::load(P, ri[g] + col);
 #pragma unroll
@@ -192,10 +194,10 @@ __device__ __forceinline__ void inrow_t(const void* __restrict__ Wa, int64_t wld
                                         int nrhs, int w, int lane, double2 (&acc)[GW][E][NR]) {
   using T = typename Elem<E>::T;
   int so[GW][E], nn[GW][E];
-  int64_t ri[GW];
+  uint32_t ri[GW];
 #pragma unroll
   for (int g = 0; g < GW; ++g) {
-    ri[g] = min<int64_t>(r0 + (g * 64 + lane) * E, wld - E);
+    ri[g] = (uint32_t)min<int64_t>(r0 + (g * 64 + lane) * E, wld - E);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int row = r0 + (g * 64 + lane) * E + e;
@@ -209,7 +211,7 @@ __device__ __forceinline__ void inrow_t(const void* __restrict__ Wa, int64_t wld
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
       const int cc = c + kWaves * u;
-      const int64_t col = (int64_t)(cc < ncol ? cc : ncol - 1) * wld;
+      const uint32_t col = (uint32_t)(cc < ncol ? cc : ncol - 1) * (uint32_t)wld;
 #pragma unroll
       for (int g = 0; g < GW; ++g) {
         wv[u][g] = Elem<E>::load(Wa, ri[g] + col);
@@ -239,7 +241,7 @@ __device__ __forceinline__ void inrow_t(const void* __restrict__ Wa, int64_t wld
 
 template <int E, int G, int NR>
 constexpr int term_red_slots() {
-  return (G > kInRowTile / (64 * E) ? G : kInRowTile / (64 * E)) * E * NR;
+  return G * E * NR;  // >= the in-row tile's 1 * E * NR
 }
 
 // Epilogue of leaf a for the RHS tile [rhs0, rhs0 + NR): z = sum of the
@@ -323,7 +325,7 @@ __device__ void term_epilogue(const TermArgs& A, int a, int rhs0, int nrhs, int*
 // workgroup that completes a leaf runs the leaf's epilogue.
 template <int E, int G, int NR, int UNR>
 __global__ __launch_bounds__(kThreads) void k_term(TermArgs A, int nrhs) {
-  constexpr int GW = kInRowTile / (64 * E);
+  constexpr int GW = 1;  // kInRowTile rows: one row per lane (E = 2: half the lanes)
   const int rhs0 = blockIdx.y * NR;
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
@@ -364,7 +366,7 @@ __global__ __launch_bounds__(kThreads) void k_term(TermArgs A, int nrhs) {
       double2 tacc[GW][E][NR];
       zero_acc(tacc);
       const int rb = A.ir.row0[a];
-      inrow_t<E, GW, NR, 4>(Elem<E>::offset(A.ir.W, A.ir.off[a]), A.ir.ld[a], A.ir.ncol[a],
+      inrow_t<E, GW, NR, (UNR > 4 ? 4 : UNR)>(Elem<E>::offset(A.ir.W, A.ir.off[a]), A.ir.ld[a], A.ir.ncol[a],
                             it.r0, it.r1, A.ir.soff + rb, A.ir.n + rb, A.xin, A.ldx, rhs0, nrhs,
                             w, lane, tacc);
       reduce_waves(tacc, w, lane, red);

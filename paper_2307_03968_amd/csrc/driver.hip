@@ -337,7 +337,8 @@ hipEvent_t pool_event(hm_matrix* h) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing-only events: no system-scope fence when they are recorded
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
@@ -657,6 +658,19 @@ int build_device(hm_matrix* h, hipStream_t st) {
     for (int b : inrow[a]) put_u(b, 0, -1);          // read from LDS, no source
     for (auto& sl : gslices[a]) put_u(sl.first, sl.second, (int32_t)(N + tb[sl.first]));
   }
+
+  // kernels address one panel, W stack or group with 32-bit element offsets
+  for (int a = 0; a < nl; ++a)
+    if ((int64_t)even_ld(H.leaf_size[a]) * ncols[a] >= ((int64_t)1 << 31) ||
+        (int64_t)ir_ld[a] * ir_ncol[a] >= ((int64_t)1 << 31)) {
+      set_error("a leaf panel exceeds 2^31 elements");
+      return HM_EINVAL;
+    }
+  for (const Group& G : groups)
+    if ((int64_t)G.ld * G.n >= ((int64_t)1 << 31)) {
+      set_error("a stage-A group exceeds 2^31 elements");
+      return HM_EINVAL;
+    }
 
   // ---- upload
   std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
