@@ -145,6 +145,7 @@ typedef struct {
   int64_t apply_entries[HM_MAX_LEVELS];
   int64_t stageA_entries[HM_MAX_LEVELS];
   int64_t coeffs[HM_MAX_LEVELS];
+  int32_t num_instances;            /* 1, or the count of a batched handle  */
 } hm_info;
 
 /* Kernel classes timed by hm_profile_enable. */
@@ -174,6 +175,18 @@ typedef struct hm_matrix* hm_matrix_t;
 int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
                hm_matrix_t* out);
 
+/* Batched build: `count` independent problems (sizes may differ) with the
+ * same options, merged into one block-diagonal H-matrix so that one
+ * persistent launch per series term serves all of them.  Vectors passed to
+ * hmat_apply / ps_solve on the handle hold the instances one after another
+ * (instance i at rows off_i .. off_i + n_i - 1, off_i = n_0 + ... + n_{i-1}),
+ * each in its own original point order.  Levels of a batched handle count
+ * from the top: level -1 (or HM_MAX_LEVELS - 1) selects every instance's
+ * leaf-level far blocks, HM_MAX_LEVELS - 1 - d adds the blocks up to d levels
+ * above each instance's leaf level.  hmat_info reports levels the same way. */
+int hmat_build_batched(const hm_problem* probs, int32_t count, const hm_build_opts* opts,
+                       void* hip_stream, hm_matrix_t* out);
+
 /* Structure statistics (host only, no device access). */
 int hmat_info(hm_matrix_t h, hm_info* out);
 
@@ -197,6 +210,24 @@ int ps_solve(hm_matrix_t h, const ps_opts* opts, const void* b_dev, int64_t ldb,
  * raw little-endian data.  For checking the build against an independent
  * implementation. */
 int hmat_export(hm_matrix_t h, const char* path);
+
+/* Launch tuning of a device handle.  mm_min_rhs: from this many
+ * right-hand sides on, the term and stage-A products of ps_solve and
+ * hmat_apply run as matrix-core (MFMA) contractions over tiles of 16, 32 or
+ * 64 right-hand sides (FP32 blocks: three real products per complex one;
+ * FP64: four); below it, one-RHS-tile streaming kernels run (default 8).
+ * term_wgs: persistent workgroups per term launch (the work lists are split
+ * evenly over them; default: compute units x resident workgroups per unit).
+ * Results do not depend on either value beyond rounding order.  Changing
+ * term_wgs rebuilds the work lists (synchronises the stream); the handle
+ * must not be in use on another stream meanwhile.  In hmat_tune a field of
+ * 0 keeps its value and -1 restores the default. */
+typedef struct {
+  int32_t mm_min_rhs;
+  int32_t term_wgs;
+} hm_tuning;
+int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
+int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
 
 /* Per-kernel timing for measurement: while enabled, every launch of the
  * classes above is bracketed by HIP events recorded on the launch stream.

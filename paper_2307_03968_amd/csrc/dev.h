@@ -103,12 +103,24 @@ struct TermArgs {
 
 constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)
 constexpr int kGroupTile = 128;  // rows per stage-A group item
+// Many right-hand sides (MFMA path): stage A uses groups over all far blocks
+// (in-row ones included) by source cluster, with their own W copies and t
+// slots; items are 64-row tiles.
+constexpr int kGroupTileMM = 64;
+
 
 // ---- launchers (return hipError_t of the launch) ---------------------------
 hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm, double2* out,
                              int64_t ldo, int64_t n, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, double2* x,
                               int64_t ldx, int64_t n, int nrhs, hipStream_t st);
+// many-RHS variants on MFMA (FP32 3M, FP64 4M), right-hand sides in tiles
+// of 16/32/64 per workgroup
+hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
+                          hipStream_t st);
+hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
+                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs,
+                            hipStream_t st);
 // nwg persistent workgroups; grid.y covers the right-hand sides
 hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
                        hipStream_t st);

@@ -3,6 +3,7 @@
 // packs and enqueues; every step of the solve runs in the kernels of
 // device.hip on the caller's stream.
 #include <hip/hip_runtime.h>
+#include <omp.h>
 
 #include <algorithm>
 #include <chrono>
@@ -61,6 +62,8 @@ struct hm_matrix {
   int device = -1;
   int64_t N = 0, T = 0;
   int nl = 0, max_m = 0, L = 0, lmin = -1, nlev = 1;
+  int ninst = 1;
+  std::vector<int64_t> inst_off;
   double build_ms = 0;
   int64_t bytes = 0;
   std::vector<void*> allocs;
@@ -100,8 +103,25 @@ struct hm_matrix {
   std::vector<hm::GroupList> sa;
   std::vector<int64_t> ent_R, ent_M, ent_W, ncoef;
   hm::TermList tl_dinv;
+  // many right-hand sides (matrix-core kernels): every far block goes
+  // through stage A (groups over all far blocks by source cluster), so the
+  // panels' in-row U columns read their t from xin like the global ones
+  int32_t* src_mm = nullptr;
+  double2* Wmm64 = nullptr;
+  float2* Wmm32 = nullptr;
+  hm::Group* groups_mm = nullptr;
+  std::vector<hm::TermList> tl_apply_mm, tl_series_mm;
+  std::vector<hm::GroupList> sa_mm;
+  int mm_min_rhs = 8;           // right-hand sides from which the MFMA kernels run
+  // per-leaf column layout of the panels, kept to rebuild the work lists
+  std::vector<int64_t> near_cols, ir_cols;
+  std::vector<int32_t> ir_ncol_h;
+  std::vector<std::vector<int64_t>> ir_end, gl_end;
+  std::vector<void*> list_allocs;  // device work lists (rebuilt by hmat_tune)
+  int64_t list_bytes = 0;
   int64_t partial_rows = 0;
   int term_wgs = 1024;          // persistent workgroups of a term kernel
+  int term_wgs_auto = 1024;
   int32_t* counters = nullptr;  // workspace
   // workspace
   int ws_nrhs = 0;
@@ -120,6 +140,7 @@ struct hm_matrix {
     for (auto& r : prof_recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : ws_allocs) (void)hipFree(p);
+    for (void* p : list_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
     if (norms_host) (void)hipHostFree(norms_host);
   }
@@ -129,7 +150,9 @@ namespace hm {
 
 namespace {
 
-int dalloc(hm_matrix* h, void** p, size_t bytes) {
+// Device allocation owned by the handle (freed with it), or by the work
+// lists when `lists` is set (freed when they are rebuilt).
+int dalloc(hm_matrix* h, void** p, size_t bytes, bool lists = false) {
   *p = nullptr;
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
@@ -138,14 +161,15 @@ int dalloc(hm_matrix* h, void** p, size_t bytes) {
     set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
     return HM_ENOMEM;
   }
-  h->allocs.push_back(*p);
+  (lists ? h->list_allocs : h->allocs).push_back(*p);
   h->bytes += (int64_t)bytes;
+  if (lists) h->list_bytes += (int64_t)bytes;
   return HM_OK;
 }
 
 template <typename T>
-int upload(hm_matrix* h, T** dst, const std::vector<T>& v, hipStream_t st) {
-  STCHK(dalloc(h, (void**)dst, v.size() * sizeof(T)));
+int upload(hm_matrix* h, T** dst, const std::vector<T>& v, hipStream_t st, bool lists = false) {
+  STCHK(dalloc(h, (void**)dst, v.size() * sizeof(T), lists));
   if (!v.empty()) HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));  // host vectors may be freed after return
   return HM_OK;
@@ -250,10 +274,10 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   tl.nwg = G;
   tl.npieces = (int)items.size();
   tl.rows = rows;
-  STCHK(upload(h, &tl.items, by_wg, st));
-  STCHK(upload(h, &tl.wptr, wptr, st));
-  STCHK(upload(h, &tl.lptr, lptr, st));
-  STCHK(upload(h, &tl.lprow, lprow, st));
+  STCHK(upload(h, &tl.items, by_wg, st, true));
+  STCHK(upload(h, &tl.wptr, wptr, st, true));
+  STCHK(upload(h, &tl.lptr, lptr, st, true));
+  STCHK(upload(h, &tl.lprow, lprow, st, true));
   h->partial_rows = std::max(h->partial_rows, rows);
   return HM_OK;
 }
@@ -297,12 +321,12 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   return HM_OK;
 }
 
-PanelSet apply_set(const hm_matrix* h, bool f32) {
-  return PanelSet{f32 ? (const void*)h->R32 : (const void*)h->R64, h->R_off, h->src, h->R_col,
+PanelSet apply_set(const hm_matrix* h, bool f32, const int32_t* src) {
+  return PanelSet{f32 ? (const void*)h->R32 : (const void*)h->R64, h->R_off, src, h->R_col,
                   h->leaf_m};
 }
-PanelSet series_set(const hm_matrix* h, bool f32) {
-  return PanelSet{f32 ? (const void*)h->M32 : (const void*)h->M64, h->M_off, h->src, h->M_col,
+PanelSet series_set(const hm_matrix* h, bool f32, const int32_t* src) {
+  return PanelSet{f32 ? (const void*)h->M32 : (const void*)h->M64, h->M_off, src, h->M_col,
                   h->leaf_m};
 }
 PanelSet dinv_set(const hm_matrix* h) {
@@ -374,13 +398,45 @@ struct ProfScope {
 // tree order (ld N), or in original order through the permutation when
 // rhs_perm is set (ld ldr).  When out is set the final x is also written
 // there in original order (ld ldo).
+// From h->mm_min_rhs right-hand sides on, the term and stage-A products run
+// on the matrix cores (MM kernels, their own lists and stage-A groups).
+struct Path {
+  bool mm;
+  const void* W;
+  const Group* groups;
+  const std::vector<GroupList>* sa;
+  const std::vector<TermList>* tl_series;
+  const std::vector<TermList>* tl_apply;
+  const int32_t* src;
+};
+
+Path pick_path(const hm_matrix* h, bool f32, int nrhs) {
+  if (nrhs >= h->mm_min_rhs)
+    return Path{true, f32 ? (const void*)h->Wmm32 : (const void*)h->Wmm64, h->groups_mm,
+                &h->sa_mm, &h->tl_series_mm, &h->tl_apply_mm, h->src_mm};
+  return Path{false, f32 ? (const void*)h->W32 : (const void*)h->W64, h->groups, &h->sa,
+              &h->tl_series, &h->tl_apply, h->src};
+}
+
+hipError_t run_term(const hm_matrix* h, const Path& P, bool f32, const TermArgs& t,
+                    const TermList& tl, int nrhs, hipStream_t st) {
+  return P.mm ? launch_term_mm(f32, h->max_m, t, tl.nwg, nrhs, st)
+              : launch_term(f32, h->max_m, t, tl.nwg, nrhs, st);
+}
+
+hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupList& sa,
+                      double2* xin, int64_t ldx, int nrhs, hipStream_t st) {
+  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st)
+              : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
+}
+
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
                 bool want_norms, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
-  const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
+  const Path P = pick_path(h, f32, nrhs);
   {
     TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, rhs, ldr);
     t.in_perm = rhs_perm ? h->perm : nullptr;
@@ -390,15 +446,14 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     t.ldxa = N;
     t.accumulate = 0;
     if (K == 0 && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-    TIMED(HM_K_TERM_DINV, launch_term(false, h->max_m, t, h->tl_dinv.nwg, nrhs, st));
+    TIMED(HM_K_TERM_DINV, run_term(h, P, false, t, h->tl_dinv, nrhs, st));
   }
   if (want_norms) HIPCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch, h->norms, st));
-  const TermList& tl = h->tl_series[li];
-  const GroupList& sa = h->sa[li];
+  const TermList& tl = (*P.tl_series)[li];
+  const GroupList& sa = (*P.sa)[li];
   for (int k = 1; k <= K; ++k) {
-    if (sa.n > 0)
-      TIMED(HM_K_STAGEA, launch_stageA(f32, W, h->groups, sa.items, sa.n, y_cur, ldin, N, nrhs, st));
-    TermArgs t = term_args(h, series_set(h, f32), tl, f32, y_cur, ldin);
+    if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, ldin, nrhs, st));
+    TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, y_cur, ldin);
     t.alpha = -1.0;
     t.yout = y_nxt;
     t.ldy = ldin;
@@ -406,7 +461,7 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     t.ldxa = N;
     t.accumulate = 1;
     if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-    TIMED(HM_K_TERM_SERIES, launch_term(f32, h->max_m, t, tl.nwg, nrhs, st));
+    TIMED(HM_K_TERM_SERIES, run_term(h, P, f32, t, tl, nrhs, st));
     std::swap(y_cur, y_nxt);
   }
   if (want_norms)
@@ -419,12 +474,11 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
 int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double beta,
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
-  const void* W = f32 ? (const void*)h->W32 : (const void*)h->W64;
-  const GroupList& sa = h->sa[li];
-  if (sa.n > 0)
-    TIMED(HM_K_STAGEA, launch_stageA(f32, W, h->groups, sa.items, sa.n, h->xin0, ldin, N, nrhs, st));
-  const TermList& tl = h->tl_apply[li];
-  TermArgs t = term_args(h, apply_set(h, f32), tl, f32, h->xin0, ldin);
+  const Path P = pick_path(h, f32, nrhs);
+  const GroupList& sa = (*P.sa)[li];
+  if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, h->xin0, ldin, nrhs, st));
+  const TermList& tl = (*P.tl_apply)[li];
+  TermArgs t = term_args(h, apply_set(h, f32, P.src), tl, f32, h->xin0, ldin);
   t.alpha = alpha;
   t.beta = beta;
   t.v = v;
@@ -432,7 +486,7 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
   t.yout = out_tree;
   t.ldy = N;
   if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-  TIMED(HM_K_TERM_APPLY, launch_term(f32, h->max_m, t, tl.nwg, nrhs, st));
+  TIMED(HM_K_TERM_APPLY, run_term(h, P, f32, t, tl, nrhs, st));
   return HM_OK;
 }
 
@@ -443,6 +497,54 @@ bool check_arch(std::string* arch) {
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
   *arch = prop.gcnArchName;
   return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+// Term-kernel work lists for every level (one resident round of h->term_wgs
+// persistent workgroups): one-RHS lists (dense column ranges + in-row stack
+// rows), many-RHS lists (dense column ranges only: in-row U columns read t
+// like the global ones), and the D^{-1} list.  Replaces earlier lists.
+int build_lists(hm_matrix* h, hipStream_t st) {
+  HIPCHK(hipStreamSynchronize(st));
+  for (void* p : h->list_allocs) (void)hipFree(p);
+  h->list_allocs.clear();
+  h->bytes -= h->list_bytes;
+  h->list_bytes = 0;
+  const int64_t old_rows = h->partial_rows;
+  h->partial_rows = 0;
+  const HostH& H = h->H;
+  const int nl = h->nl;
+  h->tl_apply.assign(h->nlev, TermList());
+  h->tl_series.assign(h->nlev, TermList());
+  h->tl_apply_mm.assign(h->nlev, TermList());
+  h->tl_series_mm.assign(h->nlev, TermList());
+  std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
+  std::vector<int64_t> irr(nl), irc(nl), zero(nl, 0);
+  for (int li = 0; li < h->nlev; ++li) {
+    for (int pass = 0; pass < 4; ++pass) {  // apply, series, apply MM, series MM
+      const bool series = pass & 1, mm = pass >= 2;
+      for (int a = 0; a < nl; ++a) {
+        const int64_t m = H.leaf_size[a];
+        const int64_t head = (series ? 0 : m) + h->near_cols[a];  // [D |] near
+        const int64_t gstart = head + h->ir_cols[a];
+        dense[a].clear();
+        dense[a].push_back({0, head + (mm ? h->ir_end[li][a] : 0)});
+        if (h->gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + h->gl_end[li][a]});
+        irr[a] = h->ir_end[li][a];
+        irc[a] = head;
+      }
+      TermList& tl = mm ? (series ? h->tl_series_mm[li] : h->tl_apply_mm[li])
+                        : (series ? h->tl_series[li] : h->tl_apply[li]);
+      STCHK(make_termlist(h, dense, mm ? zero : irr, irc, h->ir_ncol_h, tl, st));
+    }
+  }
+  for (int a = 0; a < nl; ++a) {
+    dense[a].clear();
+    dense[a].push_back({0, H.leaf_size[a]});
+  }
+  STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (h->partial_rows > old_rows) h->ws_nrhs = 0;  // workspace is sized by partial_rows
+  return HM_OK;
 }
 
 // ------------------------------------------------------------ device build
@@ -472,53 +574,76 @@ int build_device(hm_matrix* h, hipStream_t st) {
     if (H.leaf_off[a] == H.far[b].t_off && H.leaf_size[a] == H.far[b].m) row_leaf[b] = a;
   }
 
-  // ---- stage-A groups over global blocks: by source cluster, finest first
-  std::map<std::pair<int32_t, int32_t>, int> gkey;  // (s_off, n) -> group
-  for (int b = 0; b < nfar; ++b)
-    if (row_leaf[b] < 0) gkey.emplace(std::make_pair(H.far[b].s_off, H.far[b].n), 0);
-  int ng = 0;
-  for (auto& kv : gkey) kv.second = ng++;
-  std::vector<std::vector<int>> gblocks(ng);
-  for (int b = 0; b < nfar; ++b)
-    if (row_leaf[b] < 0) gblocks[gkey[{H.far[b].s_off, H.far[b].n}]].push_back(b);
-  std::vector<Group> groups(ng);
-  std::vector<int32_t> tb(nfar, -1);
-  std::vector<std::vector<int32_t>> grows(ng, std::vector<int32_t>(h->nlev, 0));
-  int64_t T = 0, wtot = 0;
-  for (auto& kv : gkey) {
-    const int g = kv.second;
-    auto& bl = gblocks[g];
-    std::sort(bl.begin(), bl.end(), [&](int x, int y) {
-      if (H.far[x].level != H.far[y].level) return H.far[x].level > H.far[y].level;
-      return H.far[x].t_off < H.far[y].t_off;
-    });
-    int32_t R = 0;
-    for (int b : bl) {
-      tb[b] = (int32_t)(T + R);
-      R += rank(b);
-    }
-    groups[g] = Group{kv.first.first, kv.first.second, (int32_t)T, even_ld(R), wtot};
-    T += R;
-    wtot += (int64_t)even_ld(R) * kv.first.second;
-    for (int li = 0; li < h->nlev; ++li) {
-      int32_t rr = 0;
+  // ---- stage-A groups: far blocks by source cluster, finest level first;
+  // rows = (block, q), t slot of block b at tb[b].  The one-RHS kernels
+  // group only the global blocks (in-row ones are folded into the term
+  // kernel); the many-RHS kernels group every far block.
+  struct GroupSet {
+    std::vector<Group> groups;
+    std::vector<std::vector<int>> blocks;
+    std::vector<std::vector<int32_t>> rows;  // rows of group g at level li
+    std::vector<int32_t> tb;
+    int64_t T = 0, wtot = 0;
+  };
+  auto make_groups = [&](bool all, GroupSet& gs) {
+    std::map<std::pair<int32_t, int32_t>, int> key;  // (s_off, n) -> group
+    for (int b = 0; b < nfar; ++b)
+      if (all || row_leaf[b] < 0) key.emplace(std::make_pair(H.far[b].s_off, H.far[b].n), 0);
+    int ng = 0;
+    for (auto& kv : key) kv.second = ng++;
+    gs.blocks.assign(ng, {});
+    for (int b = 0; b < nfar; ++b)
+      if (all || row_leaf[b] < 0) gs.blocks[key[{H.far[b].s_off, H.far[b].n}]].push_back(b);
+    gs.groups.assign(ng, Group{});
+    gs.tb.assign(nfar, -1);
+    gs.rows.assign(ng, std::vector<int32_t>(h->nlev, 0));
+    for (auto& kv : key) {
+      const int g = kv.second;
+      auto& bl = gs.blocks[g];
+      std::sort(bl.begin(), bl.end(), [&](int x, int y) {
+        if (H.far[x].level != H.far[y].level) return H.far[x].level > H.far[y].level;
+        return H.far[x].t_off < H.far[y].t_off;
+      });
+      int32_t R = 0;
       for (int b : bl) {
-        if (H.far[b].level < lev_of(li)) break;
-        rr += rank(b);
+        gs.tb[b] = (int32_t)(gs.T + R);
+        R += rank(b);
       }
-      grows[g][li] = rr;
+      gs.groups[g] = Group{kv.first.first, kv.first.second, (int32_t)gs.T, even_ld(R), gs.wtot};
+      gs.T += R;
+      gs.wtot += (int64_t)even_ld(R) * kv.first.second;
+      for (int li = 0; li < h->nlev; ++li) {
+        int32_t rr = 0;
+        for (int b : bl) {
+          if (H.far[b].level < lev_of(li)) break;
+          rr += rank(b);
+        }
+        gs.rows[g][li] = rr;
+      }
     }
-  }
-  h->T = T;
-  std::vector<double2> W((size_t)std::max<int64_t>(wtot, 1), make_double2(0.0, 0.0));
+  };
+  auto fill_W = [&](const GroupSet& gs, std::vector<double2>& W) {
+    W.assign((size_t)std::max<int64_t>(gs.wtot, 1), make_double2(0.0, 0.0));
+    const int ng = (int)gs.groups.size();
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int g = 0; g < ng; ++g) {
-    const Group& G = groups[g];
-    int32_t row = 0;
-    for (int b : gblocks[g])
-      for (int q = 0; q < rank(b); ++q, ++row)
-        for (int j = 0; j < G.n; ++j) W[G.w_off + row + (int64_t)j * G.ld] = wval(b, q, j);
-  }
+    for (int g = 0; g < ng; ++g) {
+      const Group& G = gs.groups[g];
+      int32_t row = 0;
+      for (int b : gs.blocks[g])
+        for (int q = 0; q < rank(b); ++q, ++row)
+          for (int j = 0; j < G.n; ++j) W[G.w_off + row + (int64_t)j * G.ld] = wval(b, q, j);
+    }
+  };
+  GroupSet gs1, gsm;
+  make_groups(false, gs1);
+  make_groups(true, gsm);
+  const std::vector<int32_t>& tb = gs1.tb;
+  const int ng = (int)gs1.groups.size();
+  const int64_t wtot = gs1.wtot, wtot_mm = gsm.wtot;
+  // one t region after the N tree-order rows serves both layouts
+  h->T = std::max(gs1.T, gsm.T);
+  std::vector<double2> W;
+  fill_W(gs1, W);
 
   // ---- per leaf: in-row blocks (finest first) and global slices (finest first)
   std::vector<std::vector<int>> inrow(nl);
@@ -617,7 +742,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
     ptot += m;
   }
   std::vector<double2> R((size_t)std::max<int64_t>(rtot, 1), make_double2(0.0, 0.0));
-  std::vector<int32_t> src((size_t)std::max<int64_t>(ctot, 1));
+  std::vector<int32_t> src((size_t)std::max<int64_t>(ctot, 1)), src_mm(src.size());
   std::vector<double2> D((size_t)lutot);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
@@ -625,12 +750,13 @@ int build_device(hm_matrix* h, hipStream_t st) {
     const int64_t ld = even_ld(m);
     double2* P = R.data() + R_off[a];
     int32_t* S = src.data() + R_col[a];
+    int32_t* S2 = src_mm.data() + R_col[a];
     int64_t c = 0;
     auto put_block = [&](const NearBlock& nb) {
       const int n = H.leaf_size[nb.s_leaf];
       const cplx* z = H.near_data.data() + nb.data;
       for (int j = 0; j < n; ++j, ++c) {
-        S[c] = H.leaf_off[nb.s_leaf] + j;
+        S[c] = S2[c] = H.leaf_off[nb.s_leaf] + j;
         for (int i = 0; i < m; ++i) {
           const cplx v = z[i + (size_t)j * m];
           P[i + c * ld] = make_double2(v.real(), v.imag());
@@ -638,11 +764,13 @@ int build_device(hm_matrix* h, hipStream_t st) {
       }
     };
     auto put_u = [&](int b, int row_in_block, int32_t src_base) {
+      const int32_t src_mm_base = (int32_t)(N + gsm.tb[b]);
       const FarBlock& fb = H.far[b];
       const LowRank& lr = H.lowrank[fb.src];
       const std::vector<cplx>& U = fb.transposed ? lr.V : lr.U;  // m_b x r
       for (int q = 0; q < lr.r; ++q, ++c) {
         S[c] = src_base < 0 ? 0 : (int32_t)(src_base + q);
+        S2[c] = src_mm_base + q;
         for (int i = 0; i < m; ++i) {
           const cplx v = U[row_in_block + i + (size_t)q * fb.m];
           P[i + c * ld] = make_double2(v.real(), v.imag());
@@ -666,11 +794,16 @@ int build_device(hm_matrix* h, hipStream_t st) {
       set_error("a leaf panel exceeds 2^31 elements");
       return HM_EINVAL;
     }
-  for (const Group& G : groups)
-    if ((int64_t)G.ld * G.n >= ((int64_t)1 << 31)) {
-      set_error("a stage-A group exceeds 2^31 elements");
-      return HM_EINVAL;
-    }
+  for (const GroupSet* gs : {&gs1, &gsm})
+    for (const Group& G : gs->groups)
+      if ((int64_t)G.ld * G.n >= ((int64_t)1 << 31)) {
+        set_error("a stage-A group exceeds 2^31 elements");
+        return HM_EINVAL;
+      }
+  if (N + h->T >= ((int64_t)1 << 31)) {  // panel sources are 32-bit rows of [x | t]
+    set_error("n plus the far-block coefficient count exceeds 2^31");
+    return HM_EINVAL;
+  }
 
   // ---- upload
   std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
@@ -691,7 +824,12 @@ int build_device(hm_matrix* h, hipStream_t st) {
   std::vector<double2>().swap(D);
   STCHK(upload(h, &h->W64, W, st));
   std::vector<double2>().swap(W);
-  STCHK(upload(h, &h->groups, groups, st));
+  STCHK(upload(h, &h->groups, gs1.groups, st));
+  STCHK(upload(h, &h->groups_mm, gsm.groups, st));
+  STCHK(upload(h, &h->src_mm, src_mm, st));
+  fill_W(gsm, W);
+  STCHK(upload(h, &h->Wmm64, W, st));
+  std::vector<double2>().swap(W);
   STCHK(upload(h, &h->IR64, IR, st));
   std::vector<double2>().swap(IR);
   STCHK(upload(h, &h->ir_off, ir_off, st));
@@ -738,72 +876,60 @@ int build_device(hm_matrix* h, hipStream_t st) {
     STCHK(dalloc(h, (void**)&h->M32, sizeof(float2) * std::max<int64_t>(mtot, 1)));
     STCHK(dalloc(h, (void**)&h->W32, sizeof(float2) * std::max<int64_t>(wtot, 1)));
     STCHK(dalloc(h, (void**)&h->IR32, sizeof(float2) * std::max<int64_t>(irtot, 1)));
+    STCHK(dalloc(h, (void**)&h->Wmm32, sizeof(float2) * std::max<int64_t>(wtot_mm, 1)));
     HIPCHK(launch_cast(h->R64, h->R32, rtot, st));
     HIPCHK(launch_cast(h->M64, h->M32, mtot, st));
     HIPCHK(launch_cast(h->W64, h->W32, wtot, st));
     HIPCHK(launch_cast(h->IR64, h->IR32, irtot, st));
+    HIPCHK(launch_cast(h->Wmm64, h->Wmm32, wtot_mm, st));
   }
 
-  // ---- work lists per level: one resident round of persistent workgroups
-  {
-    hipDeviceProp_t prop;
-    HIPCHK(hipGetDeviceProperties(&prop, h->device));
-    const int occ = std::min(term_occupancy(false, h->max_m), term_occupancy(true, h->max_m));
-    h->term_wgs = std::max(1, prop.multiProcessorCount * occ);
-  }
-  h->tl_apply.assign(h->nlev, TermList());
-  h->tl_series.assign(h->nlev, TermList());
+  // ---- stage-A items and entry counts per level
+  h->near_cols = near_cols;
+  h->ir_cols = ir_cols;
+  h->ir_ncol_h = ir_ncol;
+  h->ir_end = ir_end;
+  h->gl_end = gl_end;
   h->sa.assign(h->nlev, GroupList());
+  h->sa_mm.assign(h->nlev, GroupList());
   h->ent_R.assign(h->nlev, 0);
   h->ent_M.assign(h->nlev, 0);
   h->ent_W.assign(h->nlev, 0);
   h->ncoef.assign(h->nlev, 0);
-  std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
-  std::vector<int64_t> irr(nl), irc(nl);
   for (int li = 0; li < h->nlev; ++li) {
     int64_t eR = 0, eM = 0, eW = 0, nc = 0;
-    for (int pass = 0; pass < 2; ++pass) {  // 0: apply panels, 1: series panels
-      for (int a = 0; a < nl; ++a) {
-        const int64_t m = H.leaf_size[a];
-        const int64_t base = pass == 0 ? 0 : -m;  // series panels have no D columns
-        const int64_t gstart = base + m + near_cols[a] + ir_cols[a];
-        dense[a].clear();
-        dense[a].push_back({0, base + m + near_cols[a]});
-        if (gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + gl_end[li][a]});
-        irr[a] = ir_end[li][a];
-        irc[a] = base + m + near_cols[a];
-        const int64_t cols = (base + m + near_cols[a]) + ir_end[li][a] + gl_end[li][a];
-        (pass == 0 ? eR : eM) += m * cols;
-      }
-      STCHK(make_termlist(h, dense, irr, irc, ir_ncol, pass == 0 ? h->tl_apply[li] : h->tl_series[li], st));
+    for (int a = 0; a < nl; ++a) {
+      const int64_t m = H.leaf_size[a];
+      const int64_t cols = near_cols[a] + ir_end[li][a] + gl_end[li][a];
+      eR += m * (m + cols);
+      eM += m * cols;
     }
-    std::vector<GroupItem> items;
+    std::vector<GroupItem> items, items_mm;
     for (int g = 0; g < ng; ++g) {
-      const int rows = grows[g][li];
-      eW += (int64_t)rows * groups[g].n;
-      nc += rows;
+      const int rows = gs1.rows[g][li];
       for (int r0 = 0; r0 < rows; r0 += kGroupTile) items.push_back({g, r0, rows, 0});
     }
-    for (int a = 0; a < nl; ++a)
-      for (int b : inrow[a]) {
-        if (H.far[b].level < lev_of(li)) break;
-        eW += (int64_t)rank(b) * H.far[b].n;
-        nc += rank(b);
-      }
+    for (int g = 0; g < (int)gsm.groups.size(); ++g) {
+      const int rows = gsm.rows[g][li];
+      eW += (int64_t)rows * gsm.groups[g].n;
+      nc += rows;
+      for (int r0 = 0; r0 < rows; r0 += kGroupTileMM) items_mm.push_back({g, r0, rows, 0});
+    }
     STCHK(upload_groups(h, items, h->sa[li], st));
+    STCHK(upload_groups(h, items_mm, h->sa_mm[li], st));
     h->ent_R[li] = eR;
     h->ent_M[li] = eM;
     h->ent_W[li] = eW;
     h->ncoef[li] = nc;
   }
   {
-    std::vector<int64_t> zero(nl, 0);
-    for (int a = 0; a < nl; ++a) {
-      dense[a].clear();
-      dense[a].push_back({0, H.leaf_size[a]});
-    }
-    STCHK(make_termlist(h, dense, zero, zero, ir_ncol, h->tl_dinv, st));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, h->device));
+    const int occ = std::min(term_occupancy(false, h->max_m), term_occupancy(true, h->max_m));
+    h->term_wgs_auto = std::max(1, prop.multiProcessorCount * occ);
+    h->term_wgs = h->term_wgs_auto;
   }
+  STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
   return HM_OK;
 }
@@ -851,6 +977,7 @@ void fill_info(const hm_matrix* h, hm_info* out) {
   }
   out->device_bytes = h->bytes;
   out->build_ms = h->build_ms;
+  out->num_instances = h->ninst;
   for (int li = 0; li < (int)h->ent_M.size(); ++li) {
     const int lev = (h->lmin < 0) ? h->L : h->lmin + li;
     if (lev < 0 || lev >= HM_MAX_LEVELS) continue;
@@ -885,13 +1012,7 @@ const char* hm_strerror(int s) {
   }
 }
 
-int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
-               hm_matrix_t* out) {
-  if (!out) { set_error("null output handle"); return HM_EINVAL; }
-  *out = nullptr;
-  STCHK(validate_problem(prob, opts));
-  const auto t0 = std::chrono::steady_clock::now();
-  std::unique_ptr<hm_matrix> h(new hm_matrix());
+static Problem copy_problem(const hm_problem* prob) {
   Problem p;
   p.n = prob->n;
   p.kind = prob->kind;
@@ -899,8 +1020,13 @@ int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stre
   p.h = prob->h;
   p.xyz.assign(prob->xyz, prob->xyz + 3 * prob->n);
   if (prob->kind == HM_VOLUME) p.chi.assign(prob->chi, prob->chi + prob->n);
-  STCHK(build_host(p, *opts, h->H));
-  h->N = p.n;
+  return p;
+}
+
+// Device part of a build, shared by the single and batched builds.
+static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts, void* hip_stream,
+                        std::chrono::steady_clock::time_point t0, hm_matrix_t* out) {
+  h->N = h->H.prob.n;
   h->nl = (int)h->H.leaf_size.size();
   h->max_m = h->H.max_leaf;
   h->L = h->H.tree.depth;
@@ -927,6 +1053,52 @@ int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stre
   h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return HM_OK;
+}
+
+int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
+               hm_matrix_t* out) {
+  if (!out) { set_error("null output handle"); return HM_EINVAL; }
+  *out = nullptr;
+  STCHK(validate_problem(prob, opts));
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<hm_matrix> h(new hm_matrix());
+  STCHK(build_host(copy_problem(prob), *opts, h->H));
+  h->inst_off = {0, prob->n};
+  return finish_build(h, opts, hip_stream, t0, out);
+}
+
+int hmat_build_batched(const hm_problem* probs, int32_t count, const hm_build_opts* opts,
+                       void* hip_stream, hm_matrix_t* out) {
+  if (!out) { set_error("null output handle"); return HM_EINVAL; }
+  *out = nullptr;
+  if (!probs || count < 1) { set_error("need count >= 1 problems"); return HM_EINVAL; }
+  int64_t total = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    STCHK(validate_problem(&probs[i], opts));
+    total += probs[i].n;
+  }
+  if (total > (int64_t)1 << 28) { set_error("total n too large"); return HM_EINVAL; }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_ptr<hm_matrix> h(new hm_matrix());
+  std::vector<HostH> parts(count);
+  std::vector<int> status(count, HM_OK);
+  std::vector<std::string> errs(count);
+  hm_build_opts inner = *opts;
+  inner.num_threads = 1;  // parallel over instances instead
+  const int nthreads = opts->num_threads > 0 ? opts->num_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  for (int32_t i = 0; i < count; ++i) {
+    status[i] = build_host(copy_problem(&probs[i]), inner, parts[i]);
+    if (status[i] != HM_OK) errs[i] = hm_last_error();
+  }
+  for (int32_t i = 0; i < count; ++i)
+    if (status[i] != HM_OK) {
+      set_error("instance " + std::to_string(i) + ": " + errs[i]);
+      return status[i];
+    }
+  merge_hosts(parts, h->H, h->inst_off);
+  h->ninst = count;
+  return finish_build(h, opts, hip_stream, t0, out);
 }
 
 int hmat_info(hm_matrix_t h, hm_info* out) {
@@ -1073,6 +1245,33 @@ int hmat_export(hm_matrix_t h, const char* path) {
   HIPCHK(hipMemcpy(lu.data(), h->LU, sizeof(cplx) * dtot, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(piv.data(), h->piv, sizeof(int32_t) * h->N, hipMemcpyDeviceToHost));
   return export_host(h->H, path, &lu, &piv);
+}
+
+int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
+  if (!h || !t) { set_error("null argument"); return HM_EINVAL; }
+  if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
+  if (t->mm_min_rhs < -1 || t->term_wgs < -1 || t->term_wgs > (1 << 20)) {
+    set_error("bad tuning values");
+    return HM_EINVAL;
+  }
+  if (t->mm_min_rhs > 0) h->mm_min_rhs = t->mm_min_rhs;
+  if (t->mm_min_rhs == -1) h->mm_min_rhs = 8;
+  int wgs = h->term_wgs;
+  if (t->term_wgs > 0) wgs = t->term_wgs;
+  if (t->term_wgs == -1) wgs = h->term_wgs_auto;
+  if (wgs != h->term_wgs) {
+    HIPCHK(hipSetDevice(h->device));
+    h->term_wgs = wgs;
+    STCHK(build_lists(h, (hipStream_t)hip_stream));
+  }
+  return HM_OK;
+}
+
+int hmat_get_tuning(hm_matrix_t h, hm_tuning* out) {
+  if (!h || !out) { set_error("null argument"); return HM_EINVAL; }
+  out->mm_min_rhs = h->mm_min_rhs;
+  out->term_wgs = h->term_wgs;
+  return HM_OK;
 }
 
 int hm_profile_enable(hm_matrix_t h, int32_t enable) {

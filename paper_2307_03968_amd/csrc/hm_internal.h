@@ -102,6 +102,16 @@ struct HostH {
 
 int build_host(const Problem& p, const hm_build_opts& o, HostH& out);
 
+// Level of a far block in a merged (batched) H-matrix: kTopLevel minus its
+// distance above the leaf level of its own instance, so that "leaf level"
+// (level -1) selects every instance's leaf-level blocks.
+constexpr int32_t kTopLevel = HM_MAX_LEVELS - 1;
+
+// Concatenate independent H-matrices into one block-diagonal H-matrix
+// (instances keep their own points, leaves and blocks, offset in tree
+// order).  parts are consumed.
+void merge_hosts(std::vector<HostH>& parts, HostH& out, std::vector<int64_t>& inst_off);
+
 // Export helper (binary named arrays).
 int export_host(const HostH& H, const char* path, const std::vector<cplx>* lu_host,
                 const std::vector<int32_t>* piv_host);

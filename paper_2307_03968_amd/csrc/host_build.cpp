@@ -130,6 +130,63 @@ int build_host(const Problem& p, const hm_build_opts& o, HostH& H) {
   return HM_OK;
 }
 
+// ---------------------------------------------------------------- batching
+void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst_off) {
+  H = HostH();
+  int64_t n = 0, nd = 0;
+  int32_t nleaf = 0, nlr = 0;
+  bool any_volume = false;
+  for (auto& P : parts) any_volume = any_volume || P.prob.kind == HM_VOLUME;
+  inst_off.assign(parts.size() + 1, 0);
+  H.prob.kind = parts.empty() ? HM_SURFACE : parts[0].prob.kind;
+  H.tree.depth = kTopLevel;
+  H.min_far_level = -1;
+  for (size_t i = 0; i < parts.size(); ++i) {
+    HostH& P = parts[i];
+    inst_off[i] = n;
+    const int32_t L = P.tree.depth;
+    for (int64_t q = 0; q < P.prob.n; ++q) {
+      H.tree.perm.push_back(P.tree.perm[q] + n);
+      H.tree.leaf_of.push_back(P.tree.leaf_of[q] + nleaf);
+    }
+    for (size_t a = 0; a < P.leaf_off.size(); ++a) {
+      H.leaf_off.push_back((int32_t)(P.leaf_off[a] + n));
+      H.leaf_size.push_back(P.leaf_size[a]);
+    }
+    for (const NearBlock& b : P.near) H.near.push_back({b.t_leaf + nleaf, b.s_leaf + nleaf, b.data + nd});
+    H.near_data.insert(H.near_data.end(), P.near_data.begin(), P.near_data.end());
+    for (const FarBlock& f : P.far) {
+      FarBlock g = f;
+      g.t_off += (int32_t)n;
+      g.s_off += (int32_t)n;
+      g.level = kTopLevel - (L - f.level);
+      g.src += nlr;
+      H.far.push_back(g);
+      H.min_far_level = (H.min_far_level < 0) ? g.level : std::min(H.min_far_level, g.level);
+    }
+    for (auto& lr : P.lowrank) H.lowrank.push_back(std::move(lr));
+    if (any_volume) {
+      if (P.prob.kind == HM_VOLUME)
+        H.chi_tree.insert(H.chi_tree.end(), P.chi_tree.begin(), P.chi_tree.end());
+      else
+        H.chi_tree.insert(H.chi_tree.end(), (size_t)P.prob.n, 1.0);
+    }
+    H.max_leaf = std::max(H.max_leaf, P.max_leaf);
+    n += P.prob.n;
+    nd += (int64_t)P.near_data.size();
+    nleaf += (int32_t)P.leaf_off.size();
+    nlr += (int32_t)P.lowrank.size();
+    P = HostH();  // release the part
+  }
+  inst_off[parts.size()] = n;
+  H.prob.n = n;
+  std::sort(H.far.begin(), H.far.end(), [](const FarBlock& a, const FarBlock& b) {
+    if (a.level != b.level) return a.level > b.level;
+    if (a.t_off != b.t_off) return a.t_off < b.t_off;
+    return a.s_off < b.s_off;
+  });
+}
+
 // ---------------------------------------------------------------- export
 namespace {
 struct Writer {

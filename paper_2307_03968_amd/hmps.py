@@ -50,6 +50,10 @@ class ps_stats(C.Structure):
                 ("growth", C.c_double), ("t_ms", C.c_double)]
 
 
+class hm_tuning(C.Structure):
+    _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32)]
+
+
 class hm_info(C.Structure):
     _fields_ = [("n", C.c_int64), ("leaf_level", C.c_int32), ("num_leaves", C.c_int32),
                 ("max_leaf", C.c_int32), ("min_far_level", C.c_int32),
@@ -62,7 +66,8 @@ class hm_info(C.Structure):
                 ("series_entries", C.c_int64 * HM_MAX_LEVELS),
                 ("apply_entries", C.c_int64 * HM_MAX_LEVELS),
                 ("stageA_entries", C.c_int64 * HM_MAX_LEVELS),
-                ("coeffs", C.c_int64 * HM_MAX_LEVELS)]
+                ("coeffs", C.c_int64 * HM_MAX_LEVELS),
+                ("num_instances", C.c_int32)]
 
 
 HM_K_STAGEA, HM_K_TERM_SERIES, HM_K_TERM_APPLY, HM_K_TERM_DINV, HM_K_COUNT = range(5)
@@ -91,6 +96,8 @@ def _lib():
         lib = C.CDLL(LIB_PATH)
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         lib.hmat_build.argtypes = [C.POINTER(hm_problem), C.POINTER(hm_build_opts), vp, C.POINTER(vp)]
+        lib.hmat_build_batched.argtypes = [C.POINTER(hm_problem), i32, C.POINTER(hm_build_opts), vp,
+                                           C.POINTER(vp)]
         lib.hmat_info.argtypes = [vp, C.POINTER(hm_info)]
         lib.hmat_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, vp]
         lib.ps_solve.argtypes = [vp, C.POINTER(ps_opts), vp, i64, vp, i64, i32, C.POINTER(ps_stats), vp]
@@ -98,11 +105,14 @@ def _lib():
         lib.hmat_free.argtypes = [vp]
         lib.hm_profile_enable.argtypes = [vp, i32]
         lib.hm_profile_read.argtypes = [vp, C.POINTER(hm_kernel_time)]
+        lib.hmat_tune.argtypes = [vp, C.POINTER(hm_tuning), vp]
+        lib.hmat_get_tuning.argtypes = [vp, C.POINTER(hm_tuning)]
         lib.hm_strerror.argtypes = [C.c_int]
         lib.hm_strerror.restype = C.c_char_p
         lib.hm_last_error.restype = C.c_char_p
-        for f in ("hmat_build", "hmat_info", "hmat_apply", "ps_solve", "hmat_export", "hmat_free",
-                  "hm_profile_enable", "hm_profile_read"):
+        for f in ("hmat_build", "hmat_build_batched", "hmat_info", "hmat_apply", "ps_solve",
+                  "hmat_export", "hmat_free", "hm_profile_enable", "hm_profile_read", "hmat_tune",
+                  "hmat_get_tuning"):
             getattr(lib, f).restype = C.c_int
         _LIB = lib
     return _LIB
@@ -142,20 +152,33 @@ class HMatrix:
 
     def __init__(self, prob, leaf_max: int, eta: float = 1.0, aca_tol: float = 1e-4,
                  max_rank: int = 0, flags: int = 0, num_threads: int = 0, stream=None):
+        """``prob``: one problem, or a list of problems for a batched handle
+        (hmat_build_batched)."""
         lib = _lib()
-        xyz = np.ascontiguousarray(prob.xyz, dtype=np.float64)
-        chi = None if prob.chi is None else np.ascontiguousarray(prob.chi, dtype=np.float64)
-        p = hm_problem(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), int(prob.kind),
-                       float(prob.k), float(prob.h),
-                       chi.ctypes.data_as(C.POINTER(C.c_double)) if chi is not None else None)
+        probs = list(prob) if isinstance(prob, (list, tuple)) else [prob]
+        keep = []
+        arr = (hm_problem * len(probs))()
+        for i, p in enumerate(probs):
+            xyz = np.ascontiguousarray(p.xyz, dtype=np.float64)
+            chi = None if p.chi is None else np.ascontiguousarray(p.chi, dtype=np.float64)
+            keep += [xyz, chi]
+            arr[i] = hm_problem(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), int(p.kind),
+                                float(p.k), float(p.h),
+                                chi.ctypes.data_as(C.POINTER(C.c_double)) if chi is not None else None)
         o = hm_build_opts(int(leaf_max), float(eta), float(aca_tol), int(max_rank), int(flags),
                           int(num_threads))
         self.host_only = bool(flags & HM_BUILD_HOST_ONLY)
         st = C.c_void_p(None) if self.host_only else _stream(stream)
         h = C.c_void_p()
-        _check(lib.hmat_build(C.byref(p), C.byref(o), st, C.byref(h)), "hmat_build")
+        if isinstance(prob, (list, tuple)):
+            _check(lib.hmat_build_batched(arr, len(probs), C.byref(o), st, C.byref(h)),
+                   "hmat_build_batched")
+        else:
+            _check(lib.hmat_build(C.byref(arr[0]), C.byref(o), st, C.byref(h)), "hmat_build")
         self._h = h
-        self.n = int(xyz.shape[0])
+        self.sizes = [int(p.xyz.shape[0]) for p in probs]
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value is not None:
@@ -183,6 +206,16 @@ class HMatrix:
                           "entries": i.far_entries[lev]}
                     for lev in range(HM_MAX_LEVELS) if i.far_blocks[lev]}
         return d
+
+    def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, stream=None) -> None:
+        """hmat_tune: 0 keeps a value, -1 restores its default."""
+        t = hm_tuning(int(mm_min_rhs), int(term_wgs))
+        _check(_lib().hmat_tune(self._h, C.byref(t), _stream(stream)), "hmat_tune")
+
+    def tuning(self) -> dict:
+        t = hm_tuning()
+        _check(_lib().hmat_get_tuning(self._h, C.byref(t)), "hmat_get_tuning")
+        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs}
 
     def export(self, path: str) -> None:
         _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")

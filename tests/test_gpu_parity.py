@@ -250,3 +250,122 @@ def test_full_size_sphere_24576():
     _say("series f32 sphere_24576")
     x = _host(h.solve(_dev(b), K=4, precision=hmps.HM_F32_APPLY))
     assert series.rel_err(x, series.series(H, b, 4)) <= TOL_F32
+
+
+def test_batched_instances_match_per_instance_oracle():
+    """One batched handle (three instances: sphere, volume cube, a sphere
+    without far blocks) solves every instance as its own oracle would, at the
+    leaf level and one and two levels above each instance's leaf level."""
+    probs = [W.sphere_problem(1200, math.sqrt(1200 / 1536)),
+             W.cube_problem(10, 10 / 16),
+             W.sphere_problem(450, math.sqrt(450 / 1536), seed=7)]
+    leaf, tol, K, nrhs = 32, 1e-5, 3, 3
+    _say("build batched sphere_1200 + cube_1000 + sphere_450 leaf=32")
+    h = hmps.HMatrix(probs, leaf, 1.0, tol)
+    Hs = [hmatrix.HMatrix(p, leaf, 1.0, tol) for p in probs]
+    bs = [W.plane_waves(p.xyz, W.directions(nrhs, 3, instance=i)) for i, p in enumerate(probs)]
+    b = np.vstack(bs)
+    top = hmps.HM_MAX_LEVELS - 1
+    for d in (0, 1, 2):
+        for prec, tol_s in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+            _say(f"batched series level=top-{d} precision={prec}")
+            x = _host(h.solve(_dev(b), K=K, level=top - d, precision=prec))
+            for i, H in enumerate(Hs):
+                o0, o1 = h.offsets[i], h.offsets[i + 1]
+                ref = series.series(H, bs[i], K, H.L - d)
+                assert series.rel_err(x[o0:o1], ref) <= tol_s, (i, d, prec)
+        _say(f"batched hmat_apply level=top-{d}")
+        y = _host(h.apply(_dev(b), level=top - d))
+        for i, H in enumerate(Hs):
+            o0, o1 = h.offsets[i], h.offsets[i + 1]
+            assert series.rel_err(y[o0:o1], series.apply_Z(H, bs[i], H.L - d)) <= 1e-12, (i, d)
+    x1 = _host(h.solve(_dev(b), K=K))
+    x0 = _host(h.solve(_dev(b), K=K, level=-1))
+    assert np.array_equal(x0, x1)
+    h.close()
+
+
+# ---------------------------------------------------------------- many RHS
+@pytest.fixture(scope="module")
+def many_rhs(ragged_depth):
+    """64 plane waves on the ragged-depth sphere (leaves of 34/35 and 68)."""
+    c = ragged_depth
+    return c, W.plane_waves(c.prob.xyz, W.directions(64, 9))
+
+
+@pytest.mark.parametrize("nrhs", [1, 16, 17, 33, 64])
+def test_mfma_series_each_level(many_rhs, nrhs):
+    """The matrix-core kernels (forced from one right-hand side on) against
+    the oracle, at every level, FP64 (4M) and FP32 (3M)."""
+    c, B = many_rhs
+    b = B[:, :nrhs]
+    c.h.tune(mm_min_rhs=1)
+    try:
+        for lev in [-1] + list(reversed(c.H.far_levels)):
+            ref = series.series(c.H, b, 3, lev)
+            for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+                _say(f"mfma series {c.name} nrhs={nrhs} level={lev} precision={prec}")
+                x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
+                assert series.rel_err(x, ref) <= tol, (lev, prec)
+            _say(f"mfma hmat_apply {c.name} nrhs={nrhs} level={lev}")
+            y = _host(c.h.apply(_dev(b), level=lev))
+            assert series.rel_err(y, series.apply_Z(c.H, b, lev)) <= 1e-12
+    finally:
+        c.h.tune(mm_min_rhs=-1)
+
+
+def test_mfma_matches_streaming_path(many_rhs):
+    """Both kernel families on the same 24 right-hand sides: FP64 results
+    agree to rounding; FP32 to the FP32 bar."""
+    c, B = many_rhs
+    b = _dev(B[:, :24])
+    c.h.tune(mm_min_rhs=1000)
+    _say("streaming path nrhs=24")
+    x_s = _host(c.h.solve(b, K=4))
+    x_s32 = _host(c.h.solve(b, K=4, precision=hmps.HM_F32_APPLY))
+    c.h.tune(mm_min_rhs=-1)
+    assert c.h.tuning()["mm_min_rhs"] == 8
+    _say("mfma path nrhs=24")
+    x_m = _host(c.h.solve(b, K=4))
+    x_m32 = _host(c.h.solve(b, K=4, precision=hmps.HM_F32_APPLY))
+    assert series.rel_err(x_m, x_s) <= 1e-12
+    assert series.rel_err(x_m32, x_s) <= TOL_F32 and series.rel_err(x_s32, x_s) <= TOL_F32
+
+
+def test_mfma_volume_and_large_leaves():
+    """Volume kernel (contrast folded into W) and leaves up to 250 points
+    (four 16-row tiles per wave) on the matrix-core path, 20 RHS."""
+    cases = [("cube_1728_leaf40", W.cube_problem(12, 12 / 16), 40, 1e-5),
+             ("sphere_6000_leaf250", W.sphere_problem(6000, math.sqrt(6000 / 1536)), 250, 1e-4)]
+    for name, prob, leaf, tol in cases:
+        _say(f"build {name}")
+        H = hmatrix.HMatrix(prob, leaf, 1.0, tol)
+        h = hmps.HMatrix(prob, leaf, 1.0, tol)
+        b = W.plane_waves(prob.xyz, W.directions(20, 11))
+        for lev in [-1] + list(H.far_levels):
+            ref = series.series(H, b, 3, lev)
+            for prec, tol_s in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+                _say(f"mfma series {name} level={lev} precision={prec}")
+                x = _host(h.solve(_dev(b), K=3, level=lev, precision=prec))
+                assert series.rel_err(x, ref) <= tol_s, (name, lev, prec)
+        h.close()
+
+
+def test_retuned_work_lists_same_result(many_rhs):
+    """Re-splitting the term work over another workgroup count changes only
+    the rounding order."""
+    c, B = many_rhs
+    b = _dev(B[:, :5])
+    x0 = _host(c.h.solve(b, K=4))
+    default = c.h.tuning()["term_wgs"]
+    try:
+        for wgs in (37, 3000):
+            _say(f"retune term_wgs={wgs}")
+            c.h.tune(term_wgs=wgs)
+            assert c.h.tuning()["term_wgs"] == wgs
+            x1 = _host(c.h.solve(b, K=4))
+            assert series.rel_err(x1, x0) <= 1e-13
+    finally:
+        c.h.tune(term_wgs=-1)
+    assert c.h.tuning()["term_wgs"] == default
+    assert np.array_equal(_host(c.h.solve(b, K=4)), x0)

@@ -135,6 +135,10 @@ def test_device_calls_on_host_only_handle():
     o = hmps.ps_opts(2, -1, 0, 0, 0, 1e-9)
     assert lib.ps_solve(h.handle, C.byref(o), None, 100, None, 100, 1, None, None) == hmps.HM_ESTATE
     assert lib.hmat_apply(h.handle, -1, 0, None, 100, None, 100, 1, None) == hmps.HM_ESTATE
+    t = hmps.hm_tuning(4, 0)
+    assert lib.hmat_tune(h.handle, C.byref(t), None) == hmps.HM_ESTATE
+    assert lib.hmat_tune(h.handle, None, None) == hmps.HM_EINVAL
+    assert h.tuning()["mm_min_rhs"] == 8
     h.close()
 
 
@@ -144,3 +148,39 @@ def test_single_point_and_single_leaf():
         info = h.info()
         assert info["num_leaves"] == 1 and info["min_far_level"] == -1
         h.close()
+
+
+def test_batched_build_is_block_diagonal(tmp_path):
+    """hmat_build_batched merges independent instances (different sizes and
+    kinds) into one block-diagonal H-matrix: each diagonal block equals that
+    instance's oracle H-matrix, nothing couples two instances, and far
+    levels count down from the top so that HM_MAX_LEVELS - 1 is every
+    instance's leaf level.  The last instance has no far block at all."""
+    probs = [W.sphere_problem(1200, math.sqrt(1200 / 1536)),
+             W.cube_problem(10, 10 / 16),
+             W.sphere_problem(450, math.sqrt(450 / 1536), seed=7)]
+    leaf, tol = 32, 1e-5
+    h = hmps.HMatrix(probs, leaf, 1.0, tol, flags=HOST)
+    assert h.sizes == [1200, 1000, 450]
+    path = str(tmp_path / "hb.bin")
+    h.export(path)
+    E = hmps.read_export(path)
+    n = h.n
+    A_lib = _lib_dense(E, n)
+    top = hmps.HM_MAX_LEVELS - 1
+    perm = []
+    for i, p in enumerate(probs):
+        o0, o1 = h.offsets[i], h.offsets[i + 1]
+        H = hmatrix.HMatrix(p, leaf, 1.0, tol)
+        perm.append(H.perm + o0)
+        A_or = H.dense(min(H.far_levels) if H.far_levels else -1)
+        blk = A_lib[o0:o1, o0:o1]
+        assert np.linalg.norm(blk - A_or) <= 1e-12 * np.linalg.norm(A_or), i
+        assert not A_lib[o0:o1, :o0].any() and not A_lib[o0:o1, o1:].any()
+        rows = [r for r in E["far"] if o0 <= r[0] < o1]
+        assert sorted({int(r[4]) for r in rows}) == sorted(top - (H.L - lv) for lv in H.far_levels)
+        assert len(rows) == len(H.far)
+    assert np.array_equal(E["perm"], np.concatenate(perm))
+    info = h.info()
+    assert info["num_instances"] == 3 and info["leaf_level"] == top
+    h.close()
