@@ -1,21 +1,33 @@
 """Benchmark of the power-series H-matrix solve on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sphere_24576]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                     [--precision f64|f32] [--no-oracle] [--no-extras]
+
+Workloads:
+  sphere_24576  (default) surface, N = 24,576, leaf <= 128, tol 1e-4, K = 4,
+                one plane wave, FP64; side runs: H-matvec, FP32 blocks,
+                refinement
+  cube_32768    volume, N = 32^3, leaf <= 128, tol 1e-5, K = 5, 64 plane
+                waves; FP64 (4M) and FP32 (3M) matrix-core kernels
+  batched_256   256 surface instances, N log-uniform in [512, 8192], leaf <= 64,
+                tol 1e-4, K = 4, 16 plane waves each, one batched handle,
+                autotuned, solves replayed from a captured HIP graph; FP32
+                blocks with FP64 refinement against the plain FP64 path
+  sphere_1536   the small surface case
 
 A step is one power-series solve (Sec. IV): permute in, y_0 = D^{-1} b,
 K terms of stage A + D^{-1}-premultiplied near/far panel product + term
 update, permute out, for the workload's right-hand sides, with the H-matrix
 (blocks, leaf LU and inverse) already resident in HBM.  The result is checked
-against the FP64 oracle; only a result within 1e-8 counts as solved.
+against the FP64 oracle; only a result within 1e-8 of its reference counts as
+solved.
 
-Prints one JSON line (rank 0).  Progress goes to stderr.
+Prints one JSON line.  Progress goes to stderr.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -26,7 +38,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}   # dense MFMA (= vector) peaks
 SOLVED_TOL = 1e-8
+METRIC = "solved RHS/s at rel.err<=1e-8 vs FP64 oracle"
 
 
 def log(msg):
@@ -53,17 +67,404 @@ def blas_threads():
         return len(os.sched_getaffinity(0))
 
 
+def timed(fn, reps, stream):
+    """Average ms of fn() over reps calls, HIP events on `stream`."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def profiled(h, fn, reps):
+    """Per-kernel-class launches and average duration (library HIP events
+    around every launch, recorded on the launch stream) over reps calls."""
+    import torch
+    from paper_2307_03968_amd import hmps
+    lib = hmps._lib()
+    assert lib.hm_profile_enable(h.handle, 1) == 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = (hmps.hm_kernel_time * hmps.HM_K_COUNT)()
+    assert lib.hm_profile_read(h.handle, kt) == 0
+    lib.hm_profile_enable(h.handle, 0)
+    names = ["stageA", "term_series", "term_apply", "term_dinv"]
+    return wall, {nm: {"launches": kt[i].launches,
+                       "avg_us": 1e3 * kt[i].total_ms / max(1, kt[i].launches)}
+                  for i, nm in enumerate(names)}
+
+
+def latency(fn, reps):
+    """Per-request latency: each call issued and waited for on its own."""
+    import torch
+    lat = []
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        lat.append(1e3 * (time.perf_counter() - t1))
+    return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
+
+
+def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T):
+    """Roofline of one series-term launch.  Algorithmic bytes: the level's
+    series panel entries (D^{-1}[near | U]); on the one-RHS kernels also the
+    W rows of the in-row far blocks read in the same launch; plus the
+    vectors (y_{k-1} with its t part read, y_k written, x read and
+    written).  Flops (matrix-core kernels): executed real flops, 6 per
+    complex multiply-add in FP32 (3M), 8 in FP64 (4M)."""
+    elem = 16 if prec == "f64" else 8
+    ent = info["series_entries"][level]
+    went = 0 if mm else info["stageA_entries"][level]
+    vec = 16 * nrhs * ((n + (T if mm else 0)) + 3 * n)
+    nbytes = elem * (ent + went) + vec
+    gbps = nbytes / (avg_us * 1e-6) / 1e9
+    out = {"bound": "hbm", "kernel": "k_term_mm (one series term)" if mm else "k_term (one series term)",
+           "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+           "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": avg_us}
+    if mm:
+        flops = (6 if prec == "f32" else 8) * ent * nrhs
+        tf = flops / (avg_us * 1e-6) / 1e12
+        fl = {"bound": "mfma", "achieved": tf, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+              "frac": tf / PEAK_TFLOPS[prec], "flops_per_launch": flops,
+              "effective_TFLOPs_8_per_cmac": 8 * ent * nrhs / (avg_us * 1e-6) / 1e12}
+        if fl["frac"] >= out["frac"]:
+            hb = {k: out[k] for k in ("achieved", "frac")}
+            out.update(fl)
+            out["hbm_side"] = hb
+        else:
+            out["mfma_side"] = {k: fl[k] for k in ("achieved", "frac", "peak")}
+    return out
+
+
+# --------------------------------------------------------------------------
+def bench_single(a):
+    import torch
+    from paper_2307_03968_amd import hmps
+
+    wl = workload(a.workload)
+    cube = wl.problem.kind == 1
+    pname = a.precision or "f64"
+    prec = hmps.HM_F64 if pname == "f64" else hmps.HM_F32_APPLY
+    log(f"library build {wl.name} n={wl.problem.n} leaf={wl.leaf_max} tol={wl.aca_tol}")
+    t0 = time.perf_counter()
+    h = hmps.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol, progress=log)
+    build_s = time.perf_counter() - t0
+    info = h.info()
+    L = info["leaf_level"]
+    level = L if wl.level < 0 else wl.level
+    b_np = wl.rhs()
+    nrhs = b_np.shape[1]
+    n = wl.problem.n
+    b = torch.from_numpy(np.ascontiguousarray(b_np)).to("cuda")
+    stream = torch.cuda.current_stream()
+    mm = nrhs >= h.tuning()["mm_min_rhs"]
+    solve = lambda p=prec: h.solve(b, K=wl.K, level=wl.level, precision=p)  # noqa: E731
+
+    for _ in range(a.warmup):
+        x = solve()
+    torch.cuda.synchronize()
+    log(f"timed region: {a.steps} solves")
+    wall, kernels = profiled(h, solve, a.steps)
+    x = solve()
+    lat = latency(solve, a.steps)
+    if a.copy_calibration > 0:
+        nbytes = a.copy_calibration << 20
+        src_buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst_buf = torch.empty_like(src_buf)
+        for _ in range(3):
+            dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src_buf, dst_buf
+    ms_per_step = wall * 1e3 / a.steps
+    x_np = x.cpu().numpy()
+    T = info["coeffs"][level]
+    roof = term_roofline(info, level, n, nrhs, pname, mm, kernels["term_series"]["avg_us"], T)
+    if not mm:
+        assert kernels["stageA"]["launches"] == 0, "the leaf-level one-RHS path has no stage A"
+    elem = 16 if prec == hmps.HM_F64 else 8
+    per_solve_bytes = (wl.K * elem * (info["series_entries"][level] + info["stageA_entries"][level])
+                       + 16 * info["diag_entries"])
+
+    rel = cpu = None
+    extras = {}
+    H = ref = None
+    if not a.no_oracle:
+        from oracle import hmatrix, series
+        log("oracle build (host, FP64)")
+        t1 = time.perf_counter()
+        H = hmatrix.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol, progress=log)
+        oracle_build_s = time.perf_counter() - t1
+        log("oracle series")
+        t1 = time.perf_counter()
+        ref = series.series(H, b_np, wl.K, wl.level)
+        first_s = time.perf_counter() - t1
+        rel = series.rel_err(x_np, ref)
+        log(f"rel.err vs oracle x_K = {rel:.3e}")
+        # bounded sample: repeat the oracle's solve of the same workload
+        reps, cpu_s = 1, first_s
+        t1 = time.perf_counter()
+        while time.perf_counter() - t1 + first_s < a.cpu_seconds:
+            series.series(H, b_np, wl.K, wl.level)
+            reps += 1
+        cpu_s = first_s + (time.perf_counter() - t1)
+        cpu = {"value": reps * nrhs / cpu_s, "unit": "RHS/s", "cores": blas_threads(),
+               "kind": "oracle",
+               "sample": f"{reps} sequential numpy/scipy FP64 series solves of the same "
+                         f"workload ({nrhs} RHS each) in {cpu_s:.1f} s; oracle H build "
+                         f"{oracle_build_s:.1f} s not included"}
+    tol = 1e-10 if prec == hmps.HM_F64 else 1e-4
+    solved = rel is not None and rel <= min(tol, SOLVED_TOL)
+    value = (a.steps * nrhs / wall) if solved else 0.0
+
+    if not a.no_extras:
+        reps = 20
+        xr = torch.randn(n, dtype=torch.complex128, device="cuda")
+        for _ in range(3):
+            h.apply(xr, level=wl.level)
+        mv_ms = timed(lambda: h.apply(xr, level=wl.level), reps, stream)
+        mv_bytes = 16 * (info["apply_entries"][level] + info["stageA_entries"][level]) + 32 * n
+        extras["hmatvec_1rhs_f64"] = {"ms": mv_ms, "bytes": mv_bytes,
+                                      "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
+                                      "frac_hbm_peak": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+        other = hmps.HM_F32_APPLY if prec == hmps.HM_F64 else hmps.HM_F64
+        oname = "f32" if other == hmps.HM_F32_APPLY else "f64"
+        for _ in range(3):
+            xo = solve(other)
+        o_ms = timed(lambda: solve(other), reps, stream)
+        xo = solve(other)
+        extras[f"series_{oname}"] = {"ms_per_solve": o_ms, "RHS_per_s": nrhs * 1e3 / o_ms}
+        if mm:
+            _, ko = profiled(h, lambda: solve(other), 5)
+            extras[f"series_{oname}"]["roofline"] = term_roofline(
+                info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T)
+            extras[f"series_{oname}"]["kernels"] = ko
+        if H is not None:
+            from oracle import series
+            extras[f"series_{oname}"]["rel_err_vs_oracle_xK"] = series.rel_err(xo.cpu().numpy(), ref)
+            extras[f"series_{pname}"] = {"rel_err_vs_oracle_xK": rel}
+            rho = series.rho(H, wl.level, iters=60)
+            extras["rho"] = rho
+            if rho ** (wl.K + 1) < 0.9:
+                log("oracle x* by GMRES for the refinement check")
+                xs = series.solve_gmres(H, b_np, wl.level, tol=1e-13)
+                for rname, p in (("f32_apply", hmps.HM_F32_APPLY), ("f64", hmps.HM_F64)):
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    xr_, st = h.solve(b, K=wl.K, level=wl.level, precision=p,
+                                      kind=hmps.PS_REFINE, max_passes=400, refine_tol=1e-10,
+                                      stats=True)
+                    torch.cuda.synchronize()
+                    ref_s = time.perf_counter() - t1
+                    err = series.rel_err(xr_.cpu().numpy(), xs)
+                    extras[f"refine_{rname}"] = {
+                        "ms_per_solve": 1e3 * ref_s, "passes": max(s["passes"] for s in st),
+                        "rel_err_vs_oracle_xstar": err,
+                        "solved_RHS_per_s": (nrhs / ref_s) if err <= SOLVED_TOL else 0.0}
+            else:
+                extras["refine"] = (f"not attainable by the method: rho = {rho:.3f}, "
+                                    f"rho^(K+1) = {rho ** (wl.K + 1):.3f} >= 1 per pass")
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": pname, "data": "synthetic",
+        "config": {"workload": wl.name, "N": n, "kind": "volume" if cube else "surface",
+                   "leaf_max": wl.leaf_max, "eta": wl.eta, "aca_tol": wl.aca_tol, "K": wl.K,
+                   "level": level, "nrhs": nrhs,
+                   "kernels": "matrix-core (MFMA)" if mm else "streaming one-RHS tiles",
+                   "precision": "complex128" if prec == hmps.HM_F64
+                   else "complex64 blocks, complex128 vectors"},
+        "rel_err_vs_oracle": rel, "latency_ms": lat, "roofline": roof,
+        "per_solve_algorithmic_bytes": per_solve_bytes, "kernels": kernels, "build_s": build_s,
+        "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+    return 0
+
+
+# --------------------------------------------------------------------------
+def bench_batched(a):
+    """256 instances in one batched handle, 16 RHS each (one column block
+    of 16 per instance), mixed precision: FP32 blocks, FP64 LU / residual /
+    refinement; replayed from captured HIP graphs."""
+    import torch
+    import workloads as W
+    from paper_2307_03968_amd import hmps
+
+    count = a.instances
+    sizes = W.batched_sizes(count)
+    wls = [W.batched_instance(i, int(nn)) for i, nn in enumerate(sizes)]
+    K, nrhs = wls[0].K, wls[0].nrhs
+    log(f"library build of {count} instances, total N = {int(sizes.sum())}")
+    t0 = time.perf_counter()
+    h = hmps.HMatrix([w.problem for w in wls], 64, 1.0, 1e-4, progress=log)
+    build_s = time.perf_counter() - t0
+    info = h.info()
+    n = h.n
+    level = info["leaf_level"]
+    bs = [w.rhs() for w in wls]
+    b = torch.from_numpy(np.ascontiguousarray(np.vstack(bs))).to("cuda")
+    stream = torch.cuda.current_stream()
+    F32, F64 = hmps.HM_F32_APPLY, hmps.HM_F64
+
+    log("autotune (FP32 series, 16 RHS)")
+    best, best_ms = h.autotune(nrhs, K=K, precision=F32)
+    log(f"autotune: {best} {best_ms:.3f} ms")
+    mm = nrhs >= best["mm_min_rhs"]
+
+    def graph_of(**kw):
+        out = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            h.solve(b, out=out, **kw)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            h.solve(b, out=out, **kw)
+        return g, out
+
+    # ---- FP32 series (the batched launch path), graph replay
+    g32, out32 = graph_of(K=K, precision=F32)
+    for _ in range(a.warmup):
+        g32.replay()
+    torch.cuda.synchronize()
+    log(f"timed region: {a.steps} graph replays of the FP32 series")
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        g32.replay()
+    torch.cuda.synchronize()
+    wall32 = time.perf_counter() - t0
+    x32 = out32.t().cpu().numpy()
+    lat32 = latency(g32.replay, a.steps)
+    # kernel durations from eager solves (same kernels as in the graph)
+    _, kernels = profiled(h, lambda: h.solve(b, K=K, precision=F32), 5)
+    T = info["coeffs"][level]
+    roof = term_roofline(info, level, n, nrhs, "f32", mm, kernels["term_series"]["avg_us"], T)
+
+    # ---- plain FP64 series on the same handle (same tuning), graph replay
+    g64, out64 = graph_of(K=K, precision=F64)
+    g64.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        g64.replay()
+    torch.cuda.synchronize()
+    wall64 = time.perf_counter() - t0
+    x64 = out64.t().cpu().numpy()
+    lat64 = latency(g64.replay, a.steps)
+    _, k64 = profiled(h, lambda: h.solve(b, K=K, precision=F64), 3)
+
+    # ---- refinement to x*: adaptive once for the pass count, then the
+    # fixed-pass solve captured and replayed
+    log("adaptive FP32 refinement (pass count)")
+    _, st = h.solve(b, K=K, precision=F32, kind=hmps.PS_REFINE, max_passes=400, refine_tol=1e-10,
+                    stats=True)
+    passes = max(s["passes"] for s in st)
+    log(f"refinement: {passes} passes")
+    gr, outr = graph_of(K=K, precision=F32, kind=hmps.PS_REFINE_FIXED, max_passes=passes,
+                        refine_tol=1e-10)
+    gr.replay()
+    torch.cuda.synchronize()
+    rsteps = max(2, a.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(rsteps):
+        gr.replay()
+    torch.cuda.synchronize()
+    wallr = time.perf_counter() - t0
+    xr = outr.t().cpu().numpy()
+    latr = latency(gr.replay, rsteps)
+
+    # ---- oracle on a sample of instances (smallest, largest, 4 seeded)
+    rel = {"series_f32": 0.0, "series_f64": 0.0, "refine_f32_vs_xstar": 0.0}
+    cpu = None
+    sample = []
+    if not a.no_oracle:
+        from oracle import hmatrix, series
+        g = np.random.default_rng(7)
+        sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                         *g.choice(count, size=min(4, count), replace=False).tolist()})
+        cpu_t, cpu_rhs = 0.0, 0
+        for i in sample:
+            o0, o1 = h.offsets[i], h.offsets[i + 1]
+            log(f"oracle instance {i} n={sizes[i]}")
+            H = hmatrix.HMatrix(wls[i].problem, 64, 1.0, 1e-4)
+            t1 = time.perf_counter()
+            ref = series.series(H, bs[i], K)
+            cpu_t += time.perf_counter() - t1
+            cpu_rhs += nrhs
+            rel["series_f32"] = max(rel["series_f32"], series.rel_err(x32[o0:o1], ref))
+            rel["series_f64"] = max(rel["series_f64"], series.rel_err(x64[o0:o1], ref))
+            xs = (series.solve_exact(H, bs[i]) if sizes[i] <= 4096
+                  else series.solve_gmres(H, bs[i], tol=1e-13))
+            rel["refine_f32_vs_xstar"] = max(rel["refine_f32_vs_xstar"],
+                                             series.rel_err(xr[o0:o1], xs))
+        cpu = {"value": cpu_rhs / cpu_t, "unit": "RHS/s", "cores": blas_threads(),
+               "kind": "oracle",
+               "sample": f"numpy/scipy FP64 series of {len(sample)} sampled instances "
+                         f"(N = {[int(sizes[i]) for i in sample]}, {nrhs} RHS each) in "
+                         f"{cpu_t:.1f} s; oracle builds not included"}
+        log(f"rel.err on the sample: {rel}")
+    tot = count * nrhs
+    ok = lambda key, tol: (not a.no_oracle) and rel[key] <= tol  # noqa: E731
+    value = tot * rsteps / wallr if ok("refine_f32_vs_xstar", SOLVED_TOL) else 0.0
+    extras = {
+        "series_f32_graph": {"RHS_per_s": tot * a.steps / wall32, "ms_per_solve": 1e3 * wall32 / a.steps,
+                             "rel_err_vs_oracle_xK_sample": rel["series_f32"], "tolerance": 1e-4,
+                             "latency_ms": lat32},
+        "series_f64_graph": {"RHS_per_s": tot * a.steps / wall64, "ms_per_solve": 1e3 * wall64 / a.steps,
+                             "rel_err_vs_oracle_xK_sample": rel["series_f64"], "tolerance": 1e-10,
+                             "solved_RHS_per_s": (tot * a.steps / wall64) if ok("series_f64", 1e-10) else 0.0,
+                             "latency_ms": lat64, "kernels": k64,
+                             "roofline": term_roofline(info, level, n, nrhs, "f64", mm,
+                                                       k64["term_series"]["avg_us"], T)},
+        "refine_f32_graph": {"passes": passes, "ms_per_solve": 1e3 * wallr / rsteps,
+                             "rel_err_vs_oracle_xstar_sample": rel["refine_f32_vs_xstar"]},
+        "autotune": {"choice": best, "ms": best_ms},
+        "oracle_sample_instances": sample,
+    }
+    out = {
+        "metric": METRIC, "value": value, "unit": "RHS/s", "n_gpus": 1, "steps": rsteps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * wallr / rsteps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched_{count}", "instances": count, "N_total": n,
+                   "N_range": [int(sizes.min()), int(sizes.max())], "kind": "surface",
+                   "leaf_max": 64, "eta": 1.0, "aca_tol": 1e-4, "K": K, "level": "leaf",
+                   "nrhs_per_instance": nrhs,
+                   "precision": "complex64 blocks, complex128 LU/residual/refinement",
+                   "path": "refinement to x* (fixed pass count), HIP graph replay"},
+        "rel_err_vs_oracle": rel["refine_f32_vs_xstar"] if not a.no_oracle else None,
+        "latency_ms": latr, "roofline": roof, "kernels": kernels, "build_s": build_s,
+        "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+    h.close()
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="sphere_24576")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--precision", default=None, choices=["f64", "f32"])
+    ap.add_argument("--instances", type=int, default=256, help="batched_*: instance count")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle check and CPU baseline (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the H-matvec, FP32 and refinement side measurements")
+                    help="skip the side measurements (H-matvec, other precision, refinement)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy a MIB-MiB device buffer 3 times (a plain "
@@ -77,200 +478,13 @@ def main(argv=None):
         return 2
 
     import torch
-    from paper_2307_03968_amd import hmps
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    wl = workload(a.workload)
-    prec = hmps.HM_F64 if a.precision == "f64" else hmps.HM_F32_APPLY
-    log(f"library build {wl.name} n={wl.problem.n} leaf={wl.leaf_max} tol={wl.aca_tol}")
-    t0 = time.perf_counter()
-    h = hmps.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol)
-    build_s = time.perf_counter() - t0
-    info = h.info()
-    L = info["leaf_level"]
-    level = L if wl.level < 0 else wl.level
-    b_np = wl.rhs()
-    nrhs = b_np.shape[1]
-    b = torch.from_numpy(np.ascontiguousarray(b_np)).to("cuda")
-    x = None
-    stream = torch.cuda.current_stream()
-
-    for _ in range(a.warmup):
-        x = h.solve(b, K=wl.K, level=wl.level, precision=prec)
-    torch.cuda.synchronize()
-
-    log(f"timed region: {a.steps} solves")
-    # per-kernel HIP events (timing-only, no system fence) are recorded by the
-    # library around every launch inside the timed region
-    h_prof = hmps._lib().hm_profile_enable(h.handle, 1)
-    assert h_prof == 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(a.steps):
-        x = h.solve(b, K=wl.K, level=wl.level, precision=prec)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = (hmps.hm_kernel_time * hmps.HM_K_COUNT)()
-    assert hmps._lib().hm_profile_read(h.handle, kt) == 0
-    hmps._lib().hm_profile_enable(h.handle, 0)
-    # single-request latency: each solve issued and waited for on its own
-    lat = []
-    for i in range(a.steps):
-        t1 = time.perf_counter()
-        h.solve(b, K=wl.K, level=wl.level, precision=prec)
-        torch.cuda.synchronize()
-        lat.append(1e3 * (time.perf_counter() - t1))
-    step_ms = np.array(lat)
-    if a.copy_calibration > 0:
-        nbytes = a.copy_calibration << 20
-        src_buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst_buf = torch.empty_like(src_buf)
-        for _ in range(3):
-            dst_buf.copy_(src_buf)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {nbytes} bytes")
-        del src_buf, dst_buf
-    ms_per_step = wall * 1e3 / a.steps
-    x_np = x.cpu().numpy()
-
-    # ---- dominant kernel: one power-series term (k_term), algorithmic bytes:
-    # series panel entries D^{-1}[near | U] + W entries of the level's far
-    # blocks (all in-row at the leaf level, no separate stage-A pass), the
-    # input y_{k-1}, the output y_k and x read + written.
-    elem = 16 if prec == hmps.HM_F64 else 8
-    n = wl.problem.n
-    ent = info["series_entries"][level]
-    went = info["stageA_entries"][level]
-    kt_names = ["stageA", "term_series", "term_apply", "term_dinv"]
-    kernels = {name: {"launches": kt[i].launches,
-                      "avg_us": 1e3 * kt[i].total_ms / max(1, kt[i].launches)}
-               for i, name in enumerate(kt_names)}
-    assert kt[hmps.HM_K_STAGEA].launches == 0, "roofline bytes below assume no separate stage A"
-    term_bytes = elem * (ent + went) + 16 * (4 * n)
-    term = kt[hmps.HM_K_TERM_SERIES]
-    term_ms = term.total_ms / max(1, term.launches)
-    achieved = term_bytes / (term_ms * 1e-3) / 1e9
-    per_solve_bytes = wl.K * (elem * (ent + went)) + 16 * info["diag_entries"]
-
-    # ---- oracle check and CPU baseline
-    rel = None
-    cpu = None
-    extras = {}
-    H = None
-    if not a.no_oracle:
-        from oracle import hmatrix, series
-        log("oracle build (host, FP64)")
-        t1 = time.perf_counter()
-        H = hmatrix.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol)
-        oracle_build_s = time.perf_counter() - t1
-        log("oracle series")
-        ref = series.series(H, b_np, wl.K, wl.level)
-        rel = series.rel_err(x_np, ref)
-        log(f"rel.err vs oracle x_K = {rel:.3e}")
-        # bounded sample: repeat the oracle's solve of the same workload
-        t1 = time.perf_counter()
-        reps = 0
-        while reps < 1 or time.perf_counter() - t1 < a.cpu_seconds:
-            series.series(H, b_np, wl.K, wl.level)
-            reps += 1
-        cpu_s = time.perf_counter() - t1
-        cpu = {"value": reps * nrhs / cpu_s, "unit": "RHS/s", "cores": blas_threads(),
-               "kind": "oracle",
-               "sample": f"{reps} sequential numpy/scipy FP64 series solves of the same "
-                         f"workload ({nrhs} RHS each) in {cpu_s:.1f} s; oracle H build "
-                         f"{oracle_build_s:.1f} s not included"}
-    solved = rel is not None and rel <= SOLVED_TOL
-    value = (a.steps * nrhs / wall) if solved else 0.0
-
-    # ---- side measurements: H-matvec GB/s, FP32 apply, refinement
-    if not a.no_extras:
-        xr = torch.randn(n, dtype=torch.complex128, device="cuda")
-        for _ in range(3):
-            h.apply(xr, level=wl.level)
-        torch.cuda.synchronize()
-        reps = 20
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            h.apply(xr, level=wl.level)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        mv_ms = e0.elapsed_time(e1) / reps
-        mv_bytes = 16 * (info["apply_entries"][level] + info["stageA_entries"][level]) + 32 * n
-        extras["hmatvec"] = {"ms": mv_ms, "bytes": mv_bytes,
-                             "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
-                             "frac_hbm_peak": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
-        # FP32 apply series
-        for _ in range(3):
-            x32 = h.solve(b, K=wl.K, level=wl.level, precision=hmps.HM_F32_APPLY)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(reps):
-            x32 = h.solve(b, K=wl.K, level=wl.level, precision=hmps.HM_F32_APPLY)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        f32_ms = e0.elapsed_time(e1) / reps
-        extras["series_f32_apply"] = {"ms_per_solve": f32_ms, "RHS_per_s": nrhs * 1e3 / f32_ms}
-        if H is not None:
-            extras["series_f32_apply"]["rel_err_vs_oracle_xK"] = series.rel_err(x32.cpu().numpy(), ref)
-            extras["series_f64"] = {"rel_err_vs_oracle_xK": rel}
-            rho = series.rho(H, wl.level, iters=60)
-            extras["rho"] = rho
-            if rho ** (wl.K + 1) < 0.9:
-                log("oracle x* by GMRES for the refinement check")
-                xs = series.solve_gmres(H, b_np, wl.level, tol=1e-13)
-                for pname, p in (("f32_apply", hmps.HM_F32_APPLY), ("f64", hmps.HM_F64)):
-                    torch.cuda.synchronize()
-                    t1 = time.perf_counter()
-                    xr_, st = h.solve(b, K=wl.K, level=wl.level, precision=p,
-                                      kind=hmps.PS_REFINE, max_passes=400, refine_tol=1e-10,
-                                      stats=True)
-                    torch.cuda.synchronize()
-                    ref_s = time.perf_counter() - t1
-                    err = series.rel_err(xr_.cpu().numpy(), xs)
-                    extras[f"refine_{pname}"] = {
-                        "ms_per_solve": 1e3 * ref_s, "passes": st[0]["passes"],
-                        "rel_err_vs_oracle_xstar": err,
-                        "solved_RHS_per_s": (nrhs / ref_s) if err <= SOLVED_TOL else 0.0}
-            else:
-                extras["refine"] = (f"not attainable by the method: rho^(K+1) = "
-                                    f"{rho ** (wl.K + 1):.3f}")
-
-    out = {
-        "metric": "solved RHS/s at rel.err<=1e-8 vs FP64 oracle",
-        "value": value,
-        "unit": "RHS/s",
-        "n_gpus": 1,
-        "steps": a.steps,
-        "warmup": a.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == hmps.HM_F64 else "f32",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "N": n, "kind": "surface" if wl.problem.kind == 0 else "volume",
-                   "leaf_max": wl.leaf_max, "eta": wl.eta, "aca_tol": wl.aca_tol, "K": wl.K,
-                   "level": level, "nrhs": nrhs,
-                   "precision": "complex128" if prec == hmps.HM_F64 else "complex64 blocks, complex128 vectors"},
-        "rel_err_vs_oracle": rel,
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99))},
-        "roofline": {"bound": "hbm", "kernel": "k_term (one series term)", "achieved": achieved,
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None, "bytes_per_launch": term_bytes,
-                     "avg_launch_us": term_ms * 1e3},
-        "per_solve_algorithmic_bytes": per_solve_bytes,
-        "kernels": kernels,
-        "build_s": build_s,
-        "device_bytes": info["device_bytes"],
-        "cpu_baseline": cpu,
-        "extras": extras,
-    }
-    print(json.dumps(out), flush=True)
-    h.close()
-    return 0
+    if a.workload.startswith("batched"):
+        if "_" in a.workload:
+            a.instances = int(a.workload.split("_")[1])
+        return bench_batched(a)
+    return bench_single(a)
 
 
 if __name__ == "__main__":

@@ -59,8 +59,19 @@ enum { HM_F64 = 0, HM_F32_APPLY = 1 };
 /* PS_SERIES: return x_K.  PS_REFINE: x <- x + P_K(b - Z_l x) passes (P_K is
  * the K-term series operator, residual in FP64) until the correction is
  * below refine_tol relative to x; the fixed point is Z_l^{-1} b and the
- * per-pass error factor is rho(D^{-1} R_l)^{K+1}. */
-enum { PS_SERIES = 0, PS_REFINE = 1 };
+ * per-pass error factor is rho(D^{-1} R_l)^{K+1}.  PS_REFINE_FIXED: exactly
+ * max_passes such passes with no host synchronisation (refine_tol only
+ * decides the diverged flag of the statistics).  PS_SERIES and
+ * PS_REFINE_FIXED without statistics only enqueue device work: once a
+ * first call with the same nrhs has sized the workspace, a call can be
+ * recorded by stream capture into a HIP graph and replayed.  Such a graph
+ * refers to the handle's workspace and work lists: it stays valid until
+ * hmat_free, a call with more right-hand sides than any before the capture
+ * (the workspace grows), or a change of term_wgs (hmat_tune,
+ * hmat_autotune), whichever comes first.
+ * Norm-based quantities (growth, ||d|| / ||x||) are taken per instance of a
+ * batched handle and the maximum over instances is reported. */
+enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2 };
 
 #define HM_BUILD_HOST_ONLY 0x1u /* build tree, partition and blocks on the host
                                    only: no device memory, for hmat_export /
@@ -98,6 +109,10 @@ typedef struct {
   int32_t max_rank;     /* 0 = min(m, n)                                    */
   uint32_t flags;       /* HM_BUILD_*                                       */
   int32_t num_threads;  /* host threads for the build, 0 = all             */
+  /* optional: called on the building thread as the build advances (phase
+   * done, instances built); msg is valid during the call only */
+  void (*progress)(const char* msg, void* user);
+  void* progress_user;
 } hm_build_opts;
 
 typedef struct {
@@ -106,16 +121,17 @@ typedef struct {
                            level only (the paper's runs); levels below the
                            coarsest far level act as the coarsest          */
   int32_t precision;    /* HM_F64 or HM_F32_APPLY                           */
-  int32_t kind;         /* PS_SERIES or PS_REFINE                           */
-  int32_t max_passes;   /* PS_REFINE: pass limit                            */
+  int32_t kind;         /* PS_SERIES, PS_REFINE or PS_REFINE_FIXED          */
+  int32_t max_passes;   /* PS_REFINE: pass limit; PS_REFINE_FIXED: passes  */
   double refine_tol;    /* PS_REFINE: stop when ||d|| <= tol ||x|| per RHS   */
 } ps_opts;
 
 /* Per right-hand side statistics.  Filling them synchronises the stream. */
 typedef struct {
   int32_t passes;       /* refinement passes done (0 for PS_SERIES)         */
-  int32_t diverged;     /* 1 if growth > 1 or non-finite values             */
-  double resid_rel;     /* PS_REFINE: last ||d|| / ||x||; else 0           */
+  int32_t diverged;     /* 1 if growth > 1 or non-finite values, or (both
+                           refinement kinds) last ||d|| > refine_tol ||x||  */
+  double resid_rel;     /* refinement: last ||d|| / ||x||; else 0          */
   double growth;        /* ||y_K|| / ||y_0|| of the (last) series           */
   double t_ms;          /* wall time of the whole call (same for all RHS)   */
 } ps_stats;
@@ -225,9 +241,21 @@ int hmat_export(hm_matrix_t h, const char* path);
 typedef struct {
   int32_t mm_min_rhs;
   int32_t term_wgs;
+  int32_t rhs_tile;   /* MFMA right-hand-side tile per workgroup: 16, 32 or
+                         64 (0 or -1 in hmat_tune: chosen from nrhs)       */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
+
+/* Autotuner: times ps_solve with opts (series kind) on nrhs zero
+ * right-hand sides (vectors the call allocates and frees) for every
+ * candidate tuning -- term_wgs in {auto, auto/2, 2 auto, 4 auto} times
+ * {streaming kernels, MFMA kernels with RHS tiles 16/32/64 up to nrhs} --
+ * and keeps the fastest on the handle (median of five timed calls after
+ * two warm-ups, HIP events on hip_stream).  best and best_ms (nullable)
+ * receive the choice and its time per solve.  Synchronises the stream. */
+int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_stream,
+                  hm_tuning* best, double* best_ms);
 
 /* Per-kernel timing for measurement: while enabled, every launch of the
  * classes above is bracketed by HIP events recorded on the launch stream.

@@ -48,7 +48,9 @@ class NearBlock:
 
 class HMatrix:
     def __init__(self, prob, leaf_max: int, eta: float = 1.0, aca_tol: float = 1e-4,
-                 max_rank: int = 0):
+                 max_rank: int = 0, progress=None):
+        """``progress`` (optional callable taking a string) is told how the
+        build advances (long builds); it does not change the result."""
         self.prob = prob
         self.n = prob.n
         self.tree = _cl.build_tree(prob.xyz, leaf_max)
@@ -69,7 +71,12 @@ class HMatrix:
 
         self.far: List[FarBlock] = []
         done = {}
-        for t, s, lev in self.part.far:
+        if progress:
+            progress(f"oracle: {len(self.near)} near blocks filled, "
+                     f"{len(self.part.far) // 2} far blocks to compress")
+        for q, (t, s, lev) in enumerate(self.part.far):
+            if progress and q % 4000 == 0 and q:
+                progress(f"oracle: far block pair {q} of {len(self.part.far)}")
             if t.off < s.off:
                 rows = self.perm[t.off:t.off + t.size]
                 cols = self.perm[s.off:s.off + s.size]

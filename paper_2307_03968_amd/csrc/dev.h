@@ -101,6 +101,10 @@ struct TermArgs {
   const int64_t* out_perm;
 };
 
+struct NormItem {
+  int64_t r0, r1;
+};
+
 constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)
 constexpr int kGroupTile = 128;  // rows per stage-A group item
 // Many right-hand sides (MFMA path): stage A uses groups over all far blocks
@@ -115,11 +119,11 @@ hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm,
 hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, double2* x,
                               int64_t ldx, int64_t n, int nrhs, hipStream_t st);
 // many-RHS variants on MFMA (FP32 3M, FP64 4M), right-hand sides in tiles
-// of 16/32/64 per workgroup
-hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
+// of `tile` = 16/32/64 per workgroup (0: by nrhs)
+hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
                           hipStream_t st);
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs,
+                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs, int tile,
                             hipStream_t st);
 // nwg persistent workgroups; grid.y covers the right-hand sides
 hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
@@ -146,12 +150,15 @@ hipError_t launch_premul(const double2* Dinv, const int64_t* dinv_off, const dou
 constexpr int kPremulCols = 32;  // columns per tile of launch_premul
 hipError_t launch_cast(const double2* in, float2* out, int64_t n, hipStream_t st);
 // per column c < nrhs: out[c] = sum_i |v[i + c*ld]|^2 in a fixed order
-hipError_t launch_norm2(const double2* v, int64_t ld, int64_t n, int nrhs, double* scratch,
-                        double* out, hipStream_t st);
+// squared norms per (segment, column) -> out[c * nseg + g]; scratch holds
+// nitems * nrhs doubles
+hipError_t launch_norm2(const double2* v, int64_t ld, const NormItem* items, int nitems,
+                        const int32_t* seg_ptr, int nseg, int nrhs, double* scratch, double* out,
+                        hipStream_t st);
 // y[i + c*ldy] (+)= alpha x[i + c*ldx]
 hipError_t launch_axpy(double alpha, const double2* x, int64_t ldx, double2* y, int64_t ldy,
                        int64_t n, int nrhs, int accumulate, hipStream_t st);
 
-constexpr int kNormBlocks = 128;  // partial sums per column in launch_norm2
+constexpr int64_t kNormRows = 8192;  // rows per norm item
 
 }  // namespace hm

@@ -649,13 +649,19 @@ __global__ void k_cast(const double2* __restrict__ in, float2* __restrict__ out,
 }
 
 // ---------------------------------------------------------------- norms
-__global__ __launch_bounds__(kThreads) void k_norm2_partial(const double2* __restrict__ v,
-                                                            int64_t ld, int64_t n,
-                                                            double* __restrict__ scratch) {
+// Squared 2-norms per (segment, right-hand side): a segment is one instance
+// of a batched handle (the whole vector otherwise).  Item q covers rows
+// [items[q].r0, items[q].r1) of segment items[q].seg; a workgroup reduces
+// one item of one column, then the items of a segment are summed in order
+// (the result does not depend on timing).
+__global__ __launch_bounds__(kThreads) void k_norm2_items(const double2* __restrict__ v,
+                                                          int64_t ld,
+                                                          const NormItem* __restrict__ items,
+                                                          double* __restrict__ scratch) {
   const int c = blockIdx.y;
+  const NormItem it = items[blockIdx.x];
   double s = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < n;
-       q += (int64_t)gridDim.x * kThreads) {
+  for (int64_t q = it.r0 + threadIdx.x; q < it.r1; q += kThreads) {
     const double2 z = v[q + c * ld];
     s = fma(z.x, z.x, s);
     s = fma(z.y, z.y, s);
@@ -670,13 +676,15 @@ __global__ __launch_bounds__(kThreads) void k_norm2_partial(const double2* __res
   if (threadIdx.x == 0) scratch[(int64_t)c * gridDim.x + blockIdx.x] = sm[0];
 }
 
-__global__ void k_norm2_final(const double* __restrict__ scratch, int nb, int nrhs,
-                              double* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= nrhs) return;
+__global__ void k_norm2_segments(const double* __restrict__ scratch, int nitems,
+                                 const int32_t* __restrict__ seg_ptr, int nseg, int nrhs,
+                                 double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nseg * nrhs) return;
+  const int c = t / nseg, g = t % nseg;
   double s = 0.0;
-  for (int i = 0; i < nb; ++i) s += scratch[(int64_t)c * nb + i];
-  out[c] = s;
+  for (int i = seg_ptr[g]; i < seg_ptr[g + 1]; ++i) s += scratch[(int64_t)c * nitems + i];
+  out[t] = s;
 }
 
 __global__ void k_axpy(double alpha, const double2* __restrict__ x, int64_t ldx,
@@ -838,13 +846,14 @@ hipError_t launch_cast(const double2* in, float2* out, int64_t n, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_norm2(const double2* v, int64_t ld, int64_t n, int nrhs, double* scratch,
-                        double* out, hipStream_t st) {
-  if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_norm2_partial, dim3(kNormBlocks, nrhs), dim3(kThreads), 0, st, v, ld, n,
+hipError_t launch_norm2(const double2* v, int64_t ld, const NormItem* items, int nitems,
+                        const int32_t* seg_ptr, int nseg, int nrhs, double* scratch, double* out,
+                        hipStream_t st) {
+  if (nrhs <= 0 || nitems <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_norm2_items, dim3(nitems, nrhs), dim3(kThreads), 0, st, v, ld, items,
                      scratch);
-  hipLaunchKernelGGL(k_norm2_final, dim3((nrhs + 63) / 64), dim3(64), 0, st, scratch,
-                     kNormBlocks, nrhs, out);
+  hipLaunchKernelGGL(k_norm2_segments, dim3(blocks_for((int64_t)nseg * nrhs, 64)), dim3(64), 0, st,
+                     scratch, nitems, seg_ptr, nseg, nrhs, out);
   return hipGetLastError();
 }
 

@@ -324,11 +324,16 @@ __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__
     }
 }
 
-inline int pick_nt(int nrhs) { return nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4); }
+// 16-column RHS tiles per workgroup: the requested tile (16, 32 or 64), or
+// by nrhs when 0
+inline int pick_nt(int nrhs, int tile) {
+  if (tile == 16 || tile == 32 || tile == 64) return tile / 16;
+  return nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+}
 
 template <bool F32, int RT>
-hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, hipStream_t st) {
-  const int nt = pick_nt(nrhs);
+hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, int tile, hipStream_t st) {
+  const int nt = pick_nt(nrhs, tile);
   const dim3 grid(nwg, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
     hipLaunchKernelGGL((k_term_mm<F32, RT, 1>), grid, dim3(kThreads), 0, st, a, nrhs);
@@ -341,8 +346,8 @@ hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, hipStream_t st) {
 
 template <bool F32>
 hipError_t stageA_mm_p(const void* W, const Group* groups, const GroupItem* items, int nitems,
-                       double2* xin, int64_t ldx, int64_t N, int nrhs, hipStream_t st) {
-  const int nt = pick_nt(nrhs);
+                       double2* xin, int64_t ldx, int64_t N, int nrhs, int tile, hipStream_t st) {
+  const int nt = pick_nt(nrhs, tile);
   const dim3 grid(nitems, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
     hipLaunchKernelGGL((k_stageA_mm<F32, 1>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
@@ -358,27 +363,27 @@ hipError_t stageA_mm_p(const void* W, const Group* groups, const GroupItem* item
 
 }  // namespace
 
-hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
+hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
                           hipStream_t st) {
   if (nwg <= 0 || nrhs <= 0) return hipSuccess;
   if (max_m > 256) return hipErrorInvalidValue;
   const int rt = (max_m + 63) / 64;  // 16-row tiles per wave
   if (f32) {
-    if (rt <= 1) return term_mm_rt<true, 1>(a, nwg, nrhs, st);
-    if (rt <= 2) return term_mm_rt<true, 2>(a, nwg, nrhs, st);
-    return term_mm_rt<true, 4>(a, nwg, nrhs, st);
+    if (rt <= 1) return term_mm_rt<true, 1>(a, nwg, nrhs, tile, st);
+    if (rt <= 2) return term_mm_rt<true, 2>(a, nwg, nrhs, tile, st);
+    return term_mm_rt<true, 4>(a, nwg, nrhs, tile, st);
   }
-  if (rt <= 1) return term_mm_rt<false, 1>(a, nwg, nrhs, st);
-  if (rt <= 2) return term_mm_rt<false, 2>(a, nwg, nrhs, st);
-  return term_mm_rt<false, 4>(a, nwg, nrhs, st);
+  if (rt <= 1) return term_mm_rt<false, 1>(a, nwg, nrhs, tile, st);
+  if (rt <= 2) return term_mm_rt<false, 2>(a, nwg, nrhs, tile, st);
+  return term_mm_rt<false, 4>(a, nwg, nrhs, tile, st);
 }
 
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs,
+                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs, int tile,
                             hipStream_t st) {
   if (nitems <= 0 || nrhs <= 0) return hipSuccess;
-  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xin, ldx, N, nrhs, st)
-             : stageA_mm_p<false>(W, groups, items, nitems, xin, ldx, N, nrhs, st);
+  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xin, ldx, N, nrhs, tile, st)
+             : stageA_mm_p<false>(W, groups, items, nitems, xin, ldx, N, nrhs, tile, st);
 }
 
 }  // namespace hm

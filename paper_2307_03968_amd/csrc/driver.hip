@@ -113,6 +113,7 @@ struct hm_matrix {
   std::vector<hm::TermList> tl_apply_mm, tl_series_mm;
   std::vector<hm::GroupList> sa_mm;
   int mm_min_rhs = 8;           // right-hand sides from which the MFMA kernels run
+  int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
   // per-leaf column layout of the panels, kept to rebuild the work lists
   std::vector<int64_t> near_cols, ir_cols;
   std::vector<int32_t> ir_ncol_h;
@@ -129,6 +130,10 @@ struct hm_matrix {
           *dt = nullptr, *partial = nullptr;
   double *nscratch = nullptr, *norms = nullptr;
   double* norms_host = nullptr;  // pinned
+  // norm segments (one per instance) and their row items
+  hm::NormItem* norm_items = nullptr;
+  int32_t* norm_seg = nullptr;
+  int n_norm_items = 0, nseg = 1;
   std::vector<void*> ws_allocs;
   // per-kernel timing
   bool prof = false;
@@ -167,8 +172,8 @@ int dalloc(hm_matrix* h, void** p, size_t bytes, bool lists = false) {
   return HM_OK;
 }
 
-template <typename T>
-int upload(hm_matrix* h, T** dst, const std::vector<T>& v, hipStream_t st, bool lists = false) {
+template <typename T, typename A>
+int upload(hm_matrix* h, T** dst, const std::vector<T, A>& v, hipStream_t st, bool lists = false) {
   STCHK(dalloc(h, (void**)dst, v.size() * sizeof(T), lists));
   if (!v.empty()) HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));  // host vectors may be freed after return
@@ -310,13 +315,14 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   STCHK(al((void**)&h->rt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->dt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->partial, sizeof(double2) * h->partial_rows * nrhs));
-  STCHK(al((void**)&h->nscratch, sizeof(double) * kNormBlocks * nrhs * 2));
-  STCHK(al((void**)&h->norms, sizeof(double) * nrhs * 2));
+  STCHK(al((void**)&h->nscratch, sizeof(double) * h->n_norm_items * nrhs * 2));
+  STCHK(al((void**)&h->norms, sizeof(double) * h->nseg * nrhs * 2));
   STCHK(al((void**)&h->counters, sizeof(int32_t) * h->nl * nrhs));
   HIPCHK(hipMemset(h->counters, 0, sizeof(int32_t) * h->nl * nrhs));
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   h->norms_host = nullptr;
-  HIPCHK(hipHostMalloc((void**)&h->norms_host, sizeof(double) * nrhs * 2, hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&h->norms_host, sizeof(double) * h->nseg * nrhs * 2,
+                       hipHostMallocDefault));
   h->ws_nrhs = nrhs;
   return HM_OK;
 }
@@ -398,6 +404,15 @@ struct ProfScope {
 // tree order (ld N), or in original order through the permutation when
 // rhs_perm is set (ld ldr).  When out is set the final x is also written
 // there in original order (ld ldo).
+// Squared norms of v per (instance, column) into slot 0 or 1 of h->norms
+// (slot * nseg * nrhs + c * nseg + instance).
+hipError_t norms_into(hm_matrix* h, const double2* v, int64_t ld, int nrhs, int slot,
+                      hipStream_t st) {
+  return launch_norm2(v, ld, h->norm_items, h->n_norm_items, h->norm_seg, h->nseg, nrhs,
+                      h->nscratch + (int64_t)slot * h->n_norm_items * nrhs,
+                      h->norms + (int64_t)slot * h->nseg * nrhs, st);
+}
+
 // From h->mm_min_rhs right-hand sides on, the term and stage-A products run
 // on the matrix cores (MM kernels, their own lists and stage-A groups).
 struct Path {
@@ -420,13 +435,14 @@ Path pick_path(const hm_matrix* h, bool f32, int nrhs) {
 
 hipError_t run_term(const hm_matrix* h, const Path& P, bool f32, const TermArgs& t,
                     const TermList& tl, int nrhs, hipStream_t st) {
-  return P.mm ? launch_term_mm(f32, h->max_m, t, tl.nwg, nrhs, st)
+  return P.mm ? launch_term_mm(f32, h->max_m, t, tl.nwg, nrhs, h->rhs_tile, st)
               : launch_term(f32, h->max_m, t, tl.nwg, nrhs, st);
 }
 
 hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupList& sa,
                       double2* xin, int64_t ldx, int nrhs, hipStream_t st) {
-  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st)
+  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs,
+                                 h->rhs_tile, st)
               : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
 }
 
@@ -448,7 +464,7 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     if (K == 0 && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
     TIMED(HM_K_TERM_DINV, run_term(h, P, false, t, h->tl_dinv, nrhs, st));
   }
-  if (want_norms) HIPCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch, h->norms, st));
+  if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
   const TermList& tl = (*P.tl_series)[li];
   const GroupList& sa = (*P.sa)[li];
   for (int k = 1; k <= K; ++k) {
@@ -464,8 +480,7 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     TIMED(HM_K_TERM_SERIES, run_term(h, P, f32, t, tl, nrhs, st));
     std::swap(y_cur, y_nxt);
   }
-  if (want_norms)
-    HIPCHK(launch_norm2(y_cur, ldin, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
+  if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
   return HM_OK;
 }
 
@@ -622,8 +637,8 @@ int build_device(hm_matrix* h, hipStream_t st) {
       }
     }
   };
-  auto fill_W = [&](const GroupSet& gs, std::vector<double2>& W) {
-    W.assign((size_t)std::max<int64_t>(gs.wtot, 1), make_double2(0.0, 0.0));
+  auto fill_W = [&](const GroupSet& gs, bigvec<double2>& W) {
+    W = bigvec<double2>((size_t)std::max<int64_t>(gs.wtot, 1));  // zeroed (pad rows stay 0)
     const int ng = (int)gs.groups.size();
 #pragma omp parallel for schedule(dynamic, 1)
     for (int g = 0; g < ng; ++g) {
@@ -642,7 +657,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   const int64_t wtot = gs1.wtot, wtot_mm = gsm.wtot;
   // one t region after the N tree-order rows serves both layouts
   h->T = std::max(gs1.T, gsm.T);
-  std::vector<double2> W;
+  bigvec<double2> W;
   fill_W(gs1, W);
 
   // ---- per leaf: in-row blocks (finest first) and global slices (finest first)
@@ -706,7 +721,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
     irtot += (int64_t)ir_ld[a] * nmax;
     irrows += ir_cols[a];
   }
-  std::vector<double2> IR((size_t)std::max<int64_t>(irtot, 1), make_double2(0.0, 0.0));
+  bigvec<double2> IR((size_t)std::max<int64_t>(irtot, 1));  // zeroed
   std::vector<int32_t> ir_soff((size_t)std::max<int64_t>(irrows, 1)), ir_n((size_t)std::max<int64_t>(irrows, 1));
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
@@ -741,9 +756,9 @@ int build_device(hm_matrix* h, hipStream_t st) {
     piv_off[a] = ptot;
     ptot += m;
   }
-  std::vector<double2> R((size_t)std::max<int64_t>(rtot, 1), make_double2(0.0, 0.0));
+  bigvec<double2> R((size_t)std::max<int64_t>(rtot, 1));  // zeroed (pad rows stay 0)
   std::vector<int32_t> src((size_t)std::max<int64_t>(ctot, 1)), src_mm(src.size());
-  std::vector<double2> D((size_t)lutot);
+  bigvec<double2> D((size_t)lutot);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
     const int m = H.leaf_size[a];
@@ -811,7 +826,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->leaf_off, loff, st));
   STCHK(upload(h, &h->leaf_m, lm, st));
   STCHK(upload(h, &h->R64, R, st));
-  std::vector<double2>().swap(R);
+  bigvec<double2>().swap(R);
   STCHK(upload(h, &h->src, src, st));
   STCHK(upload(h, &h->R_off, R_off, st));
   STCHK(upload(h, &h->R_col, R_col, st));
@@ -821,17 +836,17 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->Dinv_off, Dinv_off, st));
   STCHK(upload(h, &h->piv_off, piv_off, st));
   STCHK(upload(h, &h->LU, D, st));
-  std::vector<double2>().swap(D);
+  bigvec<double2>().swap(D);
   STCHK(upload(h, &h->W64, W, st));
-  std::vector<double2>().swap(W);
+  bigvec<double2>().swap(W);
   STCHK(upload(h, &h->groups, gs1.groups, st));
   STCHK(upload(h, &h->groups_mm, gsm.groups, st));
   STCHK(upload(h, &h->src_mm, src_mm, st));
   fill_W(gsm, W);
   STCHK(upload(h, &h->Wmm64, W, st));
-  std::vector<double2>().swap(W);
+  bigvec<double2>().swap(W);
   STCHK(upload(h, &h->IR64, IR, st));
-  std::vector<double2>().swap(IR);
+  bigvec<double2>().swap(IR);
   STCHK(upload(h, &h->ir_off, ir_off, st));
   STCHK(upload(h, &h->ir_ld, ir_ld, st));
   STCHK(upload(h, &h->ir_ncol, ir_ncol, st));
@@ -929,6 +944,23 @@ int build_device(hm_matrix* h, hipStream_t st) {
     h->term_wgs_auto = std::max(1, prop.multiProcessorCount * occ);
     h->term_wgs = h->term_wgs_auto;
   }
+  // ---- norm items: per instance (tree-order rows stay contiguous per
+  // instance), rows in chunks of kNormRows
+  {
+    std::vector<NormItem> items;
+    std::vector<int32_t> seg(1, 0);
+    const int ns = (int)h->inst_off.size() - 1;
+    if (ns < 1) { set_error("internal: no instance offsets"); return HM_EINVAL; }
+    for (int g = 0; g < ns; ++g) {
+      for (int64_t r = h->inst_off[g]; r < h->inst_off[g + 1]; r += kNormRows)
+        items.push_back({r, std::min(r + kNormRows, h->inst_off[g + 1])});
+      seg.push_back((int32_t)items.size());
+    }
+    h->nseg = ns;
+    h->n_norm_items = (int)items.size();
+    STCHK(upload(h, &h->norm_items, items, st));
+    STCHK(upload(h, &h->norm_seg, seg, st));
+  }
   STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
   return HM_OK;
@@ -994,6 +1026,19 @@ void fill_info(const hm_matrix* h, hm_info* out) {
 using namespace hm;
 
 // ====================================================================== C-ABI
+namespace hm {
+// Host allocation failures inside a build surface as HM_ENOMEM.
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    set_error("host memory exhausted during the build");
+    return HM_ENOMEM;
+  }
+}
+}  // namespace hm
+
 extern "C" {
 
 const char* hm_last_error(void) { return g_err.c_str(); }
@@ -1010,6 +1055,10 @@ const char* hm_strerror(int s) {
     case HM_ESTATE: return "invalid handle state";
     default: return "unknown status";
   }
+}
+
+static void report(const hm_build_opts* o, const std::string& msg) {
+  if (o->progress) o->progress(msg.c_str(), o->progress_user);
 }
 
 static Problem copy_problem(const hm_problem* prob) {
@@ -1040,9 +1089,11 @@ static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts
       return HM_EHIP;
     }
     HIPCHK(hipGetDevice(&h->device));
+    report(opts, "host build done, packing and uploading blocks");
     STCHK(build_device(h.get(), (hipStream_t)hip_stream));
+    report(opts, "device build done");
     if (!(opts->flags & HM_BUILD_KEEP_HOST)) {
-      std::vector<cplx>().swap(h->H.near_data);
+      bigvec<cplx>().swap(h->H.near_data);
       for (auto& lr : h->H.lowrank) {
         std::vector<cplx>().swap(lr.U);
         std::vector<cplx>().swap(lr.V);
@@ -1055,8 +1106,8 @@ static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts
   return HM_OK;
 }
 
-int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
-               hm_matrix_t* out) {
+static int hmat_build_impl(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
+                           hm_matrix_t* out) {
   if (!out) { set_error("null output handle"); return HM_EINVAL; }
   *out = nullptr;
   STCHK(validate_problem(prob, opts));
@@ -1067,8 +1118,9 @@ int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stre
   return finish_build(h, opts, hip_stream, t0, out);
 }
 
-int hmat_build_batched(const hm_problem* probs, int32_t count, const hm_build_opts* opts,
-                       void* hip_stream, hm_matrix_t* out) {
+static int hmat_build_batched_impl(const hm_problem* probs, int32_t count,
+                                   const hm_build_opts* opts, void* hip_stream,
+                                   hm_matrix_t* out) {
   if (!out) { set_error("null output handle"); return HM_EINVAL; }
   *out = nullptr;
   if (!probs || count < 1) { set_error("need count >= 1 problems"); return HM_EINVAL; }
@@ -1080,25 +1132,37 @@ int hmat_build_batched(const hm_problem* probs, int32_t count, const hm_build_op
   if (total > (int64_t)1 << 28) { set_error("total n too large"); return HM_EINVAL; }
   const auto t0 = std::chrono::steady_clock::now();
   std::unique_ptr<hm_matrix> h(new hm_matrix());
+  // instances one after another, each with the build's threads (the block
+  // loops inside an instance parallelise well; instances in parallel
+  // contend on the allocator and page faults)
   std::vector<HostH> parts(count);
-  std::vector<int> status(count, HM_OK);
-  std::vector<std::string> errs(count);
-  hm_build_opts inner = *opts;
-  inner.num_threads = 1;  // parallel over instances instead
-  const int nthreads = opts->num_threads > 0 ? opts->num_threads : omp_get_max_threads();
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+  int64_t done_n = 0;
   for (int32_t i = 0; i < count; ++i) {
-    status[i] = build_host(copy_problem(&probs[i]), inner, parts[i]);
-    if (status[i] != HM_OK) errs[i] = hm_last_error();
-  }
-  for (int32_t i = 0; i < count; ++i)
-    if (status[i] != HM_OK) {
-      set_error("instance " + std::to_string(i) + ": " + errs[i]);
-      return status[i];
+    const int st = build_host(copy_problem(&probs[i]), *opts, parts[i]);
+    if (st != HM_OK) {
+      set_error("instance " + std::to_string(i) + ": " + hm_last_error());
+      return st;
     }
+    done_n += probs[i].n;
+    if (i + 1 == count || (i + 1) % 32 == 0)
+      report(opts, "host blocks of " + std::to_string(i + 1) + " of " + std::to_string(count) +
+                       " instances (" + std::to_string(done_n) + " of " + std::to_string(total) +
+                       " points)");
+  }
   merge_hosts(parts, h->H, h->inst_off);
+  report(opts, "instances merged");
   h->ninst = count;
   return finish_build(h, opts, hip_stream, t0, out);
+}
+
+int hmat_build(const hm_problem* prob, const hm_build_opts* opts, void* hip_stream,
+               hm_matrix_t* out) {
+  return guarded([&] { return hmat_build_impl(prob, opts, hip_stream, out); });
+}
+
+int hmat_build_batched(const hm_problem* probs, int32_t count, const hm_build_opts* opts,
+                       void* hip_stream, hm_matrix_t* out) {
+  return guarded([&] { return hmat_build_batched_impl(probs, count, opts, hip_stream, out); });
 }
 
 int hmat_info(hm_matrix_t h, hm_info* out) {
@@ -1140,8 +1204,12 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   }
   if (o->K < 0 || o->K > 10000) { set_error("K must be in [0, 10000]"); return HM_EINVAL; }
   if (o->precision != HM_F64 && o->precision != HM_F32_APPLY) { set_error("bad precision"); return HM_EINVAL; }
-  if (o->kind != PS_SERIES && o->kind != PS_REFINE) { set_error("bad kind"); return HM_EINVAL; }
-  if (o->kind == PS_REFINE && (o->max_passes < 0 || !(o->refine_tol > 0))) {
+  if (o->kind != PS_SERIES && o->kind != PS_REFINE && o->kind != PS_REFINE_FIXED) {
+    set_error("bad kind");
+    return HM_EINVAL;
+  }
+  const bool refine = o->kind != PS_SERIES, adaptive = o->kind == PS_REFINE;
+  if (refine && (o->max_passes < 0 || !(o->refine_tol > 0))) {
     set_error("refinement needs max_passes >= 0 and refine_tol > 0");
     return HM_EINVAL;
   }
@@ -1154,14 +1222,16 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   STCHK(ensure_workspace(h, nrhs));
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t N = h->N, ldin = h->N + h->T;
-  const bool want = per_rhs != nullptr || o->kind == PS_REFINE;
+  const int ns = h->nseg;
+  // host reads of norms happen only with stats or adaptive refinement;
+  // otherwise the call only enqueues work (a stream capture can record it)
+  const bool want = per_rhs != nullptr || adaptive;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   if (per_rhs) {
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
   }
-  const bool refine = o->kind == PS_REFINE;
   if (refine) {
     HIPCHK(launch_permute_in((const double2*)b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
     STCHK(series_core(h, li, f32, o->K, h->bt, N, false, h->xt, nullptr, 0, nrhs, want, st));
@@ -1172,41 +1242,49 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   std::vector<double> growth(nrhs, 0.0), resid(nrhs, 0.0);
   std::vector<int> passes(nrhs, 0), done(nrhs, 0);
   auto read_norms = [&]() -> int {
-    HIPCHK(hipMemcpyAsync(h->norms_host, h->norms, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->norms_host, h->norms, sizeof(double) * 2 * ns * nrhs,
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return HM_OK;
   };
+  // max over instances of sqrt(slot 1 / slot 0) for column c
+  auto ratio = [&](int c) {
+    double r = 0.0;
+    for (int g = 0; g < ns; ++g) {
+      const double a = std::sqrt(h->norms_host[(int64_t)c * ns + g]);
+      const double b = std::sqrt(h->norms_host[(int64_t)(nrhs + c) * ns + g]);
+      const double q = (a > 0) ? b / a : (b > 0 ? INFINITY : 0.0);
+      if (!(q <= r)) r = q;  // keeps NaN / inf
+    }
+    return r;
+  };
   if (want) {
     STCHK(read_norms());
-    for (int c = 0; c < nrhs; ++c) {
-      const double n0 = std::sqrt(h->norms_host[c]), nk = std::sqrt(h->norms_host[nrhs + c]);
-      growth[c] = (n0 > 0) ? nk / n0 : (nk > 0 ? INFINITY : 0.0);
-    }
+    for (int c = 0; c < nrhs; ++c) growth[c] = ratio(c);
   }
-  if (o->kind == PS_REFINE) {
-    for (int pass = 1; pass <= o->max_passes; ++pass) {
-      // r = b - Z_l x in FP64 (all blocks including D)
-      HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
-      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, nullptr, 0, st));
-      // d = P_K r, x += d
-      STCHK(series_core(h, li, f32, o->K, h->rt, N, false, h->dt, nullptr, 0, nrhs, false, st));
-      HIPCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
-      HIPCHK(launch_norm2(h->dt, N, N, nrhs, h->nscratch, h->norms, st));
-      HIPCHK(launch_norm2(h->xt, N, N, nrhs, h->nscratch + kNormBlocks * nrhs, h->norms + nrhs, st));
-      STCHK(read_norms());
-      bool all = true;
-      for (int c = 0; c < nrhs; ++c) {
-        const double nd = std::sqrt(h->norms_host[c]), nx = std::sqrt(h->norms_host[nrhs + c]);
-        const double rel = nx > 0 ? nd / nx : (nd > 0 ? INFINITY : 0.0);
-        if (!done[c]) {
-          resid[c] = rel;
-          passes[c] = pass;
-          if (rel <= o->refine_tol) done[c] = 1;
-        }
-        all = all && done[c];
+  for (int pass = 1; refine && pass <= o->max_passes; ++pass) {
+    // r = b - Z_l x in FP64 (all blocks including D)
+    HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+    STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, nullptr, 0, st));
+    // d = P_K r, x += d
+    STCHK(series_core(h, li, f32, o->K, h->rt, N, false, h->dt, nullptr, 0, nrhs, false, st));
+    HIPCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
+    const bool check = adaptive || (per_rhs && pass == o->max_passes);
+    if (!check) continue;
+    HIPCHK(norms_into(h, h->xt, N, nrhs, 0, st));
+    HIPCHK(norms_into(h, h->dt, N, nrhs, 1, st));
+    STCHK(read_norms());
+    bool all = true;
+    for (int c = 0; c < nrhs; ++c) {
+      const double rel = ratio(c);  // max over instances of |d| / |x|
+      if (!done[c]) {
+        resid[c] = rel;
+        passes[c] = pass;
+        if (rel <= o->refine_tol) done[c] = 1;
       }
-      if (all) break;
+      all = all && done[c];
     }
+    if (adaptive && all) break;
   }
   if (refine) HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
   int status = HM_OK;
@@ -1223,8 +1301,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
       s.growth = growth[c];
       s.resid_rel = resid[c];
       s.t_ms = ms;
-      const bool bad = !(growth[c] <= 1.0) ||
-                       (o->kind == PS_REFINE && !(resid[c] <= o->refine_tol));
+      const bool bad = !(growth[c] <= 1.0) || (refine && !(resid[c] <= o->refine_tol));
       s.diverged = bad ? 1 : 0;
       if (bad) status = HM_EDIVERGED;
     }
@@ -1250,12 +1327,16 @@ int hmat_export(hm_matrix_t h, const char* path) {
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
   if (!h || !t) { set_error("null argument"); return HM_EINVAL; }
   if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
-  if (t->mm_min_rhs < -1 || t->term_wgs < -1 || t->term_wgs > (1 << 20)) {
+  if (t->mm_min_rhs < -1 || t->term_wgs < -1 || t->term_wgs > (1 << 20) ||
+      !(t->rhs_tile == -1 || t->rhs_tile == 0 || t->rhs_tile == 16 || t->rhs_tile == 32 ||
+        t->rhs_tile == 64)) {
     set_error("bad tuning values");
     return HM_EINVAL;
   }
   if (t->mm_min_rhs > 0) h->mm_min_rhs = t->mm_min_rhs;
   if (t->mm_min_rhs == -1) h->mm_min_rhs = 8;
+  if (t->rhs_tile > 0) h->rhs_tile = t->rhs_tile;
+  if (t->rhs_tile == -1) h->rhs_tile = 0;
   int wgs = h->term_wgs;
   if (t->term_wgs > 0) wgs = t->term_wgs;
   if (t->term_wgs == -1) wgs = h->term_wgs_auto;
@@ -1271,6 +1352,82 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out) {
   if (!h || !out) { set_error("null argument"); return HM_EINVAL; }
   out->mm_min_rhs = h->mm_min_rhs;
   out->term_wgs = h->term_wgs;
+  out->rhs_tile = h->rhs_tile;
+  return HM_OK;
+}
+
+// Times ps_solve (series kind) for every candidate tuning on zero vectors
+// of nrhs columns and keeps the fastest (median of 5 timed calls after 2).
+int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_stream,
+                  hm_tuning* best, double* best_ms) {
+  if (!h || !opts || nrhs < 1) { set_error("null argument or nrhs < 1"); return HM_EINVAL; }
+  if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
+  HIPCHK(hipSetDevice(h->device));
+  hipStream_t st = (hipStream_t)hip_stream;
+  ps_opts o = *opts;
+  o.kind = PS_SERIES;
+  void *b = nullptr, *x = nullptr;
+  const size_t bytes = sizeof(double2) * (size_t)h->N * nrhs;
+  HIPCHK(hipMalloc(&b, bytes));
+  if (hipMalloc(&x, bytes) != hipSuccess) { (void)hipFree(b); set_error("hipMalloc failed"); return HM_ENOMEM; }
+  struct Buf { void *b, *x; ~Buf() { (void)hipFree(b); (void)hipFree(x); } } bufs{b, x};
+  HIPCHK(hipMemsetAsync(b, 0, bytes, st));
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  struct Ev { hipEvent_t a, b; ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); } } evs{e0, e1};
+  auto time_one = [&](double* ms) -> int {
+    for (int r = 0; r < 2; ++r) STCHK(ps_solve(h, &o, b, h->N, x, h->N, nrhs, nullptr, st));
+    std::vector<double> t;
+    for (int r = 0; r < 5; ++r) {
+      HIPCHK(hipEventRecord(e0, st));
+      STCHK(ps_solve(h, &o, b, h->N, x, h->N, nrhs, nullptr, st));
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float f = 0;
+      HIPCHK(hipEventElapsedTime(&f, e0, e1));
+      t.push_back(f);
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return HM_OK;
+  };
+  const int autow = h->term_wgs_auto;
+  std::vector<int> wgs = {autow, std::max(1, autow / 2), 2 * autow, 4 * autow};
+  struct Cand { int mm_min, tile; };
+  std::vector<Cand> paths = {{1 << 30, 0}};  // streaming kernels
+  if (nrhs >= 2) {
+    paths.push_back({1, 16});
+    if (nrhs > 16) paths.push_back({1, 32});
+    if (nrhs > 32) paths.push_back({1, 64});
+  }
+  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile};
+  double bms = INFINITY;
+  for (int w : wgs) {
+    if (w != h->term_wgs) {
+      h->term_wgs = w;
+      STCHK(build_lists(h, st));
+    }
+    for (const Cand& c : paths) {
+      h->mm_min_rhs = c.mm_min;
+      h->rhs_tile = c.tile;
+      double ms = 0;
+      STCHK(time_one(&ms));
+      if (ms < bms) {
+        bms = ms;
+        bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile};
+      }
+    }
+  }
+  h->mm_min_rhs = bt.mm_min_rhs;
+  h->rhs_tile = bt.rhs_tile;
+  if (h->term_wgs != bt.term_wgs) {
+    h->term_wgs = bt.term_wgs;
+    STCHK(build_lists(h, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (best) *best = bt;
+  if (best_ms) *best_ms = bms;
   return HM_OK;
 }
 

@@ -2,9 +2,15 @@
 // the solver driver.  Not part of the C-ABI.
 #pragma once
 
+#include <sys/mman.h>
+
 #include <complex>
 #include <cstdint>
+#include <cstdlib>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "hmps.h"
@@ -12,6 +18,62 @@
 namespace hm {
 
 using cplx = std::complex<double>;
+
+// Allocator for large host arrays (blocks, panels): zeroed storage (calloc,
+// or 2 MiB-aligned anonymous mappings from 8 MiB on) whose elements are not
+// stored to on value initialisation, so that the parallel fills are the
+// first touch of the pages (a serial zero fill of tens of GB would dominate
+// the build of large batches).
+template <typename T>
+struct BigAlloc {
+  using value_type = T;
+  static constexpr size_t kBig = (size_t)8 << 20, kHuge = (size_t)2 << 20, kPage = 4096;
+  BigAlloc() = default;
+  template <typename U>
+  BigAlloc(const BigAlloc<U>&) {}
+  static size_t mapped(size_t bytes) { return (bytes + kPage - 1) / kPage * kPage; }
+  T* allocate(size_t n) {
+    const size_t bytes = n * sizeof(T);
+    if (bytes < kBig) {
+      void* p = std::calloc(bytes ? bytes : 1, 1);
+      if (!p) throw std::bad_alloc();
+      return static_cast<T*>(p);
+    }
+    const size_t len = mapped(bytes);
+    void* raw = mmap(nullptr, len + kHuge, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    if (raw == MAP_FAILED) throw std::bad_alloc();
+    const uintptr_t r = reinterpret_cast<uintptr_t>(raw);
+    const uintptr_t a = (r + kHuge - 1) / kHuge * kHuge;
+    if (a > r) munmap(raw, a - r);
+    if (r + len + kHuge > a + len) munmap(reinterpret_cast<void*>(a + len), r + len + kHuge - (a + len));
+    return reinterpret_cast<T*>(a);
+  }
+  void deallocate(T* p, size_t n) {
+    const size_t bytes = n * sizeof(T);
+    if (bytes < kBig)
+      std::free(p);
+    else
+      munmap(p, mapped(bytes));
+  }
+  // Storage comes zeroed (calloc or fresh anonymous pages), so value
+  // initialisation (zero for the arithmetic and complex types stored here)
+  // needs no store: large arrays are first touched by the parallel fills.
+  template <typename U>
+  void construct(U* p) noexcept {
+    static_assert(std::is_trivially_copyable<U>::value, "BigAlloc holds plain values");
+    (void)p;
+  }
+  template <typename U, typename... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+  template <typename U>
+  bool operator==(const BigAlloc<U>&) const { return true; }
+  template <typename U>
+  bool operator!=(const BigAlloc<U>&) const { return false; }
+};
+template <typename T>
+using bigvec = std::vector<T, BigAlloc<T>>;
 
 // ---------------------------------------------------------------- errors
 void set_error(const std::string& msg);
@@ -92,7 +154,7 @@ struct HostH {
   double eta = 1, tol = 1e-4;
   std::vector<int32_t> leaf_off, leaf_size;      // per leaf
   std::vector<NearBlock> near;                   // incl. diagonal, sorted by (t, s)
-  std::vector<cplx> near_data;
+  bigvec<cplx> near_data;
   std::vector<LowRank> lowrank;                  // compressed (t before s) blocks
   std::vector<FarBlock> far;                     // both orientations
   std::vector<double> chi_tree;                  // volume: chi in tree order

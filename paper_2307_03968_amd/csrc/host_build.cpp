@@ -50,7 +50,7 @@ int build_host(const Problem& p, const hm_build_opts& o, HostH& H) {
     nb.data = tot;
     tot += (int64_t)H.leaf_size[nb.t_leaf] * H.leaf_size[nb.s_leaf];
   }
-  H.near_data.assign(tot, cplx(0));
+  H.near_data = bigvec<cplx>((size_t)tot);  // zeroed; every block is written below
   std::atomic<int> bad{0};
   const int nthreads = o.num_threads > 0 ? o.num_threads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
@@ -141,6 +141,9 @@ void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst
   H.prob.kind = parts.empty() ? HM_SURFACE : parts[0].prob.kind;
   H.tree.depth = kTopLevel;
   H.min_far_level = -1;
+  size_t near_total = 0;
+  for (auto& P : parts) near_total += P.near_data.size();
+  H.near_data.reserve(near_total);
   for (size_t i = 0; i < parts.size(); ++i) {
     HostH& P = parts[i];
     inst_off[i] = n;

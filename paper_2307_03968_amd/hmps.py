@@ -25,7 +25,7 @@ HM_OK, HM_ENOTREADY, HM_EDIVERGED = 0, 1, 2
 HM_EINVAL, HM_ENOMEM, HM_EHIP, HM_EBUSY, HM_ESTATE = -1, -2, -3, -4, -5
 HM_SURFACE, HM_VOLUME = 0, 1
 HM_F64, HM_F32_APPLY = 0, 1
-PS_SERIES, PS_REFINE = 0, 1
+PS_SERIES, PS_REFINE, PS_REFINE_FIXED = 0, 1, 2
 HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST = 0x1, 0x2, 0x4
 HM_MAX_LEVELS = 32
 
@@ -35,9 +35,13 @@ class hm_problem(C.Structure):
                 ("k", C.c_double), ("h", C.c_double), ("chi", C.POINTER(C.c_double))]
 
 
+PROGRESS_FN = C.CFUNCTYPE(None, C.c_char_p, C.c_void_p)
+
+
 class hm_build_opts(C.Structure):
     _fields_ = [("leaf_max", C.c_int32), ("eta", C.c_double), ("aca_tol", C.c_double),
-                ("max_rank", C.c_int32), ("flags", C.c_uint32), ("num_threads", C.c_int32)]
+                ("max_rank", C.c_int32), ("flags", C.c_uint32), ("num_threads", C.c_int32),
+                ("progress", PROGRESS_FN), ("progress_user", C.c_void_p)]
 
 
 class ps_opts(C.Structure):
@@ -51,7 +55,7 @@ class ps_stats(C.Structure):
 
 
 class hm_tuning(C.Structure):
-    _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32)]
+    _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32), ("rhs_tile", C.c_int32)]
 
 
 class hm_info(C.Structure):
@@ -107,12 +111,14 @@ def _lib():
         lib.hm_profile_read.argtypes = [vp, C.POINTER(hm_kernel_time)]
         lib.hmat_tune.argtypes = [vp, C.POINTER(hm_tuning), vp]
         lib.hmat_get_tuning.argtypes = [vp, C.POINTER(hm_tuning)]
+        lib.hmat_autotune.argtypes = [vp, C.POINTER(ps_opts), i32, vp, C.POINTER(hm_tuning),
+                                      C.POINTER(C.c_double)]
         lib.hm_strerror.argtypes = [C.c_int]
         lib.hm_strerror.restype = C.c_char_p
         lib.hm_last_error.restype = C.c_char_p
         for f in ("hmat_build", "hmat_build_batched", "hmat_info", "hmat_apply", "ps_solve",
                   "hmat_export", "hmat_free", "hm_profile_enable", "hm_profile_read", "hmat_tune",
-                  "hmat_get_tuning"):
+                  "hmat_get_tuning", "hmat_autotune"):
             getattr(lib, f).restype = C.c_int
         _LIB = lib
     return _LIB
@@ -151,9 +157,11 @@ class HMatrix:
     """Owning wrapper of an hm_matrix_t."""
 
     def __init__(self, prob, leaf_max: int, eta: float = 1.0, aca_tol: float = 1e-4,
-                 max_rank: int = 0, flags: int = 0, num_threads: int = 0, stream=None):
+                 max_rank: int = 0, flags: int = 0, num_threads: int = 0, stream=None,
+                 progress=None):
         """``prob``: one problem, or a list of problems for a batched handle
-        (hmat_build_batched)."""
+        (hmat_build_batched).  ``progress``: optional callable taking the
+        build's progress messages (str)."""
         lib = _lib()
         probs = list(prob) if isinstance(prob, (list, tuple)) else [prob]
         keep = []
@@ -165,8 +173,9 @@ class HMatrix:
             arr[i] = hm_problem(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), int(p.kind),
                                 float(p.k), float(p.h),
                                 chi.ctypes.data_as(C.POINTER(C.c_double)) if chi is not None else None)
+        cb = PROGRESS_FN(lambda msg, _u: progress(msg.decode())) if progress else PROGRESS_FN()
         o = hm_build_opts(int(leaf_max), float(eta), float(aca_tol), int(max_rank), int(flags),
-                          int(num_threads))
+                          int(num_threads), cb, None)
         self.host_only = bool(flags & HM_BUILD_HOST_ONLY)
         st = C.c_void_p(None) if self.host_only else _stream(stream)
         h = C.c_void_p()
@@ -207,15 +216,25 @@ class HMatrix:
                     for lev in range(HM_MAX_LEVELS) if i.far_blocks[lev]}
         return d
 
-    def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, stream=None) -> None:
+    def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, rhs_tile: int = 0, stream=None) -> None:
         """hmat_tune: 0 keeps a value, -1 restores its default."""
-        t = hm_tuning(int(mm_min_rhs), int(term_wgs))
+        t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile))
         _check(_lib().hmat_tune(self._h, C.byref(t), _stream(stream)), "hmat_tune")
 
     def tuning(self) -> dict:
         t = hm_tuning()
         _check(_lib().hmat_get_tuning(self._h, C.byref(t)), "hmat_get_tuning")
-        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs}
+        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile}
+
+    def autotune(self, nrhs: int, K: int, level: int = -1, precision: int = HM_F64,
+                 stream=None):
+        """hmat_autotune: returns (tuning dict, ms per solve of the choice)."""
+        o = ps_opts(int(K), int(level), int(precision), PS_SERIES, 0, 1e-9)
+        t = hm_tuning()
+        ms = C.c_double()
+        _check(_lib().hmat_autotune(self._h, C.byref(o), int(nrhs), _stream(stream), C.byref(t),
+                                    C.byref(ms)), "hmat_autotune")
+        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile}, ms.value
 
     def export(self, path: str) -> None:
         _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")

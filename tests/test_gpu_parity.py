@@ -369,3 +369,86 @@ def test_retuned_work_lists_same_result(many_rhs):
         c.h.tune(term_wgs=-1)
     assert c.h.tuning()["term_wgs"] == default
     assert np.array_equal(_host(c.h.solve(b, K=4)), x0)
+
+
+# ---------------------------------------------------------------- refinement, graphs, tuning
+def test_refine_fixed_matches_adaptive(sphere):
+    """PS_REFINE_FIXED with the pass count adaptive refinement needed gives
+    the same x, bit for bit (same kernels, same order)."""
+    b = _dev(sphere.b)
+    _say("adaptive refine sphere_1536 f32")
+    x1, st = sphere.h.solve(b, K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE,
+                            max_passes=200, refine_tol=1e-10, stats=True)
+    p = st[0]["passes"]
+    _say(f"fixed refine passes={p}")
+    x2, st2 = sphere.h.solve(b, K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE_FIXED,
+                             max_passes=p, refine_tol=1e-10, stats=True)
+    assert np.array_equal(_host(x1), _host(x2))
+    assert st2[0]["passes"] == p and st2[0]["diverged"] == 0
+    assert st2[0]["resid_rel"] == st[0]["resid_rel"]
+
+
+def test_batched_refine_each_instance_reaches_xstar():
+    """Refinement on a batched handle stops on the per-instance criterion:
+    every instance reaches its own x* = Z_l^{-1} b to 1e-8 (FP32 blocks)."""
+    probs = [W.sphere_problem(n, math.sqrt(n / 1536), instance=i)
+             for i, n in enumerate((700, 1100, 300))]
+    h = hmps.HMatrix(probs, 64, 1.0, 1e-4)
+    Hs = [hmatrix.HMatrix(p, 64, 1.0, 1e-4) for p in probs]
+    bs = [W.plane_waves(p.xyz, W.directions(2, 3, instance=i)) for i, p in enumerate(probs)]
+    for H in Hs:
+        assert series.rho(H) ** 5 < 1
+    _say("batched refine 3 instances f32")
+    x, st = h.solve(_dev(np.vstack(bs)), K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE,
+                    max_passes=300, refine_tol=1e-11, stats=True)
+    x = _host(x)
+    for i, H in enumerate(Hs):
+        o0, o1 = h.offsets[i], h.offsets[i + 1]
+        assert series.rel_err(x[o0:o1], series.solve_exact(H, bs[i])) <= TOL_REFINE, i
+    assert all(s["diverged"] == 0 for s in st)
+    h.close()
+
+
+def test_graph_replay_matches_eager(sphere, many_rhs):
+    """ps_solve recorded by stream capture (series on the streaming and the
+    MFMA kernels, fixed-pass refinement) and replayed several times, with
+    eager work and synchronisation between replays: every replay equals the
+    eager result bit for bit."""
+    c, B = many_rhs
+    cases = [(sphere.h, _dev(sphere.b), dict(K=4)),
+             (c.h, _dev(B[:, :16]), dict(K=3, precision=hmps.HM_F32_APPLY)),
+             (sphere.h, _dev(sphere.b), dict(K=4, precision=hmps.HM_F32_APPLY,
+                                            kind=hmps.PS_REFINE_FIXED, max_passes=6))]
+    for h, b, kw in cases:
+        _say(f"graph capture {kw}")
+        ref = _host(h.solve(b, **kw))
+        out = torch.empty_like(b.t().contiguous() if b.dim() == 2 else b.reshape(1, -1))
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            h.solve(b, out=out, **kw)  # sizes the workspace before capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            h.solve(b, out=out, **kw)
+        for rep in range(3):
+            out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            got = out.reshape(-1).cpu().numpy() if b.dim() == 1 else out.t().cpu().numpy()
+            assert np.array_equal(got, ref), rep
+            _host(h.solve(b, **kw))  # eager work between replays
+        del g
+
+
+def test_autotune_choice_keeps_results(many_rhs):
+    c, B = many_rhs
+    b = _dev(B[:, :20])
+    ref = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
+    _say("autotune nrhs=20 f32")
+    best, ms = c.h.autotune(20, K=3, precision=hmps.HM_F32_APPLY)
+    assert ms > 0 and c.h.tuning() == best
+    x = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
+    assert series.rel_err(x, ref) <= 1e-5
+    c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1)
