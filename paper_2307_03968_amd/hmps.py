@@ -128,7 +128,7 @@ def header_functions():
     """Names of the functions include/hmps.h declares."""
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+(?:\s+|\s*\*+\s*)(\w+)\s*\(", txt, flags=re.M)))
 
 
 def _check(status: int, what: str, allow=(HM_OK,)):
