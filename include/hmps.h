@@ -133,7 +133,11 @@ typedef struct {
                            refinement kinds) last ||d|| > refine_tol ||x||  */
   double resid_rel;     /* refinement: last ||d|| / ||x||; else 0          */
   double growth;        /* ||y_K|| / ||y_0|| of the (last) series           */
-  double t_ms;          /* wall time of the whole call (same for all RHS)   */
+  double t_ms;          /* wall time of the whole call (same for all RHS);
+                           server tickets: submit to done                  */
+  int32_t built;        /* server tickets: 1 if the request's batch had to
+                           build its geometry (cold), else 0               */
+  int32_t reserved_;
 } ps_stats;
 
 #define HM_MAX_LEVELS 32
@@ -267,6 +271,47 @@ int hm_profile_read(hm_matrix_t h, hm_kernel_time* out);
 
 /* Release the handle and all its device memory (synchronises the device). */
 int hmat_free(hm_matrix_t h);
+
+/* ---- request server (continuous batching) ----------------------------------
+ * A server owns worker threads, one HIP stream each (max_slots), and a cache
+ * of device-resident geometries (trees, LU factors, blocks) under an HBM
+ * budget.  ps_submit queues a solve of nrhs (1..64) right-hand sides on the
+ * geometry geom_key; the first submit of a key must give its problem and
+ * build options (both copied; later submits may pass NULL).  b_host (n x
+ * nrhs complex128, column-major, original order) is copied, so the caller
+ * may reuse it at once.  A free worker takes the oldest queued request
+ * whose geometry is not in use and every later queued request of the same
+ * geometry and options up to 64 right-hand sides in all, and solves them as
+ * one ps_solve; batches of different geometries run at the same time on
+ * different streams, and requests that arrive meanwhile join the next
+ * batch of their geometry.  A geometry is built on its first batch and
+ * kept; to admit a build, least recently used geometries without queued
+ * or running requests are freed until blocks plus workspaces fit the
+ * budget (a geometry that cannot fit an idle device fails with HM_ENOMEM).
+ * Results: ps_poll returns HM_ENOTREADY while the ticket is queued or
+ * running; once it is done (or failed) it copies x (n x nrhs, original
+ * order) to x_host and the per-RHS statistics (t_ms = submit-to-done
+ * latency) to per_rhs, when non-null, and releases the ticket (a later poll
+ * of it is HM_EINVAL).  Server calls are thread-safe.  hbm_budget_bytes 0
+ * means 90% of the device memory free at creation. */
+typedef struct hm_server* hm_server_t;
+typedef uint64_t hm_ticket_t;
+enum { PS_QUEUED = 0, PS_RUNNING = 1, PS_DONE = 2, PS_FAILED = 3 };
+typedef struct {
+  int64_t budget_bytes, resident_bytes, resident_geometries;
+  int64_t builds, evictions;         /* geometry builds (incl. rebuilds)    */
+  int64_t batches, batch_rhs;        /* solves issued and their columns     */
+  int64_t requests_submitted, requests_done, requests_failed, rhs_done;
+  int64_t queued;
+} ps_server_stats;
+int ps_server_create(size_t hbm_budget_bytes, int32_t max_slots, hm_server_t* out);
+int ps_submit(hm_server_t s, uint64_t geom_key, const hm_problem* prob,
+              const hm_build_opts* build_opts, const ps_opts* opts, const void* b_host,
+              int32_t nrhs, hm_ticket_t* out);
+int ps_poll(hm_server_t s, hm_ticket_t ticket, void* x_host, ps_stats* per_rhs, int32_t* state);
+int ps_server_info(hm_server_t s, ps_server_stats* out);
+/* Waits for running batches, fails queued tickets, frees every geometry. */
+int ps_server_destroy(hm_server_t s);
 
 /* ---- errors ----------------------------------------------------------------- */
 const char* hm_strerror(int status);

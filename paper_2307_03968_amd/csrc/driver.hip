@@ -126,6 +126,7 @@ struct hm_matrix {
   int32_t* counters = nullptr;  // workspace
   // workspace
   int ws_nrhs = 0;
+  int64_t ws_bytes = 0;
   double2 *xin0 = nullptr, *xin1 = nullptr, *xt = nullptr, *bt = nullptr, *rt = nullptr,
           *dt = nullptr, *partial = nullptr;
   double *nscratch = nullptr, *norms = nullptr;
@@ -297,6 +298,7 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   for (void* p : h->ws_allocs) (void)hipFree(p);
   h->ws_allocs.clear();
   h->ws_nrhs = 0;
+  h->ws_bytes = 0;
   const int64_t ldin = h->N + h->T;
   auto al = [&](void** p, size_t bytes) -> int {
     hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
@@ -306,6 +308,7 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
       return HM_ENOMEM;
     }
     h->ws_allocs.push_back(*p);
+    h->ws_bytes += (int64_t)std::max<size_t>(bytes, 16);
     return HM_OK;
   };
   STCHK(al((void**)&h->xin0, sizeof(double2) * ldin * nrhs));
@@ -1073,8 +1076,8 @@ static Problem copy_problem(const hm_problem* prob) {
 }
 
 // Device part of a build, shared by the single and batched builds.
-static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts, void* hip_stream,
-                        std::chrono::steady_clock::time_point t0, hm_matrix_t* out) {
+// Fields derived from the host part, then the device part of a build.
+static void prepare_fields(hm_matrix* h, const hm_build_opts* opts) {
   h->N = h->H.prob.n;
   h->nl = (int)h->H.leaf_size.size();
   h->max_m = h->H.max_leaf;
@@ -1082,25 +1085,33 @@ static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts
   h->lmin = h->H.min_far_level;
   h->host_only = (opts->flags & HM_BUILD_HOST_ONLY) != 0;
   h->has_f32 = (opts->flags & HM_BUILD_NO_F32) == 0;
-  if (!h->host_only) {
-    std::string arch;
-    if (!check_arch(&arch)) {
-      set_error("no usable gfx950 device (found '" + arch + "')");
-      return HM_EHIP;
-    }
-    HIPCHK(hipGetDevice(&h->device));
-    report(opts, "host build done, packing and uploading blocks");
-    STCHK(build_device(h.get(), (hipStream_t)hip_stream));
-    report(opts, "device build done");
-    if (!(opts->flags & HM_BUILD_KEEP_HOST)) {
-      bigvec<cplx>().swap(h->H.near_data);
-      for (auto& lr : h->H.lowrank) {
-        std::vector<cplx>().swap(lr.U);
-        std::vector<cplx>().swap(lr.V);
-      }
-      h->host_kept = false;
-    }
+}
+
+static int device_part(hm_matrix* h, const hm_build_opts* opts, void* hip_stream) {
+  std::string arch;
+  if (!check_arch(&arch)) {
+    set_error("no usable gfx950 device (found '" + arch + "')");
+    return HM_EHIP;
   }
+  HIPCHK(hipGetDevice(&h->device));
+  report(opts, "host build done, packing and uploading blocks");
+  STCHK(build_device(h, (hipStream_t)hip_stream));
+  report(opts, "device build done");
+  if (!(opts->flags & HM_BUILD_KEEP_HOST)) {
+    bigvec<cplx>().swap(h->H.near_data);
+    for (auto& lr : h->H.lowrank) {
+      std::vector<cplx>().swap(lr.U);
+      std::vector<cplx>().swap(lr.V);
+    }
+    h->host_kept = false;
+  }
+  return HM_OK;
+}
+
+static int finish_build(std::unique_ptr<hm_matrix>& h, const hm_build_opts* opts, void* hip_stream,
+                        std::chrono::steady_clock::time_point t0, hm_matrix_t* out) {
+  prepare_fields(h.get(), opts);
+  if (!h->host_only) STCHK(device_part(h.get(), opts, hip_stream));
   h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h.release();
   return HM_OK;
@@ -1466,3 +1477,75 @@ int hmat_free(hm_matrix_t h) {
 }
 
 }  // extern "C"
+
+namespace hm {
+
+int build_host_phase(const hm_problem* prob, const hm_build_opts* opts, hm_matrix_t* out) {
+  return guarded([&]() -> int {
+    if (!out) { set_error("null output handle"); return HM_EINVAL; }
+    *out = nullptr;
+    STCHK(validate_problem(prob, opts));
+    std::unique_ptr<hm_matrix> h(new hm_matrix());
+    const auto t0 = std::chrono::steady_clock::now();
+    STCHK(build_host(copy_problem(prob), *opts, h->H));
+    h->inst_off = {0, prob->n};
+    hm_build_opts o = *opts;
+    o.flags &= ~HM_BUILD_HOST_ONLY;
+    prepare_fields(h.get(), &o);
+    h->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = h.release();
+    return HM_OK;
+  });
+}
+
+int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_stream) {
+  return guarded([&]() -> int {
+    const auto t0 = std::chrono::steady_clock::now();
+    STCHK(device_part(h, opts, hip_stream));
+    h->build_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return HM_OK;
+  });
+}
+
+// Device bytes the device part of the build will allocate (panels FP64 and
+// FP32, D^{-1}-premultiplied panels, LU and D^{-1}, stage-A W copies for both
+// kernel families, in-row stacks), plus the workspace for nrhs right-hand
+// sides; from block sizes only, to within a few percent.
+int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
+  const HostH& H = h->H;
+  int64_t P = 0, Dm = 0, Wn = 0, T = 0;
+  for (const NearBlock& nb : H.near) {
+    const int64_t m = even_ld(H.leaf_size[nb.t_leaf]);
+    P += m * H.leaf_size[nb.s_leaf];
+    if (nb.t_leaf == nb.s_leaf) Dm += (int64_t)H.leaf_size[nb.t_leaf] * H.leaf_size[nb.t_leaf];
+  }
+  for (const FarBlock& fb : H.far) {
+    const int64_t r = H.lowrank[fb.src].r;
+    P += r * fb.m;
+    Wn += r * fb.n;
+    T += r;
+  }
+  const int64_t f32 = h->has_f32 ? 1 : 0;
+  const int64_t bytes =
+      16 * (P + (P - Dm)) + 32 * Dm + 2 * 16 * Wn + f32 * (8 * (2 * P - Dm) + 2 * 8 * Wn);
+  return bytes + workspace_bytes(h, nrhs, T);
+}
+
+// Workspace of ensure_workspace for nrhs right-hand sides (t rows T when
+// the device part is not built yet, else the handle's own).
+int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T) {
+  if (h->device >= 0) T = h->T;
+  const int64_t partial = h->partial_rows > 0 ? h->partial_rows
+                                              : 2 * h->N + (int64_t)h->term_wgs * h->max_m;
+  const int64_t items = h->n_norm_items > 0 ? h->n_norm_items : h->N / kNormRows + 1;
+  return (int64_t)nrhs * (16 * (2 * (h->N + T) + 4 * h->N + partial) + 16 * (items + h->nseg) +
+                          4 * (int64_t)h->nl);
+}
+
+int workspace_rhs(hm_matrix_t h) { return h->ws_nrhs; }
+
+int64_t resident_bytes(hm_matrix_t h) { return h->bytes + h->ws_bytes; }
+
+int64_t matrix_n(hm_matrix_t h) { return h->N; }
+
+}  // namespace hm

@@ -174,6 +174,18 @@ constexpr int32_t kTopLevel = HM_MAX_LEVELS - 1;
 // order).  parts are consumed.
 void merge_hosts(std::vector<HostH>& parts, HostH& out, std::vector<int64_t>& inst_off);
 
+// Two-phase build for the request server: the host part (tree, partition,
+// blocks) into a handle without device data, an estimate of the device bytes
+// the device part will allocate (workspace for nrhs right-hand sides
+// included), then the device part on a stream.
+int build_host_phase(const hm_problem* prob, const hm_build_opts* opts, hm_matrix_t* out);
+int64_t device_bytes_estimate(hm_matrix_t h, int nrhs);
+int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_stream);
+int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T);
+int workspace_rhs(hm_matrix_t h);        // right-hand sides the workspace holds
+int64_t resident_bytes(hm_matrix_t h);  // device blocks + workspace
+int64_t matrix_n(hm_matrix_t h);
+
 // Export helper (binary named arrays).
 int export_host(const HostH& H, const char* path, const std::vector<cplx>* lu_host,
                 const std::vector<int32_t>* piv_host);

@@ -51,7 +51,18 @@ class ps_opts(C.Structure):
 
 class ps_stats(C.Structure):
     _fields_ = [("passes", C.c_int32), ("diverged", C.c_int32), ("resid_rel", C.c_double),
-                ("growth", C.c_double), ("t_ms", C.c_double)]
+                ("growth", C.c_double), ("t_ms", C.c_double), ("built", C.c_int32),
+                ("reserved_", C.c_int32)]
+
+
+PS_QUEUED, PS_RUNNING, PS_DONE, PS_FAILED = 0, 1, 2, 3
+
+
+class ps_server_stats(C.Structure):
+    _fields_ = [(k, C.c_int64) for k in (
+        "budget_bytes", "resident_bytes", "resident_geometries", "builds", "evictions", "batches",
+        "batch_rhs", "requests_submitted", "requests_done", "requests_failed", "rhs_done",
+        "queued")]
 
 
 class hm_tuning(C.Structure):
@@ -113,12 +124,19 @@ def _lib():
         lib.hmat_get_tuning.argtypes = [vp, C.POINTER(hm_tuning)]
         lib.hmat_autotune.argtypes = [vp, C.POINTER(ps_opts), i32, vp, C.POINTER(hm_tuning),
                                       C.POINTER(C.c_double)]
+        lib.ps_server_create.argtypes = [C.c_size_t, i32, C.POINTER(vp)]
+        lib.ps_submit.argtypes = [vp, C.c_uint64, C.POINTER(hm_problem), C.POINTER(hm_build_opts),
+                                  C.POINTER(ps_opts), vp, i32, C.POINTER(C.c_uint64)]
+        lib.ps_poll.argtypes = [vp, C.c_uint64, vp, C.POINTER(ps_stats), C.POINTER(i32)]
+        lib.ps_server_info.argtypes = [vp, C.POINTER(ps_server_stats)]
+        lib.ps_server_destroy.argtypes = [vp]
         lib.hm_strerror.argtypes = [C.c_int]
         lib.hm_strerror.restype = C.c_char_p
         lib.hm_last_error.restype = C.c_char_p
         for f in ("hmat_build", "hmat_build_batched", "hmat_info", "hmat_apply", "ps_solve",
                   "hmat_export", "hmat_free", "hm_profile_enable", "hm_profile_read", "hmat_tune",
-                  "hmat_get_tuning", "hmat_autotune"):
+                  "hmat_get_tuning", "hmat_autotune", "ps_server_create", "ps_submit", "ps_poll",
+                  "ps_server_info", "ps_server_destroy"):
             getattr(lib, f).restype = C.c_int
         _LIB = lib
     return _LIB
@@ -289,3 +307,88 @@ def read_export(path: str) -> Dict[str, np.ndarray]:
             cnt = int(np.prod(shape)) if shape else 1
             out[name] = np.frombuffer(f.read(cnt * dtype.itemsize), dtype).reshape(shape)
     return out
+
+
+def _problem_struct(p):
+    """hm_problem for a workloads.Problem; returns (struct, arrays to keep alive)."""
+    xyz = np.ascontiguousarray(p.xyz, dtype=np.float64)
+    chi = None if p.chi is None else np.ascontiguousarray(p.chi, dtype=np.float64)
+    st = hm_problem(xyz.shape[0], xyz.ctypes.data_as(C.POINTER(C.c_double)), int(p.kind),
+                    float(p.k), float(p.h),
+                    chi.ctypes.data_as(C.POINTER(C.c_double)) if chi is not None else None)
+    return st, (xyz, chi)
+
+
+class Server:
+    """Owning wrapper of an hm_server_t (ps_server_create ... ps_server_destroy)."""
+
+    def __init__(self, budget_bytes: int = 0, slots: int = 2):
+        s = C.c_void_p()
+        _check(_lib().ps_server_create(int(budget_bytes), int(slots), C.byref(s)), "ps_server_create")
+        self._s = s
+        self._shape = {}
+        self._n = {}
+
+    def submit(self, key: int, b: np.ndarray, K: int, level: int = -1, precision: int = HM_F64,
+               kind: int = PS_SERIES, max_passes: int = 0, refine_tol: float = 1e-9, prob=None,
+               leaf_max: int = 64, eta: float = 1.0, aca_tol: float = 1e-4) -> int:
+        """Queue a solve of b (n x nrhs or n, complex128, original order) on
+        geometry `key`; `prob` is required the first time a key is used."""
+        b = np.asarray(b, dtype=np.complex128)
+        nrhs = 1 if b.ndim == 1 else b.shape[1]
+        bc = np.asfortranarray(b.reshape(b.shape[0], nrhs))
+        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol))
+        pp = bo = None
+        if prob is not None:
+            pst, keep = _problem_struct(prob)
+            pp = C.byref(pst)
+            bo = C.byref(hm_build_opts(int(leaf_max), float(eta), float(aca_tol), 0, 0, 0,
+                                       PROGRESS_FN(), None))
+            self._n[key] = bc.shape[0]
+        t = C.c_uint64()
+        _check(_lib().ps_submit(self._s, C.c_uint64(key), pp, bo, C.byref(o),
+                                bc.ctypes.data_as(C.c_void_p), nrhs, C.byref(t)), "ps_submit")
+        self._shape[t.value] = (bc.shape[0], nrhs, b.ndim)
+        return t.value
+
+    def poll(self, ticket: int):
+        """(state, x or None, stats list or None); raises on a failed ticket."""
+        n, nrhs, nd = self._shape[ticket]
+        x = np.empty((nrhs, n), np.complex128)
+        st = (ps_stats * nrhs)()
+        state = C.c_int32()
+        status = _lib().ps_poll(self._s, C.c_uint64(ticket), x.ctypes.data_as(C.c_void_p), st,
+                                C.byref(state))
+        if status == HM_ENOTREADY:
+            return state.value, None, None
+        del self._shape[ticket]
+        _check(status, "ps_poll (ticket %d)" % ticket, allow=(HM_OK, HM_EDIVERGED))
+        xs = x.T if nd == 2 else x[0]
+        return state.value, xs, [{k: getattr(s, k) for k, _ in ps_stats._fields_} for s in st]
+
+    def wait(self, ticket: int, timeout_s: float = 600.0, sleep_s: float = 0.0005):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            state, x, st = self.poll(ticket)
+            if x is not None:
+                return x, st
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")
+            time.sleep(sleep_s)
+
+    def info(self) -> dict:
+        i = ps_server_stats()
+        _check(_lib().ps_server_info(self._s, C.byref(i)), "ps_server_info")
+        return {k: getattr(i, k) for k, _ in ps_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_s", None) is not None and self._s.value is not None:
+            _lib().ps_server_destroy(self._s)
+            self._s = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

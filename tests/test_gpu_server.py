@@ -1,0 +1,153 @@
+"""The request server (ps_server_create / ps_submit / ps_poll) on the GPU:
+results equal the one-request-at-a-time results and the oracle, requests
+are batched, the HBM budget evicts idle geometries and refuses geometries
+that cannot fit."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import hmatrix, series
+
+torch = pytest.importorskip("torch")
+from paper_2307_03968_amd import hmps  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+GEOMS = {
+    1: (W.sphere_problem(1200, math.sqrt(1200 / 1536)), 32, 1e-6),
+    2: (W.cube_problem(10, 10 / 16), 32, 1e-5),
+    3: (W.sphere_problem(700, math.sqrt(700 / 1536), instance=3), 64, 1e-4),
+}
+
+
+@pytest.fixture(scope="module")
+def oracles():
+    return {k: hmatrix.HMatrix(p, leaf, 1.0, tol) for k, (p, leaf, tol) in GEOMS.items()}
+
+
+def _requests():
+    """(key, b) pairs: 14 requests over the three geometries, 1..9 RHS."""
+    g = np.random.default_rng(11)
+    out = []
+    for i in range(14):
+        key = [1, 2, 3, 1, 1, 2, 3, 3, 1, 2, 2, 1, 3, 1][i]
+        p = GEOMS[key][0]
+        nrhs = int(g.integers(1, 10))
+        out.append((key, W.plane_waves(p.xyz, W.directions(nrhs, 3, instance=100 + i))))
+    return out
+
+
+def _submit(srv, key, b, seen, **kw):
+    p, leaf, tol = GEOMS[key]
+    first = key not in seen
+    seen.add(key)
+    return srv.submit(key, b, prob=p if first else None, leaf_max=leaf, aca_tol=tol, **kw)
+
+
+def test_server_mix_equals_alone_and_oracle(oracles):
+    reqs = _requests()
+    K = 3
+    _say("server alone: one request at a time")
+    srv = hmps.Server(slots=1)
+    seen = set()
+    alone = []
+    for key, b in reqs:
+        x, st = srv.wait(_submit(srv, key, b, seen, K=K))
+        alone.append(x)
+    assert srv.info()["batches"] == len(reqs)
+    srv.close()
+    _say("server mix: all requests at once, three workers")
+    srv = hmps.Server(slots=3)
+    seen = set()
+    tickets = [_submit(srv, key, b, seen, K=K) for key, b in reqs[:8]]
+    first = srv.wait(tickets[0])  # later requests arrive while others run
+    tickets += [_submit(srv, key, b, seen, K=K) for key, b in reqs[8:]]
+    mix = [first[0]] + [srv.wait(t)[0] for t in tickets[1:]]
+    info = srv.info()
+    _say(f"server info {info}")
+    assert info["builds"] == 3 and info["requests_done"] == len(reqs)
+    assert info["batches"] < len(reqs), "queued requests of one geometry were not batched"
+    for (key, b), xa, xm in zip(reqs, alone, mix):
+        assert series.rel_err(xm, xa) <= 1e-12
+        assert series.rel_err(xm, series.series(oracles[key], b, K)) <= 1e-10
+    srv.close()
+
+
+def test_server_budget_evicts_idle_geometries(oracles):
+    """A budget that holds one geometry at a time: alternating requests
+    rebuild geometries after evicting the idle one; results stay right."""
+    probe = hmps.Server(slots=1)
+    sizes = {}
+    seen = set()
+    for key in (1, 3):
+        b = W.plane_waves(GEOMS[key][0].xyz, W.Z_HAT)
+        probe.wait(_submit(probe, key, b, seen, K=2))
+        sizes[key] = probe.info()["resident_bytes"] - sum(sizes.values())
+    probe.close()
+    budget = int(max(sizes.values()) + 0.5 * min(sizes.values()))
+    _say(f"server budget {budget} bytes, geometry bytes {sizes}")
+    srv = hmps.Server(budget_bytes=budget, slots=1)
+    seen = set()
+    for rep in range(2):
+        for key in (1, 3):
+            b = W.plane_waves(GEOMS[key][0].xyz, W.directions(2, 3, instance=rep))
+            x, st = srv.wait(_submit(srv, key, b, seen, K=2))
+            assert series.rel_err(x, series.series(oracles[key], b, 2)) <= 1e-10
+            assert st[0]["built"] == 1  # the other geometry had to go
+    info = srv.info()
+    assert info["evictions"] >= 3 and info["builds"] == 4
+    assert info["resident_bytes"] <= budget
+    srv.close()
+
+
+def test_server_rejects_geometry_over_budget():
+    srv = hmps.Server(budget_bytes=1 << 20, slots=1)
+    p, leaf, tol = GEOMS[1]
+    t = srv.submit(1, W.plane_waves(p.xyz, W.Z_HAT), K=2, prob=p, leaf_max=leaf, aca_tol=tol)
+    with pytest.raises(hmps.HmpsError) as e:
+        srv.wait(t)
+    assert e.value.status == hmps.HM_ENOMEM
+    assert srv.info()["requests_failed"] == 1
+    srv.close()
+
+
+def test_server_refine_to_exact_solution():
+    """Mixed precision with FP64 refinement through the server reaches
+    x* = Z_l^{-1} b to 1e-8 (sphere of 1536 points, rho^5 < 1)."""
+    wl = W.sphere_small()
+    H = hmatrix.HMatrix(wl.problem, 64, 1.0, 1e-4)
+    b = W.plane_waves(wl.problem.xyz, W.directions(3, 3))
+    srv = hmps.Server(slots=2)
+    t = srv.submit(7, b, K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE, max_passes=300,
+                   refine_tol=1e-11, prob=wl.problem, leaf_max=64, aca_tol=1e-4)
+    x, st = srv.wait(t)
+    assert series.rel_err(x, series.solve_exact(H, b)) <= 1e-8
+    assert all(s["diverged"] == 0 and s["passes"] > 0 and s["t_ms"] > 0 for s in st)
+    srv.close()
+
+
+def test_server_argument_errors():
+    import ctypes as C
+    lib = hmps._lib()
+    srv = hmps.Server(slots=1)
+    p, leaf, tol = GEOMS[3]
+    b = W.plane_waves(p.xyz, W.Z_HAT)
+    with pytest.raises(hmps.HmpsError):        # unknown key without a problem
+        srv.submit(99, b, K=2)
+    with pytest.raises(hmps.HmpsError):        # more than 64 right-hand sides
+        srv.submit(3, np.zeros((p.n, 65), np.complex128), K=2, prob=p, leaf_max=leaf)
+    state = C.c_int32()
+    assert lib.ps_poll(srv._s, C.c_uint64(12345), None, None, C.byref(state)) == hmps.HM_EINVAL
+    t = srv.submit(3, b, K=2, prob=p, leaf_max=leaf, aca_tol=tol)
+    srv.wait(t)
+    assert lib.ps_poll(srv._s, C.c_uint64(t), None, None, C.byref(state)) == hmps.HM_EINVAL
+    srv.close()
