@@ -13,6 +13,9 @@ Workloads:
                 tol 1e-4, K = 4, 16 plane waves each, one batched handle,
                 autotuned, solves replayed from a captured HIP graph; FP32
                 blocks with FP64 refinement against the plain FP64 path
+  served        Poisson request stream over 16 surface + 16 volume
+                geometries (N in [1024, 65536], 1..64 RHS) through the request
+                server; mixed precision and plain FP64
   sphere_1536   the small surface case
 
 A step is one power-series solve (Sec. IV): permute in, y_0 = D^{-1} b,
@@ -453,6 +456,183 @@ def bench_batched(a):
     return 0
 
 
+def bench_served(a):
+    """Poisson request stream through the request server (continuous
+    batching over resident geometries under the HBM budget).  Surface
+    requests: FP32 blocks with FP64 refinement to x*; volume requests: the
+    FP32 series (refinement is not attainable there, rho > 1).  The same
+    stream is then served by the plain FP64 path.  Latency = submit to done
+    (server clock), with and without requests whose batch built a geometry."""
+    import workloads as W
+    from paper_2307_03968_amd import hmps
+
+    ns, sides = W.served_pool()
+    pool = {}
+    for kind in (W.SURFACE, W.VOLUME):
+        for gi in range(16):
+            wl = W.served_workload(kind, gi, 64, 0)
+            pool[(kind, gi)] = wl
+    # per geometry a bank of 64 seeded plane waves; request r takes nrhs
+    # consecutive columns from a seeded offset
+    log("plane-wave banks")
+    bank = {k: np.asfortranarray(wl.rhs()) for k, wl in pool.items()}
+    key_of = {k: i + 1 for i, k in enumerate(sorted(pool))}
+
+    def opts_for(kind, mixed):
+        p = hmps.HM_F32_APPLY if mixed else hmps.HM_F64
+        if kind == W.SURFACE:
+            return dict(K=4, precision=p, kind=hmps.PS_REFINE, max_passes=120, refine_tol=1e-10)
+        return dict(K=5, precision=p, kind=hmps.PS_SERIES)
+
+    def run(srv, stream, mixed, seen, rate=None, keep=()):
+        """Submit the stream (open loop at its arrival times, or all at once
+        when rate is None); returns per-request records and the wall time."""
+        g = np.random.default_rng(13)
+        recs = {}
+        out = {}
+        t0 = time.perf_counter()
+        i = 0
+        pending = {}
+        while i < len(stream) or pending:
+            now = time.perf_counter() - t0
+            while i < len(stream) and (rate is None or stream[i].t_arrive <= now):
+                rq = stream[i]
+                k = (rq.kind, rq.geom)
+                wl = pool[k]
+                c0 = int(g.integers(0, 64 - rq.nrhs + 1))
+                b = bank[k][:, c0:c0 + rq.nrhs]
+                first = key_of[k] not in seen
+                seen.add(key_of[k])
+                t = srv.submit(key_of[k], b, prob=wl.problem if first else None,
+                               leaf_max=wl.leaf_max, aca_tol=wl.aca_tol, **opts_for(rq.kind, mixed))
+                pending[t] = (i, c0)
+                i += 1
+            done = []
+            for t, (ri, c0) in list(pending.items())[:256]:
+                state, x, st = srv.poll(t, want_x=ri in keep)
+                if st is not None:
+                    recs[ri] = {"ms": st[0]["t_ms"], "built": st[0]["built"],
+                                "diverged": max(s_["diverged"] for s_ in st),
+                                "passes": max(s_["passes"] for s_ in st), "c0": c0}
+                    if x is not None:
+                        out[ri] = x
+                    done.append(t)
+            for t in done:
+                del pending[t]
+            if not done:
+                nxt = stream[i].t_arrive - (time.perf_counter() - t0) if (rate and i < len(stream)) else 0.0005
+                time.sleep(min(max(nxt, 0.0), 0.0005) if pending else max(nxt, 0.0))
+        return recs, out, time.perf_counter() - t0
+
+    def summary(stream, recs, wall):
+        lat = np.array([recs[i]["ms"] for i in range(len(stream))])
+        warm = np.array([recs[i]["ms"] for i in range(len(stream)) if not recs[i]["built"]])
+        rhs = sum(rq.nrhs for rq in stream)
+        surf_ok = sum(rq.nrhs for i, rq in enumerate(stream)
+                      if rq.kind == W.SURFACE and not recs[i]["diverged"])
+        return {"requests": len(stream), "rhs": rhs, "wall_s": wall, "RHS_per_s": rhs / wall,
+                "refined_surface_RHS_per_s": surf_ok / wall,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                "latency_ms_without_cold_builds": (
+                    {"p50": float(np.percentile(warm, 50)), "p99": float(np.percentile(warm, 99))}
+                    if len(warm) else None),
+                "cold_build_requests": int(sum(recs[i]["built"] for i in range(len(stream)))),
+                "diverged_surface_requests": int(sum(1 for i, rq in enumerate(stream)
+                                                     if rq.kind == W.SURFACE and recs[i]["diverged"])),
+                "max_refine_passes": int(max(recs[i]["passes"] for i in range(len(stream))))}
+
+    results = {}
+    srv_info = {}
+    for mixed in (True, False):
+        tag = "mixed" if mixed else "f64"
+        srv = hmps.Server(budget_bytes=a.budget_gb << 30 if a.budget_gb else 0, slots=a.slots)
+        seen = set()
+        log(f"[{tag}] cold pass: one request per geometry")
+        cold_stream = [W.Request(0.0, kind, gi, 8) for (kind, gi) in sorted(pool)]
+        cold, _, cold_wall = run(srv, cold_stream, mixed, seen)
+        log(f"[{tag}] cold pass {cold_wall:.1f} s; {srv.info()}")
+        log(f"[{tag}] closed-loop burst for the saturated rate")
+        burst = W.request_stream(a.calib_requests, 1.0, seed=6)
+        brec, _, bwall = run(srv, burst, mixed, seen)
+        sat = len(burst) / bwall
+        rate = 0.7 * sat
+        log(f"[{tag}] saturated {sat:.2f} req/s; open loop at {rate:.2f} req/s")
+        stream = W.request_stream(a.requests, rate)
+        small = [i for i, rq in enumerate(stream) if pool[(rq.kind, rq.geom)].problem.n <= 6000]
+        keep = set(small[:40]) if mixed else set()
+        recs, xs, wall = run(srv, stream, mixed, seen, rate=rate, keep=keep)
+        results[tag] = summary(stream, recs, wall)
+        results[tag]["saturated_req_per_s"] = sat
+        results[tag]["offered_req_per_s"] = rate
+        results[tag]["cold_pass"] = {"wall_s": cold_wall,
+                                     "latency_ms_p50": float(np.median([r["ms"] for r in cold.values()]))}
+        srv_info[tag] = srv.info()
+        results[tag]["server"] = srv_info[tag]
+        log(f"[{tag}] {results[tag]}")
+        if mixed:
+            mixed_stream, mixed_x, mixed_recs = stream, xs, recs
+        srv.close()
+
+    # ---- oracle on a sample of the mixed-stream requests (small geometries)
+    rel = {"surface_refine_vs_xstar": 0.0, "volume_series_f32_vs_xK": 0.0}
+    cpu = None
+    checked = []
+    if not a.no_oracle:
+        from oracle import hmatrix, series
+        cand = [i for i in sorted(mixed_x) if pool[(mixed_stream[i].kind, mixed_stream[i].geom)].problem.n <= 6000]
+        pick = {}
+        for i in cand:  # one request per small geometry, at most 4
+            k = (mixed_stream[i].kind, mixed_stream[i].geom)
+            if k not in pick and len(pick) < 4:
+                pick[k] = i
+        cpu_t, cpu_rhs = 0.0, 0
+        for k, i in sorted(pick.items()):
+            rq, wl = mixed_stream[i], pool[k]
+            c0 = mixed_recs[i]["c0"]
+            b = bank[k][:, c0:c0 + rq.nrhs]
+            log(f"oracle request {i}: kind {rq.kind} N {wl.problem.n} nrhs {rq.nrhs}")
+            H = hmatrix.HMatrix(wl.problem, wl.leaf_max, 1.0, wl.aca_tol)
+            t1 = time.perf_counter()
+            ref = series.series(H, b, wl.K)
+            cpu_t += time.perf_counter() - t1
+            cpu_rhs += rq.nrhs
+            if rq.kind == W.SURFACE:
+                if not mixed_recs[i]["diverged"]:
+                    xs_ = series.solve_exact(H, b)
+                    rel["surface_refine_vs_xstar"] = max(rel["surface_refine_vs_xstar"],
+                                                         series.rel_err(mixed_x[i], xs_))
+            else:
+                rel["volume_series_f32_vs_xK"] = max(rel["volume_series_f32_vs_xK"],
+                                                     series.rel_err(mixed_x[i], ref))
+            checked.append({"request": i, "kind": int(rq.kind), "N": int(wl.problem.n), "nrhs": rq.nrhs})
+        if cpu_rhs:
+            cpu = {"value": cpu_rhs / cpu_t, "unit": "RHS/s", "cores": blas_threads(), "kind": "oracle",
+                   "sample": f"numpy/scipy FP64 series of {len(checked)} sampled requests "
+                             f"({cpu_rhs} RHS) in {cpu_t:.1f} s; oracle builds not included"}
+        log(f"rel.err on the sample: {rel}")
+    ok = (not a.no_oracle) and rel["surface_refine_vs_xstar"] <= SOLVED_TOL
+    m = results["mixed"]
+    out = {
+        "metric": METRIC + " (served stream: refined surface RHS)",
+        "value": m["refined_surface_RHS_per_s"] if ok else 0.0, "unit": "RHS/s", "n_gpus": 1,
+        "steps": m["requests"], "warmup": a.calib_requests,
+        "ms_per_step": 1e3 * m["wall_s"] / m["requests"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "served", "pool": "16 surface + 16 volume geometries, N log-uniform "
+                   "[1024, 65536]", "surface": "leaf<=64 (N<=8192) else 128, tol 1e-4, K=4, "
+                   "FP32 blocks + FP64 refinement", "volume": "leaf<=128, tol 1e-5, K=5, FP32 series",
+                   "nrhs": "U{1..64}", "slots": a.slots,
+                   "offered_rate": "0.7 x closed-loop saturated rate of the path",
+                   "budget_bytes": srv_info["mixed"]["budget_bytes"]},
+        "rel_err_vs_oracle": rel if not a.no_oracle else None,
+        "latency_ms": m["latency_ms"], "roofline": None, "cpu_baseline": cpu,
+        "extras": {"mixed": results["mixed"], "plain_f64": results["f64"],
+                   "oracle_checked_requests": checked},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -461,6 +641,11 @@ def main(argv=None):
     ap.add_argument("--workload", default="sphere_24576")
     ap.add_argument("--precision", default=None, choices=["f64", "f32"])
     ap.add_argument("--instances", type=int, default=256, help="batched_*: instance count")
+    ap.add_argument("--requests", type=int, default=600, help="served: open-loop requests")
+    ap.add_argument("--calib-requests", type=int, default=100,
+                    help="served: closed-loop burst for the saturated rate")
+    ap.add_argument("--slots", type=int, default=4, help="served: server workers")
+    ap.add_argument("--budget-gb", type=int, default=0, help="served: HBM budget (0: 90%% free)")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle check and CPU baseline (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",
@@ -480,6 +665,8 @@ def main(argv=None):
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.workload == "served":
+        return bench_served(a)
     if a.workload.startswith("batched"):
         if "_" in a.workload:
             a.instances = int(a.workload.split("_")[1])

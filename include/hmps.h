@@ -289,10 +289,11 @@ int hmat_free(hm_matrix_t h);
  * or running requests are freed until blocks plus workspaces fit the
  * budget (a geometry that cannot fit an idle device fails with HM_ENOMEM).
  * Results: ps_poll returns HM_ENOTREADY while the ticket is queued or
- * running; once it is done (or failed) it copies x (n x nrhs, original
- * order) to x_host and the per-RHS statistics (t_ms = submit-to-done
- * latency) to per_rhs, when non-null, and releases the ticket (a later poll
- * of it is HM_EINVAL).  Server calls are thread-safe.  hbm_budget_bytes 0
+ * running.  Once it is done (or failed) it returns the solve's status and
+ * copies x (n x nrhs, original order) to x_host and the per-RHS statistics
+ * (t_ms = submit-to-done latency) to per_rhs, each when non-null; a poll
+ * with x_host or per_rhs given releases the ticket (a later poll of it is
+ * HM_EINVAL), a poll with both NULL only reports the state.  Server calls are thread-safe.  hbm_budget_bytes 0
  * means 90% of the device memory free at creation. */
 typedef struct hm_server* hm_server_t;
 typedef uint64_t hm_ticket_t;

@@ -443,7 +443,7 @@ int ps_poll(hm_server_t s, hm_ticket_t t, void* x_host, ps_stats* per_rhs, int32
   } else {
     hm::set_error(r->err);
   }
-  s->tickets.erase(it);
+  if (x_host || per_rhs) s->tickets.erase(it);  // delivered: release
   return status;
 }
 

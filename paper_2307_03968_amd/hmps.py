@@ -351,19 +351,23 @@ class Server:
         self._shape[t.value] = (bc.shape[0], nrhs, b.ndim)
         return t.value
 
-    def poll(self, ticket: int):
-        """(state, x or None, stats list or None); raises on a failed ticket."""
+    def poll(self, ticket: int, want_x: bool = True):
+        """(state, x or None, stats list or None) once done (x None when
+        want_x is false); (state, None, None) while queued or running.
+        Raises on a failed ticket."""
         n, nrhs, nd = self._shape[ticket]
-        x = np.empty((nrhs, n), np.complex128)
-        st = (ps_stats * nrhs)()
         state = C.c_int32()
-        status = _lib().ps_poll(self._s, C.c_uint64(ticket), x.ctypes.data_as(C.c_void_p), st,
-                                C.byref(state))
+        status = _lib().ps_poll(self._s, C.c_uint64(ticket), None, None, C.byref(state))
         if status == HM_ENOTREADY:
             return state.value, None, None
+        x = np.empty((nrhs, n), np.complex128) if want_x else None
+        st = (ps_stats * nrhs)()
+        status = _lib().ps_poll(self._s, C.c_uint64(ticket),
+                                x.ctypes.data_as(C.c_void_p) if want_x else None, st,
+                                C.byref(state))
         del self._shape[ticket]
         _check(status, "ps_poll (ticket %d)" % ticket, allow=(HM_OK, HM_EDIVERGED))
-        xs = x.T if nd == 2 else x[0]
+        xs = None if x is None else (x.T if nd == 2 else x[0])
         return state.value, xs, [{k: getattr(s, k) for k, _ in ps_stats._fields_} for s in st]
 
     def wait(self, ticket: int, timeout_s: float = 600.0, sleep_s: float = 0.0005):
@@ -371,7 +375,7 @@ class Server:
         t0 = time.perf_counter()
         while True:
             state, x, st = self.poll(ticket)
-            if x is not None:
+            if st is not None:
                 return x, st
             if time.perf_counter() - t0 > timeout_s:
                 raise TimeoutError(f"ticket {ticket} not done after {timeout_s} s")

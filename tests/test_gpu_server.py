@@ -148,6 +148,11 @@ def test_server_argument_errors():
     state = C.c_int32()
     assert lib.ps_poll(srv._s, C.c_uint64(12345), None, None, C.byref(state)) == hmps.HM_EINVAL
     t = srv.submit(3, b, K=2, prob=p, leaf_max=leaf, aca_tol=tol)
-    srv.wait(t)
+    while lib.ps_poll(srv._s, C.c_uint64(t), None, None, C.byref(state)) == hmps.HM_ENOTREADY:
+        pass
+    assert state.value == hmps.PS_DONE  # a state-only poll keeps the result
+    assert lib.ps_poll(srv._s, C.c_uint64(t), None, None, C.byref(state)) == hmps.HM_OK
+    x, st = srv.wait(t)
+    assert x.shape == b.shape and st[0]["t_ms"] > 0
     assert lib.ps_poll(srv._s, C.c_uint64(t), None, None, C.byref(state)) == hmps.HM_EINVAL
     srv.close()
