@@ -168,6 +168,11 @@ def bench_single(a):
     n = wl.problem.n
     b = torch.from_numpy(np.ascontiguousarray(b_np)).to("cuda")
     stream = torch.cuda.current_stream()
+    tune = None
+    if nrhs > 1:
+        log("autotune")
+        tune = h.autotune(nrhs, K=wl.K, level=wl.level, precision=prec)
+        log(f"autotune: {tune}")
     mm = nrhs >= h.tuning()["mm_min_rhs"]
     solve = lambda p=prec: h.solve(b, K=wl.K, level=wl.level, precision=p)  # noqa: E731
 
@@ -289,6 +294,7 @@ def bench_single(a):
         "rel_err_vs_oracle": rel, "latency_ms": lat, "roofline": roof,
         "per_solve_algorithmic_bytes": per_solve_bytes, "kernels": kernels, "build_s": build_s,
         "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
+        "autotune": None if tune is None else {"choice": tune[0], "ms": tune[1]},
     }
     print(json.dumps(out), flush=True)
     h.close()

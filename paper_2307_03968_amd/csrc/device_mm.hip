@@ -95,61 +95,89 @@ struct MMAcc {
   }
 };
 
-// acc += P[rows of this wave's tiles, c0:c1) * Xs, the inputs of the chunk
-// being fetched into LDS by fx(c, n) (c absolute column, n RHS within the
-// tile; returns the FP64 value, zero outside the valid range).
-template <bool F32, int RT, int NT, typename FX>
+// acc += P[rows of this wave's tiles, c0:c1) * X[c0:c1, tile].  colp(c)
+// points at input column c's value for the tile's first right-hand side
+// (right-hand side n at colp(c)[n * ldx]); nv right-hand sides of the tile
+// are valid.  Software pipelined: the inputs of column chunk j + 1 are
+// loaded into registers while chunk j is multiplied (two LDS buffers, one
+// barrier per chunk); the panel loads of the next group of 16 columns are
+// issued before the products of the current group into the other of two
+// register sets (a chunk is two groups, so the sets alternate without
+// copies).  Every load is issued unconditionally at a clamped address (the
+// values past c1 or past the last right-hand side are replaced by zero),
+// so the memory-counter waits before each group cover only the loads that
+// group needs.
+template <bool F32, int RT, int NT, typename COLP>
 __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld, int row0,
-                                        int c0, int c1, const FX& fx, MMAcc<F32, RT, NT>& acc,
-                                        int w, int lane) {
+                                        int c0, int c1, const COLP& colp, int64_t ldx, int nv,
+                                        MMAcc<F32, RT, NT>& acc, int w, int lane) {
   using PR = Prec<F32>;
+  using AV = typename std::conditional<F32, float2, double2>::type;
   constexpr int NRT = 16 * NT;
-  constexpr int CH = PR::CH;
-  __shared__ typename PR::X xs[CH][NRT];  // the chunk's inputs, shared by the waves
+  constexpr int CH = 32;                       // columns per staged chunk = 2 groups
+  constexpr int NPT = kThreads / CH;           // right-hand sides apart per thread
+  constexpr int XPT = CH * NRT / kThreads;     // staged inputs per thread
+  __shared__ typename PR::X xs[2][CH][NRT + 1];  // +1: spreads the banks of column writes
+  if (c1 <= c0) return;
   const int l16 = lane & 15, kq = lane >> 4;
+  const int xk = threadIdx.x % CH, xn = threadIdx.x / CH;
   uint32_t ri[RT];
 #pragma unroll
   for (int r = 0; r < RT; ++r) ri[r] = min<uint32_t>(row0 + (w + 4 * r) * 16 + l16, ld - 1);
-  for (int cb = c0; cb < c1; cb += CH) {
-    const int nc = min(CH, c1 - cb);
-    __syncthreads();
-    for (int t = threadIdx.x; t < CH * NRT; t += kThreads) {
-      const int k = t % CH;
-      const int n = t / CH;
-      xs[k][n] = PR::cvt(k < nc ? fx(cb + k, n) : make_double2(0.0, 0.0));
+  double2 xr[XPT];
+  bool xok[XPT];
+  auto load_x = [&](int cb) {
+    const bool col_ok = cb + xk < c1;
+    const double2* base = colp(min(cb + xk, c1 - 1));
+#pragma unroll
+    for (int i = 0; i < XPT; ++i) {
+      const int n = xn + i * NPT;
+      xr[i] = base[(int64_t)min(n, nv - 1) * ldx];
+      xok[i] = col_ok && n < nv;
     }
-    __syncthreads();
-    for (int kk = 0; kk < nc; kk += 16) {
-      // four k-steps of four columns: A loads first, then the products
-      float2 af[F32 ? 4 : 1][RT];
-      double2 ad[F32 ? 1 : 4][RT];
+  };
+  auto store_x = [&](int buf) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int col = min(cb + kk + 4 * s + kq, c1 - 1);
+    for (int i = 0; i < XPT; ++i)
+      xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : make_double2(0.0, 0.0));
+  };
+  AV a0[4][RT], a1[4][RT];
+  auto load_a = [&](int cg, AV (&dst)[4][RT]) {
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          if constexpr (F32)
-            af[s][r] = PR::load_a(P, ri[r] + (uint32_t)col * ld);
-          else
-            ad[s][r] = PR::load_a(P, ri[r] + (uint32_t)col * ld);
-        }
-      }
+    for (int s = 0; s < 4; ++s) {
+      const int col = min(cg + 4 * s + kq, c1 - 1);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        if (kk + 4 * s >= nc) break;
+      for (int r = 0; r < RT; ++r) dst[s][r] = PR::load_a(P, ri[r] + (uint32_t)col * ld);
+    }
+  };
+  // columns past c1 hold zero inputs (and clamped panel columns), so every
+  // chunk runs both groups of four k-steps without branches
+  auto group = [&](const AV (&a)[4][RT], int buf, int kk) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const typename PR::X b = xs[kk + 4 * s + kq][t * 16 + l16];
+    for (int s = 0; s < 4; ++s) {
 #pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            if constexpr (F32)
-              PR::mac(acc.a[r][t], af[s][r], b);
-            else
-              PR::mac(acc.a[r][t], ad[s][r], b);
-          }
-        }
+      for (int t = 0; t < NT; ++t) {
+        const typename PR::X b = xs[buf][kk + 4 * s + kq][t * 16 + l16];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) PR::mac(acc.a[r][t], a[s][r], b);
       }
     }
+  };
+  const int nchunks = (c1 - c0 + CH - 1) / CH;
+  load_x(c0);
+  store_x(0);
+  load_a(c0, a0);
+  __syncthreads();
+  for (int j = 0; j < nchunks; ++j) {
+    const int cb = c0 + j * CH;
+    const int buf = j & 1;
+    load_x(cb + CH);  // past the last chunk: zeros, never read
+    load_a(cb + 16, a1);
+    group(a0, buf, 0);
+    load_a(cb + CH, a0);
+    group(a1, buf, 16);
+    store_x(buf ^ 1);
+    __syncthreads();
   }
 }
 
@@ -249,13 +277,14 @@ __global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs) {
     const int32_t* __restrict__ src = A.ps.src + A.ps.col_off[a];
     MMAcc<F32, RT, NT> acc;
     acc.zero();
-    auto fx = [&](int c, int n) -> double2 {
-      if (rhs0 + n >= nrhs) return make_double2(0.0, 0.0);
+    const double2* xbase = A.xin + (int64_t)rhs0 * A.ldx;
+    const int64_t* inp = A.in_perm;
+    auto colp = [&](int c) -> const double2* {
       int64_t s = src[c];
-      if (A.in_perm) s = A.in_perm[s];
-      return A.xin[s + (int64_t)(rhs0 + n) * A.ldx];
+      if (inp) s = inp[s];
+      return xbase + s;
     };
-    mm_core<F32, RT, NT>(P, ld, 0, it.c0, it.c1, fx, acc, w, lane);
+    mm_core<F32, RT, NT>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -308,11 +337,9 @@ __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__
   const int l16 = lane & 15, kq = lane >> 4;
   MMAcc<F32, 1, NT> acc;
   acc.zero();
-  auto fx = [&](int c, int n) -> double2 {
-    return (rhs0 + n < nrhs) ? xin[g.s_off + c + (int64_t)(rhs0 + n) * ldx]
-                             : make_double2(0.0, 0.0);
-  };
-  mm_core<F32, 1, NT>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, fx, acc, w, lane);
+  const double2* xbase = xin + g.s_off + (int64_t)rhs0 * ldx;
+  auto colp = [&](int c) -> const double2* { return xbase + c; };
+  mm_core<F32, 1, NT>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc, w, lane);
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -333,14 +360,17 @@ inline int pick_nt(int nrhs, int tile) {
 
 template <bool F32, int RT>
 hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, int tile, hipStream_t st) {
-  const int nt = pick_nt(nrhs, tile);
+  // FP64 with four row tiles per wave: at most 32 right-hand sides per
+  // workgroup (the 64-wide tile does not fit the register file)
+  const int nt = (!F32 && RT == 4) ? min(2, pick_nt(nrhs, tile)) : pick_nt(nrhs, tile);
   const dim3 grid(nwg, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
     hipLaunchKernelGGL((k_term_mm<F32, RT, 1>), grid, dim3(kThreads), 0, st, a, nrhs);
-  else if (nt == 2)
+  else if (nt == 2 || (!F32 && RT == 4))
     hipLaunchKernelGGL((k_term_mm<F32, RT, 2>), grid, dim3(kThreads), 0, st, a, nrhs);
   else
-    hipLaunchKernelGGL((k_term_mm<F32, RT, 4>), grid, dim3(kThreads), 0, st, a, nrhs);
+    hipLaunchKernelGGL((k_term_mm<F32, RT, (!F32 && RT == 4) ? 2 : 4>), grid, dim3(kThreads), 0,
+                       st, a, nrhs);
   return hipGetLastError();
 }
 
