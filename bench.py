@@ -116,7 +116,27 @@ def latency(fn, reps):
     return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))}
 
 
-def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T):
+def recorded_traffic(workload_name, prec, kernel):
+    """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
+    runs summarised under profiles/ (calibrated against a device copy), or
+    None when there is none or the kernel source changed since."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if not line.startswith("traffic-record:"):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
+            if (kv.get("workload"), kv.get("precision"), kv.get("kernel")) != (workload_name, prec, kernel):
+                continue
+            src = os.path.join(ROOT, kv["source"])
+            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["sha256"]:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T, workload_name=None):
     """Roofline of one series-term launch.  Algorithmic bytes: the level's
     series panel entries (D^{-1}[near | U]); on the one-RHS kernels also the
     W rows of the in-row far blocks read in the same launch; plus the
@@ -129,9 +149,12 @@ def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T):
     vec = 16 * nrhs * ((n + (T if mm else 0)) + 3 * n)
     nbytes = elem * (ent + went) + vec
     gbps = nbytes / (avg_us * 1e-6) / 1e9
+    traffic = recorded_traffic(workload_name, prec, "k_term_mm" if mm else "k_term")
     out = {"bound": "hbm", "kernel": "k_term_mm (one series term)" if mm else "k_term (one series term)",
            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
-           "traffic": None, "bytes_per_launch": nbytes, "avg_launch_us": avg_us}
+           "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_us,
+           "traffic_note": "L2-to-memory bytes per launch, 2 x FETCH_SIZE + WRITE_SIZE (profiles/)"
+                           if traffic else "no counter run for this kernel source"}
     if mm:
         flops = (6 if prec == "f32" else 8) * ent * nrhs
         tf = flops / (avg_us * 1e-6) / 1e12
@@ -195,7 +218,8 @@ def bench_single(a):
     ms_per_step = wall * 1e3 / a.steps
     x_np = x.cpu().numpy()
     T = info["coeffs"][level]
-    roof = term_roofline(info, level, n, nrhs, pname, mm, kernels["term_series"]["avg_us"], T)
+    roof = term_roofline(info, level, n, nrhs, pname, mm, kernels["term_series"]["avg_us"], T,
+                         wl.name)
     if not mm:
         assert kernels["stageA"]["launches"] == 0, "the leaf-level one-RHS path has no stage A"
     elem = 16 if prec == hmps.HM_F64 else 8
@@ -253,7 +277,7 @@ def bench_single(a):
         if mm:
             _, ko = profiled(h, lambda: solve(other), 5)
             extras[f"series_{oname}"]["roofline"] = term_roofline(
-                info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T)
+                info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T, wl.name)
             extras[f"series_{oname}"]["kernels"] = ko
         if H is not None:
             from oracle import series
