@@ -99,7 +99,37 @@ struct TermArgs {
   double2* out;              // may be null: out[out_perm[q]] = new x (or y)
   int64_t ldo;
   const int64_t* out_perm;
+  // FP32 shadows for the FP32 matrix-core kernels (ld ldx / ldy): inputs
+  // [y | t] read by them, and the FP32 copy of y the epilogue writes for
+  // the next term (may be null)
+  const float2* xin32;
+  float2* yout32;
 };
+
+// Epilogue of one entry (row i of the leaf at tree offset off, right-hand
+// side c) of a term: y = alpha z + beta v, then the y, x and output stores.
+__device__ __forceinline__ void finish_entry(const TermArgs& A, int64_t off, int i, int c,
+                                             double2 z) {
+  double2 y = make_double2(A.alpha * z.x, A.alpha * z.y);
+  if (A.v) {
+    const double2 v = A.v[off + i + (int64_t)c * A.ldv];
+    y.x = fma(A.beta, v.x, y.x);
+    y.y = fma(A.beta, v.y, y.y);
+  }
+  if (A.yout) A.yout[off + i + (int64_t)c * A.ldy] = y;
+  if (A.yout32) A.yout32[off + i + (int64_t)c * A.ldy] = make_float2((float)y.x, (float)y.y);
+  double2 res = y;
+  if (A.xacc) {
+    const int64_t q = off + i + (int64_t)c * A.ldxa;
+    if (A.accumulate) {
+      const double2 o = A.xacc[q];
+      res.x += o.x;
+      res.y += o.y;
+    }
+    A.xacc[q] = res;
+  }
+  if (A.out) A.out[A.out_perm[off + i] + (int64_t)c * A.ldo] = res;
+}
 
 struct NormItem {
   int64_t r0, r1;
@@ -123,8 +153,11 @@ hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* per
 hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
                           hipStream_t st);
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs, int tile,
-                            hipStream_t st);
+                            int nitems, double2* xin, float2* xin32, int64_t ldx, int64_t N,
+                            int nrhs, int tile, hipStream_t st);
+// out[q + c ldo] = (float) in[q + c ldi], q < n, c < nrhs
+hipError_t launch_cast2d(const double2* in, int64_t ldi, float2* out, int64_t ldo, int64_t n,
+                         int nrhs, hipStream_t st);
 // nwg persistent workgroups; grid.y covers the right-hand sides
 hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
                        hipStream_t st);

@@ -298,25 +298,7 @@ __device__ void term_epilogue(const TermArgs& A, int a, int rhs0, int nrhs, int*
     const int i = idx % m;
     const int c = rhs0 + idx / m;
     if (c >= nrhs) continue;
-    const double2 z = zacc[k];
-    double2 y = make_double2(A.alpha * z.x, A.alpha * z.y);
-    if (A.v) {
-      const double2 v = A.v[off + i + (int64_t)c * A.ldv];
-      y.x = fma(A.beta, v.x, y.x);
-      y.y = fma(A.beta, v.y, y.y);
-    }
-    if (A.yout) A.yout[off + i + (int64_t)c * A.ldy] = y;
-    double2 res = y;
-    if (A.xacc) {
-      const int64_t q = off + i + (int64_t)c * A.ldxa;
-      if (A.accumulate) {
-        const double2 o = A.xacc[q];
-        res.x += o.x;
-        res.y += o.y;
-      }
-      A.xacc[q] = res;
-    }
-    if (A.out) A.out[A.out_perm[off + i] + (int64_t)c * A.ldo] = res;
+    finish_entry(A, off, i, c, zacc[k]);
   }
 }
 
@@ -407,6 +389,13 @@ __global__ __launch_bounds__(kThreads) void k_term(TermArgs A, int nrhs) {
         }
     }
     __builtin_amdgcn_s_waitcnt(0);
+    if (A.lptr[a + 1] - A.lptr[a] == 1) {
+      // the leaf's only piece: its epilogue needs no counter
+      __syncthreads();
+      term_epilogue<NR>(A, a, rhs0, nrhs, s_prow);
+      __syncthreads();
+      continue;
+    }
     int32_t* cnt = A.counters + (int64_t)a * gridDim.y + blockIdx.y;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -642,6 +631,16 @@ __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__
   }
 }
 
+__global__ void k_cast2d(const double2* __restrict__ in, int64_t ldi, float2* __restrict__ out,
+                         int64_t ldo, int64_t n) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (q < n) {
+    const double2 v = in[q + c * ldi];
+    out[q + c * ldo] = make_float2((float)v.x, (float)v.y);
+  }
+}
+
 __global__ void k_cast(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (int64_t)gridDim.x * blockDim.x)
@@ -854,6 +853,14 @@ hipError_t launch_norm2(const double2* v, int64_t ld, const NormItem* items, int
                      scratch);
   hipLaunchKernelGGL(k_norm2_segments, dim3(blocks_for((int64_t)nseg * nrhs, 64)), dim3(64), 0, st,
                      scratch, nitems, seg_ptr, nseg, nrhs, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast2d(const double2* in, int64_t ldi, float2* out, int64_t ldo, int64_t n,
+                         int nrhs, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast2d, dim3(blocks_for(n, 256), nrhs), dim3(256), 0, st, in, ldi, out, ldo,
+                     n);
   return hipGetLastError();
 }
 

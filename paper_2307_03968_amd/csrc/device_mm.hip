@@ -46,6 +46,7 @@ struct Prec<true> {                      // FP32 blocks, 3M
     return make_float2(v.x, v.y);
   }
   __device__ static __forceinline__ X cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
+  __device__ static __forceinline__ X cvt(float2 v) { return v; }
   __device__ static __forceinline__ void mac(Acc (&acc)[3], float2 a, X b) {
     acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[0], 0, 0, 0);
     acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[1], 0, 0, 0);
@@ -96,7 +97,8 @@ struct MMAcc {
 };
 
 // acc += P[rows of this wave's tiles, c0:c1) * X[c0:c1, tile].  colp(c)
-// points at input column c's value for the tile's first right-hand side
+// points (XT: double2, or float2 for FP32 shadows of the inputs) at input
+// column c's value for the tile's first right-hand side
 // (right-hand side n at colp(c)[n * ldx]); nv right-hand sides of the tile
 // are valid.  Software pipelined: the inputs of column chunk j + 1 are
 // loaded into registers while chunk j is multiplied (two LDS buffers, one
@@ -107,7 +109,7 @@ struct MMAcc {
 // values past c1 or past the last right-hand side are replaced by zero),
 // so the memory-counter waits before each group cover only the loads that
 // group needs.
-template <bool F32, int RT, int NT, typename COLP>
+template <bool F32, int RT, int NT, typename XT, typename COLP>
 __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld, int row0,
                                         int c0, int c1, const COLP& colp, int64_t ldx, int nv,
                                         MMAcc<F32, RT, NT>& acc, int w, int lane) {
@@ -124,11 +126,11 @@ __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld,
   uint32_t ri[RT];
 #pragma unroll
   for (int r = 0; r < RT; ++r) ri[r] = min<uint32_t>(row0 + (w + 4 * r) * 16 + l16, ld - 1);
-  double2 xr[XPT];
+  XT xr[XPT];
   bool xok[XPT];
   auto load_x = [&](int cb) {
     const bool col_ok = cb + xk < c1;
-    const double2* base = colp(min(cb + xk, c1 - 1));
+    const XT* base = colp(min(cb + xk, c1 - 1));
 #pragma unroll
     for (int i = 0; i < XPT; ++i) {
       const int n = xn + i * NPT;
@@ -139,7 +141,7 @@ __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld,
   auto store_x = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < XPT; ++i)
-      xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : make_double2(0.0, 0.0));
+      xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : XT{});
   };
   AV a0[4][RT], a1[4][RT];
   auto load_a = [&](int cg, AV (&dst)[4][RT]) {
@@ -219,24 +221,7 @@ __device__ void epilogue_loop(const TermArgs& A, int a, int rhs0, int nrhs, cons
         zi += vi[u];
       }
     }
-    double2 y = make_double2(A.alpha * zr, A.alpha * zi);
-    if (A.v) {
-      const double2 v = A.v[off + i + (int64_t)c * A.ldv];
-      y.x = fma(A.beta, v.x, y.x);
-      y.y = fma(A.beta, v.y, y.y);
-    }
-    if (A.yout) A.yout[off + i + (int64_t)c * A.ldy] = y;
-    double2 res = y;
-    if (A.xacc) {
-      const int64_t q = off + i + (int64_t)c * A.ldxa;
-      if (A.accumulate) {
-        const double2 o = A.xacc[q];
-        res.x += o.x;
-        res.y += o.y;
-      }
-      A.xacc[q] = res;
-    }
-    if (A.out) A.out[A.out_perm[off + i] + (int64_t)c * A.ldo] = res;
+    finish_entry(A, off, i, c, make_double2(zr, zi));
   }
 }
 
@@ -277,14 +262,39 @@ __global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs) {
     const int32_t* __restrict__ src = A.ps.src + A.ps.col_off[a];
     MMAcc<F32, RT, NT> acc;
     acc.zero();
-    const double2* xbase = A.xin + (int64_t)rhs0 * A.ldx;
     const int64_t* inp = A.in_perm;
-    auto colp = [&](int c) -> const double2* {
-      int64_t s = src[c];
-      if (inp) s = inp[s];
-      return xbase + s;
-    };
-    mm_core<F32, RT, NT>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
+    if constexpr (F32) {
+      // FP32 blocks take FP32 inputs: read the shadow copy (the values the
+      // products would round the FP64 inputs to anyway)
+      const float2* xbase = A.xin32 + (int64_t)rhs0 * A.ldx;
+      auto colp = [&](int c) -> const float2* { return xbase + src[c]; };
+      mm_core<F32, RT, NT, float2>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
+    } else {
+      const double2* xbase = A.xin + (int64_t)rhs0 * A.ldx;
+      auto colp = [&](int c) -> const double2* {
+        int64_t s = src[c];
+        if (inp) s = inp[s];
+        return xbase + s;
+      };
+      mm_core<F32, RT, NT, double2>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
+    }
+    if constexpr (RT == 1) {
+      // small leaves: a leaf's only piece finishes its rows straight from the
+      // registers (no partial sums, no counter); larger tiles keep the
+      // register budget of the partial-sum path below
+      if (A.lptr[a + 1] - A.lptr[a] == 1) {
+        const int64_t off = A.leaf_off[a];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = w * 16 + PR::row(kq, v);
+            const int c = rhs0 + t * 16 + l16;
+            if (i < m && c < nrhs) finish_entry(A, off, i, c, PR::result(acc.a[0][t], v));
+          }
+        continue;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -301,6 +311,13 @@ __global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs) {
           }
         }
     __builtin_amdgcn_s_waitcnt(0);
+    if (A.lptr[a + 1] - A.lptr[a] == 1) {
+      // the leaf's only piece: its epilogue needs no counter
+      __syncthreads();
+      term_epilogue_mm<NRT>(A, a, rhs0, nrhs);
+      __syncthreads();
+      continue;
+    }
     int32_t* cnt = A.counters + (int64_t)a * gridDim.y + blockIdx.y;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -323,7 +340,8 @@ template <bool F32, int NT>
 __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__ W,
                                                         const Group* __restrict__ groups,
                                                         const GroupItem* __restrict__ items,
-                                                        double2* __restrict__ xin, int64_t ldx,
+                                                        double2* __restrict__ xin,
+                                                        float2* __restrict__ xin32, int64_t ldx,
                                                         int64_t N, int nrhs) {
   using PR = Prec<F32>;
   constexpr int NRT = 16 * NT;
@@ -337,17 +355,32 @@ __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__
   const int l16 = lane & 15, kq = lane >> 4;
   MMAcc<F32, 1, NT> acc;
   acc.zero();
-  const double2* xbase = xin + g.s_off + (int64_t)rhs0 * ldx;
-  auto colp = [&](int c) -> const double2* { return xbase + c; };
-  mm_core<F32, 1, NT>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc, w, lane);
+  // FP32: inputs and the t coefficients live in the FP32 shadow [y | t]
+  if constexpr (F32) {
+    const float2* xbase = xin32 + g.s_off + (int64_t)rhs0 * ldx;
+    auto colp = [&](int c) -> const float2* { return xbase + c; };
+    mm_core<F32, 1, NT, float2>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc,
+                                w, lane);
+  } else {
+    const double2* xbase = xin + g.s_off + (int64_t)rhs0 * ldx;
+    auto colp = [&](int c) -> const double2* { return xbase + c; };
+    mm_core<F32, 1, NT, double2>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc,
+                                 w, lane);
+  }
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int q = it.row0 + w * 16 + PR::row(kq, v);
       const int c = rhs0 + t * 16 + l16;
-      if (q < it.rows && c < nrhs)
-        xin[N + g.t0 + q + (int64_t)c * ldx] = PR::result(acc.a[0][t], v);
+      if (q < it.rows && c < nrhs) {
+        const double2 z = PR::result(acc.a[0][t], v);
+        const int64_t o = N + g.t0 + q + (int64_t)c * ldx;
+        if constexpr (F32)
+          xin32[o] = make_float2((float)z.x, (float)z.y);
+        else
+          xin[o] = z;
+      }
     }
 }
 
@@ -360,34 +393,35 @@ inline int pick_nt(int nrhs, int tile) {
 
 template <bool F32, int RT>
 hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, int tile, hipStream_t st) {
-  // FP64 with four row tiles per wave: at most 32 right-hand sides per
-  // workgroup (the 64-wide tile does not fit the register file)
-  const int nt = (!F32 && RT == 4) ? min(2, pick_nt(nrhs, tile)) : pick_nt(nrhs, tile);
+  // four row tiles per wave: at most 32 right-hand sides per workgroup (the
+  // 64-wide tile does not fit the register file)
+  const int nt = (RT == 4) ? min(2, pick_nt(nrhs, tile)) : pick_nt(nrhs, tile);
   const dim3 grid(nwg, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
     hipLaunchKernelGGL((k_term_mm<F32, RT, 1>), grid, dim3(kThreads), 0, st, a, nrhs);
-  else if (nt == 2 || (!F32 && RT == 4))
+  else if (nt == 2 || RT == 4)
     hipLaunchKernelGGL((k_term_mm<F32, RT, 2>), grid, dim3(kThreads), 0, st, a, nrhs);
   else
-    hipLaunchKernelGGL((k_term_mm<F32, RT, (!F32 && RT == 4) ? 2 : 4>), grid, dim3(kThreads), 0,
-                       st, a, nrhs);
+    hipLaunchKernelGGL((k_term_mm<F32, RT, RT == 4 ? 2 : 4>), grid, dim3(kThreads), 0, st, a,
+                       nrhs);
   return hipGetLastError();
 }
 
 template <bool F32>
 hipError_t stageA_mm_p(const void* W, const Group* groups, const GroupItem* items, int nitems,
-                       double2* xin, int64_t ldx, int64_t N, int nrhs, int tile, hipStream_t st) {
+                       double2* xin, float2* xin32, int64_t ldx, int64_t N, int nrhs, int tile,
+                       hipStream_t st) {
   const int nt = pick_nt(nrhs, tile);
   const dim3 grid(nitems, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
     hipLaunchKernelGGL((k_stageA_mm<F32, 1>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       ldx, N, nrhs);
+                       xin32, ldx, N, nrhs);
   else if (nt == 2)
     hipLaunchKernelGGL((k_stageA_mm<F32, 2>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       ldx, N, nrhs);
+                       xin32, ldx, N, nrhs);
   else
     hipLaunchKernelGGL((k_stageA_mm<F32, 4>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       ldx, N, nrhs);
+                       xin32, ldx, N, nrhs);
   return hipGetLastError();
 }
 
@@ -396,6 +430,7 @@ hipError_t stageA_mm_p(const void* W, const Group* groups, const GroupItem* item
 hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
                           hipStream_t st) {
   if (nwg <= 0 || nrhs <= 0) return hipSuccess;
+  if (f32 && (!a.xin32 || a.in_perm)) return hipErrorInvalidValue;  // FP32 reads the shadow
   if (max_m > 256) return hipErrorInvalidValue;
   const int rt = (max_m + 63) / 64;  // 16-row tiles per wave
   if (f32) {
@@ -409,11 +444,12 @@ hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int n
 }
 
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, int64_t ldx, int64_t N, int nrhs, int tile,
-                            hipStream_t st) {
+                            int nitems, double2* xin, float2* xin32, int64_t ldx, int64_t N,
+                            int nrhs, int tile, hipStream_t st) {
   if (nitems <= 0 || nrhs <= 0) return hipSuccess;
-  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xin, ldx, N, nrhs, tile, st)
-             : stageA_mm_p<false>(W, groups, items, nitems, xin, ldx, N, nrhs, tile, st);
+  if (f32 && !xin32) return hipErrorInvalidValue;
+  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xin, xin32, ldx, N, nrhs, tile, st)
+             : stageA_mm_p<false>(W, groups, items, nitems, xin, xin32, ldx, N, nrhs, tile, st);
 }
 
 }  // namespace hm

@@ -129,6 +129,7 @@ struct hm_matrix {
   int64_t ws_bytes = 0;
   double2 *xin0 = nullptr, *xin1 = nullptr, *xt = nullptr, *bt = nullptr, *rt = nullptr,
           *dt = nullptr, *partial = nullptr;
+  float2 *xin32_0 = nullptr, *xin32_1 = nullptr;  // FP32 shadows of [y | t]
   double *nscratch = nullptr, *norms = nullptr;
   double* norms_host = nullptr;  // pinned
   // norm segments (one per instance) and their row items
@@ -313,6 +314,8 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   };
   STCHK(al((void**)&h->xin0, sizeof(double2) * ldin * nrhs));
   STCHK(al((void**)&h->xin1, sizeof(double2) * ldin * nrhs));
+  STCHK(al((void**)&h->xin32_0, sizeof(float2) * ldin * nrhs));
+  STCHK(al((void**)&h->xin32_1, sizeof(float2) * ldin * nrhs));
   STCHK(al((void**)&h->xt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->bt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->rt, sizeof(double2) * h->N * nrhs));
@@ -443,8 +446,8 @@ hipError_t run_term(const hm_matrix* h, const Path& P, bool f32, const TermArgs&
 }
 
 hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupList& sa,
-                      double2* xin, int64_t ldx, int nrhs, hipStream_t st) {
-  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs,
+                      double2* xin, float2* xin32, int64_t ldx, int nrhs, hipStream_t st) {
+  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, xin32, ldx, h->N, nrhs,
                                  h->rhs_tile, st)
               : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
 }
@@ -456,10 +459,15 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
   const Path P = pick_path(h, f32, nrhs);
+  // the FP32 matrix-core kernels read FP32 shadows of [y | t]
+  const bool shadow = P.mm && f32;
+  float2* y32_cur = shadow ? h->xin32_0 : nullptr;
+  float2* y32_nxt = shadow ? h->xin32_1 : nullptr;
   {
     TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, rhs, ldr);
     t.in_perm = rhs_perm ? h->perm : nullptr;
     t.yout = y_cur;
+    t.yout32 = y32_cur;
     t.ldy = ldin;
     t.xacc = x_tree;
     t.ldxa = N;
@@ -471,10 +479,12 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
   const TermList& tl = (*P.tl_series)[li];
   const GroupList& sa = (*P.sa)[li];
   for (int k = 1; k <= K; ++k) {
-    if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, ldin, nrhs, st));
+    if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, y32_cur, ldin, nrhs, st));
     TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, y_cur, ldin);
+    t.xin32 = y32_cur;
     t.alpha = -1.0;
     t.yout = y_nxt;
+    t.yout32 = y32_nxt;
     t.ldy = ldin;
     t.xacc = x_tree;
     t.ldxa = N;
@@ -482,6 +492,7 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
     TIMED(HM_K_TERM_SERIES, run_term(h, P, f32, t, tl, nrhs, st));
     std::swap(y_cur, y_nxt);
+    std::swap(y32_cur, y32_nxt);
   }
   if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
   return HM_OK;
@@ -493,10 +504,14 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
   const Path P = pick_path(h, f32, nrhs);
+  const bool shadow = P.mm && f32;
+  if (shadow) HIPCHK(launch_cast2d(h->xin0, ldin, h->xin32_0, ldin, N, nrhs, st));
+  float2* x32 = shadow ? h->xin32_0 : nullptr;
   const GroupList& sa = (*P.sa)[li];
-  if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, h->xin0, ldin, nrhs, st));
+  if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, h->xin0, x32, ldin, nrhs, st));
   const TermList& tl = (*P.tl_apply)[li];
   TermArgs t = term_args(h, apply_set(h, f32, P.src), tl, f32, h->xin0, ldin);
+  t.xin32 = x32;
   t.alpha = alpha;
   t.beta = beta;
   t.v = v;
@@ -1538,7 +1553,7 @@ int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T) {
   const int64_t partial = h->partial_rows > 0 ? h->partial_rows
                                               : 2 * h->N + (int64_t)h->term_wgs * h->max_m;
   const int64_t items = h->n_norm_items > 0 ? h->n_norm_items : h->N / kNormRows + 1;
-  return (int64_t)nrhs * (16 * (2 * (h->N + T) + 4 * h->N + partial) + 16 * (items + h->nseg) +
+  return (int64_t)nrhs * (24 * (2 * (h->N + T)) + 16 * (4 * h->N + partial) + 16 * (items + h->nseg) +
                           4 * (int64_t)h->nl);
 }
 
