@@ -191,11 +191,9 @@ def bench_single(a):
     n = wl.problem.n
     b = torch.from_numpy(np.ascontiguousarray(b_np)).to("cuda")
     stream = torch.cuda.current_stream()
-    tune = None
-    if nrhs > 1:
-        log("autotune")
-        tune = h.autotune(nrhs, K=wl.K, level=wl.level, precision=prec)
-        log(f"autotune: {tune}")
+    log("autotune")
+    tune = h.autotune(nrhs, K=wl.K, level=wl.level, precision=prec)
+    log(f"autotune: {tune}")
     mm = nrhs >= h.tuning()["mm_min_rhs"]
     solve = lambda p=prec: h.solve(b, K=wl.K, level=wl.level, precision=p)  # noqa: E731
 
@@ -203,7 +201,15 @@ def bench_single(a):
         x = solve()
     torch.cuda.synchronize()
     log(f"timed region: {a.steps} solves")
-    wall, kernels = profiled(h, solve, a.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        x = solve()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the same solves again with HIP events around every launch (on the
+    # launch stream) for the per-kernel durations of the roofline
+    _, kernels = profiled(h, solve, a.steps)
     x = solve()
     lat = latency(solve, a.steps)
     if a.copy_calibration > 0:

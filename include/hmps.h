@@ -238,8 +238,8 @@ int hmat_export(hm_matrix_t h, const char* path);
  * FP64: four); below it, one-RHS-tile streaming kernels run (default 8).
  * term_wgs: persistent workgroups per term launch (the work lists are split
  * evenly over them; default: compute units x resident workgroups per unit).
- * Results do not depend on either value beyond rounding order.  Changing
- * term_wgs rebuilds the work lists (synchronises the stream); the handle
+ * Results do not depend on these values beyond rounding order.  Changing
+ * term_wgs or inrow_pct rebuilds the work lists (synchronises the stream); the handle
  * must not be in use on another stream meanwhile.  In hmat_tune a field of
  * 0 keeps its value and -1 restores the default. */
 typedef struct {
@@ -247,6 +247,10 @@ typedef struct {
   int32_t term_wgs;
   int32_t rhs_tile;   /* MFMA right-hand-side tile per workgroup: 16, 32 or
                          64 (0 or -1 in hmat_tune: chosen from nrhs)       */
+  int32_t inrow_pct;  /* streaming kernels: cost weight (percent) of a row of
+                         a leaf-level low-rank block against a dense panel
+                         column in the even split of the work (default 100;
+                         changing it rebuilds the work lists)              */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
@@ -254,7 +258,8 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
 /* Autotuner: times ps_solve with opts (series kind) on nrhs zero
  * right-hand sides (vectors the call allocates and frees) for every
  * candidate tuning -- term_wgs in {auto, auto/2, 2 auto, 4 auto} times
- * {streaming kernels, MFMA kernels with RHS tiles 16/32/64 up to nrhs} --
+ * {streaming kernels with inrow_pct 100/150/200, MFMA kernels with RHS
+ * tiles 16/32/64 up to nrhs} --
  * and keeps the fastest on the handle (median of five timed calls after
  * two warm-ups, HIP events on hip_stream).  best and best_ms (nullable)
  * receive the choice and its time per solve.  Synchronises the stream. */

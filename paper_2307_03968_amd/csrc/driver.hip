@@ -114,6 +114,7 @@ struct hm_matrix {
   std::vector<hm::GroupList> sa_mm;
   int mm_min_rhs = 8;           // right-hand sides from which the MFMA kernels run
   int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
+  int inrow_pct = 100;          // cost weight (%) of in-row rows in the work split
   // per-leaf column layout of the panels, kept to rebuild the work lists
   std::vector<int64_t> near_cols, ir_cols;
   std::vector<int32_t> ir_ncol_h;
@@ -214,7 +215,8 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     for (auto& r : dense[a])
       if (r.second > r.first) segs.push_back({a, 0, r.first, r.second, 0, m});
     if (inrow_rows[a] > 0)
-      segs.push_back({a, 1, 0, inrow_rows[a], inrow_col[a], (int64_t)inrow_ncol[a] + m});
+      segs.push_back({a, 1, 0, inrow_rows[a], inrow_col[a],
+                      ((int64_t)inrow_ncol[a] + m) * h->inrow_pct / 100});
     if (segs.size() == first) segs.push_back({a, 0, 0, 0, 0, 0});  // epilogue only
     for (size_t k = first; k < segs.size(); ++k) total += (segs[k].u1 - segs[k].u0) * segs[k].cost;
   }
@@ -1359,6 +1361,10 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
     set_error("bad tuning values");
     return HM_EINVAL;
   }
+  if (t->inrow_pct < -1 || t->inrow_pct > 1000) {
+    set_error("bad tuning values");
+    return HM_EINVAL;
+  }
   if (t->mm_min_rhs > 0) h->mm_min_rhs = t->mm_min_rhs;
   if (t->mm_min_rhs == -1) h->mm_min_rhs = 8;
   if (t->rhs_tile > 0) h->rhs_tile = t->rhs_tile;
@@ -1366,9 +1372,13 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
   int wgs = h->term_wgs;
   if (t->term_wgs > 0) wgs = t->term_wgs;
   if (t->term_wgs == -1) wgs = h->term_wgs_auto;
-  if (wgs != h->term_wgs) {
+  int pct = h->inrow_pct;
+  if (t->inrow_pct > 0) pct = t->inrow_pct;
+  if (t->inrow_pct == -1) pct = 100;
+  if (wgs != h->term_wgs || pct != h->inrow_pct) {
     HIPCHK(hipSetDevice(h->device));
     h->term_wgs = wgs;
+    h->inrow_pct = pct;
     STCHK(build_lists(h, (hipStream_t)hip_stream));
   }
   return HM_OK;
@@ -1379,6 +1389,7 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out) {
   out->mm_min_rhs = h->mm_min_rhs;
   out->term_wgs = h->term_wgs;
   out->rhs_tile = h->rhs_tile;
+  out->inrow_pct = h->inrow_pct;
   return HM_OK;
 }
 
@@ -1420,6 +1431,8 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
   };
   const int autow = h->term_wgs_auto;
   std::vector<int> wgs = {autow, std::max(1, autow / 2), 2 * autow, 4 * autow};
+  // in-row weights matter only for the streaming kernels' work split
+  std::vector<int> pcts = {100, 150, 200};
   struct Cand { int mm_min, tile; };
   std::vector<Cand> paths = {{1 << 30, 0}};  // streaming kernels
   if (nrhs >= 2) {
@@ -1427,28 +1440,33 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
     if (nrhs > 16) paths.push_back({1, 32});
     if (nrhs > 32) paths.push_back({1, 64});
   }
-  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile};
+  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct};
   double bms = INFINITY;
   for (int w : wgs) {
-    if (w != h->term_wgs) {
-      h->term_wgs = w;
-      STCHK(build_lists(h, st));
-    }
-    for (const Cand& c : paths) {
-      h->mm_min_rhs = c.mm_min;
-      h->rhs_tile = c.tile;
-      double ms = 0;
-      STCHK(time_one(&ms));
-      if (ms < bms) {
-        bms = ms;
-        bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile};
+    for (int pct : pcts) {
+      if (w != h->term_wgs || pct != h->inrow_pct) {
+        h->term_wgs = w;
+        h->inrow_pct = pct;
+        STCHK(build_lists(h, st));
+      }
+      for (const Cand& c : paths) {
+        if (pct != 100 && c.mm_min == 1) continue;  // MFMA lists have no in-row rows
+        h->mm_min_rhs = c.mm_min;
+        h->rhs_tile = c.tile;
+        double ms = 0;
+        STCHK(time_one(&ms));
+        if (ms < bms) {
+          bms = ms;
+          bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile, pct};
+        }
       }
     }
   }
   h->mm_min_rhs = bt.mm_min_rhs;
   h->rhs_tile = bt.rhs_tile;
-  if (h->term_wgs != bt.term_wgs) {
+  if (h->term_wgs != bt.term_wgs || h->inrow_pct != bt.inrow_pct) {
     h->term_wgs = bt.term_wgs;
+    h->inrow_pct = bt.inrow_pct;
     STCHK(build_lists(h, st));
   }
   HIPCHK(hipStreamSynchronize(st));

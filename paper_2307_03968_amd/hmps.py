@@ -66,7 +66,8 @@ class ps_server_stats(C.Structure):
 
 
 class hm_tuning(C.Structure):
-    _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32), ("rhs_tile", C.c_int32)]
+    _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32), ("rhs_tile", C.c_int32),
+                ("inrow_pct", C.c_int32)]
 
 
 class hm_info(C.Structure):
@@ -234,15 +235,17 @@ class HMatrix:
                     for lev in range(HM_MAX_LEVELS) if i.far_blocks[lev]}
         return d
 
-    def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, rhs_tile: int = 0, stream=None) -> None:
+    def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, rhs_tile: int = 0, inrow_pct: int = 0,
+             stream=None) -> None:
         """hmat_tune: 0 keeps a value, -1 restores its default."""
-        t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile))
+        t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile), int(inrow_pct))
         _check(_lib().hmat_tune(self._h, C.byref(t), _stream(stream)), "hmat_tune")
 
     def tuning(self) -> dict:
         t = hm_tuning()
         _check(_lib().hmat_get_tuning(self._h, C.byref(t)), "hmat_get_tuning")
-        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile}
+        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
+                "inrow_pct": t.inrow_pct}
 
     def autotune(self, nrhs: int, K: int, level: int = -1, precision: int = HM_F64,
                  stream=None):
@@ -252,7 +255,8 @@ class HMatrix:
         ms = C.c_double()
         _check(_lib().hmat_autotune(self._h, C.byref(o), int(nrhs), _stream(stream), C.byref(t),
                                     C.byref(ms)), "hmat_autotune")
-        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile}, ms.value
+        return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
+                "inrow_pct": t.inrow_pct}, ms.value
 
     def export(self, path: str) -> None:
         _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")

@@ -451,4 +451,4 @@ def test_autotune_choice_keeps_results(many_rhs):
     assert ms > 0 and c.h.tuning() == best
     x = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
     assert series.rel_err(x, ref) <= 1e-5
-    c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1)
+    c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1, inrow_pct=-1)
