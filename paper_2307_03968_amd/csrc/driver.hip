@@ -1268,7 +1268,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
                       ldx, nrhs, want, st));
   }
   std::vector<double> growth(nrhs, 0.0), resid(nrhs, 0.0);
-  std::vector<int> passes(nrhs, 0), done(nrhs, 0);
+  std::vector<int> passes(nrhs, 0), done(nrhs, 0), rising(nrhs, 0);
   auto read_norms = [&]() -> int {
     HIPCHK(hipMemcpyAsync(h->norms_host, h->norms, sizeof(double) * 2 * ns * nrhs,
                           hipMemcpyDeviceToHost, st));
@@ -1306,9 +1306,12 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     for (int c = 0; c < nrhs; ++c) {
       const double rel = ratio(c);  // max over instances of |d| / |x|
       if (!done[c]) {
+        // a correction that grew five passes in a row means the series
+        // does not contract (rho^(K+1) >= 1): stop, reported as diverged
+        rising[c] = (pass > 1 && !(rel < resid[c])) ? rising[c] + 1 : 0;
         resid[c] = rel;
         passes[c] = pass;
-        if (rel <= o->refine_tol) done[c] = 1;
+        if (rel <= o->refine_tol || (adaptive && rising[c] >= 5)) done[c] = 1;
       }
       all = all && done[c];
     }

@@ -452,3 +452,15 @@ def test_autotune_choice_keeps_results(many_rhs):
     x = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
     assert series.rel_err(x, ref) <= 1e-5
     c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1, inrow_pct=-1)
+
+
+def test_refine_stops_when_the_series_does_not_contract(cube):
+    """rho(D^{-1} R) = 1.13 on the 1,000-point cube: refinement cannot reach
+    x*; the corrections grow and the solve stops early, flagged diverged."""
+    rho = series.rho(cube.H)
+    assert rho ** 6 > 1
+    _say("refine cube_1000 (divergent)")
+    x, st = cube.h.solve(_dev(cube.b), K=5, precision=hmps.HM_F64, kind=hmps.PS_REFINE,
+                         max_passes=200, refine_tol=1e-10, stats=True)
+    for s in st:
+        assert s["diverged"] == 1 and s["passes"] < 60, s
