@@ -58,7 +58,7 @@ enum { HM_SURFACE = 0, HM_VOLUME = 1 };
 enum { HM_F64 = 0, HM_F32_APPLY = 1 };
 /* PS_SERIES: return x_K.  PS_REFINE: x <- x + P_K(b - Z_l x) passes (P_K is
  * the K-term series operator, residual in FP64) until the correction is
- * below refine_tol relative to x (or until it has grown five passes in a
+ * below refine_tol relative to x (or until its norm has grown five passes in a
  * row: the series does not contract, reported as diverged); the fixed
  * point is Z_l^{-1} b and the per-pass error factor is rho(D^{-1} R_l)^{K+1}.  PS_REFINE_FIXED: exactly
  * max_passes such passes with no host synchronisation (refine_tol only

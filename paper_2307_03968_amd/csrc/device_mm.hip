@@ -98,17 +98,21 @@ struct MMAcc {
 
 // acc += P[rows of this wave's tiles, c0:c1) * X[c0:c1, tile].  colp(c)
 // points (XT: double2, or float2 for FP32 shadows of the inputs) at input
-// column c's value for the tile's first right-hand side
-// (right-hand side n at colp(c)[n * ldx]); nv right-hand sides of the tile
-// are valid.  Software pipelined: the inputs of column chunk j + 1 are
-// loaded into registers while chunk j is multiplied (two LDS buffers, one
-// barrier per chunk); the panel loads of the next group of 16 columns are
-// issued before the products of the current group into the other of two
-// register sets (a chunk is two groups, so the sets alternate without
-// copies).  Every load is issued unconditionally at a clamped address (the
-// values past c1 or past the last right-hand side are replaced by zero),
-// so the memory-counter waits before each group cover only the loads that
-// group needs.
+// column c's value for the tile's first right-hand side (right-hand side n
+// at colp(c)[n * ldx]); nv right-hand sides of the tile are valid.
+// Software pipelined one chunk of NG groups of 16 columns ahead: the inputs
+// of chunk j + 1 are loaded into registers while chunk j is multiplied (two
+// LDS buffers, one barrier per chunk), and each group's panel registers are
+// refilled with the same group of the next chunk right after their
+// products (NG register sets, no copies).  Every load is issued
+// unconditionally at a clamped address (values past c1 or past the last
+// right-hand side are replaced by zero), so the memory-counter waits before
+// each group cover only the loads that group needs.
+template <bool F32, int RT>
+struct Groups {  // groups of 16 columns per staged chunk (4 measured no faster)
+  static constexpr int NG = 2;
+};
+
 template <bool F32, int RT, int NT, typename XT, typename COLP>
 __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld, int row0,
                                         int c0, int c1, const COLP& colp, int64_t ldx, int nv,
@@ -116,7 +120,8 @@ __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld,
   using PR = Prec<F32>;
   using AV = typename std::conditional<F32, float2, double2>::type;
   constexpr int NRT = 16 * NT;
-  constexpr int CH = 32;                       // columns per staged chunk = 2 groups
+  constexpr int NG = Groups<F32, RT>::NG;
+  constexpr int CH = 16 * NG;                  // columns per staged chunk
   constexpr int NPT = kThreads / CH;           // right-hand sides apart per thread
   constexpr int XPT = CH * NRT / kThreads;     // staged inputs per thread
   __shared__ typename PR::X xs[2][CH][NRT + 1];  // +1: spreads the banks of column writes
@@ -140,10 +145,9 @@ __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld,
   };
   auto store_x = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < XPT; ++i)
-      xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : XT{});
+    for (int i = 0; i < XPT; ++i) xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : XT{});
   };
-  AV a0[4][RT], a1[4][RT];
+  AV a[NG][4][RT];
   auto load_a = [&](int cg, AV (&dst)[4][RT]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
@@ -153,31 +157,33 @@ __device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld,
     }
   };
   // columns past c1 hold zero inputs (and clamped panel columns), so every
-  // chunk runs both groups of four k-steps without branches
-  auto group = [&](const AV (&a)[4][RT], int buf, int kk) {
+  // chunk runs all its groups of four k-steps without branches
+  auto group = [&](const AV (&av)[4][RT], int buf, int kk) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const typename PR::X b = xs[buf][kk + 4 * s + kq][t * 16 + l16];
 #pragma unroll
-        for (int r = 0; r < RT; ++r) PR::mac(acc.a[r][t], a[s][r], b);
+        for (int r = 0; r < RT; ++r) PR::mac(acc.a[r][t], av[s][r], b);
       }
     }
   };
   const int nchunks = (c1 - c0 + CH - 1) / CH;
   load_x(c0);
   store_x(0);
-  load_a(c0, a0);
+#pragma unroll
+  for (int g = 0; g < NG; ++g) load_a(c0 + 16 * g, a[g]);
   __syncthreads();
   for (int j = 0; j < nchunks; ++j) {
     const int cb = c0 + j * CH;
     const int buf = j & 1;
     load_x(cb + CH);  // past the last chunk: zeros, never read
-    load_a(cb + 16, a1);
-    group(a0, buf, 0);
-    load_a(cb + CH, a0);
-    group(a1, buf, 16);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      group(a[g], buf, 16 * g);
+      load_a(cb + CH + 16 * g, a[g]);
+    }
     store_x(buf ^ 1);
     __syncthreads();
   }

@@ -1269,6 +1269,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   }
   std::vector<double> growth(nrhs, 0.0), resid(nrhs, 0.0);
   std::vector<int> passes(nrhs, 0), done(nrhs, 0), rising(nrhs, 0);
+  std::vector<double> prev_d((size_t)ns * nrhs, INFINITY);  // ||d|| per (column, instance)
   auto read_norms = [&]() -> int {
     HIPCHK(hipMemcpyAsync(h->norms_host, h->norms, sizeof(double) * 2 * ns * nrhs,
                           hipMemcpyDeviceToHost, st));
@@ -1305,10 +1306,22 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     bool all = true;
     for (int c = 0; c < nrhs; ++c) {
       const double rel = ratio(c);  // max over instances of |d| / |x|
+      // a correction whose norm grew (for some instance not yet within the
+      // tolerance) five passes in a row means the series does not contract
+      // (rho^(K+1) >= 1): stop, reported as diverged
+      bool grew = false;
+      for (int g = 0; g < ns; ++g) {
+        const double xn = std::sqrt(h->norms_host[(int64_t)c * ns + g]);
+        const double dn = std::sqrt(h->norms_host[(int64_t)(nrhs + c) * ns + g]);
+        double& pd = prev_d[(size_t)c * ns + g];
+        // instances already within the tolerance sit at their rounding
+        // floor, where the correction no longer shrinks: they do not count
+        const bool open = !(dn <= o->refine_tol * xn);
+        if (open && !(dn < pd)) grew = true;
+        pd = dn;
+      }
       if (!done[c]) {
-        // a correction that grew five passes in a row means the series
-        // does not contract (rho^(K+1) >= 1): stop, reported as diverged
-        rising[c] = (pass > 1 && !(rel < resid[c])) ? rising[c] + 1 : 0;
+        rising[c] = grew ? rising[c] + 1 : 0;
         resid[c] = rel;
         passes[c] = pass;
         if (rel <= o->refine_tol || (adaptive && rising[c] >= 5)) done[c] = 1;
