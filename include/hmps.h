@@ -167,6 +167,10 @@ typedef struct {
   int64_t stageA_entries[HM_MAX_LEVELS];
   int64_t coeffs[HM_MAX_LEVELS];
   int32_t num_instances;            /* 1, or the count of a batched handle  */
+  int64_t half_entries[HM_MAX_LEVELS]; /* panel entries the half-storage
+                                        product reads per term: near
+                                        blocks (t, s > t) once, plus the
+                                        far U columns (0: not symmetric) */
 } hm_info;
 
 /* Kernel classes timed by hm_profile_enable. */
@@ -252,6 +256,13 @@ typedef struct {
                          a leaf-level low-rank block against a dense panel
                          column in the even split of the work (default 100;
                          changing it rebuilds the work lists)              */
+  int32_t half_storage; /* 1: one right-hand side on a symmetric (surface)
+                         problem (below mm_min_rhs) runs the half-storage
+                         product: each off-diagonal near block Z_ts, s > t,
+                         is read once and applied in both orientations
+                         (Z_st = Z_ts^T), then D^{-1} (series) or D
+                         (H-matvec) is applied block by block (default);
+                         2: the premultiplied panels                    */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
@@ -260,7 +271,8 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
  * right-hand sides (vectors the call allocates and frees) for every
  * candidate tuning -- term_wgs in {auto, auto/2, 2 auto, 4 auto} times
  * {streaming kernels with inrow_pct 100/150/200, MFMA kernels with RHS
- * tiles 16/32/64 up to nrhs} --
+ * tiles 16/32/64 up to nrhs}, and the half-storage kernel where it
+ * applies --
  * and keeps the fastest on the handle (median of five timed calls after
  * two warm-ups, HIP events on hip_stream).  best and best_ms (nullable)
  * receive the choice and its time per solve.  Synchronises the stream. */

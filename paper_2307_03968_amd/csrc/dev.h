@@ -135,6 +135,44 @@ struct NormItem {
   int64_t r0, r1;
 };
 
+// Half-storage product R y for symmetric (surface) problems, one
+// right-hand side.  Z_st = Z_ts^T, so per row leaf t only the near blocks
+// Z_ts with s > t are stored, side by side as the leaf's half panel (ld
+// even(m_t), unpremultiplied).  Streaming a half-panel column j (row jj of
+// source leaf s) gives both u_t += Z[:, j] y_s[jj] and v_j = Z[:, j]^T y_t,
+// which is row jj of Z_st y_t: v_j goes to slot j of the vector vb and the
+// epilogue of leaf s adds it in.  Far blocks keep their per-orientation
+// form (in-row W stacks and the U columns of the apply panels).  The
+// workgroup that completes a leaf writes z = alpha R y + beta v through the
+// TermArgs epilogue; the diagonal block (D or D^{-1}) is a second,
+// block-diagonal launch of the ordinary term kernel.
+// Pieces are TermItems with the apply panels as the panel set, taken by the
+// persistent workgroups one at a time from a queue (a device counter):
+//  kind 0: apply-panel columns [c0, c1) through src (global far U slices)
+//  kind 1: in-row far rows [r0, r1) of the W stack, apply-panel columns c0..
+//  kind 2: half-panel columns [c0, c1) of the leaf; its v values go to the
+//          leaves vleaf[r0, r1) (the blocks the columns cover)
+struct HalfArgs {
+  TermArgs t;                // ps = apply panels; lptr/lprow = u partials
+  const void* hp;            // half panels: double2 (FP64) or float2 (FP32)
+  const int64_t* hp_off;     // per leaf: element offset of its half panel
+  const int32_t* hp_col;     // per leaf (+ end): first global half-panel column
+  const int32_t* hsrc;       // per global half-panel column: row of y it reads
+  double2* vb;               // per global half-panel column: v
+  const int32_t* vptr;       // per leaf: first entry in vstart (nleaves + 1)
+  const int32_t* vstart;     // vb slot of row 0 of block (t, leaf), t < leaf, by t
+  const int32_t* lcnt;       // per leaf: counter increments before its epilogue
+  const int32_t* vleaf;      // target leaves of the kind-2 pieces
+  int npieces;               // pieces in t.items, taken in order from a queue
+  int32_t* queue;            // [next piece, workgroups done]; zero between launches
+};
+hipError_t launch_half(bool f32, int max_m, const HalfArgs& a, int nwg, hipStream_t st);
+int half_occupancy(bool f32, int max_m);
+constexpr int kMaxVLeaves = 8;  // target leaves (blocks) per kind-2 piece
+constexpr int kHalfMaxLeaf = 128;  // largest leaf the half-storage product serves
+constexpr int kHalfChunk = 1024;   // input columns of a kind-0 half-list piece (at most)
+constexpr int kHalfPieceCols = 384;  // half-panel columns of a kind-2 piece (at most)
+
 constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)
 constexpr int kGroupTile = 128;  // rows per stage-A group item
 // Many right-hand sides (MFMA path): stage A uses groups over all far blocks

@@ -1,0 +1,406 @@
+// Half-storage product kernel of libhmps for symmetric (surface) problems,
+// one right-hand side: z = alpha R y + beta v with every off-diagonal near
+// block read once (the symmetric operator of Sec. II carried into the
+// series of Sec. IV).
+//
+// The surface operator is symmetric, so the near block Z_st (s > t) is the
+// transpose of Z_ts.  Each row leaf t keeps only its blocks Z_ts, s > t,
+// side by side as one column-major half panel.  A workgroup streams a range
+// of half-panel columns exactly as the ordinary term kernel streams panel
+// columns (lane = row, 16-byte loads, eight columns in flight per wave) and
+// forms two products from each loaded column j:
+//   u_t += Z[:, j] y[src_j]                     (rows of t, like a panel)
+//   v_j  = Z[:, j]^T y_t                        (one value per column)
+// v_j is a sum over the rows, i.e. over the lanes of one wave: eight columns
+// are reduced together with a butterfly whose first three exchanges halve
+// the set of columns (ten exchanges for eight sums) and stored to slot j of
+// vb.  v_j is row jj of Z_st y_t when column j is row jj of leaf s, so the
+// epilogue of leaf s adds the vb slots of its blocks (t, s) to its partial
+// sums.  Far blocks are unchanged (in-row W stacks and the U columns of the
+// apply panels, unpremultiplied).
+//
+// Completion: each piece counts once for its own leaf and once for every
+// leaf its v values go to; the workgroup that brings a leaf's counter to
+// its total sums the leaf's u partials and vb slots in a fixed order and
+// writes z.  The diagonal block is applied by a separate block-diagonal
+// launch of the term kernel (D^{-1} z for a series term, D x + z for the
+// H-matvec).  Relative to the D^{-1}-premultiplied panels this reads the
+// off-diagonal near blocks once instead of twice.
+#include <hip/hip_runtime.h>
+
+#include "dev.h"
+
+namespace hm {
+
+namespace {
+
+#include "gemv_inl.h"
+
+// 32-bit lane moves within rows of the wave (DPP), applied to both halves
+// of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over the sixteen lanes of each row of the wave (every lane of the
+// row ends with the total): quad_perm [1,0,3,2], quad_perm [2,3,0,1], the
+// mirror within each half row (lane i <-> 7 - i) pairs the quads, the
+// mirror within the row (lane i <-> 15 - i) pairs the half rows.
+__device__ __forceinline__ double sum16_lanes(double v) {
+  v += dpp_d<0xB1>(v);
+  v += dpp_d<0x4E>(v);
+  v += dpp_d<0x141>(v);
+  v += dpp_d<0x140>(v);
+  return v;
+}
+
+// Device-coherent (agent-scope) store of a value read by other workgroups
+// of the same launch.
+__device__ __forceinline__ void store_agent(double2* q, double2 z) {
+  double* d = reinterpret_cast<double*>(q);
+  __hip_atomic_store(d, z.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(d + 1, z.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// acc += a * x (complex) with nxy = -x.y given: the negation sits on the
+// operand shared by many products instead of on each loaded element.
+__device__ __forceinline__ void cmac_n(double2& acc, double2 a, double2 x, double nxy) {
+  acc.x = fma(a.x, x.x, acc.x);
+  acc.x = fma(a.y, nxy, acc.x);
+  acc.y = fma(a.x, x.y, acc.y);
+  acc.y = fma(a.y, x.x, acc.y);
+}
+
+// 16-byte buffer load (non-temporal) of byte offset voff + IMM from the
+// buffer rsrc: offsets past the buffer's size read zeros.
+typedef int ivec4 __attribute__((ext_vector_type(4)));
+template <int E>
+__device__ __forceinline__ typename Elem<E>::T bload(__amdgpu_buffer_rsrc_t rs, uint32_t voff) {
+  const ivec4 v = __builtin_bit_cast(ivec4, __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 0, 2));
+  if constexpr (E == 1) {
+    const dvec2 d = __builtin_bit_cast(dvec2, v);
+    return make_double2(d.x, d.y);
+  } else {
+    const fvec4 f = __builtin_bit_cast(fvec4, v);
+    return make_float4(f.x, f.y, f.z, f.w);
+  }
+}
+
+// Half-panel columns [cb, ce) of one leaf (column-major, leading dimension
+// ld, nb bytes in all).  Lane (r, c) = (lane & 15, lane >> 4) reads rows
+// 16E g + E r .. + E-1 (g < RG) of column c of a four-column step, so a load
+// instruction reads 256 contiguous bytes of each of four columns and each
+// tile is read once.  Loads go through a buffer descriptor of the panel:
+// one offset register per step, the row groups as immediate offsets, and
+// rows past the panel's end read zeros (rows past m of other columns are
+// read but meet y_t = 0, and their u is never stored).  Wave w takes NC
+// four-column steps at a time (columns j0 + 4 kWaves st + c) and issues
+// all their loads before using them.  Per lane:
+//   u[g] (the lane's rows, partial over its columns) += Z x_c
+//   p    (column c, partial over the lane's rows)    += Z^T y_t
+// p is summed over the sixteen row lanes of its column (DPP) and kept in
+// LDS (vl[j - cb]); the caller writes the chunk's v values out in one
+// coalesced pass, so the streaming loop issues no global stores.  Columns
+// past ce re-read column ce - 1 with a zero input and keep no v.
+template <int E, int RG, int NC>
+__device__ __forceinline__ void half_tile(const void* __restrict__ P, uint32_t ld, uint32_t nb,
+                                          int cb, int ce, int w, int lane, const double2* xs,
+                                          const double2* ys, double2 (&u)[RG][E], double2* vl) {
+  using T = typename Elem<E>::T;
+  constexpr uint32_t kES = E == 1 ? 16 : 8;  // bytes per complex element
+  const int r = lane & 15, c = lane >> 4;
+  // the descriptor is wave-uniform (one leaf per piece); say so, so that it
+  // lives in scalar registers
+  const uint64_t pa = reinterpret_cast<uint64_t>(P);
+  const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
+  const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
+  void* pu = reinterpret_cast<void*>(((uint64_t)phi << 32) | plo);
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      pu, 0, (int)__builtin_amdgcn_readfirstlane(nb), 0x00020000);
+  const uint32_t lane_off = (uint32_t)(E * r) * kES;
+  const uint32_t ldb = ld * kES;
+  double2 yt[RG][E];
+  double nyt[RG][E];
+#pragma unroll
+  for (int g = 0; g < RG; ++g)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      yt[g][e] = ys[16 * E * g + E * r + e];
+      nyt[g][e] = -yt[g][e].y;
+    }
+  for (int j0 = cb + 4 * w; j0 < ce; j0 += 4 * kWaves * NC) {
+    T a[NC][RG];
+#pragma unroll
+    for (int st = 0; st < NC; ++st) {
+      const uint32_t vo = lane_off + (uint32_t)min(j0 + 4 * kWaves * st + c, ce - 1) * ldb;
+#pragma unroll
+      for (int g = 0; g < RG; ++g) a[st][g] = bload<E>(rs, vo + g * 16 * E * kES);
+    }
+#pragma unroll
+    for (int st = 0; st < NC; ++st) {
+      const int jj = j0 + 4 * kWaves * st + c;
+      const bool ok = jj < ce;
+      const double2 x = ok ? xs[jj - cb] : zero2();
+      const double nx = -x.y;
+      double2 pv = zero2();
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double2 z = Elem<E>::get(a[st][g], e);
+          cmac_n(u[g][e], z, x, nx);
+          cmac_n(pv, z, yt[g][e], nyt[g][e]);
+        }
+      pv.x = sum16_lanes(pv.x);
+      pv.y = sum16_lanes(pv.y);
+      if (r == 0 && ok) vl[jj - cb] = pv;
+    }
+  }
+}
+
+// z += the n entries base[offs[k] + row] (row = thread index < m), in list
+// order; offsets staged through LDS, eight loads in flight per thread.
+__device__ __forceinline__ void gather_sum(const double2* base, const int32_t* offs, int n, int m,
+                                           int* s_off, double2& z) {
+  for (int q0 = 0; q0 < n; q0 += kThreads) {
+    const int nq = min(kThreads, n - q0);
+    __syncthreads();
+    if ((int)threadIdx.x < nq) s_off[threadIdx.x] = offs[q0 + threadIdx.x];
+    __syncthreads();
+    if ((int)threadIdx.x < m) {
+      const double* pc = reinterpret_cast<const double*>(base + threadIdx.x);
+      for (int p = 0; p < nq; p += 8) {
+        double vr[8], vi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (p + u < nq) {
+            const double* q = pc + 2 * (int64_t)s_off[p + u];
+            vr[u] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            vi[u] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          } else {
+            vr[u] = 0.0;
+            vi[u] = 0.0;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          z.x += vr[u];
+          z.y += vi[u];
+        }
+      }
+    }
+  }
+}
+
+// Epilogue of leaf a: z = its u partials then its vb slots (fixed order),
+// then y = alpha z + beta v and the stores of the TermArgs epilogue; the
+// leaf's counter is cleared for the next launch.
+__device__ void half_epilogue(const HalfArgs& A, int a, int* s_off) {
+  const int m = A.t.ps.leaf_m[a];
+  double2 z = zero2();
+  gather_sum(A.t.partial, A.t.lprow + A.t.lptr[a], A.t.lptr[a + 1] - A.t.lptr[a], m, s_off, z);
+  gather_sum(A.vb, A.vstart + A.vptr[a], A.vptr[a + 1] - A.vptr[a], m, s_off, z);
+  if ((int)threadIdx.x < m) finish_entry(A.t, A.t.leaf_off[a], threadIdx.x, 0, z);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(A.t.counters + a, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Persistent workgroup over its run of pieces (see the file comment).
+// Half-panel pieces use the row-group tiles of half_tile (RG groups of 16E
+// rows); the far pieces use the lane-per-row GEMV of the term kernel (G
+// groups of 64E rows).
+template <int E, int G, int RG, int NC>
+__global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
+  constexpr int UNR = 8;
+  constexpr int MR = 16 * E * RG;  // rows a half-panel piece covers
+  const TermArgs& T = A.t;
+  const int w = wave_id();
+  const int lane = threadIdx.x & 63;
+  __shared__ double2 red[(kWaves - 1) * G * E * 64];
+  __shared__ double2 ured[kWaves][MR];
+  __shared__ double2 ys[MR];
+  __shared__ double2 tbuf[kInRowTile];
+  __shared__ double2 xs[kHalfChunk];
+  __shared__ double2 vl[kHalfChunk];
+  __shared__ int s_off[kThreads];
+  __shared__ int s_last[kMaxVLeaves + 1];
+  __shared__ int s_nlast, s_next;
+  // Pieces come from a queue: a workgroup takes the next ticket as it
+  // starts a piece (the atomic's result is needed only when the piece is
+  // done), so faster workgroups take more pieces and no static split has
+  // to predict how long each piece takes.
+  if (threadIdx.x == 0)
+    s_next = __hip_atomic_fetch_add(A.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  int p = s_next;
+  while (p < A.npieces) {
+    int ticket = 0;
+    if (threadIdx.x == 0)
+      ticket = __hip_atomic_fetch_add(A.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const TermItem it = T.items[p];
+    const int a = it.leaf;
+    const int m = T.ps.leaf_m[a];
+    const int64_t ld = m + (m & 1);
+    const int nc = it.c1 - it.c0;  // at most kHalfChunk for kinds 0 and 2
+    if (it.kind == 2) {
+      const int64_t off = T.leaf_off[a];
+      const int32_t* __restrict__ hsrc = A.hsrc + A.hp_col[a];
+      for (int i = threadIdx.x; i < MR; i += kThreads) ys[i] = i < m ? T.xin[off + i] : zero2();
+      for (int k = threadIdx.x; k < nc; k += kThreads) xs[k] = T.xin[hsrc[it.c0 + k]];
+      __syncthreads();
+      const void* HP = Elem<E>::offset(A.hp, A.hp_off[a]);
+      const uint32_t nbytes =
+          (uint32_t)(ld * (A.hp_col[a + 1] - A.hp_col[a]) * (E == 1 ? 16 : 8));
+      double2 u[RG][E];
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) u[g][e] = zero2();
+      half_tile<E, RG, NC>(HP, (uint32_t)ld, nbytes, it.c0, it.c1, w, lane, xs, ys, u, vl);
+      // u over the four column lanes of each row (lane bits 4, 5), then
+      // over the waves in a fixed order
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int sh = 16; sh < 64; sh <<= 1) {
+            u[g][e].x += __shfl_xor(u[g][e].x, sh);
+            u[g][e].y += __shfl_xor(u[g][e].y, sh);
+          }
+      if ((lane >> 4) == 0) {
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+          for (int e = 0; e < E; ++e) ured[w][16 * E * g + E * lane + e] = u[g][e];
+      }
+      __syncthreads();
+      for (int i = threadIdx.x; i < m; i += kThreads) {
+        double2 z = ured[0][i];
+#pragma unroll
+        for (int v = 1; v < kWaves; ++v) {
+          z.x += ured[v][i].x;
+          z.y += ured[v][i].y;
+        }
+        store_agent(T.partial + it.prow + i, z);
+      }
+      double2* vb = A.vb + A.hp_col[a] + it.c0;
+      for (int k = threadIdx.x; k < nc; k += kThreads) store_agent(vb + k, vl[k]);
+    } else {
+      // far pieces (kind 0, 1) and pieces of leaves with no work of their
+      // own (which publish zeros): lane-per-row GEMV on the apply panel
+      double2 acc[G][E][1];
+      zero_acc(acc);
+      if (it.kind == 0) {
+        const void* P = Elem<E>::offset(T.ps.data, T.ps.panel_off[a]);
+        const int32_t* __restrict__ src = T.ps.src + T.ps.col_off[a];
+        for (int k = threadIdx.x; k < nc; k += kThreads) xs[k] = T.xin[src[it.c0 + k]];
+        __syncthreads();
+        const double2* xq = xs - it.c0;
+        auto X = [&](int c, int) -> double2 { return xq[c]; };
+        tall_gemv<E, G, 1, UNR>(P, ld, m, 0, it.c0, it.c1, w, lane, X, acc);
+      } else if (it.kind == 1) {
+        const void* P = Elem<E>::offset(T.ps.data, T.ps.panel_off[a]);
+        double2 tacc[1][E][1];
+        zero_acc(tacc);
+        const int rb = T.ir.row0[a];
+        inrow_t<E, 1, 1, 4>(Elem<E>::offset(T.ir.W, T.ir.off[a]), T.ir.ld[a], T.ir.ncol[a],
+                            it.r0, it.r1, T.ir.soff + rb, T.ir.n + rb, T.xin, T.ldx, 0, 1, w,
+                            lane, tacc);
+        reduce_waves(tacc, w, lane, red);
+        if (w == 0) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int k = lane * E + e;
+            if (k < kInRowTile) tbuf[k] = tacc[0][e][0];
+          }
+        }
+        __syncthreads();
+        auto X = [&](int c, int) -> double2 { return tbuf[c - it.c0]; };
+        tall_gemv<E, G, 1, UNR>(P, ld, m, 0, it.c0, it.c0 + (it.r1 - it.r0), w, lane, X, acc);
+      }
+      reduce_waves(acc, w, lane, red);
+      if (w == 0) {
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const int i = (g * 64 + lane) * E + e;
+            if (i < m) store_agent(T.partial + it.prow + i, acc[g][e][0]);
+          }
+      }
+    }
+    // every store of the piece is complete before it is counted
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) s_nlast = 0;
+    __syncthreads();
+    const int nv = it.kind == 2 ? it.r1 - it.r0 : 0;
+    if ((int)threadIdx.x <= nv) {
+      const int leaf = threadIdx.x == 0 ? a : A.vleaf[it.r0 + threadIdx.x - 1];
+      const int old = __hip_atomic_fetch_add(T.counters + leaf, 1, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+      if (old == A.lcnt[leaf] - 1) s_last[atomicAdd(&s_nlast, 1)] = leaf;
+    }
+    __syncthreads();
+    const int nlast = s_nlast;
+    for (int k = 0; k < nlast; ++k) half_epilogue(A, s_last[k], s_off);
+    if (threadIdx.x == 0) s_next = ticket;
+    __syncthreads();
+    p = s_next;
+  }
+  // the last workgroup out clears the queue for the next launch (every
+  // workgroup has taken its last ticket before it counts itself out)
+  if (threadIdx.x == 0) {
+    const int done = __hip_atomic_fetch_add(A.queue + 1, 1, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    if (done == (int)gridDim.x - 1) {
+      __hip_atomic_store(A.queue, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(A.queue + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+template <int E, int G, int RG, int NC>
+int occ_half() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_half<E, G, RG, NC>, kThreads, 0) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
+}
+
+// Variants by the largest leaf: G = row groups of 64E rows (far pieces),
+// RG = row groups of 16E rows and NC = four-column steps in flight
+// (half-panel tiles; RG * NC loads of 16 bytes per lane in flight).
+#define HALF_VARIANTS(X)                                                       \
+  X(true, 64, 2, 1, 2, 8) X(true, 96, 2, 1, 3, 5) X(true, 128, 2, 1, 4, 3)      \
+  X(false, 64, 1, 1, 4, 6) X(false, 96, 1, 2, 6, 4) X(false, 128, 1, 2, 8, 2)
+
+}  // namespace
+
+hipError_t launch_half(bool f32, int max_m, const HalfArgs& a, int nwg, hipStream_t st) {
+  if (nwg <= 0) return hipSuccess;
+  if (max_m > kHalfMaxLeaf) return hipErrorInvalidValue;
+#define X(F, MM, E, G, RG, NC)                                                                \
+  if (f32 == F && max_m <= MM) {                                                             \
+    hipLaunchKernelGGL((k_half<E, G, RG, NC>), dim3(nwg), dim3(kThreads), 0, st, a);         \
+    return hipGetLastError();                                                                \
+  }
+  HALF_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int half_occupancy(bool f32, int max_m) {
+#define X(F, MM, E, G, RG, NC) \
+  if (f32 == F && max_m <= MM) return occ_half<E, G, RG, NC>();
+  HALF_VARIANTS(X)
+#undef X
+  return 1;
+}
+
+}  // namespace hm

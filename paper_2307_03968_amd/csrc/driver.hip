@@ -111,6 +111,29 @@ struct hm_matrix {
   float2* Wmm32 = nullptr;
   hm::Group* groups_mm = nullptr;
   std::vector<hm::TermList> tl_apply_mm, tl_series_mm;
+  // half-storage product (symmetric problems, one right-hand side): per
+  // row leaf t its near blocks (t, s > t) side by side (half panels), the
+  // source row and v slot of every half-panel column, and per-level lists
+  // whose pieces are half-panel column ranges plus the far pieces of the
+  // apply panels
+  double2* H64 = nullptr;
+  float2* H32 = nullptr;
+  int64_t* hp_off = nullptr;
+  int32_t *hp_col = nullptr, *hsrc = nullptr, *vptr = nullptr, *vstart = nullptr;
+  double2* vb = nullptr;          // one value per half-panel column
+  double2* zbuf = nullptr;        // z = R y (tree order, N)
+  int32_t* hq = nullptr;          // piece queue of the half-storage kernel (2 ints)
+  bool half_ok = false;
+  std::vector<int64_t> hp_ncol;   // per leaf: half-panel columns
+  std::vector<std::vector<int32_t>> hp_bcol, hp_bleaf;  // per leaf: block starts, leaves
+  struct HalfList {
+    hm::TermList tl;
+    int32_t *lcnt = nullptr, *vleaf = nullptr;
+  };
+  std::vector<HalfList> half;
+  std::vector<int64_t> ent_half;  // entries read per half-storage product, per level
+  int use_half = 1;               // 1: half storage where available, 2: panels
+  int half_pct = 100;             // cost weight (%) of half-panel columns in the work split
   std::vector<hm::GroupList> sa_mm;
   int mm_min_rhs = 8;           // right-hand sides from which the MFMA kernels run
   int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
@@ -124,6 +147,7 @@ struct hm_matrix {
   int64_t partial_rows = 0;
   int term_wgs = 1024;          // persistent workgroups of a term kernel
   int term_wgs_auto = 1024;
+  int half_wgs_auto = 512;      // resident round of the half-storage kernel
   int32_t* counters = nullptr;  // workspace
   // workspace
   int ws_nrhs = 0;
@@ -205,13 +229,15 @@ int level_index(const hm_matrix* h, int level, int* li) {
 // pieces at most kInRowTile rows).
 int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t, int64_t>>>& dense,
                   const std::vector<int64_t>& inrow_rows, const std::vector<int64_t>& inrow_col,
-                  const std::vector<int32_t>& inrow_ncol, TermList& tl, hipStream_t st) {
+                  const std::vector<int32_t>& inrow_ncol, TermList& tl, hipStream_t st,
+                  hm_matrix::HalfList* hl = nullptr) {
   struct Seg { int leaf, kind; int64_t u0, u1, col0, cost; };
   std::vector<Seg> segs;
   int64_t total = 0;
   for (int a = 0; a < h->nl; ++a) {
     const int64_t m = h->H.leaf_size[a];
     const size_t first = segs.size();
+    if (hl && h->hp_ncol[a] > 0) segs.push_back({a, 2, 0, h->hp_ncol[a], 0, m * h->half_pct / 100});
     for (auto& r : dense[a])
       if (r.second > r.first) segs.push_back({a, 0, r.first, r.second, 0, m});
     if (inrow_rows[a] > 0)
@@ -220,14 +246,74 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     if (segs.size() == first) segs.push_back({a, 0, 0, 0, 0, 0});  // epilogue only
     for (size_t k = first; k < segs.size(); ++k) total += (segs[k].u1 - segs[k].u0) * segs[k].cost;
   }
-  const int G = std::max(1, h->term_wgs);
+  // the half-storage kernel's own resident round unless a count was set
+  const int G = std::max(1, hl && h->term_wgs == h->term_wgs_auto ? h->half_wgs_auto : h->term_wgs);
   std::vector<TermItem> items;
-  std::vector<int32_t> wg_of;
+  std::vector<int32_t> wg_of, vleaf, lcnt(hl ? h->nl : 0, 0);
   int64_t rows = 0, done = 0;
+  if (hl) {
+    // Half lists are consumed dynamically (each workgroup takes the next
+    // piece from a queue): pieces of bounded size, largest estimated cost
+    // first so that the last pieces taken are small.
+    std::vector<std::pair<int64_t, TermItem>> pcs;
+    for (const Seg& sg : segs) {
+      const int m = h->H.leaf_size[sg.leaf];
+      int64_t u = sg.u0;
+      do {
+        int64_t k = sg.u1 - u;
+        if (sg.kind == 1) k = std::min<int64_t>(k, kInRowTile);  // starts stay even
+        if (sg.kind == 0) k = std::min<int64_t>(k, kHalfChunk);
+        std::vector<int32_t>::const_iterator b0, b1;
+        if (sg.kind == 2) {
+          k = std::min<int64_t>(k, kHalfPieceCols);
+          const std::vector<int32_t>& bc = h->hp_bcol[sg.leaf];
+          b0 = std::upper_bound(bc.begin(), bc.end(), (int32_t)u) - 1;
+          const int64_t nb = (int64_t)bc.size() - 1;
+          const int64_t lim = std::min<int64_t>(b0 - bc.begin() + kMaxVLeaves, nb);
+          k = std::min<int64_t>(k, bc[lim] - u);
+          b1 = std::upper_bound(bc.begin(), bc.end(), (int32_t)(u + k - 1));
+        }
+        TermItem it{sg.leaf, sg.kind, 0, 0, 0, 0, (int32_t)rows, 0};
+        if (sg.kind == 1) {
+          it.r0 = (int32_t)u;
+          it.r1 = (int32_t)(u + k);
+          it.c0 = (int32_t)(sg.col0 + u);
+          it.c1 = (int32_t)(sg.col0 + u + k);
+        } else {
+          it.c0 = (int32_t)u;
+          it.c1 = (int32_t)(u + k);
+        }
+        if (sg.kind == 2) {
+          const std::vector<int32_t>& bl = h->hp_bleaf[sg.leaf];
+          const int64_t q0 = b0 - h->hp_bcol[sg.leaf].begin(), q1 = b1 - h->hp_bcol[sg.leaf].begin();
+          it.r0 = (int32_t)vleaf.size();
+          for (int64_t q = q0; q < q1; ++q) {
+            vleaf.push_back(bl[q]);
+            lcnt[bl[q]]++;
+          }
+          it.r1 = (int32_t)vleaf.size();
+        }
+        pcs.push_back({k * sg.cost, it});
+        rows += m;
+        u += k;
+      } while (u < sg.u1);
+    }
+    std::stable_sort(pcs.begin(), pcs.end(),
+                     [](const std::pair<int64_t, TermItem>& x, const std::pair<int64_t, TermItem>& y) {
+                       return x.first > y.first;
+                     });
+    for (auto& pc : pcs) {
+      items.push_back(pc.second);
+      wg_of.push_back(0);
+    }
+  }
   auto wg_at = [&](int64_t cost) {
     return total > 0 ? (int)std::min<int64_t>(G - 1, (cost * G) / total) : 0;
   };
-  for (const Seg& sg : segs) {
+  // other lists: pieces split evenly over the G workgroups by cost, each
+  // workgroup taking a contiguous run
+  for (size_t si = 0; si < (hl ? 0 : segs.size()); ++si) {
+    const Seg& sg = segs[si];
     const int m = h->H.leaf_size[sg.leaf];
     int64_t u = sg.u0;
     do {
@@ -262,10 +348,13 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     } while (u < sg.u1);
   }
   for (const TermItem& it : items)
-    if (it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > kInRowTile)) {
-      set_error("internal: bad in-row piece");
+    if ((it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > kInRowTile)) ||
+        (it.kind == 2 && (it.r1 - it.r0 < 1 || it.r1 - it.r0 > kMaxVLeaves)) ||
+        (hl && it.c1 - it.c0 > kHalfChunk && it.kind != 1)) {
+      set_error("internal: bad term piece");
       return HM_EINVAL;
     }
+  if (rows >= ((int64_t)1 << 31)) { set_error("term partial rows exceed 2^31"); return HM_EINVAL; }
   // group pieces by workgroup (stable: pieces of one workgroup keep their order)
   std::vector<int32_t> wptr(G + 1, 0);
   for (int g : wg_of) wptr[g + 1]++;
@@ -287,6 +376,11 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   STCHK(upload(h, &tl.wptr, wptr, st, true));
   STCHK(upload(h, &tl.lptr, lptr, st, true));
   STCHK(upload(h, &tl.lprow, lprow, st, true));
+  if (hl) {
+    for (int a = 0; a < h->nl; ++a) lcnt[a] += lptr[a + 1] - lptr[a];
+    STCHK(upload(h, &hl->lcnt, lcnt, st, true));
+    STCHK(upload(h, &hl->vleaf, vleaf, st, true));
+  }
   h->partial_rows = std::max(h->partial_rows, rows);
   return HM_OK;
 }
@@ -454,6 +548,34 @@ hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupLi
               : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
 }
 
+// The half-storage product serves one right-hand side of a symmetric
+// problem, when the tuning allows it.
+bool use_half(const hm_matrix* h, int li, int nrhs) {
+  return nrhs == 1 && nrhs < h->mm_min_rhs && h->use_half == 1 && h->half_ok &&
+         li < (int)h->half.size();
+}
+
+// z = alpha R x + beta v into zbuf (x = [y | t], tree order), for level li.
+HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int64_t ldx) {
+  const hm_matrix::HalfList& L = h->half[li];
+  HalfArgs a{};
+  a.t = term_args(h, apply_set(h, f32, h->src), L.tl, f32, xin, ldx);
+  a.t.yout = h->zbuf;
+  a.t.ldy = h->N;
+  a.hp = f32 ? (const void*)h->H32 : (const void*)h->H64;
+  a.hp_off = h->hp_off;
+  a.hp_col = h->hp_col;
+  a.hsrc = h->hsrc;
+  a.vb = h->vb;
+  a.vptr = h->vptr;
+  a.vstart = h->vstart;
+  a.lcnt = L.lcnt;
+  a.vleaf = L.vleaf;
+  a.npieces = L.tl.npieces;
+  a.queue = h->hq;
+  return a;
+}
+
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
                 bool want_norms, hipStream_t st) {
@@ -480,6 +602,30 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
   if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
   const TermList& tl = (*P.tl_series)[li];
   const GroupList& sa = (*P.sa)[li];
+  if (use_half(h, li, nrhs)) {
+    // half storage: z = R y (near blocks read once), then y = -D^{-1} z
+    // with the block-diagonal D^{-1} list
+    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
+    const void* W1 = f32 ? (const void*)h->W32 : (const void*)h->W64;
+    for (int k = 1; k <= K; ++k) {
+      if (sa1.n > 0)
+        TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, y_cur, ldin, N, 1, st));
+      const HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
+      TIMED(HM_K_TERM_SERIES, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
+      TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, h->zbuf, N);
+      t.alpha = -1.0;
+      t.yout = y_nxt;
+      t.ldy = ldin;
+      t.xacc = x_tree;
+      t.ldxa = N;
+      t.accumulate = 1;
+      if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+      TIMED(HM_K_TERM_DINV, launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st));
+      std::swap(y_cur, y_nxt);
+    }
+    if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
+    return HM_OK;
+  }
   for (int k = 1; k <= K; ++k) {
     if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, y32_cur, ldin, nrhs, st));
     TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, y_cur, ldin);
@@ -505,6 +651,30 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
 int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double beta,
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
+  if (use_half(h, li, nrhs)) {
+    // z = alpha R x + beta v (near blocks read once), then
+    // y = alpha D x + z with the diagonal blocks of the apply panels
+    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
+    const void* W1 = f32 ? (const void*)h->W32 : (const void*)h->W64;
+    if (sa1.n > 0)
+      TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, h->xin0, ldin, N, 1, st));
+    HalfArgs ha = half_args(h, li, f32, h->xin0, ldin);
+    ha.t.alpha = alpha;
+    ha.t.beta = beta;
+    ha.t.v = v;
+    ha.t.ldv = N;
+    TIMED(HM_K_TERM_APPLY, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
+    TermArgs t = term_args(h, apply_set(h, f32, h->src), h->tl_dinv, f32, h->xin0, ldin);
+    t.alpha = alpha;
+    t.beta = 1.0;
+    t.v = h->zbuf;
+    t.ldv = N;
+    t.yout = out_tree;
+    t.ldy = N;
+    if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+    TIMED(HM_K_TERM_DINV, launch_term(f32, h->max_m, t, h->tl_dinv.nwg, 1, st));
+    return HM_OK;
+  }
   const Path P = pick_path(h, f32, nrhs);
   const bool shadow = P.mm && f32;
   if (shadow) HIPCHK(launch_cast2d(h->xin0, ldin, h->xin32_0, ldin, N, nrhs, st));
@@ -552,8 +722,22 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   h->tl_series.assign(h->nlev, TermList());
   h->tl_apply_mm.assign(h->nlev, TermList());
   h->tl_series_mm.assign(h->nlev, TermList());
+  h->half.assign(h->half_ok ? h->nlev : 0, hm_matrix::HalfList());
   std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
   std::vector<int64_t> irr(nl), irc(nl), zero(nl, 0);
+  for (int li = 0; li < h->nlev && h->half_ok; ++li) {
+    // half storage: half-panel columns, then the far part of the apply
+    // panels [D | near | in-row far | global far]
+    for (int a = 0; a < nl; ++a) {
+      const int64_t head = H.leaf_size[a] + h->near_cols[a];
+      const int64_t gstart = head + h->ir_cols[a];
+      dense[a].clear();
+      if (h->gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + h->gl_end[li][a]});
+      irr[a] = h->ir_end[li][a];
+      irc[a] = head;
+    }
+    STCHK(make_termlist(h, dense, irr, irc, h->ir_ncol_h, h->half[li].tl, st, &h->half[li]));
+  }
   for (int li = 0; li < h->nlev; ++li) {
     for (int pass = 0; pass < 4; ++pass) {  // apply, series, apply MM, series MM
       const bool series = pass & 1, mm = pass >= 2;
@@ -579,6 +763,108 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv, st));
   HIPCHK(hipStreamSynchronize(st));
   if (h->partial_rows > old_rows) h->ws_nrhs = 0;  // workspace is sized by partial_rows
+  return HM_OK;
+}
+
+// Half-storage data (symmetric problems only: every instance a surface
+// problem).  Per row leaf t, its near blocks (t, s > t) in increasing s side
+// by side, unpremultiplied (ld = even m_t).  Column j of the half panel of t
+// is row jj of its block's leaf s: it reads y[off_s + jj] (hsrc) and its v
+// value goes to vb slot hp_col[t] + j, which the epilogue of s adds (vstart,
+// blocks ordered by t).
+int build_half(hm_matrix* h, hipStream_t st) {
+  const HostH& H = h->H;
+  const int nl = h->nl;
+  h->half_ok = false;
+  h->hp_ncol.assign(nl, 0);
+  h->hp_bcol.assign(nl, std::vector<int32_t>());
+  h->hp_bleaf.assign(nl, std::vector<int32_t>());
+  h->ent_half.assign(h->nlev, 0);
+  if (!H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf) return HM_OK;
+  std::vector<std::vector<int>> blk(nl);
+  for (int q = 0; q < (int)H.near.size(); ++q)
+    if (H.near[q].t_leaf < H.near[q].s_leaf) blk[H.near[q].t_leaf].push_back(q);
+  std::vector<int64_t> hp_off(nl + 1, 0);
+  std::vector<int32_t> hp_col(nl + 1, 0);
+  int64_t cols = 0, tot = 0;
+  for (int t = 0; t < nl; ++t) {
+    std::sort(blk[t].begin(), blk[t].end(),
+              [&](int x, int y) { return H.near[x].s_leaf < H.near[y].s_leaf; });
+    std::vector<int32_t>& bc = h->hp_bcol[t];
+    std::vector<int32_t>& bl = h->hp_bleaf[t];
+    int64_t c = 0;
+    for (int q : blk[t]) {
+      bc.push_back((int32_t)c);
+      bl.push_back(H.near[q].s_leaf);
+      c += H.leaf_size[H.near[q].s_leaf];
+    }
+    bc.push_back((int32_t)c);
+    const int64_t ld = even_ld(H.leaf_size[t]);
+    // 32-bit byte offsets within one half panel (FP64 elements)
+    if (ld * c * 16 >= ((int64_t)1 << 31)) { set_error("half panel too large"); return HM_EINVAL; }
+    h->hp_ncol[t] = c;
+    hp_off[t] = tot;
+    hp_col[t] = (int32_t)cols;
+    tot += ld * c;
+    cols += c;
+    if (cols >= ((int64_t)1 << 31)) { set_error("half-panel columns exceed 2^31"); return HM_EINVAL; }
+  }
+  hp_off[nl] = tot;
+  hp_col[nl] = (int32_t)cols;
+  std::vector<int32_t> hsrc((size_t)cols);
+  std::vector<std::vector<int32_t>> vs(nl);
+  for (int t = 0; t < nl; ++t)
+    for (size_t b = 0; b < h->hp_bleaf[t].size(); ++b) {
+      const int s = h->hp_bleaf[t][b];
+      const int64_t c0 = hp_col[t] + h->hp_bcol[t][b];
+      for (int jj = 0; jj < H.leaf_size[s]; ++jj) hsrc[c0 + jj] = H.leaf_off[s] + jj;
+      vs[s].push_back((int32_t)c0);
+    }
+  std::vector<int32_t> vptr(nl + 1, 0), vstart;
+  for (int s = 0; s < nl; ++s) {
+    vptr[s + 1] = vptr[s] + (int32_t)vs[s].size();
+    vstart.insert(vstart.end(), vs[s].begin(), vs[s].end());
+  }
+  bigvec<double2> HD((size_t)std::max<int64_t>(tot, 1));  // zeroed (pad rows stay 0)
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int t = 0; t < nl; ++t) {
+    const int mt = H.leaf_size[t];
+    const int64_t ld = even_ld(mt);
+    for (size_t b = 0; b < blk[t].size(); ++b) {
+      const NearBlock& nb = H.near[blk[t][b]];
+      const int ms = H.leaf_size[nb.s_leaf];
+      const cplx* z = H.near_data.data() + nb.data;
+      double2* dst = HD.data() + hp_off[t] + (int64_t)h->hp_bcol[t][b] * ld;
+      for (int j = 0; j < ms; ++j)
+        for (int i = 0; i < mt; ++i) {
+          const cplx v = z[i + (size_t)j * mt];
+          dst[i + j * ld] = make_double2(v.real(), v.imag());
+        }
+    }
+  }
+  STCHK(upload(h, &h->H64, HD, st));
+  bigvec<double2>().swap(HD);
+  if (h->has_f32) {
+    STCHK(dalloc(h, (void**)&h->H32, sizeof(float2) * std::max<int64_t>(tot, 1)));
+    HIPCHK(launch_cast(h->H64, h->H32, tot, st));
+  }
+  hp_off.pop_back();
+  STCHK(upload(h, &h->hp_off, hp_off, st));
+  STCHK(upload(h, &h->hp_col, hp_col, st));
+  STCHK(upload(h, &h->hsrc, hsrc, st));
+  STCHK(upload(h, &h->vptr, vptr, st));
+  STCHK(upload(h, &h->vstart, vstart, st));
+  STCHK(dalloc(h, (void**)&h->vb, sizeof(double2) * std::max<int64_t>(cols, 1)));
+  STCHK(dalloc(h, (void**)&h->zbuf, sizeof(double2) * h->N));
+  STCHK(dalloc(h, (void**)&h->hq, 2 * sizeof(int32_t)));
+  HIPCHK(hipMemsetAsync(h->hq, 0, 2 * sizeof(int32_t), st));
+  for (int li = 0; li < h->nlev; ++li) {
+    int64_t e = 0;
+    for (int a = 0; a < nl; ++a)
+      e += (int64_t)H.leaf_size[a] * (h->hp_ncol[a] + h->ir_end[li][a] + h->gl_end[li][a]);
+    h->ent_half[li] = e;
+  }
+  h->half_ok = true;
   return HM_OK;
 }
 
@@ -963,6 +1249,10 @@ int build_device(hm_matrix* h, hipStream_t st) {
     const int occ = std::min(term_occupancy(false, h->max_m), term_occupancy(true, h->max_m));
     h->term_wgs_auto = std::max(1, prop.multiProcessorCount * occ);
     h->term_wgs = h->term_wgs_auto;
+    if (h->max_m <= kHalfMaxLeaf) {
+      const int hocc = std::min(half_occupancy(false, h->max_m), half_occupancy(true, h->max_m));
+      h->half_wgs_auto = std::max(1, prop.multiProcessorCount * hocc);
+    }
   }
   // ---- norm items: per instance (tree-order rows stay contiguous per
   // instance), rows in chunks of kNormRows
@@ -981,6 +1271,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
     STCHK(upload(h, &h->norm_items, items, st));
     STCHK(upload(h, &h->norm_seg, seg, st));
   }
+  STCHK(build_half(h, st));
   STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
   return HM_OK;
@@ -1037,6 +1328,7 @@ void fill_info(const hm_matrix* h, hm_info* out) {
     out->apply_entries[lev] = h->ent_R[li];
     out->stageA_entries[lev] = h->ent_W[li];
     out->coeffs[lev] = h->ncoef[li];
+    if (li < (int)h->ent_half.size()) out->half_entries[lev] = h->ent_half[li];
   }
 }
 
@@ -1377,6 +1669,12 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
     set_error("bad tuning values");
     return HM_EINVAL;
   }
+  if (t->half_storage < -1 || t->half_storage > 2) {
+    set_error("bad tuning values");
+    return HM_EINVAL;
+  }
+  if (t->half_storage > 0) h->use_half = t->half_storage;
+  if (t->half_storage == -1) h->use_half = 1;
   if (t->inrow_pct < -1 || t->inrow_pct > 1000) {
     set_error("bad tuning values");
     return HM_EINVAL;
@@ -1406,6 +1704,7 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out) {
   out->term_wgs = h->term_wgs;
   out->rhs_tile = h->rhs_tile;
   out->inrow_pct = h->inrow_pct;
+  out->half_storage = h->use_half;
   return HM_OK;
 }
 
@@ -1456,8 +1755,11 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
     if (nrhs > 16) paths.push_back({1, 32});
     if (nrhs > 32) paths.push_back({1, 64});
   }
-  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct};
+  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct, 2};
   double bms = INFINITY;
+  // one right-hand side of a symmetric problem: the half-storage product too
+  std::vector<int> halves = {2};
+  if (nrhs == 1 && h->half_ok) halves.push_back(1);
   for (int w : wgs) {
     for (int pct : pcts) {
       if (w != h->term_wgs || pct != h->inrow_pct) {
@@ -1465,19 +1767,24 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
         h->inrow_pct = pct;
         STCHK(build_lists(h, st));
       }
-      for (const Cand& c : paths) {
-        if (pct != 100 && c.mm_min == 1) continue;  // MFMA lists have no in-row rows
-        h->mm_min_rhs = c.mm_min;
-        h->rhs_tile = c.tile;
-        double ms = 0;
-        STCHK(time_one(&ms));
-        if (ms < bms) {
-          bms = ms;
-          bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile, pct};
+      for (int hs : halves) {
+        h->use_half = hs;
+        for (const Cand& c : paths) {
+          if (pct != 100 && c.mm_min == 1) continue;  // MFMA lists have no in-row rows
+          if (hs == 1 && c.mm_min == 1) continue;     // the half product is one-RHS only
+          h->mm_min_rhs = c.mm_min;
+          h->rhs_tile = c.tile;
+          double ms = 0;
+          STCHK(time_one(&ms));
+          if (ms < bms) {
+            bms = ms;
+            bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile, pct, hs};
+          }
         }
       }
     }
   }
+  h->use_half = bt.half_storage;
   h->mm_min_rhs = bt.mm_min_rhs;
   h->rhs_tile = bt.rhs_tile;
   if (h->term_wgs != bt.term_wgs || h->inrow_pct != bt.inrow_pct) {
@@ -1562,11 +1869,16 @@ int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_strea
 // sides; from block sizes only, to within a few percent.
 int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
   const HostH& H = h->H;
-  int64_t P = 0, Dm = 0, Wn = 0, T = 0;
+  int64_t P = 0, Dm = 0, Wn = 0, T = 0, Hn = 0, Hc = 0;
+  const bool sym = H.chi_tree.empty();  // half panels are built for symmetric problems
   for (const NearBlock& nb : H.near) {
     const int64_t m = even_ld(H.leaf_size[nb.t_leaf]);
     P += m * H.leaf_size[nb.s_leaf];
     if (nb.t_leaf == nb.s_leaf) Dm += (int64_t)H.leaf_size[nb.t_leaf] * H.leaf_size[nb.t_leaf];
+    if (sym && nb.t_leaf < nb.s_leaf) {
+      Hn += m * H.leaf_size[nb.s_leaf];
+      Hc += H.leaf_size[nb.s_leaf];
+    }
   }
   for (const FarBlock& fb : H.far) {
     const int64_t r = H.lowrank[fb.src].r;
@@ -1577,7 +1889,8 @@ int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
   const int64_t f32 = h->has_f32 ? 1 : 0;
   const int64_t bytes =
       16 * (P + (P - Dm)) + 32 * Dm + 2 * 16 * Wn + f32 * (8 * (2 * P - Dm) + 2 * 8 * Wn);
-  return bytes + workspace_bytes(h, nrhs, T);
+  const int64_t half = Hn > 0 ? (16 + 8 * f32) * Hn + 20 * Hc + 16 * h->N : 0;
+  return bytes + half + workspace_bytes(h, nrhs, T);
 }
 
 // Workspace of ensure_workspace for nrhs right-hand sides (t rows T when

@@ -67,7 +67,7 @@ class ps_server_stats(C.Structure):
 
 class hm_tuning(C.Structure):
     _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32), ("rhs_tile", C.c_int32),
-                ("inrow_pct", C.c_int32)]
+                ("inrow_pct", C.c_int32), ("half_storage", C.c_int32)]
 
 
 class hm_info(C.Structure):
@@ -83,7 +83,8 @@ class hm_info(C.Structure):
                 ("apply_entries", C.c_int64 * HM_MAX_LEVELS),
                 ("stageA_entries", C.c_int64 * HM_MAX_LEVELS),
                 ("coeffs", C.c_int64 * HM_MAX_LEVELS),
-                ("num_instances", C.c_int32)]
+                ("num_instances", C.c_int32),
+                ("half_entries", C.c_int64 * HM_MAX_LEVELS)]
 
 
 HM_K_STAGEA, HM_K_TERM_SERIES, HM_K_TERM_APPLY, HM_K_TERM_DINV, HM_K_COUNT = range(5)
@@ -226,7 +227,8 @@ class HMatrix:
     def info(self) -> dict:
         i = hm_info()
         _check(_lib().hmat_info(self._h, C.byref(i)), "hmat_info")
-        per_level = ("far_", "series_entries", "apply_entries", "stageA_entries", "coeffs")
+        per_level = ("far_", "series_entries", "apply_entries", "stageA_entries", "coeffs",
+                     "half_entries")
         d = {k: getattr(i, k) for k, _ in hm_info._fields_ if not k.startswith(per_level)}
         for k in per_level[1:]:
             d[k] = list(getattr(i, k))
@@ -236,16 +238,17 @@ class HMatrix:
         return d
 
     def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, rhs_tile: int = 0, inrow_pct: int = 0,
-             stream=None) -> None:
+             half_storage: int = 0, stream=None) -> None:
         """hmat_tune: 0 keeps a value, -1 restores its default."""
-        t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile), int(inrow_pct))
+        t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile), int(inrow_pct),
+                      int(half_storage))
         _check(_lib().hmat_tune(self._h, C.byref(t), _stream(stream)), "hmat_tune")
 
     def tuning(self) -> dict:
         t = hm_tuning()
         _check(_lib().hmat_get_tuning(self._h, C.byref(t)), "hmat_get_tuning")
         return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
-                "inrow_pct": t.inrow_pct}
+                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage}
 
     def autotune(self, nrhs: int, K: int, level: int = -1, precision: int = HM_F64,
                  stream=None):
@@ -256,7 +259,7 @@ class HMatrix:
         _check(_lib().hmat_autotune(self._h, C.byref(o), int(nrhs), _stream(stream), C.byref(t),
                                     C.byref(ms)), "hmat_autotune")
         return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
-                "inrow_pct": t.inrow_pct}, ms.value
+                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage}, ms.value
 
     def export(self, path: str) -> None:
         _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")

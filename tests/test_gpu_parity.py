@@ -464,3 +464,65 @@ def test_refine_stops_when_the_series_does_not_contract(cube):
                          max_passes=200, refine_tol=1e-10, stats=True)
     for s in st:
         assert s["diverged"] == 1 and s["passes"] < 60, s
+
+
+# ---------------------------------------------------------------- half storage
+def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels):
+    """Symmetric (surface) problems, one right-hand side: the half-storage
+    product (each off-diagonal near block read once, D^{-1} / D applied by a
+    block-diagonal launch) against the oracle and against the premultiplied
+    panels, at every level (levels above the leaf level add stage A and the
+    global far columns), FP64 and FP32 blocks, for the series and the
+    H-matvec, and over several work splits (a split into few workgroups
+    cuts half-panel pieces at the cap on target leaves)."""
+    for c in (ragged_depth, sphere_levels):
+        b = c.b[:, 0]
+        c.h.tune(half_storage=-1)
+        assert c.h.tuning()["half_storage"] == 1
+        try:
+            for lev in [-1] + list(reversed(c.H.far_levels)):
+                ref = series.series(c.H, b, 3, lev)
+                ref_z = series.apply_Z(c.H, b, lev)
+                c.h.tune(half_storage=2)
+                x_p = _host(c.h.solve(_dev(b), K=3, level=lev))
+                y_p = _host(c.h.apply(_dev(b), level=lev))
+                for wgs in (-1, 37, 1):
+                    c.h.tune(half_storage=1, term_wgs=wgs)
+                    for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+                        _say(f"half storage {c.name} level={lev} wgs={wgs} precision={prec}")
+                        x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
+                        assert series.rel_err(x, ref) <= tol, (lev, wgs, prec)
+                        if prec == hmps.HM_F64:
+                            assert series.rel_err(x, x_p) <= 1e-12, (lev, wgs)
+                        y = _host(c.h.apply(_dev(b), level=lev, precision=prec))
+                        tol_y = 1e-12 if prec == hmps.HM_F64 else 1e-6
+                        assert series.rel_err(y, ref_z) <= tol_y, (lev, wgs, prec)
+                        if prec == hmps.HM_F64:
+                            assert series.rel_err(y, y_p) <= 1e-13, (lev, wgs)
+        finally:
+            c.h.tune(half_storage=-1, term_wgs=-1)
+        # the half-storage product reads fewer entries than the panels
+        info = c.h.info()
+        L = info["leaf_level"]
+        assert 0 < info["half_entries"][L] < info["series_entries"][L]
+
+
+def test_half_storage_deterministic_and_refine(sphere):
+    """Fixed reduction order: repeated solves are bit-identical.  Refinement
+    (its residual b - Z x is the H-matvec epilogue with alpha = -1, beta = 1)
+    on the half path reaches x* like the panels."""
+    b = _dev(sphere.b)
+    x0 = _host(sphere.h.solve(b, K=4))
+    for _ in range(3):
+        assert np.array_equal(_host(sphere.h.solve(b, K=4)), x0)
+    xs = series.solve_exact(sphere.H, sphere.b)
+    kw = dict(K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE, max_passes=200,
+              refine_tol=1e-10)
+    _say("half storage refine sphere_1536")
+    x1 = _host(sphere.h.solve(b, **kw))
+    sphere.h.tune(half_storage=2)
+    try:
+        x2 = _host(sphere.h.solve(b, **kw))
+    finally:
+        sphere.h.tune(half_storage=-1)
+    assert series.rel_err(x1, xs) <= TOL_REFINE and series.rel_err(x2, xs) <= TOL_REFINE
