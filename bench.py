@@ -136,21 +136,26 @@ def recorded_traffic(workload_name, prec, kernel):
     return None
 
 
-def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T, workload_name=None):
+def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T, workload_name=None, half=False):
     """Roofline of one series-term launch.  Algorithmic bytes: the level's
-    series panel entries (D^{-1}[near | U]); on the one-RHS kernels also the
-    W rows of the in-row far blocks read in the same launch; plus the
-    vectors (y_{k-1} with its t part read, y_k written, x read and
-    written).  Flops (matrix-core kernels): executed real flops, 6 per
-    complex multiply-add in FP32 (3M), 8 in FP64 (4M)."""
+    series panel entries (D^{-1}[near | U]), or with half storage the
+    entries of the scaled operator S it reads (near blocks s > t once, far
+    U columns); on the one-RHS kernels also the W rows of the far blocks
+    read in the same launch; plus the vectors (y_{k-1} with its t part
+    read, y_k written, x read and written).  Flops (matrix-core kernels):
+    executed real flops, 6 per complex multiply-add in FP32 (3M), 8 in
+    FP64 (4M)."""
     elem = 16 if prec == "f64" else 8
-    ent = info["series_entries"][level]
+    ent = info["half_entries" if half else "series_entries"][level]
     went = 0 if mm else info["stageA_entries"][level]
     vec = 16 * nrhs * ((n + (T if mm else 0)) + 3 * n)
     nbytes = elem * (ent + went) + vec
     gbps = nbytes / (avg_us * 1e-6) / 1e9
-    traffic = recorded_traffic(workload_name, prec, "k_term_mm" if mm else "k_term")
-    out = {"bound": "hbm", "kernel": "k_term_mm (one series term)" if mm else "k_term (one series term)",
+    kname = "k_term_mm" if mm else ("k_half" if half else "k_term")
+    traffic = recorded_traffic(workload_name, prec, kname)
+    label = {"k_term_mm": "k_term_mm (one series term)", "k_term": "k_term (one series term)",
+             "k_half": "k_half (one scaled series term, half storage)"}[kname]
+    out = {"bound": "hbm", "kernel": label,
            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
            "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_us,
            "traffic_note": "L2-to-memory bytes per launch, 2 x FETCH_SIZE + WRITE_SIZE (profiles/)"
@@ -195,6 +200,10 @@ def bench_single(a):
     tune = h.autotune(nrhs, K=wl.K, level=wl.level, precision=prec)
     log(f"autotune: {tune}")
     mm = nrhs >= h.tuning()["mm_min_rhs"]
+    # one right-hand side of a symmetric problem: the scaled series on half
+    # storage when the tuning keeps it
+    half = (not mm and nrhs == 1 and not cube and h.tuning()["half_storage"] == 1
+            and info["half_entries"][level] > 0)
     solve = lambda p=prec: h.solve(b, K=wl.K, level=wl.level, precision=p)  # noqa: E731
 
     for _ in range(a.warmup):
@@ -225,12 +234,15 @@ def bench_single(a):
     x_np = x.cpu().numpy()
     T = info["coeffs"][level]
     roof = term_roofline(info, level, n, nrhs, pname, mm, kernels["term_series"]["avg_us"], T,
-                         wl.name)
+                         wl.name, half)
     if not mm:
         assert kernels["stageA"]["launches"] == 0, "the leaf-level one-RHS path has no stage A"
     elem = 16 if prec == hmps.HM_F64 else 8
-    per_solve_bytes = (wl.K * elem * (info["series_entries"][level] + info["stageA_entries"][level])
-                       + 16 * info["diag_entries"])
+    # K terms, then the block-diagonal steps: D^{-1} b, or C^{-1} b and
+    # C^{-T} x on the scaled series
+    per_solve_bytes = (wl.K * elem * (info["half_entries" if half else "series_entries"][level]
+                                      + info["stageA_entries"][level])
+                       + (2 if half else 1) * 16 * info["diag_entries"])
 
     rel = cpu = None
     extras = {}
@@ -318,7 +330,8 @@ def bench_single(a):
         "config": {"workload": wl.name, "N": n, "kind": "volume" if cube else "surface",
                    "leaf_max": wl.leaf_max, "eta": wl.eta, "aca_tol": wl.aca_tol, "K": wl.K,
                    "level": level, "nrhs": nrhs,
-                   "kernels": "matrix-core (MFMA)" if mm else "streaming one-RHS tiles",
+                   "kernels": "matrix-core (MFMA)" if mm else (
+                       "scaled series, half storage (k_half)" if half else "streaming one-RHS tiles"),
                    "precision": "complex128" if prec == hmps.HM_F64
                    else "complex64 blocks, complex128 vectors"},
         "rel_err_vs_oracle": rel, "latency_ms": lat, "roofline": roof,

@@ -118,10 +118,15 @@ struct hm_matrix {
   // apply panels
   double2* H64 = nullptr;
   float2* H32 = nullptr;
+  double2 *HF64 = nullptr, *IRT64 = nullptr, *WT64 = nullptr;  // scaled far data
+  float2 *HF32 = nullptr, *IRT32 = nullptr, *WT32 = nullptr;
+  int64_t *hf_off = nullptr, *hf_col = nullptr;
+  double2 *CH = nullptr, *CHT = nullptr;  // C_a^{-1}, C_a^{-T} panels (ld even m)
+  int64_t* ch_off = nullptr;
   int64_t* hp_off = nullptr;
   int32_t *hp_col = nullptr, *hsrc = nullptr, *vptr = nullptr, *vstart = nullptr;
   double2* vb = nullptr;          // one value per half-panel column
-  double2* zbuf = nullptr;        // z = R y (tree order, N)
+  double2* zbuf = nullptr;        // sum of the scaled terms (tree order, N)
   int32_t* hq = nullptr;          // piece queue of the half-storage kernel (2 ints)
   bool half_ok = false;
   std::vector<int64_t> hp_ncol;   // per leaf: half-panel columns
@@ -548,20 +553,21 @@ hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupLi
               : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
 }
 
-// The half-storage product serves one right-hand side of a symmetric
+// The half-storage series serves one right-hand side of a symmetric
 // problem, when the tuning allows it.
 bool use_half(const hm_matrix* h, int li, int nrhs) {
   return nrhs == 1 && nrhs < h->mm_min_rhs && h->use_half == 1 && h->half_ok &&
          li < (int)h->half.size();
 }
 
-// z = alpha R x + beta v into zbuf (x = [y | t], tree order), for level li.
+// One scaled term product at level li: input yhat = [y | t] (tree order).
 HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int64_t ldx) {
   const hm_matrix::HalfList& L = h->half[li];
   HalfArgs a{};
-  a.t = term_args(h, apply_set(h, f32, h->src), L.tl, f32, xin, ldx);
-  a.t.yout = h->zbuf;
-  a.t.ldy = h->N;
+  a.t = term_args(h, PanelSet{f32 ? (const void*)h->HF32 : (const void*)h->HF64, h->hf_off, h->src,
+                              h->hf_col, h->leaf_m},
+                  L.tl, f32, xin, ldx);
+  a.t.ir.W = f32 ? (const void*)h->IRT32 : (const void*)h->IRT64;
   a.hp = f32 ? (const void*)h->H32 : (const void*)h->H64;
   a.hp_off = h->hp_off;
   a.hp_col = h->hp_col;
@@ -576,12 +582,61 @@ HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int
   return a;
 }
 
+// Block-diagonal product with the C_a^{-1} (or C_a^{-T}) panels.
+PanelSet chat_set(const hm_matrix* h, bool transposed) {
+  return PanelSet{transposed ? (const void*)h->CHT : (const void*)h->CH, h->ch_off, h->src,
+                  h->R_col, h->leaf_m};
+}
+
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
                 bool want_norms, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
+  if (use_half(h, li, nrhs)) {
+    // scaled series (see build_half): yhat_0 = C^{-1} b, yhat_k =
+    // -S yhat_{k-1} with the half-storage product, x = C^{-T} sum_k yhat_k
+    double2* xh = h->zbuf;
+    auto block_diag = [&](const PanelSet& ps, const double2* in, int64_t ldi, bool perm_in,
+                          double2* yout, int64_t ldy, double2* xacc, double2* o) -> hipError_t {
+      TermArgs t = term_args(h, ps, h->tl_dinv, false, in, ldi);
+      t.in_perm = perm_in ? h->perm : nullptr;
+      t.yout = yout;
+      t.ldy = ldy;
+      t.xacc = xacc;
+      t.ldxa = N;
+      t.accumulate = 0;
+      if (o) { t.out = o; t.ldo = ldo; t.out_perm = h->perm; }
+      return launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st);
+    };
+    TIMED(HM_K_TERM_DINV, block_diag(chat_set(h, false), rhs, ldr, rhs_perm, y_cur, ldin, xh, nullptr));
+    if (want_norms) {  // ||y_0||, y_0 = D^{-1} b
+      HIPCHK(block_diag(dinv_set(h), rhs, ldr, rhs_perm, y_nxt, ldin, nullptr, nullptr));
+      HIPCHK(norms_into(h, y_nxt, ldin, nrhs, 0, st));
+    }
+    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
+    const void* W1 = f32 ? (const void*)h->WT32 : (const void*)h->WT64;
+    for (int k = 1; k <= K; ++k) {
+      if (sa1.n > 0)
+        TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, y_cur, ldin, N, 1, st));
+      HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
+      ha.t.alpha = -1.0;
+      ha.t.yout = y_nxt;
+      ha.t.ldy = ldin;
+      ha.t.xacc = xh;
+      ha.t.ldxa = N;
+      ha.t.accumulate = 1;
+      TIMED(HM_K_TERM_SERIES, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
+      std::swap(y_cur, y_nxt);
+    }
+    if (want_norms) {  // ||y_K||, y_K = C^{-T} yhat_K
+      HIPCHK(block_diag(chat_set(h, true), y_cur, ldin, false, y_nxt, ldin, nullptr, nullptr));
+      HIPCHK(norms_into(h, y_nxt, ldin, nrhs, 1, st));
+    }
+    TIMED(HM_K_TERM_DINV, block_diag(chat_set(h, true), xh, N, false, nullptr, 0, x_tree, out));
+    return HM_OK;
+  }
   const Path P = pick_path(h, f32, nrhs);
   // the FP32 matrix-core kernels read FP32 shadows of [y | t]
   const bool shadow = P.mm && f32;
@@ -602,30 +657,6 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
   if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
   const TermList& tl = (*P.tl_series)[li];
   const GroupList& sa = (*P.sa)[li];
-  if (use_half(h, li, nrhs)) {
-    // half storage: z = R y (near blocks read once), then y = -D^{-1} z
-    // with the block-diagonal D^{-1} list
-    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
-    const void* W1 = f32 ? (const void*)h->W32 : (const void*)h->W64;
-    for (int k = 1; k <= K; ++k) {
-      if (sa1.n > 0)
-        TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, y_cur, ldin, N, 1, st));
-      const HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
-      TIMED(HM_K_TERM_SERIES, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
-      TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, h->zbuf, N);
-      t.alpha = -1.0;
-      t.yout = y_nxt;
-      t.ldy = ldin;
-      t.xacc = x_tree;
-      t.ldxa = N;
-      t.accumulate = 1;
-      if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-      TIMED(HM_K_TERM_DINV, launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st));
-      std::swap(y_cur, y_nxt);
-    }
-    if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
-    return HM_OK;
-  }
   for (int k = 1; k <= K; ++k) {
     if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, y32_cur, ldin, nrhs, st));
     TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, y_cur, ldin);
@@ -651,30 +682,6 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
 int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double beta,
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
-  if (use_half(h, li, nrhs)) {
-    // z = alpha R x + beta v (near blocks read once), then
-    // y = alpha D x + z with the diagonal blocks of the apply panels
-    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
-    const void* W1 = f32 ? (const void*)h->W32 : (const void*)h->W64;
-    if (sa1.n > 0)
-      TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, h->xin0, ldin, N, 1, st));
-    HalfArgs ha = half_args(h, li, f32, h->xin0, ldin);
-    ha.t.alpha = alpha;
-    ha.t.beta = beta;
-    ha.t.v = v;
-    ha.t.ldv = N;
-    TIMED(HM_K_TERM_APPLY, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
-    TermArgs t = term_args(h, apply_set(h, f32, h->src), h->tl_dinv, f32, h->xin0, ldin);
-    t.alpha = alpha;
-    t.beta = 1.0;
-    t.v = h->zbuf;
-    t.ldv = N;
-    t.yout = out_tree;
-    t.ldy = N;
-    if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-    TIMED(HM_K_TERM_DINV, launch_term(f32, h->max_m, t, h->tl_dinv.nwg, 1, st));
-    return HM_OK;
-  }
   const Path P = pick_path(h, f32, nrhs);
   const bool shadow = P.mm && f32;
   if (shadow) HIPCHK(launch_cast2d(h->xin0, ldin, h->xin32_0, ldin, N, nrhs, st));
@@ -726,15 +733,14 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
   std::vector<int64_t> irr(nl), irc(nl), zero(nl, 0);
   for (int li = 0; li < h->nlev && h->half_ok; ++li) {
-    // half storage: half-panel columns, then the far part of the apply
-    // panels [D | near | in-row far | global far]
+    // half storage: half-panel columns, then the scaled far panels
+    // [in-row U' | global U']
     for (int a = 0; a < nl; ++a) {
-      const int64_t head = H.leaf_size[a] + h->near_cols[a];
-      const int64_t gstart = head + h->ir_cols[a];
+      const int64_t gstart = h->ir_cols[a];
       dense[a].clear();
       if (h->gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + h->gl_end[li][a]});
       irr[a] = h->ir_end[li][a];
-      irc[a] = head;
+      irc[a] = 0;
     }
     STCHK(make_termlist(h, dense, irr, irc, h->ir_ncol_h, h->half[li].tl, st, &h->half[li]));
   }
@@ -766,13 +772,120 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   return HM_OK;
 }
 
+// ---- symmetric scaling of the series (host arithmetic on double2)
+inline double2 cm(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+inline void cmacc(double2& acc, double2 a, double2 b) {
+  acc.x += a.x * b.x - a.y * b.y;
+  acc.y += a.x * b.y + a.y * b.x;
+}
+inline double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+// D = C C^T for a complex symmetric leaf block D (m x m, column-major)
+// without pivoting (C lower triangular), and Chat = C^{-1} (lower, column-
+// major, ld m).  False when a pivot is not well away from zero relative to
+// the block's diagonal.
+bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat) {
+  std::vector<double2> C((size_t)m * m, make_double2(0.0, 0.0));
+  double dmax = 0.0;
+  for (int j = 0; j < m; ++j) dmax = std::max(dmax, std::abs(D[j + (size_t)j * m]));
+  if (!(dmax > 0.0)) return false;
+  for (int j = 0; j < m; ++j) {
+    double2 sj = make_double2(D[j + (size_t)j * m].real(), D[j + (size_t)j * m].imag());
+    for (int k = 0; k < j; ++k) {
+      const double2 c = C[j + (size_t)k * m];
+      sj.x -= c.x * c.x - c.y * c.y;
+      sj.y -= 2.0 * c.x * c.y;
+    }
+    const double mag = std::hypot(sj.x, sj.y);
+    if (!(mag > 1e-10 * dmax)) return false;
+    const cplx r = std::sqrt(cplx(sj.x, sj.y));
+    const double2 cjj = make_double2(r.real(), r.imag());
+    C[j + (size_t)j * m] = cjj;
+    for (int i = j + 1; i < m; ++i) {
+      double2 v = make_double2(D[i + (size_t)j * m].real(), D[i + (size_t)j * m].imag());
+      for (int k = 0; k < j; ++k) {
+        const double2 p = cm(C[i + (size_t)k * m], C[j + (size_t)k * m]);
+        v.x -= p.x;
+        v.y -= p.y;
+      }
+      C[i + (size_t)j * m] = cdiv(v, cjj);
+    }
+  }
+  // Chat = C^{-1}, column by column (forward substitution)
+  Chat.assign((size_t)m * m, make_double2(0.0, 0.0));
+  for (int j = 0; j < m; ++j) {
+    double2* x = Chat.data() + (size_t)j * m;
+    x[j] = cdiv(make_double2(1.0, 0.0), C[j + (size_t)j * m]);
+    for (int i = j + 1; i < m; ++i) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int k = j; k < i; ++k) cmacc(acc, C[i + (size_t)k * m], x[k]);
+      x[i] = cdiv(make_double2(-acc.x, -acc.y), C[i + (size_t)i * m]);
+    }
+  }
+  for (double2 v : Chat)
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) return false;
+  return true;
+}
+
+// x := Chat x for one column of m entries with stride 1 (Chat lower, ld m);
+// in place from the last row up.
+inline void left_chat(const double2* Ch, int m, double2* x) {
+  for (int i = m - 1; i >= 0; --i) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int l = 0; l <= i; ++l) cmacc(acc, Ch[i + (size_t)l * m], x[l]);
+    x[i] = acc;
+  }
+}
+
+// w := w Chat^T for one row segment of m entries with stride inc; in place
+// from the last entry down.
+inline void right_chatT(const double2* Ch, int m, double2* w, int64_t inc) {
+  for (int j = m - 1; j >= 0; --j) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int l = 0; l <= j; ++l) cmacc(acc, w[l * inc], Ch[j + (size_t)l * m]);
+    w[j * inc] = acc;
+  }
+}
+
+// Host copies of the far-field device arrays the half-storage data is
+// derived from (built by build_device before upload).
+struct HalfSrc {
+  const bigvec<double2>* R;                  // apply panels
+  const std::vector<int64_t>* R_off;
+  const std::vector<int64_t>* ncols;
+  const bigvec<double2>* IR;                 // in-row W stacks
+  const std::vector<int64_t>* ir_off;
+  const std::vector<int32_t>* ir_ld;
+  const std::vector<int32_t>* ir_row0;
+  const std::vector<int32_t>* ir_soff;
+  const std::vector<int32_t>* ir_n;
+  const std::vector<int64_t>* ir_cols;
+  const bigvec<double2>* W;                  // one-RHS stage-A groups
+  const std::vector<Group>* groups;
+};
+
 // Half-storage data (symmetric problems only: every instance a surface
-// problem).  Per row leaf t, its near blocks (t, s > t) in increasing s side
-// by side, unpremultiplied (ld = even m_t).  Column j of the half panel of t
-// is row jj of its block's leaf s: it reads y[off_s + jj] (hsrc) and its v
-// value goes to vb slot hp_col[t] + j, which the epilogue of s adds (vstart,
+// problem, leaves of at most kHalfMaxLeaf rows).
+//
+// Symmetric scaling: each leaf block factors as D_a = C_a C_a^T (complex
+// symmetric, C_a lower triangular, Chat_a = C_a^{-1}).  With yhat = C^T y
+// the series y_{k+1} = -D^{-1} R y_k reads yhat_{k+1} = -S yhat_k, where
+// S = Chat R Chat^T is symmetric like R; yhat_0 = Chat b and
+// x = Chat^T sum_k yhat_k.  So a term is one product with S and no
+// block-diagonal step.  The half panels hold S_ts = Chat_t Z_ts Chat_s^T for
+// the near blocks s > t of row leaf t, side by side (ld = even m_t); the far
+// part of S is U' = Chat_t U (copied from the apply panels' far columns)
+// and W' = W Chat_s^T (the in-row stacks and the one-RHS stage-A groups,
+// row segments per source leaf).  Column j of the half panel of t is row jj
+// of its block's leaf s: it reads yhat[off_s + jj] (hsrc) and its v value
+// goes to vb slot hp_col[t] + j, which the epilogue of s adds (vstart,
 // blocks ordered by t).
-int build_half(hm_matrix* h, hipStream_t st) {
+int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   const HostH& H = h->H;
   const int nl = h->nl;
   h->half_ok = false;
@@ -781,9 +894,22 @@ int build_half(hm_matrix* h, hipStream_t st) {
   h->hp_bleaf.assign(nl, std::vector<int32_t>());
   h->ent_half.assign(h->nlev, 0);
   if (!H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf) return HM_OK;
+  std::vector<int> diag(nl, -1);
   std::vector<std::vector<int>> blk(nl);
-  for (int q = 0; q < (int)H.near.size(); ++q)
-    if (H.near[q].t_leaf < H.near[q].s_leaf) blk[H.near[q].t_leaf].push_back(q);
+  for (int q = 0; q < (int)H.near.size(); ++q) {
+    const NearBlock& nb = H.near[q];
+    if (nb.t_leaf == nb.s_leaf) diag[nb.t_leaf] = q;
+    if (nb.t_leaf < nb.s_leaf) blk[nb.t_leaf].push_back(q);
+  }
+  // ---- C_a^{-1} per leaf
+  std::vector<std::vector<double2>> Ch(nl);
+  std::vector<char> ok(nl, 1);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int a = 0; a < nl; ++a)
+    ok[a] = diag[a] >= 0 && csym_factor(H.near_data.data() + H.near[diag[a]].data, H.leaf_size[a], Ch[a]);
+  for (int a = 0; a < nl; ++a)
+    if (!ok[a]) return HM_OK;  // not safely factorable: the panels serve
+  // ---- half-panel layout
   std::vector<int64_t> hp_off(nl + 1, 0);
   std::vector<int32_t> hp_col(nl + 1, 0);
   int64_t cols = 0, tot = 0;
@@ -825,6 +951,7 @@ int build_half(hm_matrix* h, hipStream_t st) {
     vptr[s + 1] = vptr[s] + (int32_t)vs[s].size();
     vstart.insert(vstart.end(), vs[s].begin(), vs[s].end());
   }
+  // ---- half panels S_ts = Chat_t Z_ts Chat_s^T
   bigvec<double2> HD((size_t)std::max<int64_t>(tot, 1));  // zeroed (pad rows stay 0)
 #pragma omp parallel for schedule(dynamic, 1)
   for (int t = 0; t < nl; ++t) {
@@ -835,18 +962,109 @@ int build_half(hm_matrix* h, hipStream_t st) {
       const int ms = H.leaf_size[nb.s_leaf];
       const cplx* z = H.near_data.data() + nb.data;
       double2* dst = HD.data() + hp_off[t] + (int64_t)h->hp_bcol[t][b] * ld;
-      for (int j = 0; j < ms; ++j)
+      for (int j = 0; j < ms; ++j) {
         for (int i = 0; i < mt; ++i) {
           const cplx v = z[i + (size_t)j * mt];
           dst[i + j * ld] = make_double2(v.real(), v.imag());
         }
+        left_chat(Ch[t].data(), mt, dst + j * ld);
+      }
+      for (int i = 0; i < mt; ++i) right_chatT(Ch[nb.s_leaf].data(), ms, dst + i, ld);
     }
   }
+  // ---- far part: U' = Chat_t U (far columns of the apply panels), and
+  // W' = W Chat_s^T per source leaf (in-row stacks, stage-A groups)
+  std::vector<int64_t> hf_off(nl);
+  int64_t ftot = 0;
+  for (int a = 0; a < nl; ++a) {
+    const int m = H.leaf_size[a];
+    hf_off[a] = ftot;
+    ftot += (int64_t)even_ld(m) * ((*hs.ncols)[a] - m - h->near_cols[a]);
+  }
+  std::vector<int64_t> R_col_h(nl);  // src index of each leaf's first far column
+  {
+    int64_t ctot = 0;
+    for (int a = 0; a < nl; ++a) {
+      R_col_h[a] = ctot + H.leaf_size[a] + h->near_cols[a];
+      ctot += (*hs.ncols)[a];
+    }
+  }
+  bigvec<double2> HF((size_t)std::max<int64_t>(ftot, 1));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int a = 0; a < nl; ++a) {
+    const int m = H.leaf_size[a];
+    const int64_t ld = even_ld(m);
+    const int64_t c0 = m + h->near_cols[a], nf = (*hs.ncols)[a] - c0;
+    const double2* srcp = hs.R->data() + (*hs.R_off)[a] + c0 * ld;
+    double2* dst = HF.data() + hf_off[a];
+    for (int64_t c = 0; c < nf; ++c) {
+      for (int i = 0; i < m; ++i) dst[i + c * ld] = srcp[i + c * ld];
+      left_chat(Ch[a].data(), m, dst + c * ld);
+    }
+  }
+  // row segments of a source range [s0, s0 + n) by leaf
+  auto by_leaf = [&](int64_t s0, int64_t n, double2* w, int64_t inc) {
+    for (int s = H.tree.leaf_of[s0]; s < nl && H.leaf_off[s] < s0 + n; ++s)
+      right_chatT(Ch[s].data(), H.leaf_size[s], w + (H.leaf_off[s] - s0) * inc, inc);
+  };
+  bigvec<double2> IRT(hs.IR->size());
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int a = 0; a < nl; ++a) {
+    const int64_t ld = (*hs.ir_ld)[a], base = (*hs.ir_off)[a];
+    const int64_t rows = (*hs.ir_cols)[a];
+    const int64_t ncol = h->ir_ncol_h[a];
+    for (int64_t e = 0; e < ld * ncol; ++e) IRT[base + e] = (*hs.IR)[base + e];
+    for (int64_t r = 0; r < rows; ++r) {
+      const int32_t k = (*hs.ir_row0)[a] + (int32_t)r;
+      by_leaf((*hs.ir_soff)[k], (*hs.ir_n)[k], IRT.data() + base + r, ld);
+    }
+  }
+  bigvec<double2> WT(hs.W->size());
+  const int ng = (int)hs.groups->size();
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int g = 0; g < ng; ++g) {
+    const Group& G = (*hs.groups)[g];
+    for (int64_t e = 0; e < (int64_t)G.ld * G.n; ++e) WT[G.w_off + e] = (*hs.W)[G.w_off + e];
+    for (int r = 0; r < G.ld; ++r) by_leaf(G.s_off, G.n, WT.data() + G.w_off + r, G.ld);
+  }
+  // ---- Chat and Chat^T as block-diagonal panels (ld = even m)
+  std::vector<int64_t> ch_off(nl);
+  int64_t chtot = 0;
+  for (int a = 0; a < nl; ++a) {
+    ch_off[a] = chtot;
+    chtot += (int64_t)even_ld(H.leaf_size[a]) * H.leaf_size[a];
+  }
+  bigvec<double2> CH((size_t)chtot), CHT((size_t)chtot);
+  for (int a = 0; a < nl; ++a) {
+    const int m = H.leaf_size[a];
+    const int64_t ld = even_ld(m);
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i) {
+        CH[ch_off[a] + i + j * ld] = Ch[a][i + (size_t)j * m];
+        CHT[ch_off[a] + i + j * ld] = Ch[a][j + (size_t)i * m];
+      }
+  }
+  // ---- upload
   STCHK(upload(h, &h->H64, HD, st));
   bigvec<double2>().swap(HD);
+  STCHK(upload(h, &h->HF64, HF, st));
+  bigvec<double2>().swap(HF);
+  STCHK(upload(h, &h->IRT64, IRT, st));
+  bigvec<double2>().swap(IRT);
+  STCHK(upload(h, &h->WT64, WT, st));
+  bigvec<double2>().swap(WT);
+  STCHK(upload(h, &h->CH, CH, st));
+  STCHK(upload(h, &h->CHT, CHT, st));
   if (h->has_f32) {
+    const int64_t n_ir = (int64_t)hs.IR->size(), n_w = (int64_t)hs.W->size();
     STCHK(dalloc(h, (void**)&h->H32, sizeof(float2) * std::max<int64_t>(tot, 1)));
+    STCHK(dalloc(h, (void**)&h->HF32, sizeof(float2) * std::max<int64_t>(ftot, 1)));
+    STCHK(dalloc(h, (void**)&h->IRT32, sizeof(float2) * std::max<int64_t>(n_ir, 1)));
+    STCHK(dalloc(h, (void**)&h->WT32, sizeof(float2) * std::max<int64_t>(n_w, 1)));
     HIPCHK(launch_cast(h->H64, h->H32, tot, st));
+    HIPCHK(launch_cast(h->HF64, h->HF32, ftot, st));
+    HIPCHK(launch_cast(h->IRT64, h->IRT32, n_ir, st));
+    HIPCHK(launch_cast(h->WT64, h->WT32, n_w, st));
   }
   hp_off.pop_back();
   STCHK(upload(h, &h->hp_off, hp_off, st));
@@ -854,6 +1072,9 @@ int build_half(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->hsrc, hsrc, st));
   STCHK(upload(h, &h->vptr, vptr, st));
   STCHK(upload(h, &h->vstart, vstart, st));
+  STCHK(upload(h, &h->hf_off, hf_off, st));
+  STCHK(upload(h, &h->hf_col, R_col_h, st));
+  STCHK(upload(h, &h->ch_off, ch_off, st));
   STCHK(dalloc(h, (void**)&h->vb, sizeof(double2) * std::max<int64_t>(cols, 1)));
   STCHK(dalloc(h, (void**)&h->zbuf, sizeof(double2) * h->N));
   STCHK(dalloc(h, (void**)&h->hq, 2 * sizeof(int32_t)));
@@ -1126,6 +1347,17 @@ int build_device(hm_matrix* h, hipStream_t st) {
     return HM_EINVAL;
   }
 
+  h->near_cols = near_cols;
+  h->ir_cols = ir_cols;
+  h->ir_ncol_h = ir_ncol;
+  h->ir_end = ir_end;
+  h->gl_end = gl_end;
+  {
+    const HalfSrc hs{&R, &R_off, &ncols, &IR, &ir_off, &ir_ld, &ir_row0, &ir_soff, &ir_n,
+                     &ir_cols, &W, &gs1.groups};
+    STCHK(build_half(h, hs, st));
+  }
+
   // ---- upload
   std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
   STCHK(upload(h, &h->perm, H.tree.perm, st));
@@ -1206,11 +1438,6 @@ int build_device(hm_matrix* h, hipStream_t st) {
   }
 
   // ---- stage-A items and entry counts per level
-  h->near_cols = near_cols;
-  h->ir_cols = ir_cols;
-  h->ir_ncol_h = ir_ncol;
-  h->ir_end = ir_end;
-  h->gl_end = gl_end;
   h->sa.assign(h->nlev, GroupList());
   h->sa_mm.assign(h->nlev, GroupList());
   h->ent_R.assign(h->nlev, 0);
@@ -1271,7 +1498,6 @@ int build_device(hm_matrix* h, hipStream_t st) {
     STCHK(upload(h, &h->norm_items, items, st));
     STCHK(upload(h, &h->norm_seg, seg, st));
   }
-  STCHK(build_half(h, st));
   STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
   return HM_OK;
@@ -1880,16 +2106,21 @@ int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
       Hc += H.leaf_size[nb.s_leaf];
     }
   }
+  int64_t Pf = 0;
   for (const FarBlock& fb : H.far) {
     const int64_t r = H.lowrank[fb.src].r;
     P += r * fb.m;
+    Pf += r * fb.m;
     Wn += r * fb.n;
     T += r;
   }
   const int64_t f32 = h->has_f32 ? 1 : 0;
   const int64_t bytes =
       16 * (P + (P - Dm)) + 32 * Dm + 2 * 16 * Wn + f32 * (8 * (2 * P - Dm) + 2 * 8 * Wn);
-  const int64_t half = Hn > 0 ? (16 + 8 * f32) * Hn + 20 * Hc + 16 * h->N : 0;
+  // half panels, their sources and v slots, the scaled far data and the
+  // C^{-1} / C^{-T} panels
+  const int64_t half =
+      Hn > 0 ? (16 + 8 * f32) * (Hn + Pf + Wn) + 20 * Hc + 16 * h->N + 32 * Dm : 0;
   return bytes + half + workspace_bytes(h, nrhs, T);
 }
 

@@ -468,13 +468,13 @@ def test_refine_stops_when_the_series_does_not_contract(cube):
 
 # ---------------------------------------------------------------- half storage
 def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels):
-    """Symmetric (surface) problems, one right-hand side: the half-storage
-    product (each off-diagonal near block read once, D^{-1} / D applied by a
-    block-diagonal launch) against the oracle and against the premultiplied
-    panels, at every level (levels above the leaf level add stage A and the
-    global far columns), FP64 and FP32 blocks, for the series and the
-    H-matvec, and over several work splits (a split into few workgroups
-    cuts half-panel pieces at the cap on target leaves)."""
+    """Symmetric (surface) problems, one right-hand side: the scaled series
+    on half storage (D = C C^T, each off-diagonal near block of
+    S = C^{-1} R C^{-T} read once) against the oracle and against the
+    premultiplied panels, at every level (levels above the leaf level add
+    stage A on the scaled W and the global far columns), FP64 and FP32
+    blocks, and over several workgroup counts.  The H-matvec keeps the
+    panels whatever the setting."""
     for c in (ragged_depth, sphere_levels):
         b = c.b[:, 0]
         c.h.tune(half_storage=-1)
