@@ -8,6 +8,7 @@ its own recurrence.
 import math
 
 import numpy as np
+import scipy.linalg
 import pytest
 
 import workloads as W
@@ -158,3 +159,43 @@ def test_multi_rhs_columns_independent(small):
     X = series.series(H, b, 3)
     for c in range(b.shape[1]):
         assert series.rel_err(series.series(H, b[:, c], 3), X[:, c]) < 1e-15
+
+
+def _csym_factor(D):
+    """D = C C^T for a complex symmetric block, C lower triangular, no
+    pivoting (plain column-by-column recurrence)."""
+    m = D.shape[0]
+    C = np.zeros_like(D)
+    for j in range(m):
+        C[j, j] = np.sqrt(D[j, j] - np.sum(C[j, :j] ** 2))
+        C[j + 1:, j] = (D[j + 1:, j] - C[j + 1:, :j] @ C[j, :j]) / C[j, j]
+    return C
+
+
+def test_scaled_series_on_symmetric_operator(small):
+    """The scaled basis the half-storage path uses on symmetric problems:
+    with D_a = C_a C_a^T, S = C^{-1} R_l C^{-T} is symmetric and
+    yhat_{k+1} = -S yhat_k, yhat_0 = C^{-1} b, x = C^{-T} sum yhat_k gives
+    the same x_K as the series (S is similar to D^{-1} R_l)."""
+    prob, H, b, _ = small
+    for level in (-1, H.far_levels[0]):
+        D, R = _dense_parts(H, level)
+        assert np.abs(D - D.T).max() <= 1e-14 * np.abs(D).max()
+        assert np.abs(R - R.T).max() <= 1e-12 * np.abs(R).max()
+        C = np.zeros_like(D)
+        for c in H.leaves:
+            sl = slice(c.off, c.off + c.size)
+            C[sl, sl] = _csym_factor(D[sl, sl])
+        assert np.abs(C @ C.T - D).max() <= 1e-13 * np.abs(D).max()
+        Ci = scipy.linalg.solve_triangular(C, np.eye(len(C)), lower=True)
+        S = Ci @ R @ Ci.T
+        assert np.abs(S - S.T).max() <= 1e-12 * np.abs(S).max()
+        bt = H.to_tree(b)
+        for K in (0, 3):
+            y = Ci @ bt
+            xh = y.copy()
+            for _ in range(K):
+                y = -S @ y
+                xh = xh + y
+            x = H.from_tree(Ci.T @ xh)
+            assert series.rel_err(x, series.series(H, b, K, level)) <= 1e-12, (level, K)
