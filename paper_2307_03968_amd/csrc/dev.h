@@ -153,14 +153,13 @@ struct NormItem {
 //  kind 2: half-panel columns [c0, c1) of the leaf; its v values go to the
 //          leaves vleaf[r0, r1) (the blocks the columns cover)
 struct HalfArgs {
-  TermArgs t;                // ps = apply panels; lptr/lprow = u partials
+  TermArgs t;                // ps = scaled far panels; lptr/lprow: the leaf's
+                             // u partial rows, then its v slots
   const void* hp;            // half panels: double2 (FP64) or float2 (FP32)
   const int64_t* hp_off;     // per leaf: element offset of its half panel
   const int32_t* hp_col;     // per leaf (+ end): first global half-panel column
   const int32_t* hsrc;       // per global half-panel column: row of y it reads
-  double2* vb;               // per global half-panel column: v
-  const int32_t* vptr;       // per leaf: first entry in vstart (nleaves + 1)
-  const int32_t* vstart;     // vb slot of row 0 of block (t, leaf), t < leaf, by t
+  int64_t vrow;              // v slot of global half-panel column j: partial row vrow + j
   const int32_t* lcnt;       // per leaf: counter increments before its epilogue
   const int32_t* vleaf;      // target leaves of the kind-2 pieces
   int npieces;               // pieces in t.items, taken in order from a queue
@@ -172,6 +171,7 @@ constexpr int kMaxVLeaves = 8;  // target leaves (blocks) per kind-2 piece
 constexpr int kHalfMaxLeaf = 128;  // largest leaf the half-storage product serves
 constexpr int kHalfChunk = 1024;   // input columns of a kind-0 half-list piece (at most)
 constexpr int kHalfPieceCols = 384;  // half-panel columns of a kind-2 piece (at most)
+constexpr int kHalfInRowTile = 128;  // W-stack rows of a half-list in-row piece (at most)
 
 constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)
 constexpr int kGroupTile = 128;  // rows per stage-A group item

@@ -161,23 +161,33 @@ __device__ __forceinline__ void half_tile(const void* __restrict__ P, uint32_t l
   }
 }
 
-// z += the n entries base[offs[k] + row] (row = thread index < m), in list
-// order; offsets staged through LDS, eight loads in flight per thread.
-__device__ __forceinline__ void gather_sum(const double2* base, const int32_t* offs, int n, int m,
-                                           int* s_off, double2& z) {
-  for (int q0 = 0; q0 < n; q0 += kThreads) {
-    const int nq = min(kThreads, n - q0);
+// Epilogue of leaf a: z = the sum of its u partials and v slots (one list
+// of partial rows), then y = alpha z + beta v and the stores of the TermArgs
+// epilogue; the leaf's counter is cleared for the next launch.  P threads
+// share a row (P = 256 / 128 or 256 / 64): thread (i, p) sums the list
+// entries p, p + P, ... with all its loads in flight at once, and the P
+// sums are added in a fixed order, so the result does not depend on timing.
+__device__ void half_epilogue(const HalfArgs& A, int a, int* s_off, double2* s_z) {
+  constexpr int kInFlight = 16;
+  const int m = A.t.ps.leaf_m[a];
+  const int P = m <= 64 ? 4 : 2;
+  const int i = threadIdx.x % (kThreads / P), p = threadIdx.x / (kThreads / P);
+  const int q0 = A.t.lptr[a], n = A.t.lptr[a + 1] - q0;
+  double zr = 0.0, zi = 0.0;
+  for (int c0 = 0; c0 < n; c0 += kThreads) {
+    const int nc = min(kThreads, n - c0);
     __syncthreads();
-    if ((int)threadIdx.x < nq) s_off[threadIdx.x] = offs[q0 + threadIdx.x];
+    if ((int)threadIdx.x < nc) s_off[threadIdx.x] = A.t.lprow[q0 + c0 + threadIdx.x];
     __syncthreads();
-    if ((int)threadIdx.x < m) {
-      const double* pc = reinterpret_cast<const double*>(base + threadIdx.x);
-      for (int p = 0; p < nq; p += 8) {
-        double vr[8], vi[8];
+    if (i < m) {
+      const double* base = reinterpret_cast<const double*>(A.t.partial + i);
+      for (int k0 = p; k0 < nc; k0 += P * kInFlight) {
+        double vr[kInFlight], vi[kInFlight];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          if (p + u < nq) {
-            const double* q = pc + 2 * (int64_t)s_off[p + u];
+        for (int u = 0; u < kInFlight; ++u) {
+          const int k = k0 + u * P;
+          if (k < nc) {
+            const double* q = base + 2 * (int64_t)s_off[k];
             vr[u] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             vi[u] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           } else {
@@ -186,26 +196,26 @@ __device__ __forceinline__ void gather_sum(const double2* base, const int32_t* o
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          z.x += vr[u];
-          z.y += vi[u];
+        for (int u = 0; u < kInFlight; ++u) {
+          zr += vr[u];
+          zi += vi[u];
         }
       }
     }
   }
-}
-
-// Epilogue of leaf a: z = its u partials then its vb slots (fixed order),
-// then y = alpha z + beta v and the stores of the TermArgs epilogue; the
-// leaf's counter is cleared for the next launch.
-__device__ void half_epilogue(const HalfArgs& A, int a, int* s_off) {
-  const int m = A.t.ps.leaf_m[a];
-  double2 z = zero2();
-  gather_sum(A.t.partial, A.t.lprow + A.t.lptr[a], A.t.lptr[a + 1] - A.t.lptr[a], m, s_off, z);
-  gather_sum(A.vb, A.vstart + A.vptr[a], A.vptr[a + 1] - A.vptr[a], m, s_off, z);
-  if ((int)threadIdx.x < m) finish_entry(A.t, A.t.leaf_off[a], threadIdx.x, 0, z);
+  if (i < m) s_z[p * 128 + i] = make_double2(zr, zi);
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    double2 z = s_z[threadIdx.x];
+    for (int r = 1; r < P; ++r) {
+      z.x += s_z[r * 128 + threadIdx.x].x;
+      z.y += s_z[r * 128 + threadIdx.x].y;
+    }
+    finish_entry(A.t, A.t.leaf_off[a], threadIdx.x, 0, z);
+  }
   if (threadIdx.x == 0)
     __hip_atomic_store(A.t.counters + a, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();  // s_z and s_off are free again
 }
 
 // Persistent workgroup over its run of pieces (see the file comment).
@@ -219,13 +229,16 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
   const TermArgs& T = A.t;
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
-  __shared__ double2 red[(kWaves - 1) * G * E * 64];
+  // LDS of the wave reductions: the far GEMV (G x E rows per lane) and the
+  // in-row stack product (kHalfInRowTile rows)
+  __shared__ double2 red[(kWaves - 1) * (G * E > kHalfInRowTile / 64 ? G * E : kHalfInRowTile / 64) * 64];
   __shared__ double2 ured[kWaves][MR];
   __shared__ double2 ys[MR];
-  __shared__ double2 tbuf[kInRowTile];
+  __shared__ double2 tbuf[kHalfInRowTile];
   __shared__ double2 xs[kHalfChunk];
   __shared__ double2 vl[kHalfChunk];
   __shared__ int s_off[kThreads];
+  __shared__ double2 s_z[4 * 128];
   __shared__ int s_last[kMaxVLeaves + 1];
   __shared__ int s_nlast, s_next;
   // Pieces come from a queue: a workgroup takes the next ticket as it
@@ -287,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
         }
         store_agent(T.partial + it.prow + i, z);
       }
-      double2* vb = A.vb + A.hp_col[a] + it.c0;
+      double2* vb = T.partial + A.vrow + A.hp_col[a] + it.c0;
       for (int k = threadIdx.x; k < nc; k += kThreads) store_agent(vb + k, vl[k]);
     } else {
       // far pieces (kind 0, 1) and pieces of leaves with no work of their
@@ -303,20 +316,20 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
         auto X = [&](int c, int) -> double2 { return xq[c]; };
         tall_gemv<E, G, 1, UNR>(P, ld, m, 0, it.c0, it.c1, w, lane, X, acc);
       } else if (it.kind == 1) {
+        constexpr int GW = kHalfInRowTile / (64 * E);  // stack rows per lane group
         const void* P = Elem<E>::offset(T.ps.data, T.ps.panel_off[a]);
-        double2 tacc[1][E][1];
+        double2 tacc[GW][E][1];
         zero_acc(tacc);
         const int rb = T.ir.row0[a];
-        inrow_t<E, 1, 1, 4>(Elem<E>::offset(T.ir.W, T.ir.off[a]), T.ir.ld[a], T.ir.ncol[a],
-                            it.r0, it.r1, T.ir.soff + rb, T.ir.n + rb, T.xin, T.ldx, 0, 1, w,
-                            lane, tacc);
+        inrow_t<E, GW, 1, 4>(Elem<E>::offset(T.ir.W, T.ir.off[a]), T.ir.ld[a], T.ir.ncol[a],
+                             it.r0, it.r1, T.ir.soff + rb, T.ir.n + rb, T.xin, T.ldx, 0, 1, w,
+                             lane, tacc);
         reduce_waves(tacc, w, lane, red);
         if (w == 0) {
 #pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const int k = lane * E + e;
-            if (k < kInRowTile) tbuf[k] = tacc[0][e][0];
-          }
+          for (int g = 0; g < GW; ++g)
+#pragma unroll
+            for (int e = 0; e < E; ++e) tbuf[(g * 64 + lane) * E + e] = tacc[g][e][0];
         }
         __syncthreads();
         auto X = [&](int c, int) -> double2 { return tbuf[c - it.c0]; };
@@ -347,7 +360,7 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
     }
     __syncthreads();
     const int nlast = s_nlast;
-    for (int k = 0; k < nlast; ++k) half_epilogue(A, s_last[k], s_off);
+    for (int k = 0; k < nlast; ++k) half_epilogue(A, s_last[k], s_off, s_z);
     if (threadIdx.x == 0) s_next = ticket;
     __syncthreads();
     p = s_next;

@@ -45,6 +45,7 @@ struct TermList {
   int nwg = 0;                 // persistent workgroups
   int npieces = 0;
   int64_t rows = 0;            // partial rows
+  int64_t vrow = 0;            // half lists: first partial row of the v slots
 };
 
 struct GroupList {
@@ -124,8 +125,9 @@ struct hm_matrix {
   double2 *CH = nullptr, *CHT = nullptr;  // C_a^{-1}, C_a^{-T} panels (ld even m)
   int64_t* ch_off = nullptr;
   int64_t* hp_off = nullptr;
-  int32_t *hp_col = nullptr, *hsrc = nullptr, *vptr = nullptr, *vstart = nullptr;
-  double2* vb = nullptr;          // one value per half-panel column
+  int32_t *hp_col = nullptr, *hsrc = nullptr;
+  int64_t hp_cols = 0;            // half-panel columns in all (v slots)
+  std::vector<int32_t> vptr_h, vstart_h;  // per leaf: v slots of its blocks (t, leaf), t < leaf
   double2* zbuf = nullptr;        // sum of the scaled terms (tree order, N)
   int32_t* hq = nullptr;          // piece queue of the half-storage kernel (2 ints)
   bool half_ok = false;
@@ -266,7 +268,7 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
       int64_t u = sg.u0;
       do {
         int64_t k = sg.u1 - u;
-        if (sg.kind == 1) k = std::min<int64_t>(k, kInRowTile);  // starts stay even
+        if (sg.kind == 1) k = std::min<int64_t>(k, kHalfInRowTile);  // starts stay even
         if (sg.kind == 0) k = std::min<int64_t>(k, kHalfChunk);
         std::vector<int32_t>::const_iterator b0, b1;
         if (sg.kind == 2) {
@@ -353,7 +355,7 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     } while (u < sg.u1);
   }
   for (const TermItem& it : items)
-    if ((it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > kInRowTile)) ||
+    if ((it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > (hl ? kHalfInRowTile : kInRowTile))) ||
         (it.kind == 2 && (it.r1 - it.r0 < 1 || it.r1 - it.r0 > kMaxVLeaves)) ||
         (hl && it.c1 - it.c0 > kHalfChunk && it.kind != 1)) {
       set_error("internal: bad term piece");
@@ -367,13 +369,28 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   std::vector<TermItem> by_wg(items.size());
   std::vector<int32_t> fill(wptr.begin(), wptr.end() - 1);
   for (size_t q = 0; q < items.size(); ++q) by_wg[fill[wg_of[q]]++] = items[q];
-  // per leaf: the partial rows of its pieces, in piece order
+  // per leaf: the partial rows of its pieces, in piece order (half lists:
+  // then the v slots of the blocks (t, leaf), t < leaf, which follow the
+  // pieces' rows in the partial buffer)
   std::vector<int32_t> lptr(h->nl + 1, 0), lprow;
   for (auto& it : items) lptr[it.leaf + 1]++;
+  if (hl)
+    for (int a = 0; a < h->nl; ++a) lptr[a + 1] += h->vptr_h[a + 1] - h->vptr_h[a];
   for (int a = 0; a < h->nl; ++a) lptr[a + 1] += lptr[a];
-  lprow.assign(items.size(), 0);
+  lprow.assign(lptr[h->nl], 0);
   std::vector<int32_t> lf(lptr.begin(), lptr.end() - 1);
   for (auto& it : items) lprow[lf[it.leaf]++] = it.prow;
+  tl.vrow = rows;
+  if (hl && rows + h->hp_cols >= ((int64_t)1 << 31)) {
+    set_error("term partial rows exceed 2^31");
+    return HM_EINVAL;
+  }
+  if (hl) {
+    for (int a = 0; a < h->nl; ++a)
+      for (int q = h->vptr_h[a]; q < h->vptr_h[a + 1]; ++q)
+        lprow[lf[a]++] = (int32_t)(rows + h->vstart_h[q]);
+    rows += h->hp_cols;
+  }
   tl.nwg = G;
   tl.npieces = (int)items.size();
   tl.rows = rows;
@@ -382,7 +399,8 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   STCHK(upload(h, &tl.lptr, lptr, st, true));
   STCHK(upload(h, &tl.lprow, lprow, st, true));
   if (hl) {
-    for (int a = 0; a < h->nl; ++a) lcnt[a] += lptr[a + 1] - lptr[a];
+    for (int a = 0; a < h->nl; ++a)
+      lcnt[a] += lptr[a + 1] - lptr[a] - (h->vptr_h[a + 1] - h->vptr_h[a]);
     STCHK(upload(h, &hl->lcnt, lcnt, st, true));
     STCHK(upload(h, &hl->vleaf, vleaf, st, true));
   }
@@ -572,9 +590,7 @@ HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int
   a.hp_off = h->hp_off;
   a.hp_col = h->hp_col;
   a.hsrc = h->hsrc;
-  a.vb = h->vb;
-  a.vptr = h->vptr;
-  a.vstart = h->vstart;
+  a.vrow = L.tl.vrow;
   a.lcnt = L.lcnt;
   a.vleaf = L.vleaf;
   a.npieces = L.tl.npieces;
@@ -1070,12 +1086,12 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   STCHK(upload(h, &h->hp_off, hp_off, st));
   STCHK(upload(h, &h->hp_col, hp_col, st));
   STCHK(upload(h, &h->hsrc, hsrc, st));
-  STCHK(upload(h, &h->vptr, vptr, st));
-  STCHK(upload(h, &h->vstart, vstart, st));
+  h->vptr_h = vptr;
+  h->vstart_h = vstart;
+  h->hp_cols = cols;
   STCHK(upload(h, &h->hf_off, hf_off, st));
   STCHK(upload(h, &h->hf_col, R_col_h, st));
   STCHK(upload(h, &h->ch_off, ch_off, st));
-  STCHK(dalloc(h, (void**)&h->vb, sizeof(double2) * std::max<int64_t>(cols, 1)));
   STCHK(dalloc(h, (void**)&h->zbuf, sizeof(double2) * h->N));
   STCHK(dalloc(h, (void**)&h->hq, 2 * sizeof(int32_t)));
   HIPCHK(hipMemsetAsync(h->hq, 0, 2 * sizeof(int32_t), st));
