@@ -526,3 +526,26 @@ def test_half_storage_deterministic_and_refine(sphere):
     finally:
         sphere.h.tune(half_storage=-1)
     assert series.rel_err(x1, xs) <= TOL_REFINE and series.rel_err(x2, xs) <= TOL_REFINE
+
+
+def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
+    """Leaves of at most 64 rows (one 16-row tile per wave) with 16-RHS
+    tiles on the matrix cores: against the oracle at every level, FP64 (4M)
+    and FP32 (3M), for 1, 16 and 23 right-hand sides (one tile, a full tile,
+    a ragged second tile), surface and volume, series and H-matvec."""
+    for c in (ragged, cube):
+        B = W.plane_waves(c.prob.xyz, W.directions(23, 13))
+        c.h.tune(mm_min_rhs=1, rhs_tile=16)
+        try:
+            for nrhs in (1, 16, 23):
+                b = B[:, :nrhs]
+                for lev in [-1] + list(reversed(c.H.far_levels)):
+                    ref = series.series(c.H, b, 3, lev)
+                    for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+                        _say(f"small-leaf mfma {c.name} nrhs={nrhs} level={lev} precision={prec}")
+                        x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
+                        assert series.rel_err(x, ref) <= tol, (c.name, nrhs, lev, prec)
+                    y = _host(c.h.apply(_dev(b), level=lev))
+                    assert series.rel_err(y, series.apply_Z(c.H, b, lev)) <= 1e-12
+        finally:
+            c.h.tune(mm_min_rhs=-1, rhs_tile=-1)
