@@ -303,6 +303,18 @@ def bench_single(a):
             extras[f"series_{pname}"] = {"rel_err_vs_oracle_xK": rel}
             rho = series.rho(H, wl.level, iters=60)
             extras["rho"] = rho
+            if not cube and nrhs == 1:
+                # the series at every coarser level (R_l with the far blocks of
+                # level >= l): FP64 solves against the oracle's x_K there
+                per_level = {}
+                for lev in sorted(H.far_levels)[:-1]:
+                    tl = timed(lambda: h.solve(b, K=wl.K, level=lev), reps, stream)
+                    xl = h.solve(b, K=wl.K, level=lev).cpu().numpy()
+                    el = series.rel_err(xl, series.series(H, b_np, wl.K, lev))
+                    per_level[str(lev)] = {"ms_per_solve": tl, "RHS_per_s": nrhs * 1e3 / tl,
+                                           "rel_err_vs_oracle_xK": el}
+                    log(f"level {lev}: {tl:.3f} ms/solve, rel.err {el:.2e}")
+                extras["series_f64_coarser_levels"] = per_level
             if rho ** (wl.K + 1) < 0.9:
                 log("oracle x* by GMRES for the refinement check")
                 xs = series.solve_gmres(H, b_np, wl.level, tol=1e-13)

@@ -604,6 +604,109 @@ PanelSet chat_set(const hm_matrix* h, bool transposed) {
                   h->R_col, h->leaf_m};
 }
 
+// Block-diagonal launch (C^{-1}, C^{-T} or D^{-1} panels, one right-hand
+// side): y = M in per leaf, then the TermArgs stores (yout, xacc, out).
+hipError_t block_pass(hm_matrix* h, const PanelSet& ps, const double2* in, int64_t ldi,
+                      bool perm_in, double2* yout, int64_t ldy, double2* xacc, int accumulate,
+                      double2* out, int64_t ldo, hipStream_t st) {
+  TermArgs t = term_args(h, ps, h->tl_dinv, false, in, ldi);
+  t.in_perm = perm_in ? h->perm : nullptr;
+  t.yout = yout;
+  t.ldy = ldy;
+  t.xacc = xacc;
+  t.ldxa = h->N;
+  t.accumulate = accumulate;
+  if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+  return launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st);
+}
+
+// K terms of the scaled series from yhat_0 in xin0 ([y | t], tree order):
+// yhat_k = -S yhat_{k-1}, each added to xh (tree order); *last receives the
+// buffer holding yhat_K.
+int scaled_terms(hm_matrix* h, int li, bool f32, int K, double2* xh, double2** last,
+                 hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T;
+  double2* y_cur = h->xin0;
+  double2* y_nxt = h->xin1;
+  const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
+  const void* W1 = f32 ? (const void*)h->WT32 : (const void*)h->WT64;
+  for (int k = 1; k <= K; ++k) {
+    if (sa1.n > 0)
+      TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, y_cur, ldin, N, 1, st));
+    HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
+    ha.t.alpha = -1.0;
+    ha.t.yout = y_nxt;
+    ha.t.ldy = ldin;
+    ha.t.xacc = xh;
+    ha.t.ldxa = N;
+    ha.t.accumulate = 1;
+    TIMED(HM_K_TERM_SERIES, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
+    std::swap(y_cur, y_nxt);
+  }
+  *last = y_cur;
+  return HM_OK;
+}
+
+// Refinement in the scaled basis (one right-hand side of a symmetric
+// problem): with xhat = C^T x and bhat = C^{-1} b the residual is
+// rhat = C^{-1} (b - Z x) = (bhat - xhat) - S xhat, which is yhat_0 of the
+// correction's series, so a pass is one FP64 product with S (w = bhat - xhat
+// kept up to date) and K terms, and no H-matvec or block-diagonal step.
+// Work vectors: xhat in zbuf, w in bt, dhat in dt.
+int scaled_refine_init(hm_matrix* h, int li, bool f32, int K, bool want_norms, hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T;
+  // yhat_0 = bhat (xin0), and a copy in rt
+  HIPCHK(block_pass(h, chat_set(h, false), h->bt, N, false, h->xin0, ldin, h->rt, 0, nullptr, 0, st));
+  if (want_norms) {  // ||y_0||, y_0 = D^{-1} b
+    HIPCHK(block_pass(h, dinv_set(h), h->bt, N, false, h->xin1, ldin, nullptr, 0, nullptr, 0, st));
+    HIPCHK(norms_into(h, h->xin1, ldin, 1, 0, st));
+  }
+  HIPCHK(launch_axpy(1.0, h->rt, N, h->zbuf, N, N, 1, 0, st));
+  double2* last = nullptr;
+  STCHK(scaled_terms(h, li, f32, K, h->zbuf, &last, st));
+  if (want_norms) {  // ||y_K||, y_K = C^{-T} yhat_K
+    double2* tmp = last == h->xin0 ? h->xin1 : h->xin0;
+    HIPCHK(block_pass(h, chat_set(h, true), last, ldin, false, tmp, ldin, nullptr, 0, nullptr, 0, st));
+    HIPCHK(norms_into(h, tmp, ldin, 1, 1, st));
+  }
+  // w = bhat - xhat
+  HIPCHK(launch_axpy(1.0, h->rt, N, h->bt, N, N, 1, 0, st));
+  HIPCHK(launch_axpy(-1.0, h->zbuf, N, h->bt, N, N, 1, 1, st));
+  return HM_OK;
+}
+
+// One refinement pass; with `check`, x = C^{-T} xhat lands in xt and the
+// correction d = C^{-T} dhat in rt for the norms.
+int scaled_refine_pass(hm_matrix* h, int li, bool f32, int K, bool check, hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T;
+  // rhat = w - S xhat in FP64, written as yhat_0 (xin0) and as dhat's first term
+  HIPCHK(launch_axpy(1.0, h->zbuf, N, h->xin1, ldin, N, 1, 0, st));
+  const GroupList& sa1 = h->sa[li];
+  if (sa1.n > 0)
+    TIMED(HM_K_STAGEA, launch_stageA(false, h->WT64, h->groups, sa1.items, sa1.n, h->xin1, ldin, N, 1, st));
+  HalfArgs ha = half_args(h, li, false, h->xin1, ldin);
+  ha.t.alpha = -1.0;
+  ha.t.beta = 1.0;
+  ha.t.v = h->bt;
+  ha.t.ldv = N;
+  ha.t.yout = h->xin0;
+  ha.t.ldy = ldin;
+  ha.t.xacc = h->dt;
+  ha.t.ldxa = N;
+  ha.t.accumulate = 0;
+  TIMED(HM_K_TERM_APPLY, launch_half(false, h->max_m, ha, h->half[li].tl.nwg, st));
+  double2* last = nullptr;
+  STCHK(scaled_terms(h, li, f32, K, h->dt, &last, st));
+  // xhat += dhat, w -= dhat
+  HIPCHK(launch_axpy(1.0, h->dt, N, h->zbuf, N, N, 1, 1, st));
+  HIPCHK(launch_axpy(-1.0, h->dt, N, h->bt, N, N, 1, 1, st));
+  if (check) {
+    HIPCHK(block_pass(h, chat_set(h, true), h->zbuf, N, false, nullptr, 0, h->xt, 0, nullptr, 0, st));
+    HIPCHK(block_pass(h, chat_set(h, true), h->dt, N, false, nullptr, 0, h->rt, 0, nullptr, 0, st));
+  }
+  return HM_OK;
+}
+
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
                 bool want_norms, hipStream_t st) {
@@ -1794,9 +1897,14 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
   }
+  // one right-hand side of a symmetric problem refines in the scaled basis
+  const bool scaled = refine && use_half(h, li, nrhs);
   if (refine) {
     HIPCHK(launch_permute_in((const double2*)b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
-    STCHK(series_core(h, li, f32, o->K, h->bt, N, false, h->xt, nullptr, 0, nrhs, want, st));
+    if (scaled)
+      STCHK(scaled_refine_init(h, li, f32, o->K, want, st));
+    else
+      STCHK(series_core(h, li, f32, o->K, h->bt, N, false, h->xt, nullptr, 0, nrhs, want, st));
   } else {
     STCHK(series_core(h, li, f32, o->K, (const double2*)b_dev, ldb, true, h->xt, (double2*)x_dev,
                       ldx, nrhs, want, st));
@@ -1826,16 +1934,20 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     for (int c = 0; c < nrhs; ++c) growth[c] = ratio(c);
   }
   for (int pass = 1; refine && pass <= o->max_passes; ++pass) {
-    // r = b - Z_l x in FP64 (all blocks including D)
-    HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
-    STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, nullptr, 0, st));
-    // d = P_K r, x += d
-    STCHK(series_core(h, li, f32, o->K, h->rt, N, false, h->dt, nullptr, 0, nrhs, false, st));
-    HIPCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
     const bool check = adaptive || (per_rhs && pass == o->max_passes);
+    if (scaled) {
+      STCHK(scaled_refine_pass(h, li, f32, o->K, check, st));
+    } else {
+      // r = b - Z_l x in FP64 (all blocks including D)
+      HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, h->rt, nullptr, 0, st));
+      // d = P_K r, x += d
+      STCHK(series_core(h, li, f32, o->K, h->rt, N, false, h->dt, nullptr, 0, nrhs, false, st));
+      HIPCHK(launch_axpy(1.0, h->dt, N, h->xt, N, N, nrhs, 1, st));
+    }
     if (!check) continue;
     HIPCHK(norms_into(h, h->xt, N, nrhs, 0, st));
-    HIPCHK(norms_into(h, h->dt, N, nrhs, 1, st));
+    HIPCHK(norms_into(h, scaled ? h->rt : h->dt, N, nrhs, 1, st));
     STCHK(read_norms());
     bool all = true;
     for (int c = 0; c < nrhs; ++c) {
@@ -1864,7 +1976,11 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     }
     if (adaptive && all) break;
   }
-  if (refine) HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
+  if (scaled)  // x = C^{-T} xhat, in original order
+    HIPCHK(block_pass(h, chat_set(h, true), h->zbuf, N, false, nullptr, 0, h->xt, 0,
+                      (double2*)x_dev, ldx, st));
+  else if (refine)
+    HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
   int status = HM_OK;
   if (per_rhs) {
     HIPCHK(hipEventRecord(ev1, st));
