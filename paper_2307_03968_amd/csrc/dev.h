@@ -170,7 +170,7 @@ int half_occupancy(bool f32, int max_m);
 constexpr int kMaxVLeaves = 8;  // target leaves (blocks) per kind-2 piece
 constexpr int kHalfMaxLeaf = 128;  // largest leaf the half-storage product serves
 constexpr int kHalfChunk = 1024;   // input columns of a kind-0 half-list piece (at most)
-constexpr int kHalfPieceCols = 384;  // half-panel columns of a kind-2 piece (at most)
+constexpr int kHalfPieceCols = 256;  // half-panel columns of a kind-2 piece (at most)
 constexpr int kHalfInRowTile = 128;  // W-stack rows of a half-list in-row piece (at most)
 
 constexpr int kInRowTile = 64;   // stack rows per kind-1 piece (one row per lane)

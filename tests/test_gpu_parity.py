@@ -549,3 +549,37 @@ def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
                     assert series.rel_err(y, series.apply_Z(c.H, b, lev)) <= 1e-12
         finally:
             c.h.tune(mm_min_rhs=-1, rhs_tile=-1)
+
+
+def test_half_storage_batched_surfaces_one_rhs():
+    """A batched handle of surface instances (one without far blocks) with
+    one right-hand side runs the scaled half-storage series: every instance
+    matches its own oracle at the leaf level and above, and refinement in
+    the scaled basis reaches each instance's x*."""
+    probs = [W.sphere_problem(n, math.sqrt(n / 1536), instance=i)
+             for i, n in enumerate((900, 1400, 300))]
+    h = hmps.HMatrix(probs, 48, 1.0, 1e-5)
+    Hs = [hmatrix.HMatrix(p, 48, 1.0, 1e-5) for p in probs]
+    bs = [W.plane_waves(p.xyz, W.directions(1, 3, instance=i))[:, 0] for i, p in enumerate(probs)]
+    b = np.concatenate(bs)
+    assert h.tuning()["half_storage"] == 1 and max(h.info()["half_entries"]) > 0
+    top = hmps.HM_MAX_LEVELS - 1
+    for d in (0, 1):
+        for prec, tol_s in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+            _say(f"half storage batched level=top-{d} precision={prec}")
+            x = _host(h.solve(_dev(b), K=3, level=top - d, precision=prec))
+            for i, H in enumerate(Hs):
+                o0, o1 = h.offsets[i], h.offsets[i + 1]
+                ref = series.series(H, bs[i], 3, H.L - d)
+                assert series.rel_err(x[o0:o1], ref) <= tol_s, (i, d, prec)
+    for H in Hs:
+        assert series.rho(H) ** 4 < 1
+    _say("half storage batched refine")
+    x, st = h.solve(_dev(b), K=3, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE,
+                    max_passes=300, refine_tol=1e-11, stats=True)
+    x = _host(x)
+    for i, H in enumerate(Hs):
+        o0, o1 = h.offsets[i], h.offsets[i + 1]
+        assert series.rel_err(x[o0:o1], series.solve_exact(H, bs[i])) <= TOL_REFINE, i
+    assert st[0]["diverged"] == 0
+    h.close()
