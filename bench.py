@@ -119,7 +119,8 @@ def latency(fn, reps):
 def recorded_traffic(workload_name, prec, kernel):
     """HBM bytes per launch of `kernel` from the FETCH_SIZE / WRITE_SIZE
     runs summarised under profiles/ (calibrated against a device copy), or
-    None when there is none or the kernel source changed since."""
+    None when there is none or any source listed with it (the kernel, its
+    shared headers) changed since."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -129,8 +130,14 @@ def recorded_traffic(workload_name, prec, kernel):
             kv = dict(t.split("=", 1) for t in line.split()[1:] if "=" in t)
             if (kv.get("workload"), kv.get("precision"), kv.get("kernel")) != (workload_name, prec, kernel):
                 continue
-            src = os.path.join(ROOT, kv["source"])
-            if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["sha256"]:
+            # sha256 over the listed sources, concatenated in the order given
+            digest = hashlib.sha256()
+            for rel in kv["source"].split(","):
+                src = os.path.join(ROOT, rel)
+                if not os.path.exists(src):
+                    return None
+                digest.update(open(src, "rb").read())
+            if digest.hexdigest() != kv["sha256"]:
                 return None
             return float(kv["bytes_per_launch"])
     return None
