@@ -72,7 +72,23 @@ enum { HM_F64 = 0, HM_F32_APPLY = 1 };
  * hmat_autotune), whichever comes first.
  * Norm-based quantities (growth, ||d|| / ||x||) are taken per instance of a
  * batched handle and the maximum over instances is reported. */
-enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2 };
+/* PS_GMRES: restarted GMRES on Z_l x = b (FP64 products with Z_l, two
+ * classical Gram-Schmidt passes per step) with the K-term series as right
+ * preconditioner in the flexible form x = sum_j (P_K v_j) y_j; precision
+ * selects the block copies the preconditioner reads.  K = 0 preconditions
+ * with D^{-1} alone (block Jacobi), which suits rho(D^{-1} R_l) >= 1, where
+ * the series itself diverges.  Each column keeps its own Krylov space and
+ * runs until ||b - Z_l x|| <= refine_tol ||b|| (checked on the true residual
+ * at the end of a cycle) or max_passes Arnoldi steps in all; restart is the
+ * cycle length (0 = 30, at most 64).  The call synchronises the stream once
+ * per step (the stopping test), so it cannot be captured into a graph.
+ * Statistics: passes = Arnoldi steps the column was active, resid_rel = the
+ * true final relative residual, growth = 0, diverged = resid_rel above
+ * refine_tol; HM_EDIVERGED is returned then.  Single-instance handles only
+ * (HM_EINVAL for a batched handle); the request server does not take it.
+ * Workspace: (2 restart + 1) vectors of N x nrhs complex128, kept on the
+ * handle. */
+enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2, PS_GMRES = 3 };
 
 #define HM_BUILD_HOST_ONLY 0x1u /* build tree, partition and blocks on the host
                                    only: no device memory, for hmat_export /
@@ -122,9 +138,12 @@ typedef struct {
                            level only (the paper's runs); levels below the
                            coarsest far level act as the coarsest          */
   int32_t precision;    /* HM_F64 or HM_F32_APPLY                           */
-  int32_t kind;         /* PS_SERIES, PS_REFINE or PS_REFINE_FIXED          */
-  int32_t max_passes;   /* PS_REFINE: pass limit; PS_REFINE_FIXED: passes  */
-  double refine_tol;    /* PS_REFINE: stop when ||d|| <= tol ||x|| per RHS   */
+  int32_t kind;         /* PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES  */
+  int32_t max_passes;   /* PS_REFINE: pass limit; PS_REFINE_FIXED: passes;
+                           PS_GMRES: Arnoldi step limit                     */
+  double refine_tol;    /* PS_REFINE: stop when ||d|| <= tol ||x|| per RHS;
+                           PS_GMRES: when ||b - Z_l x|| <= tol ||b||         */
+  int32_t restart;      /* PS_GMRES: cycle length, 0 = 30; else ignored     */
 } ps_opts;
 
 /* Per right-hand side statistics.  Filling them synchronises the stream. */

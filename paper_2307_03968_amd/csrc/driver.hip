@@ -169,6 +169,13 @@ struct hm_matrix {
   int32_t* norm_seg = nullptr;
   int n_norm_items = 0, nseg = 1;
   std::vector<void*> ws_allocs;
+  // restarted GMRES: basis and preconditioned blocks, small per-column state
+  std::vector<void*> gm_allocs;
+  int gm_m = 0, gm_nrhs = 0;
+  double2 *gm_V = nullptr, *gm_Z = nullptr, *gm_part = nullptr, *gm_h1 = nullptr,
+          *gm_h2 = nullptr, *gm_hn = nullptr, *gm_bn = nullptr, *gm_y = nullptr;
+  hm::KrylovState gm_S{};
+  double* gm_host = nullptr;  // pinned: residual estimates, then flags
   // per-kernel timing
   bool prof = false;
   struct ProfRec { int cls; hipEvent_t e0, e1; };
@@ -179,6 +186,8 @@ struct hm_matrix {
     for (auto& r : prof_recs) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
     for (auto e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : ws_allocs) (void)hipFree(p);
+    for (void* p : gm_allocs) (void)hipFree(p);
+    if (gm_host) (void)hipHostFree(gm_host);
     for (void* p : list_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
     if (norms_host) (void)hipHostFree(norms_host);
@@ -818,6 +827,147 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
   t.ldy = N;
   if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
   TIMED(HM_K_TERM_APPLY, run_term(h, P, f32, t, tl, nrhs, st));
+  return HM_OK;
+}
+
+// GMRES workspace for restart length m and nrhs columns (kept on the
+// handle, grown when a call needs more).
+constexpr int kDefaultRestart = 30;  // GMRES basis vectors per cycle unless given
+
+int ensure_gmres(hm_matrix* h, int m, int nrhs) {
+  if (m <= h->gm_m && nrhs <= h->gm_nrhs) return HM_OK;
+  m = std::max(m, h->gm_m);
+  nrhs = std::max(nrhs, h->gm_nrhs);
+  for (void* p : h->gm_allocs) (void)hipFree(p);
+  h->gm_allocs.clear();
+  if (h->gm_host) (void)hipHostFree(h->gm_host);
+  h->gm_host = nullptr;
+  h->gm_m = h->gm_nrhs = 0;
+  const int64_t N = h->N, vs = N * nrhs;
+  auto al = [&](void** p, size_t bytes) -> int {
+    hipError_t e = hipMalloc(p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("GMRES workspace hipMalloc failed: " + std::string(hipGetErrorString(e)));
+      return HM_ENOMEM;
+    }
+    h->gm_allocs.push_back(*p);
+    return HM_OK;
+  };
+  const size_t c2 = sizeof(double2);
+  STCHK(al((void**)&h->gm_V, c2 * vs * (m + 1)));
+  STCHK(al((void**)&h->gm_Z, c2 * vs * m));
+  STCHK(al((void**)&h->gm_part, c2 * kdots_partials(N, m + 1, nrhs)));
+  STCHK(al((void**)&h->gm_h1, c2 * (m + 1) * nrhs));
+  STCHK(al((void**)&h->gm_h2, c2 * (m + 1) * nrhs));
+  STCHK(al((void**)&h->gm_hn, c2 * nrhs));
+  STCHK(al((void**)&h->gm_bn, c2 * nrhs));
+  STCHK(al((void**)&h->gm_y, c2 * m * nrhs));
+  KrylovState& S = h->gm_S;
+  STCHK(al((void**)&S.R, c2 * (int64_t)(m + 1) * m * nrhs));
+  STCHK(al((void**)&S.cs, sizeof(double) * m * nrhs));
+  STCHK(al((void**)&S.sn, c2 * m * nrhs));
+  STCHK(al((void**)&S.g, c2 * (m + 1) * nrhs));
+  STCHK(al((void**)&S.act, sizeof(int32_t) * nrhs));
+  STCHK(al((void**)&S.kc, sizeof(int32_t) * nrhs));
+  STCHK(al((void**)&S.resid, sizeof(double) * nrhs));
+  STCHK(al((void**)&S.bnorm, sizeof(double) * nrhs));
+  STCHK(al((void**)&S.inv, sizeof(double) * nrhs));
+  HIPCHK(hipHostMalloc((void**)&h->gm_host, sizeof(double) * 2 * nrhs, hipHostMallocDefault));
+  h->gm_m = m;
+  h->gm_nrhs = nrhs;
+  return HM_OK;
+}
+
+// Restarted GMRES on Z_l x = b with the series as right preconditioner
+// (flexible form: x = x_0 + sum_j (P_K v_j) y_j), FP64 products with Z_l,
+// Gram-Schmidt with one reorthogonalisation pass.  b is read in original
+// order (ld ldb), x written in original order (ld ldx).  Each column runs
+// until its residual estimate is below tol and the true residual of the
+// cycle's end confirms it, or the iteration budget is spent.  iters[c] =
+// Arnoldi steps in which column c was active; rel[c] = true final
+// ||b - Z_l x|| / ||b||.
+int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, double tol,
+                const double2* b_dev, int64_t ldb, double2* x_dev, int64_t ldx, int nrhs,
+                std::vector<int>& iters, std::vector<double>& rel, hipStream_t st) {
+  const int64_t N = h->N, ldin = h->N + h->T, vs = N * nrhs;
+  STCHK(ensure_gmres(h, m, nrhs));
+  KrylovState S = h->gm_S;
+  S.m = m;
+  double2* V = h->gm_V;
+  double2* Zb = h->gm_Z;
+  double* hres = h->gm_host;               // nrhs residuals
+  double* hact = h->gm_host + nrhs;         // nrhs flags (as doubles)
+  auto dots = [&](const double2* Vb, int nvec, const double2* w, double2* out, int ldo) {
+    return launch_kdots(Vb, vs, N, w, N, nvec, nrhs, h->gm_part, out, ldo, st);
+  };
+  // b in tree order, ||b||^2; x = 0; the first residual is b
+  HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
+  HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));
+  HIPCHK(hipMemsetAsync(h->xt, 0, sizeof(double2) * vs, st));
+  HIPCHK(launch_axpy(1.0, h->bt, N, V, N, N, nrhs, 0, st));
+  iters.assign(nrhs, 0);
+  rel.assign(nrhs, 0.0);
+  std::vector<int> active(nrhs, 0);
+  int done_iters = 0;
+  auto read_state = [&](bool flags) -> int {
+    HIPCHK(hipMemcpyAsync(hres, S.resid, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    if (flags) {
+      // the int flags land in the second half of the pinned buffer
+      HIPCHK(hipMemcpyAsync(hact, S.act, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (flags) {
+      const int32_t* f = reinterpret_cast<const int32_t*>(hact);
+      for (int c = 0; c < nrhs; ++c) active[c] = f[c];
+    }
+    return HM_OK;
+  };
+  while (true) {
+    // V_0 holds r = b - Z x: ||r||, g = ||r|| e_1, V_0 = r / ||r||
+    HIPCHK(dots(V, 1, V, h->gm_hn, 1));
+    HIPCHK(launch_kstart(S, h->gm_hn, h->gm_bn, tol, nrhs, st));
+    HIPCHK(launch_kscale(V, N, S.inv, N, nrhs, st));
+    STCHK(read_state(true));
+    for (int c = 0; c < nrhs; ++c) rel[c] = hres[c];
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) any = any || active[c];
+    if (!any || done_iters >= max_iter) break;
+    int j = 0;
+    for (; j < m && done_iters < max_iter; ++j) {
+      double2* vj = V + (int64_t)j * vs;
+      double2* w = V + (int64_t)(j + 1) * vs;
+      double2* zj = Zb + (int64_t)j * vs;
+      // z_j = P_K v_j; w = Z_l z_j (FP64, all blocks including D)
+      STCHK(series_core(h, li, f32, K, vj, N, false, zj, nullptr, 0, nrhs, false, st));
+      HIPCHK(launch_axpy(1.0, zj, N, h->xin0, ldin, N, nrhs, 0, st));
+      STCHK(apply_core(h, li, false, nrhs, 1.0, 0.0, nullptr, w, nullptr, 0, st));
+      // two classical Gram-Schmidt passes against v_0 .. v_j
+      HIPCHK(dots(V, j + 1, w, h->gm_h1, m + 1));
+      HIPCHK(launch_kupdate(-1.0, V, vs, N, h->gm_h1, m + 1, j + 1, w, N, nrhs, st));
+      HIPCHK(dots(V, j + 1, w, h->gm_h2, m + 1));
+      HIPCHK(launch_kupdate(-1.0, V, vs, N, h->gm_h2, m + 1, j + 1, w, N, nrhs, st));
+      HIPCHK(dots(w, 1, w, h->gm_hn, 1));
+      HIPCHK(launch_kstep(S, j, h->gm_h1, h->gm_h2, m + 1, h->gm_hn, tol, nrhs, st));
+      HIPCHK(launch_kscale(w, N, S.inv, N, nrhs, st));
+      for (int c = 0; c < nrhs; ++c) iters[c] += active[c];
+      ++done_iters;
+      STCHK(read_state(true));
+      bool more = false;
+      for (int c = 0; c < nrhs; ++c) more = more || active[c];
+      if (!more) {
+        ++j;
+        break;
+      }
+    }
+    // x += sum_i z_i y_i over the steps of this cycle
+    HIPCHK(launch_ksolve(S, h->gm_y, nrhs, st));
+    HIPCHK(launch_kupdate(1.0, Zb, vs, N, h->gm_y, m, j, h->xt, N, nrhs, st));
+    // true residual r = b - Z x into V_0 (it starts the next cycle)
+    HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+    STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, V, nullptr, 0, st));
+  }
+  HIPCHK(launch_permute_out(h->xt, N, h->perm, x_dev, ldx, N, nrhs, st));
   return HM_OK;
 }
 
@@ -1869,9 +2019,20 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   }
   if (o->K < 0 || o->K > 10000) { set_error("K must be in [0, 10000]"); return HM_EINVAL; }
   if (o->precision != HM_F64 && o->precision != HM_F32_APPLY) { set_error("bad precision"); return HM_EINVAL; }
-  if (o->kind != PS_SERIES && o->kind != PS_REFINE && o->kind != PS_REFINE_FIXED) {
+  if (o->kind != PS_SERIES && o->kind != PS_REFINE && o->kind != PS_REFINE_FIXED &&
+      o->kind != PS_GMRES) {
     set_error("bad kind");
     return HM_EINVAL;
+  }
+  if (o->kind == PS_GMRES) {
+    if (o->max_passes < 1 || !(o->refine_tol > 0) || o->restart < 0 || o->restart > kMaxKrylov) {
+      set_error("GMRES needs max_passes >= 1, refine_tol > 0 and restart in [0, 64]");
+      return HM_EINVAL;
+    }
+    if (h->nseg != 1) {
+      set_error("GMRES solves single-instance handles only");
+      return HM_EINVAL;
+    }
   }
   const bool refine = o->kind != PS_SERIES, adaptive = o->kind == PS_REFINE;
   if (refine && (o->max_passes < 0 || !(o->refine_tol > 0))) {
@@ -1896,6 +2057,34 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
+  }
+  if (o->kind == PS_GMRES) {
+    const int m = o->restart > 0 ? o->restart : std::min(kDefaultRestart, o->max_passes);
+    std::vector<int> it;
+    std::vector<double> rr;
+    STCHK(gmres_solve(h, li, f32, o->K, m, o->max_passes, o->refine_tol, (const double2*)b_dev,
+                      ldb, (double2*)x_dev, ldx, nrhs, it, rr, st));
+    int status = HM_OK;
+    float ms = 0;
+    if (per_rhs) {
+      HIPCHK(hipEventRecord(ev1, st));
+      HIPCHK(hipEventSynchronize(ev1));
+      HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+      (void)hipEventDestroy(ev0);
+      (void)hipEventDestroy(ev1);
+    }
+    for (int c = 0; c < nrhs; ++c) {
+      const bool bad = !(rr[c] <= o->refine_tol);
+      if (bad) status = HM_EDIVERGED;
+      if (!per_rhs) continue;
+      ps_stats& s = per_rhs[c];
+      s.passes = it[c];
+      s.growth = 0.0;
+      s.resid_rel = rr[c];
+      s.t_ms = ms;
+      s.diverged = bad ? 1 : 0;
+    }
+    return status;
   }
   // one right-hand side of a symmetric problem refines in the scaled basis
   const bool scaled = refine && use_half(h, li, nrhs);

@@ -25,7 +25,7 @@ HM_OK, HM_ENOTREADY, HM_EDIVERGED = 0, 1, 2
 HM_EINVAL, HM_ENOMEM, HM_EHIP, HM_EBUSY, HM_ESTATE = -1, -2, -3, -4, -5
 HM_SURFACE, HM_VOLUME = 0, 1
 HM_F64, HM_F32_APPLY = 0, 1
-PS_SERIES, PS_REFINE, PS_REFINE_FIXED = 0, 1, 2
+PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES = 0, 1, 2, 3
 HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST = 0x1, 0x2, 0x4
 HM_MAX_LEVELS = 32
 
@@ -46,7 +46,8 @@ class hm_build_opts(C.Structure):
 
 class ps_opts(C.Structure):
     _fields_ = [("K", C.c_int32), ("level", C.c_int32), ("precision", C.c_int32),
-                ("kind", C.c_int32), ("max_passes", C.c_int32), ("refine_tol", C.c_double)]
+                ("kind", C.c_int32), ("max_passes", C.c_int32), ("refine_tol", C.c_double),
+                ("restart", C.c_int32)]
 
 
 class ps_stats(C.Structure):
@@ -277,13 +278,15 @@ class HMatrix:
 
     def solve(self, b, K: int, level: int = -1, precision: int = HM_F64, kind: int = PS_SERIES,
               max_passes: int = 0, refine_tol: float = 1e-9, stats: bool = False, out=None,
-              stream=None):
-        """Power-series solve; returns x (and per-RHS stats when asked)."""
+              stream=None, restart: int = 0):
+        """Power-series solve (or GMRES preconditioned by the series, kind =
+        PS_GMRES); returns x (and per-RHS stats when asked)."""
         import torch
         bc = _as_cols(b)
         nrhs = bc.shape[0]
         xc = torch.empty_like(bc) if out is None else out
-        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol))
+        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol),
+                    int(restart))
         st_arr = (ps_stats * nrhs)() if stats else None
         status = _lib().ps_solve(self._h, C.byref(o), C.c_void_p(bc.data_ptr()), self.n,
                                  C.c_void_p(xc.data_ptr()), self.n, nrhs,
