@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "dev.h"
+#include "krylov.h"
 
 namespace hm {
 

@@ -16,6 +16,7 @@
 
 #include "dev.h"
 #include "hm_internal.h"
+#include "krylov.h"
 
 namespace hm {
 
