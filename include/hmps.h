@@ -88,7 +88,19 @@ enum { HM_F64 = 0, HM_F32_APPLY = 1 };
  * (HM_EINVAL for a batched handle); the request server does not take it.
  * Workspace: (2 restart + 1) vectors of N x nrhs complex128, kept on the
  * handle. */
-enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2, PS_GMRES = 3 };
+/* PS_NESTED: the nested multi-level form of eq. 14-22,
+ *   x = (I + X_n)^{-1} ... (I + X_1)^{-1} D^{-1} b,
+ * with factors from the leaf level up: X_1 = D^{-1} R_L (near off-diagonal
+ * and leaf-level far blocks), X_j = (I + X_{j-1})^{-1} ... (I + X_1)^{-1}
+ * D^{-1} F_j for the far blocks F_j of the j-th level above the leaf (the
+ * paper's V_2, W_3), down to `level` (levels without far blocks are
+ * skipped).  Each inverse is its K-term power series and applying X_j
+ * applies the truncated inverses before it, so a solve costs (K + 1)^n - 1
+ * level products for n factors (HM_EINVAL above 100,000).  At the leaf level
+ * (n = 1) it equals PS_SERIES.  precision selects the block copies of the
+ * level products; D^{-1} is FP64.  Statistics: t_ms only.  Single-instance
+ * handles only; the request server does not take it. */
+enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2, PS_GMRES = 3, PS_NESTED = 4 };
 
 #define HM_BUILD_HOST_ONLY 0x1u /* build tree, partition and blocks on the host
                                    only: no device memory, for hmat_export /
@@ -138,7 +150,8 @@ typedef struct {
                            level only (the paper's runs); levels below the
                            coarsest far level act as the coarsest          */
   int32_t precision;    /* HM_F64 or HM_F32_APPLY                           */
-  int32_t kind;         /* PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES  */
+  int32_t kind;         /* PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES,
+                           PS_NESTED                                       */
   int32_t max_passes;   /* PS_REFINE: pass limit; PS_REFINE_FIXED: passes;
                            PS_GMRES: Arnoldi step limit                     */
   double refine_tol;    /* PS_REFINE: stop when ||d|| <= tol ||x|| per RHS;

@@ -12,7 +12,8 @@ series the paper uses) gives
 evaluated as y_0 = D^{-1} b, y_k = -D^{-1} (R_l y_{k-1}), x_K = sum y_k.
 K is the highest power (K + 1 terms).
 
-Also here: the exact solution x* = Z_l^{-1} b of the same H-matrix (dense LU,
+Also here: the nested multi-level form of eq. 14-22 (``nested``), the exact
+solution x* = Z_l^{-1} b of the same H-matrix (dense LU,
 or GMRES for large N), the spectral radius of D^{-1} R_l by power iteration
 (the convergence condition of the expansion, Sec. V), and residual-driven
 refinement x <- x + P_K (b - Z_l x).
@@ -67,6 +68,60 @@ def series(H, b: np.ndarray, K: int, level: int = -1, alpha=None, return_terms: 
     if return_terms:
         return out, [H.from_tree(t) for t in terms]
     return out
+
+
+def level_part(H, y: np.ndarray, j: int) -> np.ndarray:
+    """F_j y in tree order for factor j of the nested form: j = 0 holds the
+    off-diagonal near blocks and the far blocks of the leaf level L; j >= 1
+    the far blocks of level L - j exactly.  Summed over j = 0 .. L - l these
+    make R_l."""
+    lev = H.L - j
+    y = y.reshape(H.n, -1)
+    z = np.zeros_like(y, dtype=np.complex128)
+    if j == 0:
+        for blk in H.near:
+            if blk.t != blk.s:
+                z[H.leaf_range(blk.t)] += blk.Z @ y[H.leaf_range(blk.s)]
+    for b in H.far:
+        if b.level == lev:
+            z[b.t_off:b.t_off + b.m] += H._far_apply(b, y)
+    return z
+
+
+def nested(H, b: np.ndarray, K: int, level: int = -1) -> np.ndarray:
+    """The nested multi-level form of eq. 14-22:
+
+        x = (I + X_n)^{-1} ... (I + X_2)^{-1} (I + X_1)^{-1} D^{-1} b,
+
+    X_1 = U_1, X_j = (I + X_{j-1})^{-1} ... (I + X_1)^{-1} U_j (the paper's
+    V_2 and W_3), U_j = D^{-1} F_j for the level parts F_j of ``level_part``,
+    taken from the leaf level up to ``level``, so that the leaf level alone
+    is the flat series.  Each inverse is its power series with K + 1 terms,
+    (I + X)^{-1} v ~ sum_{k=0..K} (-X)^k v, and applying X_j applies the
+    truncated inverses of the factors before it (nested, not premultiplied:
+    (K + 1)^n - 1 level products in all for n factors)."""
+    squeeze = np.ndim(b) == 1
+    n = H.L - H.level(level) + 1
+
+    def U(j, y):
+        return H.solve_D(level_part(H, y, j))
+
+    def Q(j, v):  # the first j truncated inverses, innermost first
+        for i in range(j):
+            v = S(i, v)
+        return v
+
+    def S(i, u):  # sum_{k=0..K} (-X_i)^k u, X_i w = Q(i, U_i w)
+        acc = u.copy()
+        y = u
+        for _ in range(K):
+            y = -Q(i, U(i, y))
+            acc = acc + y
+        return acc
+
+    x = Q(n, H.solve_D(H.to_tree(b)))
+    out = H.from_tree(x)
+    return out[:, 0] if squeeze else out
 
 
 def apply_Z(H, x: np.ndarray, level: int = -1) -> np.ndarray:

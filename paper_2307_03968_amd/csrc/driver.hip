@@ -177,6 +177,9 @@ struct hm_matrix {
           *gm_h2 = nullptr, *gm_hn = nullptr, *gm_bn = nullptr, *gm_y = nullptr;
   hm::KrylovState gm_S{};
   double* gm_host = nullptr;  // pinned: residual estimates, then flags
+  // nested multi-level solve: a LIFO pool of N x nrhs work vectors
+  double2* nest_pool = nullptr;
+  int nest_cap = 0, nest_nrhs = 0;
   // per-kernel timing
   bool prof = false;
   struct ProfRec { int cls; hipEvent_t e0, e1; };
@@ -189,6 +192,7 @@ struct hm_matrix {
     for (void* p : ws_allocs) (void)hipFree(p);
     for (void* p : gm_allocs) (void)hipFree(p);
     if (gm_host) (void)hipHostFree(gm_host);
+    if (nest_pool) (void)hipFree(nest_pool);
     for (void* p : list_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
     if (norms_host) (void)hipHostFree(norms_host);
@@ -969,6 +973,132 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
     STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, V, nullptr, 0, st));
   }
   HIPCHK(launch_permute_out(h->xt, N, h->perm, x_dev, ldx, N, nrhs, st));
+  return HM_OK;
+}
+
+// out = D^{-1} in + beta v (tree order, ld N; v may be null when beta = 0)
+hipError_t dinv_pass(hm_matrix* h, const double2* in, const double2* v, double beta, double2* out,
+                     int nrhs, hipStream_t st) {
+  const Path P = pick_path(h, false, nrhs);
+  TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, in, h->N);
+  t.beta = beta;
+  t.v = v;
+  t.ldv = h->N;
+  t.xacc = out;
+  t.ldxa = h->N;
+  t.accumulate = 0;
+  return run_term(h, P, false, t, h->tl_dinv, nrhs, st);
+}
+
+constexpr int64_t kMaxNestedProducts = 100000;  // level products per nested solve, at most
+
+// The nested multi-level form of eq. 14-22 with factors from the leaf level
+// up: x = S_n(... S_1(D^{-1} b)), S_j v = sum_{k<=K} (-X_j)^k v with
+// X_j w = S_{j-1}(... S_1(U_j w)) (the paper's V_2, W_3: each X_j applies the
+// truncated inverses of the factors before it), U_1 = D^{-1} (R_L) (near
+// off-diagonal blocks and leaf-level far blocks), U_j = D^{-1} F_{L-j+1} for
+// the far blocks of exactly one coarser level, obtained as Z_l y - Z_{l+1} y
+// from the level products of the apply panels.  Levels with no far blocks
+// give X_j = 0 and are skipped.  All arithmetic is in the term, stage-A and
+// axpy kernels; the host only walks the recursion.  b and x in original
+// order.
+struct Nested {
+  hm_matrix* h;
+  bool f32;
+  int K, nrhs;
+  hipStream_t st;
+  std::vector<int> lev;  // level of each factor (index 0: the leaf level)
+  int top = 0;
+  int64_t N, ldin;
+  double2* get() { return h->nest_pool + (int64_t)(top++) * N * nrhs; }
+  void put() { --top; }
+  int li(int l) const { return h->lmin < 0 ? 0 : l - h->lmin; }
+  // out = U_j y
+  int U(int j, const double2* y, double2* out) {
+    HIPCHK(launch_axpy(1.0, y, N, h->xin0, ldin, N, nrhs, 0, st));
+    double2* t1 = get();
+    const int l = lev[j];
+    STCHK(apply_core(h, li(l), f32, nrhs, 1.0, 0.0, nullptr, t1, nullptr, 0, st));
+    if (j == 0) {
+      HIPCHK(dinv_pass(h, t1, y, -1.0, out, nrhs, st));  // D^{-1} Z_L y - y
+    } else {
+      double2* t2 = get();
+      STCHK(apply_core(h, li(l + 1), f32, nrhs, -1.0, 1.0, t1, t2, nullptr, 0, st));
+      HIPCHK(dinv_pass(h, t2, nullptr, 0.0, out, nrhs, st));
+      put();
+    }
+    put();
+    return HM_OK;
+  }
+  // v <- S_{j-1}(... S_0(v)) (the first j truncated inverses, in place)
+  int Q(int j, double2* v) {
+    for (int i = 0; i < j; ++i) STCHK(S(i, v));
+    return HM_OK;
+  }
+  // u <- sum_{k<=K} (-X_i)^k u, X_i w = Q(i, U_i w)
+  int S(int i, double2* u) {
+    if (K == 0) return HM_OK;
+    double2* y = get();
+    HIPCHK(launch_axpy(1.0, u, N, y, N, N, nrhs, 0, st));
+    for (int k = 1; k <= K; ++k) {
+      double2* w = get();
+      STCHK(U(i, y, w));
+      STCHK(Q(i, w));
+      HIPCHK(launch_axpy(-1.0, w, N, y, N, N, nrhs, 0, st));  // y = -X_i y
+      put();
+      HIPCHK(launch_axpy(1.0, y, N, u, N, N, nrhs, 1, st));
+    }
+    put();
+    return HM_OK;
+  }
+};
+
+int nested_solve(hm_matrix* h, int level, bool f32, int K, const double2* b_dev, int64_t ldb,
+                 double2* x_dev, int64_t ldx, int nrhs, hipStream_t st) {
+  Nested ns{h, f32, K, nrhs, st};
+  ns.N = h->N;
+  ns.ldin = h->N + h->T;
+  // factor levels: the leaf level, then each coarser level down to the
+  // requested one that holds far blocks
+  const int L = h->L;
+  int lt = level < 0 ? L : level;
+  if (lt > L) { set_error("level beyond the leaf level"); return HM_EINVAL; }
+  lt = h->lmin < 0 ? L : std::max(lt, h->lmin);
+  std::vector<int> nfar(L + 1, 0);
+  for (const auto& fb : h->H.far)
+    if (fb.level >= 0 && fb.level <= L) nfar[fb.level] += 1;
+  ns.lev.push_back(L);
+  for (int l = L - 1; l >= lt; --l)
+    if (nfar[l] > 0) ns.lev.push_back(l);
+  const int n = (int)ns.lev.size();
+  // level products: c_j = c_{j-1} + K (1 + c_{j-1})
+  double c = 0;
+  for (int j = 0; j < n; ++j) c = c + K * (1.0 + c);
+  if (c > kMaxNestedProducts) {
+    set_error("nested solve: too many level products for this K and level count");
+    return HM_EINVAL;
+  }
+  const int cap = 2 * n + 4;
+  if (cap > h->nest_cap || nrhs > h->nest_nrhs) {
+    if (h->nest_pool) (void)hipFree(h->nest_pool);
+    h->nest_pool = nullptr;
+    h->nest_cap = h->nest_nrhs = 0;
+    const int ncap = std::max(cap, 0), nr = std::max(nrhs, 1);
+    const hipError_t e = hipMalloc((void**)&h->nest_pool, sizeof(double2) * h->N * nr * ncap);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("nested workspace hipMalloc failed");
+      return HM_ENOMEM;
+    }
+    h->nest_cap = ncap;
+    h->nest_nrhs = nr;
+  }
+  double2* x = ns.get();
+  HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->bt, h->N, h->N, nrhs, st));
+  HIPCHK(dinv_pass(h, h->bt, nullptr, 0.0, x, nrhs, st));
+  STCHK(ns.Q(n, x));
+  HIPCHK(launch_permute_out(x, h->N, h->perm, x_dev, ldx, h->N, nrhs, st));
+  ns.put();
   return HM_OK;
 }
 
@@ -2021,8 +2151,12 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   if (o->K < 0 || o->K > 10000) { set_error("K must be in [0, 10000]"); return HM_EINVAL; }
   if (o->precision != HM_F64 && o->precision != HM_F32_APPLY) { set_error("bad precision"); return HM_EINVAL; }
   if (o->kind != PS_SERIES && o->kind != PS_REFINE && o->kind != PS_REFINE_FIXED &&
-      o->kind != PS_GMRES) {
+      o->kind != PS_GMRES && o->kind != PS_NESTED) {
     set_error("bad kind");
+    return HM_EINVAL;
+  }
+  if (o->kind == PS_NESTED && h->nseg != 1) {
+    set_error("the nested solve takes single-instance handles only");
     return HM_EINVAL;
   }
   if (o->kind == PS_GMRES) {
@@ -2035,7 +2169,8 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
       return HM_EINVAL;
     }
   }
-  const bool refine = o->kind != PS_SERIES, adaptive = o->kind == PS_REFINE;
+  const bool refine = o->kind == PS_REFINE || o->kind == PS_REFINE_FIXED,
+             adaptive = o->kind == PS_REFINE;
   if (refine && (o->max_passes < 0 || !(o->refine_tol > 0))) {
     set_error("refinement needs max_passes >= 0 and refine_tol > 0");
     return HM_EINVAL;
@@ -2058,6 +2193,20 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     HIPCHK(hipEventCreate(&ev0));
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
+  }
+  if (o->kind == PS_NESTED) {
+    STCHK(nested_solve(h, o->level, f32, o->K, (const double2*)b_dev, ldb, (double2*)x_dev, ldx,
+                       nrhs, st));
+    if (per_rhs) {
+      float ms = 0;
+      HIPCHK(hipEventRecord(ev1, st));
+      HIPCHK(hipEventSynchronize(ev1));
+      HIPCHK(hipEventElapsedTime(&ms, ev0, ev1));
+      (void)hipEventDestroy(ev0);
+      (void)hipEventDestroy(ev1);
+      for (int c = 0; c < nrhs; ++c) per_rhs[c] = ps_stats{0, 0, 0.0, 0.0, ms, 0, 0};
+    }
+    return HM_OK;
   }
   if (o->kind == PS_GMRES) {
     const int m = o->restart > 0 ? o->restart : std::min(kDefaultRestart, o->max_passes);

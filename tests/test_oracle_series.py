@@ -199,3 +199,76 @@ def test_scaled_series_on_symmetric_operator(small):
                 xh = xh + y
             x = H.from_tree(Ci.T @ xh)
             assert series.rel_err(x, series.series(H, b, K, level)) <= 1e-12, (level, K)
+
+
+# ---------------------------------------------------------------- nested form
+def test_level_parts_partition_R(small):
+    """The nested form's level parts (near off-diagonal + leaf-level far,
+    then one coarser level each) add up to R_l exactly: no block is dropped
+    or counted twice."""
+    prob, H, b, g = small
+    y = g.standard_normal((H.n, 2)) + 1j * g.standard_normal((H.n, 2))
+    for level in H.far_levels:
+        parts = sum(series.level_part(H, y, j) for j in range(H.L - level + 1))
+        ref = H.apply_R(y, level)
+        assert np.linalg.norm(parts - ref) <= 1e-14 * np.linalg.norm(ref)
+
+
+def test_nested_at_leaf_level_is_the_flat_series(small):
+    """One factor (leaf level only): the nested form is the flat series."""
+    prob, H, b, _ = small
+    for K in (0, 2, 4):
+        assert series.rel_err(series.nested(H, b, K, -1), series.series(H, b, K, -1)) <= 1e-14
+
+
+def test_nested_matches_dense_factor_products(small):
+    """Two factors (levels 6 and 5) evaluated with dense matrices built from
+    the assembled H-matrix: U_1 = D^{-1} R_6, U_2 = D^{-1}(R_5 - R_6),
+    S_1 = sum_k (-U_1)^k, X_2 = S_1 U_2, x = S_2 S_1 D^{-1} b."""
+    prob, H, b, _ = small
+    lo = min(H.far_levels)
+    D = H.dense(-1, "D")
+    R6, R5 = H.dense(-1, "R"), H.dense(lo, "R")
+    U1 = np.linalg.solve(D, R6)
+    U2 = np.linalg.solve(D, R5 - R6)
+    bt = H.to_tree(b)
+    for K in (1, 3):
+        S1 = sum(np.linalg.matrix_power(-U1, k) for k in range(K + 1))
+        X2 = S1 @ U2
+        S2 = sum(np.linalg.matrix_power(-X2, k) for k in range(K + 1))
+        x = S2 @ (S1 @ np.linalg.solve(D, bt))
+        xn = H.to_tree(series.nested(H, b, K, lo))
+        assert np.linalg.norm(xn - x) <= 1e-12 * np.linalg.norm(x), K
+
+
+def test_nested_factorisation_identity(small):
+    """Eq. 14-19 with exact inverses: (I + U_1)(I + V_2) = I + U_1 + U_2 for
+    V_2 = (I + U_1)^{-1} U_2, so the product of the exact factor inverses
+    applied to D^{-1} b is x* = Z_l^{-1} b."""
+    prob, H, b, _ = small
+    lo = min(H.far_levels)
+    D = H.dense(-1, "D")
+    R6, R5 = H.dense(-1, "R"), H.dense(lo, "R")
+    U1 = np.linalg.solve(D, R6)
+    U2 = np.linalg.solve(D, R5 - R6)
+    I = np.eye(H.n)
+    V2 = np.linalg.solve(I + U1, U2)
+    lhs = (I + U1) @ (I + V2)
+    assert np.linalg.norm(lhs - (I + U1 + U2)) <= 1e-12 * np.linalg.norm(I + U1 + U2)
+    x = np.linalg.solve(I + V2, np.linalg.solve(I + U1, np.linalg.solve(D, H.to_tree(b))))
+    xs = H.to_tree(series.solve_exact(H, b, lo))
+    assert np.linalg.norm(x - xs) <= 1e-11 * np.linalg.norm(xs)
+
+
+def test_nested_converges_to_the_exact_solution(small):
+    """Both factor series contract on this sphere: the nested solution at the
+    coarsest level approaches x* = Z_l^{-1} b as K grows, and faster per K
+    than the flat series (which uses K level-l products against the nested
+    form's (K + 1)^2 - 1)."""
+    prob, H, b, _ = small
+    lo = min(H.far_levels)
+    xs = series.solve_exact(H, b, lo)
+    errs = [series.rel_err(series.nested(H, b, K, lo), xs) for K in (2, 5, 10)]
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 0.05
+    assert errs[2] < series.rel_err(series.series(H, b, 10, lo), xs)
