@@ -340,6 +340,28 @@ def bench_single(a):
                                            "rel_err_vs_oracle_xK": el}
                     log(f"level {lev}: {tl:.3f} ms/solve, rel.err {el:.2e}")
                 extras["series_f64_coarser_levels"] = per_level
+                # the nested multi-level form (eq. 14-22) one level above the
+                # leaf: two factors, (K + 1)^2 - 1 level products
+                lev = H.L - 1
+                if lev in H.far_levels:
+                    kw = dict(K=wl.K, level=lev, kind=hmps.PS_NESTED)
+                    xn = h.solve(b, **kw).cpu().numpy()  # also sizes its workspace
+                    tn = timed(lambda: h.solve(b, **kw), 3, stream)
+                    log(f"oracle nested form at level {lev}")
+                    ref_n = series.nested(H, b_np, wl.K, lev)
+                    extras["nested_f64"] = {
+                        "level": lev, "K": wl.K, "level_products": (wl.K + 1) ** 2 - 1,
+                        "ms_per_solve": tn, "RHS_per_s": nrhs * 1e3 / tn,
+                        "rel_err_vs_oracle_nested": series.rel_err(xn, ref_n),
+                        "rel_diff_vs_flat_series_same_level": series.rel_err(
+                            xn, series.series(H, b_np, wl.K, lev))}
+                    # both are truncations of Z_l^{-1} b: their distance to it
+                    xs_l = series.solve_gmres(H, b_np, lev, tol=1e-12)
+                    extras["nested_f64"]["rel_err_vs_xstar_level"] = series.rel_err(xn, xs_l)
+                    extras["nested_f64"]["flat_series_rel_err_vs_xstar_level"] = series.rel_err(
+                        series.series(H, b_np, wl.K, lev), xs_l)
+                    log(f"nested level {lev}: {tn:.2f} ms/solve, rel.err "
+                        f"{extras['nested_f64']['rel_err_vs_oracle_nested']:.2e}")
             if rho ** (wl.K + 1) < 0.9:
                 log("oracle x* by GMRES for the refinement check")
                 xs = series.solve_gmres(H, b_np, wl.level, tol=1e-13)
