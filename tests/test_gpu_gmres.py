@@ -185,7 +185,7 @@ def test_gmres_argument_errors(sphere):
     assert call(sphere.h.handle, hmps.ps_opts(0, -1, 0, G, 10, 1e-9, -1)) == hmps.HM_EINVAL
     assert call(sphere.h.handle, hmps.ps_opts(0, -1, 0, G, 0, 1e-9, 0)) == hmps.HM_EINVAL
     assert call(sphere.h.handle, hmps.ps_opts(0, -1, 0, G, 10, 0.0, 0)) == hmps.HM_EINVAL
-    assert call(sphere.h.handle, hmps.ps_opts(0, -1, 0, 4, 10, 1e-9, 0)) == hmps.HM_EINVAL
+    assert call(sphere.h.handle, hmps.ps_opts(0, -1, 0, 5, 10, 1e-9, 0)) == hmps.HM_EINVAL  # no such kind
     probs = [W.sphere_problem(200, 0.4), W.sphere_problem(150, 0.35, seed=7)]
     _say("gmres batched handle refused")
     hb = hmps.HMatrix(probs, 32, 1.0, 1e-4)
