@@ -85,7 +85,8 @@ enum { HM_F64 = 0, HM_F32_APPLY = 1 };
  * Statistics: passes = Arnoldi steps the column was active, resid_rel = the
  * true final relative residual, growth = 0, diverged = resid_rel above
  * refine_tol; HM_EDIVERGED is returned then.  Single-instance handles only
- * (HM_EINVAL for a batched handle); the request server does not take it.
+ * (HM_EINVAL for a batched handle).  The request server takes it (the
+ * workspace counts against its budget).
  * Workspace: (2 restart + 1) vectors of N x nrhs complex128, kept on the
  * handle. */
 /* PS_NESTED: the nested multi-level form of eq. 14-22,
@@ -338,6 +339,9 @@ int hmat_free(hm_matrix_t h);
  * kept; to admit a build, least recently used geometries without queued
  * or running requests are freed until blocks plus workspaces fit the
  * budget (a geometry that cannot fit an idle device fails with HM_ENOMEM).
+ * Solve kinds: PS_SERIES, PS_REFINE, PS_REFINE_FIXED and PS_GMRES (whose
+ * basis, kept on the geometry, is admitted under the budget the same way);
+ * PS_NESTED is refused.
  * Results: ps_poll returns HM_ENOTREADY while the ticket is queued or
  * running.  Once it is done (or failed) it returns the solve's status and
  * copies x (n x nrhs, original order) to x_host and the per-RHS statistics

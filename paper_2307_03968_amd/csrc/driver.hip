@@ -839,6 +839,15 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
 // handle, grown when a call needs more).
 constexpr int kDefaultRestart = 30;  // GMRES basis vectors per cycle unless given
 
+// bytes of the GMRES workspace for m and nrhs (as ensure_gmres allocates it)
+int64_t gmres_bytes(int64_t N, int m, int nrhs) {
+  if (m <= 0 || nrhs <= 0) return 0;
+  const int64_t c2 = sizeof(double2), vs = N * nrhs;
+  return c2 * (vs * (2 * m + 1) + kdots_partials(N, m + 1, nrhs) + 2 * (m + 1) * nrhs + 2 * nrhs +
+               m * nrhs + (int64_t)(m + 1) * m * nrhs + m * nrhs + (m + 1) * nrhs) +
+         (int64_t)sizeof(double) * (m * nrhs + 3 * nrhs) + 2 * sizeof(int32_t) * nrhs;
+}
+
 int ensure_gmres(hm_matrix* h, int m, int nrhs) {
   if (m <= h->gm_m && nrhs <= h->gm_nrhs) return HM_OK;
   m = std::max(m, h->gm_m);
@@ -2209,7 +2218,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     return HM_OK;
   }
   if (o->kind == PS_GMRES) {
-    const int m = o->restart > 0 ? o->restart : std::min(kDefaultRestart, o->max_passes);
+    const int m = gmres_restart(*o);
     std::vector<int> it;
     std::vector<double> rr;
     STCHK(gmres_solve(h, li, f32, o->K, m, o->max_passes, o->refine_tol, (const double2*)b_dev,
@@ -2607,6 +2616,16 @@ int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T) {
 }
 
 int workspace_rhs(hm_matrix_t h) { return h->ws_nrhs; }
+
+int gmres_restart(const ps_opts& o) {
+  return o.restart > 0 ? o.restart : std::max(1, std::min(kDefaultRestart, o.max_passes));
+}
+
+int64_t gmres_growth_bytes(hm_matrix_t h, int m, int nrhs) {
+  if (m <= h->gm_m && nrhs <= h->gm_nrhs) return 0;
+  return gmres_bytes(h->N, std::max(m, h->gm_m), std::max(nrhs, h->gm_nrhs)) -
+         gmres_bytes(h->N, h->gm_m, h->gm_nrhs);
+}
 
 int64_t resident_bytes(hm_matrix_t h) { return h->bytes + h->ws_bytes; }
 

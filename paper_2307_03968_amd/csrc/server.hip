@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "hm_internal.h"
+#include "krylov.h"
 
 namespace {
 
@@ -75,7 +76,8 @@ struct Request {
 
 bool same_opts(const ps_opts& a, const ps_opts& b) {
   return a.K == b.K && a.level == b.level && a.precision == b.precision && a.kind == b.kind &&
-         a.max_passes == b.max_passes && a.refine_tol == b.refine_tol;
+         a.max_passes == b.max_passes && a.refine_tol == b.refine_tol &&
+         (a.kind != PS_GMRES || a.restart == b.restart);
 }
 
 }  // namespace
@@ -300,6 +302,22 @@ void hm_server::worker(int slot) {
       }
       if (s == HM_OK) g.bytes += extra;
     }
+    // GMRES keeps its basis on the handle: room for its growth too
+    if (s == HM_OK && o.kind == PS_GMRES) {
+      const int64_t extra = hm::gmres_growth_bytes(h, hm::gmres_restart(o), cols);
+      while (extra > 0 && !make_room(extra, key)) {
+        bool others = false;
+        for (auto& kv : geoms)
+          if (kv.first != key && (kv.second.busy || kv.second.reserved)) others = true;
+        if (!others) {
+          s = HM_ENOMEM;
+          err = "GMRES workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
+          break;
+        }
+        cv.wait(lk);
+      }
+      if (s == HM_OK) g.bytes += extra;
+    }
     lk.unlock();
 
     // ---- run: pack b, copy in, solve, copy out
@@ -380,8 +398,11 @@ int ps_submit(hm_server_t s, uint64_t geom_key, const hm_problem* prob, const hm
   }
   if (opts->K < 0 || opts->K > 10000 ||
       (opts->precision != HM_F64 && opts->precision != HM_F32_APPLY) ||
-      (opts->kind != PS_SERIES && opts->kind != PS_REFINE && opts->kind != PS_REFINE_FIXED) ||
-      (opts->kind != PS_SERIES && (opts->max_passes < 0 || !(opts->refine_tol > 0)))) {
+      (opts->kind != PS_SERIES && opts->kind != PS_REFINE && opts->kind != PS_REFINE_FIXED &&
+       opts->kind != PS_GMRES) ||
+      (opts->kind != PS_SERIES && (opts->max_passes < 0 || !(opts->refine_tol > 0))) ||
+      (opts->kind == PS_GMRES &&
+       (opts->max_passes < 1 || opts->restart < 0 || opts->restart > hm::kMaxKrylov))) {
     hm::set_error("bad solve options");
     return HM_EINVAL;
   }

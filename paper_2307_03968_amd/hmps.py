@@ -341,13 +341,15 @@ class Server:
 
     def submit(self, key: int, b: np.ndarray, K: int, level: int = -1, precision: int = HM_F64,
                kind: int = PS_SERIES, max_passes: int = 0, refine_tol: float = 1e-9, prob=None,
-               leaf_max: int = 64, eta: float = 1.0, aca_tol: float = 1e-4) -> int:
+               leaf_max: int = 64, eta: float = 1.0, aca_tol: float = 1e-4,
+               restart: int = 0) -> int:
         """Queue a solve of b (n x nrhs or n, complex128, original order) on
         geometry `key`; `prob` is required the first time a key is used."""
         b = np.asarray(b, dtype=np.complex128)
         nrhs = 1 if b.ndim == 1 else b.shape[1]
         bc = np.asfortranarray(b.reshape(b.shape[0], nrhs))
-        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol))
+        o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol),
+                    int(restart))
         pp = bo = None
         if prob is not None:
             pst, keep = _problem_struct(prob)

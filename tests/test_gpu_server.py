@@ -156,3 +156,34 @@ def test_server_argument_errors():
     assert x.shape == b.shape and st[0]["t_ms"] > 0
     assert lib.ps_poll(srv._s, C.c_uint64(t), None, None, C.byref(state)) == hmps.HM_EINVAL
     srv.close()
+
+
+def test_server_gmres_where_the_series_diverges(oracles):
+    """GMRES requests (D^{-1} preconditioner) on the cube, where the series
+    diverges (rho > 1), reach x* = Z_l^{-1} b through the server; requests of
+    the same geometry and options are batched; the GMRES basis kept on the
+    geometry counts in the resident bytes.  The nested kind and a restart
+    beyond 64 are refused."""
+    srv = hmps.Server(slots=2)
+    seen = set()
+    H = oracles[2]
+    p = GEOMS[2][0]
+    _say("server series request on the cube")
+    t0 = _submit(srv, 2, W.plane_waves(p.xyz, W.directions(2, 3, instance=200)), seen, K=2)
+    srv.wait(t0)
+    before = srv.info()["resident_bytes"]
+    bs = [W.plane_waves(p.xyz, W.directions(n, 3, instance=210 + i)) for i, n in enumerate((3, 1, 5))]
+    _say("server GMRES requests on the cube")
+    ts = [_submit(srv, 2, b, seen, K=0, kind=hmps.PS_GMRES, max_passes=500, refine_tol=1e-11)
+          for b in bs]
+    for t, b in zip(ts, bs):
+        x, st = srv.wait(t)
+        assert series.rel_err(x, series.solve_exact(H, b)) <= 1e-8
+        assert all(s["diverged"] == 0 and s["resid_rel"] <= 1e-11 and s["passes"] > 0 for s in st)
+    assert srv.info()["resident_bytes"] > before
+    with pytest.raises(hmps.HmpsError):
+        _submit(srv, 2, bs[0], seen, K=1, kind=hmps.PS_NESTED)
+    with pytest.raises(hmps.HmpsError):
+        _submit(srv, 2, bs[0], seen, K=0, kind=hmps.PS_GMRES, max_passes=10, refine_tol=1e-9,
+                restart=65)
+    srv.close()
