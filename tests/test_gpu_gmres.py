@@ -195,3 +195,13 @@ def test_gmres_argument_errors(sphere):
     assert lib.ps_solve(hb.handle, C.byref(o), C.c_void_p(bb.data_ptr()), 350,
                         C.c_void_p(xb.data_ptr()), 350, 1, None, None) == hmps.HM_EINVAL
     hb.close()
+
+
+@pytest.mark.parametrize("restart", [1, 2, 64])
+def test_gmres_restart_lengths(sphere, restart):
+    """The smallest cycles (one and two basis vectors, restarted every step
+    or two) and the largest basis (64) reach x* as well."""
+    _say(f"gmres {sphere.name} K=4 restart={restart}")
+    x, st = sphere.h.solve(_dev(sphere.b), K=4, kind=hmps.PS_GMRES, max_passes=2000,
+                           refine_tol=RES_TOL, restart=restart, stats=True)
+    _check(sphere, _host(x), st)

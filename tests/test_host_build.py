@@ -5,6 +5,7 @@ agrees with the independent FP64 oracle (no device is used).
 """
 import ctypes as C
 import math
+import os
 
 import numpy as np
 import pytest
@@ -184,3 +185,30 @@ def test_batched_build_is_block_diagonal(tmp_path):
     info = h.info()
     assert info["num_instances"] == 3 and info["leaf_level"] == top
     h.close()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes struct of the binding has the size and field offsets of
+    its C declaration in include/hmps.h (compiled here with gcc)."""
+    import ctypes as C
+    import subprocess
+    names = ["hm_problem", "hm_build_opts", "ps_opts", "ps_stats", "hm_info", "hm_kernel_time",
+             "hm_tuning", "ps_server_stats"]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hmps.h"', "int main(void) {"]
+    for nm in names:
+        py = getattr(hmps, nm)
+        lines.append(f'  printf("{nm} size %zu\\n", sizeof({nm}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{nm} {f} %zu\\n", offsetof({nm}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    for line in filter(None, out):
+        nm, what, val = line.split()
+        py = getattr(hmps, nm)
+        got = C.sizeof(py) if what == "size" else getattr(py, what).offset
+        assert got == int(val), (nm, what, got, val)
