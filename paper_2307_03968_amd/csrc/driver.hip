@@ -901,6 +901,15 @@ int ensure_gmres(hm_matrix* h, int m, int nrhs) {
 // cycle's end confirms it, or the iteration budget is spent.  iters[c] =
 // Arnoldi steps in which column c was active; rel[c] = true final
 // ||b - Z_l x|| / ||b||.
+//
+// One right-hand side of a symmetric problem iterates in the scaled basis
+// of the half-storage series instead: (I + S) xhat = bhat with
+// bhat = C^{-1} b and x = C^{-T} xhat, preconditioned by sum_k (-S)^k (the
+// same series, K terms), so every product is one half-storage launch and
+// no block-diagonal step runs inside a cycle.  Its Arnoldi estimates are
+// scaled residuals, checked against tol / 4; the stopping test is the true
+// ||b - Z_l x|| at each cycle's end (the scaled target tightens if the two
+// disagree).
 int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, double tol,
                 const double2* b_dev, int64_t ldb, double2* x_dev, int64_t ldx, int nrhs,
                 std::vector<int>& iters, std::vector<double>& rel, hipStream_t st) {
@@ -912,18 +921,47 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
   double2* Zb = h->gm_Z;
   double* hres = h->gm_host;               // nrhs residuals
   double* hact = h->gm_host + nrhs;         // nrhs flags (as doubles)
+  const bool scaled = use_half(h, li, nrhs);
+  const GroupList& sa1 = h->sa[li];
   auto dots = [&](const double2* Vb, int nvec, const double2* w, double2* out, int ldo) {
     return launch_kdots(Vb, vs, N, w, N, nvec, nrhs, h->gm_part, out, ldo, st);
   };
-  // b in tree order, ||b||^2; x = 0; the first residual is b
-  HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
-  HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));
-  HIPCHK(hipMemsetAsync(h->xt, 0, sizeof(double2) * vs, st));
-  HIPCHK(launch_axpy(1.0, h->bt, N, V, N, N, nrhs, 0, st));
+  // scaled basis: out = alpha S in + beta v (FP64 half-storage product)
+  auto s_apply = [&](const double2* in, double alpha, double beta, const double2* v,
+                     double2* out) -> int {
+    HIPCHK(launch_axpy(1.0, in, N, h->xin1, ldin, N, 1, 0, st));
+    if (sa1.n > 0)
+      TIMED(HM_K_STAGEA, launch_stageA(false, h->WT64, h->groups, sa1.items, sa1.n, h->xin1, ldin, N, 1, st));
+    HalfArgs ha = half_args(h, li, false, h->xin1, ldin);
+    ha.t.alpha = alpha;
+    ha.t.beta = beta;
+    ha.t.v = v;
+    ha.t.ldv = N;
+    ha.t.xacc = out;
+    ha.t.ldxa = N;
+    ha.t.accumulate = 0;
+    TIMED(HM_K_TERM_APPLY, launch_half(false, h->max_m, ha, h->half[li].tl.nwg, st));
+    return HM_OK;
+  };
+  // z = P v
+  auto precond = [&](const double2* v, double2* z) -> int {
+    if (!scaled) return series_core(h, li, f32, K, v, N, false, z, nullptr, 0, nrhs, false, st);
+    HIPCHK(launch_axpy(1.0, v, N, h->xin0, ldin, N, 1, 0, st));
+    HIPCHK(launch_axpy(1.0, v, N, z, N, N, 1, 0, st));
+    double2* last = nullptr;
+    return scaled_terms(h, li, f32, K, z, &last, st);
+  };
+  // w = A z (A = Z_l, or I + S in the scaled basis)
+  auto oper = [&](const double2* z, double2* w) -> int {
+    if (scaled) return s_apply(z, 1.0, 1.0, z, w);
+    HIPCHK(launch_axpy(1.0, z, N, h->xin0, ldin, N, nrhs, 0, st));
+    return apply_core(h, li, false, nrhs, 1.0, 0.0, nullptr, w, nullptr, 0, st);
+  };
   iters.assign(nrhs, 0);
   rel.assign(nrhs, 0.0);
   std::vector<int> active(nrhs, 0);
-  int done_iters = 0;
+  std::vector<double> rel_true(nrhs, 1.0);
+  double bn_true = 0.0;
   auto read_state = [&](bool flags) -> int {
     HIPCHK(hipMemcpyAsync(hres, S.resid, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     if (flags) {
@@ -937,32 +975,71 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
     }
     return HM_OK;
   };
+  // ||v||^2 of the single column of v, read to the host
+  auto host_norm2 = [&](const double2* v, double* out) -> int {
+    HIPCHK(dots(v, 1, v, h->gm_hn, 1));
+    HIPCHK(hipMemcpyAsync(hres, h->gm_hn, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *out = hres[0];
+    return HM_OK;
+  };
+  if (scaled) {
+    // b in tree order (dt), bhat = C^{-1} b (bt); xhat = 0 in xt
+    HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->dt, N, N, 1, st));
+    HIPCHK(block_pass(h, chat_set(h, false), h->dt, N, false, nullptr, 0, h->bt, 0, nullptr, 0, st));
+    double bn2 = 0.0;
+    STCHK(host_norm2(h->dt, &bn2));
+    bn_true = std::sqrt(std::max(bn2, 0.0));
+    rel_true[0] = bn_true > 0 ? 1.0 : 0.0;
+    HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));  // ||bhat||^2 for the scaled estimates
+  } else {
+    // b in tree order, ||b||^2; x = 0; the first residual is b
+    HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
+    HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));
+    HIPCHK(launch_axpy(1.0, h->bt, N, V, N, N, nrhs, 0, st));
+  }
+  HIPCHK(hipMemsetAsync(h->xt, 0, sizeof(double2) * vs, st));
+  double tol_s = scaled ? 0.25 * tol : tol;
+  int tighten = 0, done_iters = 0;
   while (true) {
-    // V_0 holds r = b - Z x: ||r||, g = ||r|| e_1, V_0 = r / ||r||
+    if (scaled) {
+      if (rel_true[0] <= tol) break;
+      // rhat = (bhat - xhat) - S xhat into V_0
+      HIPCHK(launch_axpy(1.0, h->bt, N, h->rt, N, N, 1, 0, st));
+      HIPCHK(launch_axpy(-1.0, h->xt, N, h->rt, N, N, 1, 1, st));
+      STCHK(s_apply(h->xt, -1.0, 1.0, h->rt, V));
+    }
+    // V_0 holds the residual r: ||r||, g = ||r|| e_1, V_0 = r / ||r||
     HIPCHK(dots(V, 1, V, h->gm_hn, 1));
-    HIPCHK(launch_kstart(S, h->gm_hn, h->gm_bn, tol, nrhs, st));
+    HIPCHK(launch_kstart(S, h->gm_hn, h->gm_bn, tol_s, nrhs, st));
     HIPCHK(launch_kscale(V, N, S.inv, N, nrhs, st));
     STCHK(read_state(true));
-    for (int c = 0; c < nrhs; ++c) rel[c] = hres[c];
+    if (!scaled)
+      for (int c = 0; c < nrhs; ++c) rel[c] = hres[c];
     bool any = false;
     for (int c = 0; c < nrhs; ++c) any = any || active[c];
+    if (scaled && !any && done_iters < max_iter && tighten < 3) {
+      // the scaled residual is below its target but the true one is not
+      tol_s *= 0.1;
+      ++tighten;
+      continue;
+    }
     if (!any || done_iters >= max_iter) break;
     int j = 0;
     for (; j < m && done_iters < max_iter; ++j) {
       double2* vj = V + (int64_t)j * vs;
       double2* w = V + (int64_t)(j + 1) * vs;
       double2* zj = Zb + (int64_t)j * vs;
-      // z_j = P_K v_j; w = Z_l z_j (FP64, all blocks including D)
-      STCHK(series_core(h, li, f32, K, vj, N, false, zj, nullptr, 0, nrhs, false, st));
-      HIPCHK(launch_axpy(1.0, zj, N, h->xin0, ldin, N, nrhs, 0, st));
-      STCHK(apply_core(h, li, false, nrhs, 1.0, 0.0, nullptr, w, nullptr, 0, st));
+      // z_j = P v_j; w = A z_j
+      STCHK(precond(vj, zj));
+      STCHK(oper(zj, w));
       // two classical Gram-Schmidt passes against v_0 .. v_j
       HIPCHK(dots(V, j + 1, w, h->gm_h1, m + 1));
       HIPCHK(launch_kupdate(-1.0, V, vs, N, h->gm_h1, m + 1, j + 1, w, N, nrhs, st));
       HIPCHK(dots(V, j + 1, w, h->gm_h2, m + 1));
       HIPCHK(launch_kupdate(-1.0, V, vs, N, h->gm_h2, m + 1, j + 1, w, N, nrhs, st));
       HIPCHK(dots(w, 1, w, h->gm_hn, 1));
-      HIPCHK(launch_kstep(S, j, h->gm_h1, h->gm_h2, m + 1, h->gm_hn, tol, nrhs, st));
+      HIPCHK(launch_kstep(S, j, h->gm_h1, h->gm_h2, m + 1, h->gm_hn, tol_s, nrhs, st));
       HIPCHK(launch_kscale(w, N, S.inv, N, nrhs, st));
       for (int c = 0; c < nrhs; ++c) iters[c] += active[c];
       ++done_iters;
@@ -977,11 +1054,28 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
     // x += sum_i z_i y_i over the steps of this cycle
     HIPCHK(launch_ksolve(S, h->gm_y, nrhs, st));
     HIPCHK(launch_kupdate(1.0, Zb, vs, N, h->gm_y, m, j, h->xt, N, nrhs, st));
-    // true residual r = b - Z x into V_0 (it starts the next cycle)
-    HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
-    STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, V, nullptr, 0, st));
+    if (scaled) {
+      // true residual: x = C^{-T} xhat (zbuf), r = b - Z_l x (rt)
+      HIPCHK(block_pass(h, chat_set(h, true), h->xt, N, false, nullptr, 0, h->zbuf, 0, nullptr, 0, st));
+      HIPCHK(launch_axpy(1.0, h->zbuf, N, h->xin0, ldin, N, 1, 0, st));
+      STCHK(apply_core(h, li, false, 1, -1.0, 1.0, h->dt, h->rt, nullptr, 0, st));
+      double rn2 = 0.0;
+      STCHK(host_norm2(h->rt, &rn2));
+      rel_true[0] = bn_true > 0 ? std::sqrt(std::max(rn2, 0.0)) / bn_true : 0.0;
+      if (!(rel_true[0] == rel_true[0])) break;  // not finite: stop, reported as such
+    } else {
+      // true residual r = b - Z x into V_0 (it starts the next cycle)
+      HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->bt, V, nullptr, 0, st));
+    }
   }
-  HIPCHK(launch_permute_out(h->xt, N, h->perm, x_dev, ldx, N, nrhs, st));
+  if (scaled) {
+    rel[0] = rel_true[0];
+    HIPCHK(block_pass(h, chat_set(h, true), h->xt, N, false, nullptr, 0, h->zbuf, 0, x_dev, ldx,
+                      st));
+  } else {
+    HIPCHK(launch_permute_out(h->xt, N, h->perm, x_dev, ldx, N, nrhs, st));
+  }
   return HM_OK;
 }
 
