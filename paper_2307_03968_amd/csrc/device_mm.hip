@@ -40,7 +40,6 @@ struct Prec<true> {                      // FP32 blocks, 3M
   using X = float2;                      // staged input element
   using Acc = f4v;
   static constexpr int NACC = 3;
-  static constexpr int CH = 64;          // staged columns per chunk
   __device__ static __forceinline__ float2 load_a(const void* P, uint32_t idx) {
     const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(P) + idx);
     return make_float2(v.x, v.y);
@@ -65,7 +64,6 @@ struct Prec<false> {                     // FP64 blocks, four real products
   using X = double2;
   using Acc = d4v;
   static constexpr int NACC = 2;
-  static constexpr int CH = 32;
   __device__ static __forceinline__ double2 load_a(const void* P, uint32_t idx) {
     const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P) + idx);
     return make_double2(v.x, v.y);
