@@ -342,6 +342,25 @@ def bench_single(a):
         extras["hmatvec_1rhs_f64"] = {"ms": mv_ms, "bytes": mv_bytes,
                                       "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
                                       "frac_hbm_peak": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+        if nrhs > 1:
+            # the same geometry with one right-hand side: the streaming term
+            # kernel (a GEMV), bound by HBM bandwidth
+            b1 = b[:, :1].contiguous()
+            s1 = lambda: h.solve(b1, K=wl.K, level=wl.level, precision=hmps.HM_F64)  # noqa: E731
+            for _ in range(3):
+                x1 = s1()
+            ms1 = timed(s1, reps, stream)
+            _, k1 = profiled(h, s1, reps)
+            x1 = s1()
+            extras["series_1rhs_f64"] = {
+                "ms_per_solve": ms1, "RHS_per_s": 1e3 / ms1,
+                "roofline": term_roofline(info, level, n, 1, "f64", False,
+                                          k1["term_series"]["avg_us"], T)}
+            if ref is not None:
+                extras["series_1rhs_f64"]["rel_err_vs_oracle_xK"] = series.rel_err(
+                    x1.cpu().numpy(), ref[:, :1])
+            log(f"one RHS: {ms1:.3f} ms/solve, term "
+                f"{extras['series_1rhs_f64']['roofline']['frac']:.2f} of HBM peak")
         other = hmps.HM_F32_APPLY if prec == hmps.HM_F64 else hmps.HM_F64
         oname = "f32" if other == hmps.HM_F32_APPLY else "f64"
         for _ in range(3):

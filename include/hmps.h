@@ -307,7 +307,9 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
  * tiles 16/32/64 up to nrhs}, and the half-storage kernel where it
  * applies --
  * and keeps the fastest on the handle (median of five timed calls after
- * two warm-ups, HIP events on hip_stream).  best and best_ms (nullable)
+ * two warm-ups, HIP events on hip_stream).  When an MFMA candidate wins,
+ * mm_min_rhs becomes min(nrhs, 8), so one right-hand side keeps the
+ * streaming kernels; when a streaming one wins, nrhs + 1.  best and best_ms (nullable)
  * receive the choice and its time per solve.  Synchronises the stream. */
 int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_stream,
                   hm_tuning* best, double* best_ms);

@@ -143,7 +143,7 @@ struct hm_matrix {
   int use_half = 1;               // 1: half storage where available, 2: panels
   int half_pct = 100;             // cost weight (%) of half-panel columns in the work split
   std::vector<hm::GroupList> sa_mm;
-  int mm_min_rhs = 8;           // right-hand sides from which the MFMA kernels run
+  int mm_min_rhs = hm::kMmMinRhsDefault;  // right-hand sides from which the MFMA kernels run
   int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
   int inrow_pct = 100;          // cost weight (%) of in-row rows in the work split
   // per-leaf column layout of the panels, kept to rebuild the work lists
@@ -2480,7 +2480,7 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
     return HM_EINVAL;
   }
   if (t->mm_min_rhs > 0) h->mm_min_rhs = t->mm_min_rhs;
-  if (t->mm_min_rhs == -1) h->mm_min_rhs = 8;
+  if (t->mm_min_rhs == -1) h->mm_min_rhs = kMmMinRhsDefault;
   if (t->rhs_tile > 0) h->rhs_tile = t->rhs_tile;
   if (t->rhs_tile == -1) h->rhs_tile = 0;
   int wgs = h->term_wgs;
@@ -2578,7 +2578,11 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
           STCHK(time_one(&ms));
           if (ms < bms) {
             bms = ms;
-            bt = hm_tuning{c.mm_min == 1 ? 1 : nrhs + 1, w, c.tile, pct, hs};
+            // the MFMA kernels were timed at nrhs only: they take over from
+            // min(nrhs, the default threshold) on, so one right-hand side
+            // (a GEMV, far below the MFMA ridge) keeps the streaming kernels
+            bt = hm_tuning{c.mm_min == 1 ? std::min(nrhs, kMmMinRhsDefault) : nrhs + 1, w, c.tile,
+                           pct, hs};
           }
         }
       }

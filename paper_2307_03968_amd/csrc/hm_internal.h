@@ -184,6 +184,7 @@ int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_strea
 int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T);
 int workspace_rhs(hm_matrix_t h);        // right-hand sides the workspace holds
 int64_t resident_bytes(hm_matrix_t h);  // device blocks + workspace
+constexpr int kMmMinRhsDefault = 8;  // default right-hand sides from which MFMA kernels run
 // GMRES (PS_GMRES): the cycle length a call with these options uses, and the
 // device bytes its workspace would add for m and nrhs (0 when it fits)
 int gmres_restart(const ps_opts& o);

@@ -449,6 +449,8 @@ def test_autotune_choice_keeps_results(many_rhs):
     _say("autotune nrhs=20 f32")
     best, ms = c.h.autotune(20, K=3, precision=hmps.HM_F32_APPLY)
     assert ms > 0 and c.h.tuning() == best
+    # tuned at 20 right-hand sides: one right-hand side keeps the streaming kernels
+    assert 2 <= best["mm_min_rhs"] <= 21
     x = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
     assert series.rel_err(x, ref) <= 1e-5
     c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1, inrow_pct=-1)
