@@ -368,11 +368,10 @@ def bench_single(a):
         o_ms = timed(lambda: solve(other), reps, stream)
         xo = solve(other)
         extras[f"series_{oname}"] = {"ms_per_solve": o_ms, "RHS_per_s": nrhs * 1e3 / o_ms}
-        if mm:
-            _, ko = profiled(h, lambda: solve(other), 5)
-            extras[f"series_{oname}"]["roofline"] = term_roofline(
-                info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T, wl.name)
-            extras[f"series_{oname}"]["kernels"] = ko
+        _, ko = profiled(h, lambda: solve(other), 5)
+        extras[f"series_{oname}"]["roofline"] = term_roofline(
+            info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T, wl.name, half)
+        extras[f"series_{oname}"]["kernels"] = ko
         if H is not None:
             from oracle import series
             extras[f"series_{oname}"]["rel_err_vs_oracle_xK"] = series.rel_err(xo.cpu().numpy(), ref)
@@ -389,6 +388,19 @@ def bench_single(a):
                     el = series.rel_err(xl, series.series(H, b_np, wl.K, lev))
                     per_level[str(lev)] = {"ms_per_solve": tl, "RHS_per_s": nrhs * 1e3 / tl,
                                            "rel_err_vs_oracle_xK": el}
+                    # one series term = stage A (the far-block coefficients
+                    # of the coarser levels) + the term kernel: their bytes
+                    # over their summed average durations
+                    _, kl = profiled(h, lambda: h.solve(b, K=wl.K, level=lev), 5)
+                    nt = max(1, kl["term_series"]["launches"])
+                    us = (kl["term_series"]["avg_us"] * nt
+                          + kl["stageA"]["avg_us"] * kl["stageA"]["launches"]) / nt
+                    ent = info["half_entries" if half else "series_entries"][lev]
+                    nb = 16 * (ent + info["stageA_entries"][lev]) + 16 * (
+                        n + info["coeffs"][lev] + 3 * n)
+                    per_level[str(lev)]["term_and_stageA"] = {
+                        "us": us, "bytes": nb, "GBps": nb / (us * 1e-6) / 1e9,
+                        "frac_hbm_peak": nb / (us * 1e-6) / 1e9 / HBM_PEAK_GBPS}
                     log(f"level {lev}: {tl:.3f} ms/solve, rel.err {el:.2e}")
                 extras["series_f64_coarser_levels"] = per_level
                 # the nested multi-level form (eq. 14-22) one level above the
