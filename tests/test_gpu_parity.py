@@ -252,6 +252,30 @@ def test_full_size_sphere_24576():
     assert series.rel_err(x, series.series(H, b, 4)) <= TOL_F32
 
 
+@pytest.mark.timeout(900)
+def test_full_size_cube_32768():
+    """The 32^3 dielectric cube (leaf <= 128, tol 1e-5, K = 5, 64 plane
+    waves) in the configuration the benchmark times (autotuned: matrix-core
+    kernels), FP64 and FP32 blocks, against the oracle's x_K."""
+    wl = W.cube_volume()
+    _say("oracle build cube_32768")
+    H = hmatrix.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol)
+    _say("library build cube_32768")
+    h = hmps.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol)
+    b = wl.rhs()
+    _say("autotune cube_32768 nrhs=64")
+    best, _ = h.autotune(b.shape[1], K=wl.K)
+    assert b.shape[1] >= best["mm_min_rhs"]  # the matrix-core kernels, as timed
+    ref = series.series(H, b, wl.K)
+    _say("series f64 cube_32768")
+    x = _host(h.solve(_dev(b), K=wl.K))
+    assert series.rel_err(x, ref) <= TOL_F64
+    _say("series f32 cube_32768")
+    x = _host(h.solve(_dev(b), K=wl.K, precision=hmps.HM_F32_APPLY))
+    assert series.rel_err(x, ref) <= TOL_F32
+    h.close()
+
+
 def test_batched_instances_match_per_instance_oracle():
     """One batched handle (three instances: sphere, volume cube, a sphere
     without far blocks) solves every instance as its own oracle would, at the
