@@ -182,6 +182,10 @@ constexpr int kGroupTileMM = 64;
 
 
 // ---- launchers (return hipError_t of the launch) ---------------------------
+// one right-hand side, block-diagonal panels (D^{-1}, C^{-1}, C^{-T}): one
+// workgroup per leaf, leaves of at most 128 points, epilogue as the term kernel
+hipError_t launch_block_diag(const TermArgs& a, int nl, int max_m, hipStream_t st);
+constexpr int kBlockDiagMaxLeaf = 128;
 hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm, double2* out,
                              int64_t ldo, int64_t n, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, double2* x,

@@ -507,9 +507,67 @@ inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t
 // NR (right-hand sides per workgroup) for nrhs; grid.y = ceil(nrhs / NR)
 inline int pick_nr(int nrhs) { return nrhs == 1 ? 1 : (nrhs == 2 ? 2 : 4); }
 
+// Block-diagonal product for one right-hand side (D^{-1}, C^{-1} or C^{-T}
+// blocks): one workgroup per leaf a, z = P_a x_a with P_a the leaf's m x m
+// block (column-major, leading dimension even m) and x_a gathered through
+// the panel's column sources; the two halves of the workgroup take
+// alternate columns (8 loads in flight per thread), their sums are added in
+// a fixed order, and the epilogue stores of the term kernel follow.
+__global__ __launch_bounds__(kThreads) void k_block_diag(TermArgs A) {
+  constexpr int kRows = kBlockDiagMaxLeaf;  // rows per half: the largest leaf served
+  static_assert(2 * kRows == kThreads, "two halves of one workgroup");
+  constexpr int UNR = 8;
+  __shared__ double2 xs[kRows];
+  __shared__ double2 zs[2][kRows];
+  const int a = blockIdx.x;
+  const int m = A.ps.leaf_m[a];
+  const int64_t ld = m + (m & 1);
+  const double2* __restrict__ P = reinterpret_cast<const double2*>(A.ps.data) + A.ps.panel_off[a];
+  const int32_t* __restrict__ src = A.ps.src + A.ps.col_off[a];
+  for (int j = threadIdx.x; j < m; j += kThreads) {
+    int64_t sidx = src[j];
+    if (A.in_perm) sidx = A.in_perm[sidx];
+    xs[j] = A.xin[sidx];
+  }
+  __syncthreads();
+  const int i = threadIdx.x % kRows, h = threadIdx.x / kRows;
+  double2 z = zero2();
+  if (i < m) {
+    int j = h;
+    for (; j + 2 * (UNR - 1) < m; j += 2 * UNR) {
+      double2 v[UNR];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const dvec2 q = __builtin_nontemporal_load(
+            reinterpret_cast<const dvec2*>(P + i + (int64_t)(j + 2 * u) * ld));
+        v[u] = make_double2(q.x, q.y);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) cmac(z, v[u], xs[j + 2 * u]);
+    }
+    for (; j < m; j += 2) {
+      const dvec2 q = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P + i + (int64_t)j * ld));
+      cmac(z, make_double2(q.x, q.y), xs[j]);
+    }
+  }
+  zs[h][i] = z;
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    const double2 z0 = zs[0][threadIdx.x], z1 = zs[1][threadIdx.x];
+    finish_entry(A, A.leaf_off[a], threadIdx.x, 0, make_double2(z0.x + z1.x, z0.y + z1.y));
+  }
+}
+
 }  // namespace
 
 // ============================================================== launchers
+hipError_t launch_block_diag(const TermArgs& a, int nl, int max_m, hipStream_t st) {
+  if (nl <= 0) return hipSuccess;
+  if (max_m > kBlockDiagMaxLeaf) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_block_diag, dim3(nl), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm, double2* out,
                              int64_t ldo, int64_t n, int nrhs, hipStream_t st) {
   hipLaunchKernelGGL(k_permute_in, dim3(blocks_for(n, 256), nrhs), dim3(256), 0, st, b, ldb, perm,

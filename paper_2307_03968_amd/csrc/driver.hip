@@ -618,6 +618,13 @@ PanelSet chat_set(const hm_matrix* h, bool transposed) {
                   h->R_col, h->leaf_m};
 }
 
+// One right-hand side through block-diagonal panels: one workgroup per leaf
+// where the leaves fit it, else the term kernel on the D^{-1} work list.
+hipError_t block_launch(const hm_matrix* h, const TermArgs& t, hipStream_t st) {
+  if (h->max_m <= kBlockDiagMaxLeaf) return launch_block_diag(t, h->nl, h->max_m, st);
+  return launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st);
+}
+
 // Block-diagonal launch (C^{-1}, C^{-T} or D^{-1} panels, one right-hand
 // side): y = M in per leaf, then the TermArgs stores (yout, xacc, out).
 hipError_t block_pass(hm_matrix* h, const PanelSet& ps, const double2* in, int64_t ldi,
@@ -631,7 +638,7 @@ hipError_t block_pass(hm_matrix* h, const PanelSet& ps, const double2* in, int64
   t.ldxa = h->N;
   t.accumulate = accumulate;
   if (out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
-  return launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st);
+  return block_launch(h, t, st);
 }
 
 // K terms of the scaled series from yhat_0 in xin0 ([y | t], tree order):
@@ -741,7 +748,7 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
       t.ldxa = N;
       t.accumulate = 0;
       if (o) { t.out = o; t.ldo = ldo; t.out_perm = h->perm; }
-      return launch_term(false, h->max_m, t, h->tl_dinv.nwg, 1, st);
+      return block_launch(h, t, st);
     };
     TIMED(HM_K_TERM_DINV, block_diag(chat_set(h, false), rhs, ldr, rhs_perm, y_cur, ldin, xh, nullptr));
     if (want_norms) {  // ||y_0||, y_0 = D^{-1} b
