@@ -212,3 +212,43 @@ def test_binding_structs_match_the_header(tmp_path):
         py = getattr(hmps, nm)
         got = C.sizeof(py) if what == "size" else getattr(py, what).offset
         assert got == int(val), (nm, what, got, val)
+
+
+@pytest.mark.parametrize("case", [
+    "min_not_max", "inclusive", "eta_below", "eta_equal", "diag_near", "diag_far", "gap_near",
+    "gap_far"])
+def test_library_partition_eq7_hand_worked(case, tmp_path):
+    """The library's host build partitions the hand-worked eq. 7 cases of
+    the oracle pins exactly as worked out by hand."""
+    from test_oracle_build import EQ7_CASES, eq7_expected
+    _, pts, eta, adm = [c for c in EQ7_CASES if c[0] == case][0]
+    xyz = np.array(pts, dtype=np.float64)
+    prob = W.Problem(W.SURFACE, xyz, W.WAVENUMBER, 0.1)
+    h = hmps.HMatrix(prob, 2, eta, 1e-6, flags=HOST)
+    path = str(tmp_path / "e.bin")
+    h.export(path)
+    E = hmps.read_export(path)
+    lo, ls = E["leaf_off"], E["leaf_size"]
+    assert list(zip(lo, ls)) == [(0, 2), (2, 2)]
+    near = {(int(lo[t]), int(ls[t]), int(lo[s]), int(ls[s])) for t, s, _ in E["near"]}
+    far = {((int(r[0]), int(r[1]), int(r[2]), int(r[3])), int(r[4])) for r in E["far"]}
+    exp_near, exp_far = eq7_expected(adm)
+    assert near == exp_near and far == exp_far
+    h.close()
+
+
+@pytest.mark.parametrize("key", [(1536, 1.0, 64), (24576, 4.0, 128)])
+def test_library_partition_counts_match_independent_probe(key):
+    """Near and per-level far block counts of the library's build of the
+    1,536- and 24,576-point spheres equal those of an independent
+    implementation."""
+    from test_oracle_build import PROBE_COUNTS
+    near, far = PROBE_COUNTS[key]
+    n, radius, leaf = key
+    prob = W.Problem(W.SURFACE, W.sphere_points(n, radius), W.WAVENUMBER,
+                     W.sphere_spacing(n, radius))
+    h = hmps.HMatrix(prob, leaf, 1.0, 1e-4, flags=HOST)
+    info = h.info()
+    assert info["near_blocks"] == near
+    assert {lev: d["blocks"] for lev, d in info["far"].items()} == far
+    h.close()

@@ -272,3 +272,91 @@ def test_half_hmatrix_symmetric(h_sphere, h_cube):
     A = H.dense(min(H.far_levels)) / H.chi_tree[None, :]
     off = ~np.eye(H.n, dtype=bool)
     assert np.max(np.abs(A - A.T)[off]) <= 1e-14 * np.max(np.abs(A[off]))
+
+
+# ---------------------------------------------------------------- eq. 7 reading
+# Four points, leaf_max = 2: the root splits along its longest box axis into
+# the leaves L (tree positions 0-1) and R (2-3).  The pair (L, R) is either
+# one far block at level 1 (eq. 7 holds) or a dense near block.  Each case is
+# worked out by hand from eq. 7 read as
+#     eta * dist(L, R) >= min(diam L, diam R),
+# with diam the box diagonal and dist the Euclidean gap between the boxes.
+# The comment of each case gives the numbers and which other reading would
+# decide it the other way.
+EQ7_CASES = [
+    # diam 1 and 3, gap 2: min 1 <= 2 -> far; max(1, 3) = 3 > 2 would be near
+    ("min_not_max", [(0, 0, 0), (1, 0, 0), (3, 0, 0), (6, 0, 0)], 1.0, True),
+    # diam 1 and 3, gap 1: equality -> far (inclusive); a strict test is near
+    ("inclusive", [(0, 0, 0), (1, 0, 0), (2, 0, 0), (5, 0, 0)], 1.0, True),
+    # eta multiplies the gap: 0.49 * 2 = 0.98 < 1 -> near, 0.5 * 2 = 1 -> far
+    ("eta_below", [(0, 0, 0), (1, 0, 0), (3, 0, 0), (6, 0, 0)], 0.49, False),
+    ("eta_equal", [(0, 0, 0), (1, 0, 0), (3, 0, 0), (6, 0, 0)], 0.5, True),
+    # L spans (0,0)-(1,1): diam sqrt 2 = 1.4142; gap 2.  0.70 * 2 = 1.40 ->
+    # near, 0.71 * 2 = 1.42 -> far; a diam of the longest extent (1) or of
+    # half the diagonal would make both far
+    ("diag_near", [(0, 0, 0), (1, 1, 0), (3, 0, 0), (10, 0, 0)], 0.70, False),
+    ("diag_far", [(0, 0, 0), (1, 1, 0), (3, 0, 0), (10, 0, 0)], 0.71, True),
+    # boxes apart by (2, 2, 0): gap sqrt 8 = 2.828, min diam 1.  0.35 * 2.828
+    # = 0.990 -> near, 0.36 * 2.828 = 1.018 -> far; the x gap alone (2)
+    # would make both near, the centre distance (4.47) both far
+    ("gap_near", [(0, 0, 0), (1, 0, 0), (3, 2, 0), (6, 2, 0)], 0.35, False),
+    ("gap_far", [(0, 0, 0), (1, 0, 0), (3, 2, 0), (6, 2, 0)], 0.36, True),
+]
+
+
+def eq7_expected(admissible):
+    """Blocks of the four-point tree as (t_off, t_size, s_off, s_size) sets."""
+    L, R = (0, 2), (2, 2)
+    if admissible:
+        return {L + L, R + R}, {(L + R, 1), (R + L, 1)}
+    return {L + L, L + R, R + L, R + R}, set()
+
+
+@pytest.mark.parametrize("case", [c[0] for c in EQ7_CASES])
+def test_partition_eq7_hand_worked(case):
+    """The oracle's partition of each hand-worked eq. 7 case is the block
+    list worked out by hand (no call of the oracle's admissibility test)."""
+    _, pts, eta, adm = [c for c in EQ7_CASES if c[0] == case][0]
+    xyz = np.array(pts, dtype=np.float64)
+    tree = cluster.build_tree(xyz, 2)
+    assert [(l.off, l.size) for l in tree.leaves] == [(0, 2), (2, 2)]
+    assert set(tree.perm[:2]) == {0, 1} and set(tree.perm[2:]) == {2, 3}
+    part = cluster.partition(tree, eta)
+    near = {(t.off, t.size, s.off, s.size) for t, s in part.near}
+    far = {((t.off, t.size, s.off, s.size), lev) for t, s, lev in part.far}
+    exp_near, exp_far = eq7_expected(adm)
+    assert near == exp_near and far == exp_far
+
+
+def test_partition_eq7_two_points():
+    """Two one-point leaves: the root pair holds the diagonal and is split;
+    each point with itself is a near block, the two cross pairs are far at
+    level 1 (diam 0 <= eta * dist)."""
+    tree = cluster.build_tree(np.array([[0.0, 0, 0], [1.0, 0, 0]]), 1)
+    part = cluster.partition(tree, 1.0)
+    assert {(t.off, s.off) for t, s in part.near} == {(0, 0), (1, 1)}
+    assert {(t.off, s.off, lev) for t, s, lev in part.far} == {(0, 1, 1), (1, 0, 1)}
+
+
+# Block counts of an independent throwaway implementation of the same
+# readings (tree split, eq. 7, coarsest admissible pair), on the seeded
+# 1,536-point (radius 1, leaf <= 64) and 24,576-point (radius 4, leaf <= 128)
+# spheres: near blocks including the diagonal, far blocks per level, both
+# orientations.
+PROBE_COUNTS = {
+    (1536, 1.0, 64): (756, {5: 268}),
+    (24576, 4.0, 128): (6014, {5: 218, 6: 1714, 7: 3078, 8: 5834}),
+}
+
+
+@pytest.mark.parametrize("key", sorted(PROBE_COUNTS))
+def test_partition_counts_match_independent_probe(key):
+    n, radius, leaf = key
+    tree = cluster.build_tree(W.sphere_points(n, radius), leaf)
+    part = cluster.partition(tree, 1.0)
+    near, far = PROBE_COUNTS[key]
+    assert len(part.near) == near
+    got = {}
+    for _, _, lev in part.far:
+        got[lev] = got.get(lev, 0) + 1
+    assert got == far
