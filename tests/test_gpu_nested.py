@@ -14,6 +14,7 @@ import pytest
 
 import workloads as W
 from oracle import hmatrix, series
+from parity import assert_close
 
 torch = pytest.importorskip("torch")
 from paper_2307_03968_amd import hmps  # noqa: E402
@@ -63,7 +64,7 @@ def test_nested_each_level_and_K(sphere_levels):
                 _say(f"nested {c.name} level={lev} K={K} precision={prec}")
                 x = _host(c.h.solve(_dev(c.b), K=K, level=lev, precision=prec,
                                     kind=hmps.PS_NESTED))
-                assert series.rel_err(x, ref) <= tol, (lev, K, prec)
+                assert_close(x, ref, tol, (lev, K, prec))
 
 
 def test_nested_leaf_level_equals_series(sphere_levels):
@@ -73,7 +74,7 @@ def test_nested_leaf_level_equals_series(sphere_levels):
     b = _dev(c.b)
     xn = _host(c.h.solve(b, K=4, kind=hmps.PS_NESTED))
     xs = _host(c.h.solve(b, K=4))
-    assert series.rel_err(xn, xs) <= 1e-13
+    assert_close(xn, xs, 1e-13)
 
 
 def test_nested_volume():
@@ -84,7 +85,7 @@ def test_nested_volume():
         ref = series.nested(c.H, c.b, 2, lev)
         _say(f"nested {c.name} level={lev} K=2")
         x = _host(c.h.solve(_dev(c.b), K=2, level=lev, kind=hmps.PS_NESTED))
-        assert series.rel_err(x, ref) <= TOL_F64, lev
+        assert_close(x, ref, TOL_F64, lev)
     c.h.close()
 
 
@@ -100,7 +101,7 @@ def test_nested_matrix_core_ragged_depths():
                 _say(f"nested {c.name} nrhs=17 mfma level={lev} precision={prec}")
                 x = _host(c.h.solve(_dev(c.b), K=2, level=lev, precision=prec,
                                     kind=hmps.PS_NESTED))
-                assert series.rel_err(x, ref) <= tol, (lev, prec)
+                assert_close(x, ref, tol, (lev, prec))
     finally:
         c.h.tune(mm_min_rhs=-1)
     c.h.close()

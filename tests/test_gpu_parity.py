@@ -14,6 +14,7 @@ import pytest
 
 import workloads as W
 from oracle import hmatrix, series
+from parity import assert_close
 
 torch = pytest.importorskip("torch")
 from paper_2307_03968_amd import hmps  # noqa: E402
@@ -84,17 +85,17 @@ def test_series_ragged_depths_each_level(ragged_depth):
         for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
             _say(f"series {c.name} level={lev} precision={prec}")
             x = _host(c.h.solve(_dev(c.b), K=3, level=lev, precision=prec))
-            assert series.rel_err(x, series.series(c.H, c.b, 3, lev)) <= tol, (lev, prec)
+            assert_close(x, series.series(c.H, c.b, 3, lev), tol, (lev, prec))
         _say(f"hmat_apply {c.name} level={lev}")
         y = _host(c.h.apply(_dev(c.b), level=lev))
-        assert series.rel_err(y, series.apply_Z(c.H, c.b, lev)) <= 1e-12
+        assert_close(y, series.apply_Z(c.H, c.b, lev), 1e-12)
 
 
 def test_series_f64_sphere(sphere):
     _say("series f64 sphere_1536 K=4 leaf level")
     x = _host(sphere.h.solve(_dev(sphere.b), K=4))
     ref = series.series(sphere.H, sphere.b, 4)
-    assert series.rel_err(x, ref) <= TOL_F64
+    assert_close(x, ref, TOL_F64)
 
 
 @pytest.mark.parametrize("K", [0, 1, 3])
@@ -104,14 +105,14 @@ def test_series_f64_each_level(sphere_levels, K):
         _say(f"series f64 {c.name} K={K} level={lev}")
         x = _host(c.h.solve(_dev(c.b), K=K, level=lev))
         ref = series.series(c.H, c.b, K, lev)
-        assert series.rel_err(x, ref) <= TOL_F64, (K, lev)
+        assert_close(x, ref, TOL_F64, (K, lev))
 
 
 def test_series_f64_volume(cube):
     _say("series f64 cube_1000 K=5")
     x = _host(cube.h.solve(_dev(cube.b), K=5))
     ref = series.series(cube.H, cube.b, 5)
-    assert series.rel_err(x, ref) <= TOL_F64
+    assert_close(x, ref, TOL_F64)
 
 
 @pytest.mark.parametrize("nrhs", [1, 2, 5, 7])
@@ -120,7 +121,7 @@ def test_series_ragged_leaves_many_rhs(ragged, nrhs):
     _say(f"series f64 {ragged.name} nrhs={nrhs}")
     x = _host(ragged.h.solve(_dev(b), K=4))
     ref = series.series(ragged.H, b, 4)
-    assert series.rel_err(x, ref) <= TOL_F64
+    assert_close(x, ref, TOL_F64)
 
 
 @pytest.mark.parametrize("precision", [hmps.HM_F64, hmps.HM_F32_APPLY])
@@ -133,7 +134,7 @@ def test_hmatvec(sphere_levels, cube, precision):
             _say(f"hmat_apply {c.name} precision={precision} level={lev}")
             y = _host(c.h.apply(_dev(x), level=lev, precision=precision))
             ref = series.apply_Z(c.H, x, lev)
-            assert series.rel_err(y, ref) <= tol, (c.name, lev)
+            assert_close(y, ref, tol, (c.name, lev))
 
 
 def test_series_f32_apply(sphere, cube):
@@ -141,7 +142,7 @@ def test_series_f32_apply(sphere, cube):
         _say(f"series f32 {c.name}")
         x = _host(c.h.solve(_dev(c.b), K=K, precision=hmps.HM_F32_APPLY))
         ref = series.series(c.H, c.b, K)
-        assert series.rel_err(x, ref) <= TOL_F32
+        assert_close(x, ref, TOL_F32)
 
 
 @pytest.mark.parametrize("precision", [hmps.HM_F32_APPLY, hmps.HM_F64])
@@ -155,7 +156,7 @@ def test_refine_reaches_exact_solution(sphere, precision):
                            max_passes=200, refine_tol=1e-10, stats=True)
     x = _host(x)
     xs = series.solve_exact(sphere.H, sphere.b)
-    assert series.rel_err(x, xs) <= TOL_REFINE
+    assert_close(x, xs, TOL_REFINE)
     assert st[0]["diverged"] == 0 and 1 <= st[0]["passes"] < 200
 
 
@@ -178,7 +179,7 @@ def test_single_leaf_is_direct_solve():
     ref = np.linalg.solve(entries.dense(prob), b)
     for K in (0, 2):
         x = _host(h.solve(_dev(b), K=K))
-        assert series.rel_err(x, ref) <= TOL_F64
+        assert_close(x, ref, TOL_F64)
 
 
 def test_deterministic(sphere):
@@ -246,10 +247,10 @@ def test_full_size_sphere_24576():
     for lev in (-1, min(H.far_levels)):
         _say(f"series f64 sphere_24576 level={lev}")
         x = _host(h.solve(_dev(b), K=4, level=lev))
-        assert series.rel_err(x, series.series(H, b, 4, lev)) <= TOL_F64
+        assert_close(x, series.series(H, b, 4, lev), TOL_F64)
     _say("series f32 sphere_24576")
     x = _host(h.solve(_dev(b), K=4, precision=hmps.HM_F32_APPLY))
-    assert series.rel_err(x, series.series(H, b, 4)) <= TOL_F32
+    assert_close(x, series.series(H, b, 4), TOL_F32)
 
 
 @pytest.mark.timeout(900)
@@ -269,10 +270,10 @@ def test_full_size_cube_32768():
     ref = series.series(H, b, wl.K)
     _say("series f64 cube_32768")
     x = _host(h.solve(_dev(b), K=wl.K))
-    assert series.rel_err(x, ref) <= TOL_F64
+    assert_close(x, ref, TOL_F64)
     _say("series f32 cube_32768")
     x = _host(h.solve(_dev(b), K=wl.K, precision=hmps.HM_F32_APPLY))
-    assert series.rel_err(x, ref) <= TOL_F32
+    assert_close(x, ref, TOL_F32)
     h.close()
 
 
@@ -297,12 +298,12 @@ def test_batched_instances_match_per_instance_oracle():
             for i, H in enumerate(Hs):
                 o0, o1 = h.offsets[i], h.offsets[i + 1]
                 ref = series.series(H, bs[i], K, H.L - d)
-                assert series.rel_err(x[o0:o1], ref) <= tol_s, (i, d, prec)
+                assert_close(x[o0:o1], ref, tol_s, (i, d, prec))
         _say(f"batched hmat_apply level=top-{d}")
         y = _host(h.apply(_dev(b), level=top - d))
         for i, H in enumerate(Hs):
             o0, o1 = h.offsets[i], h.offsets[i + 1]
-            assert series.rel_err(y[o0:o1], series.apply_Z(H, bs[i], H.L - d)) <= 1e-12, (i, d)
+            assert_close(y[o0:o1], series.apply_Z(H, bs[i], H.L - d), 1e-12, (i, d))
     x1 = _host(h.solve(_dev(b), K=K))
     x0 = _host(h.solve(_dev(b), K=K, level=-1))
     assert np.array_equal(x0, x1)
@@ -330,10 +331,10 @@ def test_mfma_series_each_level(many_rhs, nrhs):
             for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
                 _say(f"mfma series {c.name} nrhs={nrhs} level={lev} precision={prec}")
                 x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
-                assert series.rel_err(x, ref) <= tol, (lev, prec)
+                assert_close(x, ref, tol, (lev, prec))
             _say(f"mfma hmat_apply {c.name} nrhs={nrhs} level={lev}")
             y = _host(c.h.apply(_dev(b), level=lev))
-            assert series.rel_err(y, series.apply_Z(c.H, b, lev)) <= 1e-12
+            assert_close(y, series.apply_Z(c.H, b, lev), 1e-12)
     finally:
         c.h.tune(mm_min_rhs=-1)
 
@@ -352,8 +353,9 @@ def test_mfma_matches_streaming_path(many_rhs):
     _say("mfma path nrhs=24")
     x_m = _host(c.h.solve(b, K=4))
     x_m32 = _host(c.h.solve(b, K=4, precision=hmps.HM_F32_APPLY))
-    assert series.rel_err(x_m, x_s) <= 1e-12
-    assert series.rel_err(x_m32, x_s) <= TOL_F32 and series.rel_err(x_s32, x_s) <= TOL_F32
+    assert_close(x_m, x_s, 1e-12)
+    assert_close(x_m32, x_s, TOL_F32)
+    assert_close(x_s32, x_s, TOL_F32)
 
 
 def test_mfma_volume_and_large_leaves():
@@ -371,7 +373,7 @@ def test_mfma_volume_and_large_leaves():
             for prec, tol_s in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
                 _say(f"mfma series {name} level={lev} precision={prec}")
                 x = _host(h.solve(_dev(b), K=3, level=lev, precision=prec))
-                assert series.rel_err(x, ref) <= tol_s, (name, lev, prec)
+                assert_close(x, ref, tol_s, (name, lev, prec))
         h.close()
 
 
@@ -388,7 +390,7 @@ def test_retuned_work_lists_same_result(many_rhs):
             c.h.tune(term_wgs=wgs)
             assert c.h.tuning()["term_wgs"] == wgs
             x1 = _host(c.h.solve(b, K=4))
-            assert series.rel_err(x1, x0) <= 1e-13
+            assert_close(x1, x0, 1e-13)
     finally:
         c.h.tune(term_wgs=-1)
     assert c.h.tuning()["term_wgs"] == default
@@ -428,7 +430,7 @@ def test_batched_refine_each_instance_reaches_xstar():
     x = _host(x)
     for i, H in enumerate(Hs):
         o0, o1 = h.offsets[i], h.offsets[i + 1]
-        assert series.rel_err(x[o0:o1], series.solve_exact(H, bs[i])) <= TOL_REFINE, i
+        assert_close(x[o0:o1], series.solve_exact(H, bs[i]), TOL_REFINE, i)
     assert all(s["diverged"] == 0 for s in st)
     h.close()
 
@@ -476,7 +478,7 @@ def test_autotune_choice_keeps_results(many_rhs):
     # tuned at 20 right-hand sides: one right-hand side keeps the streaming kernels
     assert 2 <= best["mm_min_rhs"] <= 21
     x = _host(c.h.solve(b, K=3, precision=hmps.HM_F32_APPLY))
-    assert series.rel_err(x, ref) <= 1e-5
+    assert_close(x, ref, 1e-5)
     c.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1, inrow_pct=-1)
 
 
@@ -517,14 +519,14 @@ def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels):
                     for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
                         _say(f"half storage {c.name} level={lev} wgs={wgs} precision={prec}")
                         x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
-                        assert series.rel_err(x, ref) <= tol, (lev, wgs, prec)
+                        assert_close(x, ref, tol, (lev, wgs, prec))
                         if prec == hmps.HM_F64:
-                            assert series.rel_err(x, x_p) <= 1e-12, (lev, wgs)
+                            assert_close(x, x_p, 1e-12, (lev, wgs))
                         y = _host(c.h.apply(_dev(b), level=lev, precision=prec))
                         tol_y = 1e-12 if prec == hmps.HM_F64 else 1e-6
-                        assert series.rel_err(y, ref_z) <= tol_y, (lev, wgs, prec)
+                        assert_close(y, ref_z, tol_y, (lev, wgs, prec))
                         if prec == hmps.HM_F64:
-                            assert series.rel_err(y, y_p) <= 1e-13, (lev, wgs)
+                            assert_close(y, y_p, 1e-13, (lev, wgs))
         finally:
             c.h.tune(half_storage=-1, term_wgs=-1)
         # the half-storage product reads fewer entries than the panels
@@ -551,7 +553,8 @@ def test_half_storage_deterministic_and_refine(sphere):
         x2 = _host(sphere.h.solve(b, **kw))
     finally:
         sphere.h.tune(half_storage=-1)
-    assert series.rel_err(x1, xs) <= TOL_REFINE and series.rel_err(x2, xs) <= TOL_REFINE
+    assert_close(x1, xs, TOL_REFINE)
+    assert_close(x2, xs, TOL_REFINE)
 
 
 def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
@@ -570,9 +573,9 @@ def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
                     for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
                         _say(f"small-leaf mfma {c.name} nrhs={nrhs} level={lev} precision={prec}")
                         x = _host(c.h.solve(_dev(b), K=3, level=lev, precision=prec))
-                        assert series.rel_err(x, ref) <= tol, (c.name, nrhs, lev, prec)
+                        assert_close(x, ref, tol, (c.name, nrhs, lev, prec))
                     y = _host(c.h.apply(_dev(b), level=lev))
-                    assert series.rel_err(y, series.apply_Z(c.H, b, lev)) <= 1e-12
+                    assert_close(y, series.apply_Z(c.H, b, lev), 1e-12)
         finally:
             c.h.tune(mm_min_rhs=-1, rhs_tile=-1)
 
@@ -597,7 +600,7 @@ def test_half_storage_batched_surfaces_one_rhs():
             for i, H in enumerate(Hs):
                 o0, o1 = h.offsets[i], h.offsets[i + 1]
                 ref = series.series(H, bs[i], 3, H.L - d)
-                assert series.rel_err(x[o0:o1], ref) <= tol_s, (i, d, prec)
+                assert_close(x[o0:o1], ref, tol_s, (i, d, prec))
     for H in Hs:
         assert series.rho(H) ** 4 < 1
     _say("half storage batched refine")
@@ -606,6 +609,107 @@ def test_half_storage_batched_surfaces_one_rhs():
     x = _host(x)
     for i, H in enumerate(Hs):
         o0, o1 = h.offsets[i], h.offsets[i + 1]
-        assert series.rel_err(x[o0:o1], series.solve_exact(H, bs[i])) <= TOL_REFINE, i
+        assert_close(x[o0:o1], series.solve_exact(H, bs[i]), TOL_REFINE, i)
     assert st[0]["diverged"] == 0
+    h.close()
+
+
+# ---------------------------------------------------------------- the batched configuration
+def _c4_sizes():
+    """16 ragged surface instances: 14 seeded sizes of the 256-instance
+    batch (those up to 3,000 points, so the oracle's dense x* stays cheap),
+    one fully dense instance (512 points, no far block) and one of 8,192."""
+    s = [int(n) for n in W.batched_sizes(256) if n <= 3000][:14]
+    return s + [512, 8192]
+
+
+@pytest.mark.timeout(900)
+def test_batched_16_instances_mfma_graph_replay():
+    """The batched configuration on its own path: one handle of 16 ragged
+    instances, 16 plane waves each, the matrix-core term and stage-A kernels
+    (the default from 8 right-hand sides on), FP64 (4M) and FP32 (3M) blocks,
+    eager and replayed from captured HIP graphs; every instance against its
+    own oracle x_K, and refinement (FP32 blocks, FP64 residual) captured with
+    its pass count and replayed, every instance against its own x*.  Then
+    the autotuner's choice (what the benchmark times) once more."""
+    sizes = _c4_sizes()
+    wls = [W.batched_instance(i, n) for i, n in enumerate(sizes)]
+    K, nrhs = wls[0].K, wls[0].nrhs
+    _say(f"build batched c4 sizes={sizes}")
+    h = hmps.HMatrix([w.problem for w in wls], 64, 1.0, 1e-4)
+    assert h.tuning()["mm_min_rhs"] <= nrhs
+    Hs, bs, refs, xss = [], [], [], []
+    for i, w in enumerate(wls):
+        _say(f"oracle instance {i} n={sizes[i]}")
+        H = hmatrix.HMatrix(w.problem, 64, 1.0, 1e-4)
+        if sizes[i] in (512, 8192):
+            assert (len(H.far) == 0) == (sizes[i] == 512)
+        b = w.rhs()
+        Hs.append(H)
+        bs.append(b)
+        refs.append(series.series(H, b, K))
+        xss.append(series.solve_exact(H, b))
+        if sizes[i] <= 3000:  # refinement contracts (rho^(K+1) < 1)
+            assert series.rho(H) ** (K + 1) < 1
+    b = _dev(np.vstack(bs))
+
+    def per_instance(x, want, tol, what):
+        for i in range(len(sizes)):
+            o0, o1 = h.offsets[i], h.offsets[i + 1]
+            assert_close(x[o0:o1], want[i], tol, (what, i, sizes[i]))
+
+    def graph_of(**kw):
+        out = torch.empty((nrhs, h.n), dtype=torch.complex128, device="cuda")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            h.solve(b, out=out, **kw)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            h.solve(b, out=out, **kw)
+        return g, out
+
+    def replay_equal(g, out, ref, reps=3):
+        for rep in range(reps):
+            out.zero_()
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(out.t().cpu().numpy(), ref), rep
+            _host(h.solve(b, K=K))  # eager work between replays
+
+    for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
+        _say(f"batched c4 series precision={prec}")
+        x = _host(h.solve(b, K=K, precision=prec))
+        per_instance(x, refs, tol, f"series p{prec}")
+        _say(f"batched c4 graph precision={prec}")
+        g, out = graph_of(K=K, precision=prec)
+        replay_equal(g, out, x)
+        del g
+    _say("batched c4 adaptive refinement f32")
+    x, st = h.solve(b, K=K, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE, max_passes=400,
+                    refine_tol=1e-10, stats=True)
+    x = _host(x)
+    passes = max(s_["passes"] for s_ in st)
+    assert all(s_["diverged"] == 0 for s_ in st) and passes < 400
+    per_instance(x, xss, TOL_REFINE, "refine")
+    _say(f"batched c4 fixed refinement graph passes={passes}")
+    g, out = graph_of(K=K, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE_FIXED,
+                      max_passes=passes, refine_tol=1e-10)
+    out.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    xg = out.t().cpu().numpy()
+    per_instance(xg, xss, TOL_REFINE, "refine graph")
+    replay_equal(g, out, xg, reps=2)
+    del g
+    _say("batched c4 autotune f32")
+    best, _ = h.autotune(nrhs, K=K, precision=hmps.HM_F32_APPLY)
+    g, out = graph_of(K=K, precision=hmps.HM_F32_APPLY)
+    out.zero_()
+    g.replay()
+    torch.cuda.synchronize()
+    per_instance(out.t().cpu().numpy(), refs, TOL_F32, ("autotuned", best))
+    del g
     h.close()

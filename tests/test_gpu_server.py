@@ -10,6 +10,7 @@ import pytest
 
 import workloads as W
 from oracle import hmatrix, series
+from parity import assert_close
 
 torch = pytest.importorskip("torch")
 from paper_2307_03968_amd import hmps  # noqa: E402
@@ -77,8 +78,8 @@ def test_server_mix_equals_alone_and_oracle(oracles):
     assert info["builds"] == 3 and info["requests_done"] == len(reqs)
     assert info["batches"] < len(reqs), "queued requests of one geometry were not batched"
     for (key, b), xa, xm in zip(reqs, alone, mix):
-        assert series.rel_err(xm, xa) <= 1e-12
-        assert series.rel_err(xm, series.series(oracles[key], b, K)) <= 1e-10
+        assert_close(xm, xa, 1e-12)
+        assert_close(xm, series.series(oracles[key], b, K), 1e-10)
     srv.close()
 
 
@@ -101,7 +102,7 @@ def test_server_budget_evicts_idle_geometries(oracles):
         for key in (1, 3):
             b = W.plane_waves(GEOMS[key][0].xyz, W.directions(2, 3, instance=rep))
             x, st = srv.wait(_submit(srv, key, b, seen, K=2))
-            assert series.rel_err(x, series.series(oracles[key], b, 2)) <= 1e-10
+            assert_close(x, series.series(oracles[key], b, 2), 1e-10)
             assert st[0]["built"] == 1  # the other geometry had to go
     info = srv.info()
     assert info["evictions"] >= 3 and info["builds"] == 4
@@ -130,7 +131,7 @@ def test_server_refine_to_exact_solution():
     t = srv.submit(7, b, K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE, max_passes=300,
                    refine_tol=1e-11, prob=wl.problem, leaf_max=64, aca_tol=1e-4)
     x, st = srv.wait(t)
-    assert series.rel_err(x, series.solve_exact(H, b)) <= 1e-8
+    assert_close(x, series.solve_exact(H, b), 1e-8)
     assert all(s["diverged"] == 0 and s["passes"] > 0 and s["t_ms"] > 0 for s in st)
     srv.close()
 
@@ -178,7 +179,7 @@ def test_server_gmres_where_the_series_diverges(oracles):
           for b in bs]
     for t, b in zip(ts, bs):
         x, st = srv.wait(t)
-        assert series.rel_err(x, series.solve_exact(H, b)) <= 1e-8
+        assert_close(x, series.solve_exact(H, b), 1e-8)
         assert all(s["diverged"] == 0 and s["resid_rel"] <= 1e-11 and s["passes"] > 0 for s in st)
     assert srv.info()["resident_bytes"] > before
     with pytest.raises(hmps.HmpsError):
