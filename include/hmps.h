@@ -289,13 +289,14 @@ typedef struct {
                          a leaf-level low-rank block against a dense panel
                          column in the even split of the work (default 100;
                          changing it rebuilds the work lists)              */
-  int32_t half_storage; /* 1: one right-hand side on a symmetric (surface)
-                         problem (below mm_min_rhs) runs the half-storage
-                         product: each off-diagonal near block Z_ts, s > t,
-                         is read once and applied in both orientations
-                         (Z_st = Z_ts^T), then D^{-1} (series) or D
-                         (H-matvec) is applied block by block (default);
-                         2: the premultiplied panels                    */
+  int32_t half_storage; /* 1 (default): the series, refinement and GMRES
+                         of one right-hand side on a symmetric (surface)
+                         problem (below mm_min_rhs) run in the scaled basis
+                         D = C C^T, S = C^{-1} R C^{-T} on half storage:
+                         each off-diagonal near block S_ts, s > t, is read
+                         once and applied in both orientations
+                         (S_st = S_ts^T); 2: the D^{-1}-premultiplied
+                         panels.  hmat_apply reads the panels either way */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);

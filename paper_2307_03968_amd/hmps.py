@@ -164,6 +164,18 @@ def _stream(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _on_stream(stream, *tensors):
+    """Order a call on `stream` after the work of torch's current stream
+    (which produced the inputs and allocated the temporaries) and keep the
+    caching allocator from reusing the tensors before `stream` is done."""
+    import torch
+    if stream is None or stream == torch.cuda.current_stream():
+        return
+    stream.wait_stream(torch.cuda.current_stream())
+    for t in tensors:
+        t.record_stream(stream)
+
+
 def _as_cols(t):
     """(n,) or (n, nrhs) complex128 CUDA tensor -> (nrhs, n) contiguous."""
     import torch
@@ -271,6 +283,7 @@ class HMatrix:
         xc = _as_cols(x)
         nrhs = xc.shape[0]
         yc = torch.empty_like(xc) if out is None else out
+        _on_stream(stream, xc, yc)
         _check(_lib().hmat_apply(self._h, level, precision, C.c_void_p(xc.data_ptr()), self.n,
                                  C.c_void_p(yc.data_ptr()), self.n, nrhs, _stream(stream)),
                "hmat_apply")
@@ -285,6 +298,7 @@ class HMatrix:
         bc = _as_cols(b)
         nrhs = bc.shape[0]
         xc = torch.empty_like(bc) if out is None else out
+        _on_stream(stream, bc, xc)
         o = ps_opts(int(K), int(level), int(precision), int(kind), int(max_passes), float(refine_tol),
                     int(restart))
         st_arr = (ps_stats * nrhs)() if stats else None
