@@ -261,6 +261,26 @@ int hmat_apply(hm_matrix_t h, int32_t level, int32_t precision, const void* x_de
 int ps_solve(hm_matrix_t h, const ps_opts* opts, const void* b_dev, int64_t ldb, void* x_dev,
              int64_t ldx, int32_t nrhs, ps_stats* per_rhs, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ps_solve
+ * without statistics whose workspace (the [y | t] vectors, their FP32
+ * shadows, refinement vectors, split-K partial sums and counters) lives in a
+ * static device array of HM_NOALLOC_SCRATCH_BYTES bytes that the library
+ * holds on each device it runs on until the process ends.  Kinds PS_SERIES
+ * and PS_REFINE_FIXED only (else HM_EINVAL); other arguments as ps_solve,
+ * same kernels and the same results bit for bit.  A call whose workspace
+ * would exceed the array (it grows with nrhs and with N plus the stage-A
+ * coefficients of the handle) fails with HM_EINVAL before any device work.
+ * The call itself allocates nothing and does not synchronise; the handle's
+ * own device data (built by hmat_build) is read as with ps_solve.  Every
+ * call on one device shares that device's array: calls that overlap in
+ * time on one device (on different streams or from different threads) race
+ * and give wrong results; the counters that must start at zero are
+ * cleared by each call (a fill kernel, so the call can be captured). */
+#define HM_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ps_solve_noalloc(hm_matrix_t h, const ps_opts* opts, const void* b_dev, int64_t ldb,
+                     void* x_dev, int64_t ldx, int32_t nrhs, void* hip_stream);
+
 /* Write the host-side H-matrix (permutation, blocks, factors) to `path` as
  * (needs HM_BUILD_HOST_ONLY or HM_BUILD_KEEP_HOST, else HM_ESTATE)
  * a sequence of named arrays: u32 name length, name bytes, u32 dtype code

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -2087,6 +2088,99 @@ int guarded(F&& f) {
 }
 }  // namespace hm
 
+// ====================================================================== no allocation
+// Workspace of ps_solve_noalloc, for callers that cannot allocate device
+// memory: a file-scope device array (static data of the code object, one
+// copy per device, HM_NOALLOC_SCRATCH_BYTES bytes, held until the process
+// ends).  In host code `scratch` names only a host-side stand-in; the
+// array's device address on each device comes from hipGetSymbolAddress,
+// taken once per device with that device current, and only that address
+// reaches kernels.
+static __device__ __align__(256) unsigned char scratch[HM_NOALLOC_SCRATCH_BYTES];
+
+namespace hm {
+namespace {
+
+__global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev (the current device).
+int scratch_address(int dev, unsigned char** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= kMaxDevices) { set_error("device index out of range"); return HM_EINVAL; }
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      return HM_EHIP;
+    }
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return HM_OK;
+}
+
+// The workspace buffers a series or fixed-pass refinement reads and writes.
+struct WsView {
+  double2 *xin0, *xin1, *xt, *bt, *rt, *dt, *partial;
+  float2 *xin32_0, *xin32_1;
+  int32_t* counters;
+};
+
+// Lays the workspace for nrhs right-hand sides out from base in 256-byte
+// aligned pieces (base null: measures only); returns its size in bytes.
+int64_t carve_workspace(const hm_matrix* h, int nrhs, unsigned char* base, WsView* v) {
+  int64_t off = 0;
+  auto take = [&](int64_t bytes) -> unsigned char* {
+    unsigned char* q = base ? base + off : nullptr;
+    off += (std::max<int64_t>(bytes, 16) + 255) / 256 * 256;
+    return q;
+  };
+  const int64_t ldin = h->N + h->T;
+  WsView w{};
+  w.xin0 = (double2*)take(16 * ldin * nrhs);
+  w.xin1 = (double2*)take(16 * ldin * nrhs);
+  w.xin32_0 = (float2*)take(8 * ldin * nrhs);
+  w.xin32_1 = (float2*)take(8 * ldin * nrhs);
+  w.xt = (double2*)take(16 * h->N * nrhs);
+  w.bt = (double2*)take(16 * h->N * nrhs);
+  w.rt = (double2*)take(16 * h->N * nrhs);
+  w.dt = (double2*)take(16 * h->N * nrhs);
+  w.partial = (double2*)take(16 * h->partial_rows * nrhs);
+  w.counters = (int32_t*)take(4 * (int64_t)h->nl * nrhs);
+  if (v) *v = w;
+  return off;
+}
+
+// Points the handle's workspace fields at a WsView for the length of a
+// call, then restores them.
+struct WsSwap {
+  hm_matrix* h;
+  WsView saved;
+  WsSwap(hm_matrix* h_, const WsView& w) : h(h_) {
+    saved = WsView{h->xin0, h->xin1, h->xt, h->bt, h->rt, h->dt, h->partial,
+                   h->xin32_0, h->xin32_1, h->counters};
+    set(w);
+  }
+  void set(const WsView& w) {
+    h->xin0 = w.xin0; h->xin1 = w.xin1; h->xt = w.xt; h->bt = w.bt; h->rt = w.rt; h->dt = w.dt;
+    h->partial = w.partial; h->xin32_0 = w.xin32_0; h->xin32_1 = w.xin32_1;
+    h->counters = w.counters;
+  }
+  ~WsSwap() { set(saved); }
+};
+
+}  // namespace
+}  // namespace hm
+
 extern "C" {
 
 const char* hm_last_error(void) { return g_err.c_str(); }
@@ -2250,8 +2344,11 @@ int hmat_apply(hm_matrix_t h, int32_t level, int32_t precision, const void* x_de
   return HM_OK;
 }
 
-int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, void* x_dev,
-             int64_t ldx, int32_t nrhs, ps_stats* per_rhs, void* hip_stream) {
+// ps_solve's body; own_ws: size the handle's own workspace (otherwise the
+// caller has pointed the workspace fields at memory it provides).
+static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb,
+                         void* x_dev, int64_t ldx, int32_t nrhs, ps_stats* per_rhs,
+                         void* hip_stream, bool own_ws) {
   if (!h || !o) { set_error("null argument"); return HM_EINVAL; }
   if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
   if (nrhs < 0 || (nrhs > 0 && (!b_dev || !x_dev)) || ldb < h->N || ldx < h->N) {
@@ -2291,7 +2388,7 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
   int li = 0;
   STCHK(level_index(h, o->level, &li));
   HIPCHK(hipSetDevice(h->device));
-  STCHK(ensure_workspace(h, nrhs));
+  if (own_ws) STCHK(ensure_workspace(h, nrhs));
   hipStream_t st = (hipStream_t)hip_stream;
   const int64_t N = h->N, ldin = h->N + h->T;
   const int ns = h->nseg;
@@ -2450,6 +2547,11 @@ int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, vo
     }
   }
   return status;
+}
+
+int ps_solve(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb, void* x_dev,
+             int64_t ldx, int32_t nrhs, ps_stats* per_rhs, void* hip_stream) {
+  return ps_solve_impl(h, o, b_dev, ldb, x_dev, ldx, nrhs, per_rhs, hip_stream, true);
 }
 
 int hmat_export(hm_matrix_t h, const char* path) {
@@ -2631,6 +2733,38 @@ int hm_profile_read(hm_matrix_t h, hm_kernel_time* out) {
     out[r.cls].total_ms += ms;
   }
   return HM_OK;
+}
+
+int ps_solve_noalloc(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t ldb,
+                     void* x_dev, int64_t ldx, int32_t nrhs, void* hip_stream) {
+  if (!h || !o) { set_error("null argument"); return HM_EINVAL; }
+  if (h->host_only) { set_error("handle was built host-only"); return HM_ESTATE; }
+  if (o->kind != PS_SERIES && o->kind != PS_REFINE_FIXED) {
+    set_error("ps_solve_noalloc takes PS_SERIES and PS_REFINE_FIXED only");
+    return HM_EINVAL;
+  }
+  if (nrhs <= 0) return nrhs == 0 ? HM_OK : (set_error("nrhs must be >= 0"), HM_EINVAL);
+  const int64_t need = carve_workspace(h, nrhs, nullptr, nullptr);
+  if (need > (int64_t)HM_NOALLOC_SCRATCH_BYTES) {
+    set_error("ps_solve_noalloc: the workspace of " + std::to_string(nrhs) +
+              " right-hand sides needs " + std::to_string(need) + " bytes, more than the " +
+              std::to_string((int64_t)HM_NOALLOC_SCRATCH_BYTES) + "-byte static scratch");
+    return HM_EINVAL;
+  }
+  HIPCHK(hipSetDevice(h->device));
+  unsigned char* base = nullptr;
+  STCHK(scratch_address(h->device, &base));
+  WsView w{};
+  carve_workspace(h, nrhs, base, &w);
+  hipStream_t st = (hipStream_t)hip_stream;
+  // the split-K counters must start at zero (the array keeps the last call's
+  // contents); a fill kernel, not a memset node, so the call stays capturable
+  const int64_t nc = (int64_t)h->nl * nrhs;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 1024)),
+                     dim3(256), 0, st, w.counters, nc);
+  HIPCHK(hipGetLastError());
+  WsSwap swap(h, w);
+  return ps_solve_impl(h, o, b_dev, ldb, x_dev, ldx, nrhs, nullptr, hip_stream, false);
 }
 
 int hmat_free(hm_matrix_t h) {

@@ -28,6 +28,7 @@ HM_F64, HM_F32_APPLY = 0, 1
 PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES, PS_NESTED = 0, 1, 2, 3, 4
 HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST = 0x1, 0x2, 0x4
 HM_MAX_LEVELS = 32
+HM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class hm_problem(C.Structure):
@@ -119,6 +120,7 @@ def _lib():
         lib.hmat_info.argtypes = [vp, C.POINTER(hm_info)]
         lib.hmat_apply.argtypes = [vp, i32, i32, vp, i64, vp, i64, i32, vp]
         lib.ps_solve.argtypes = [vp, C.POINTER(ps_opts), vp, i64, vp, i64, i32, C.POINTER(ps_stats), vp]
+        lib.ps_solve_noalloc.argtypes = [vp, C.POINTER(ps_opts), vp, i64, vp, i64, i32, vp]
         lib.hmat_export.argtypes = [vp, C.c_char_p]
         lib.hmat_free.argtypes = [vp]
         lib.hm_profile_enable.argtypes = [vp, i32]
@@ -137,7 +139,7 @@ def _lib():
         lib.hm_strerror.restype = C.c_char_p
         lib.hm_last_error.restype = C.c_char_p
         for f in ("hmat_build", "hmat_build_batched", "hmat_info", "hmat_apply", "ps_solve",
-                  "hmat_export", "hmat_free", "hm_profile_enable", "hm_profile_read", "hmat_tune",
+                  "ps_solve_noalloc", "hmat_export", "hmat_free", "hm_profile_enable", "hm_profile_read", "hmat_tune",
                   "hmat_get_tuning", "hmat_autotune", "ps_server_create", "ps_submit", "ps_poll",
                   "ps_server_info", "ps_server_destroy"):
             getattr(lib, f).restype = C.c_int
