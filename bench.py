@@ -63,6 +63,20 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+def cpu_model():
+    """The host CPU's model name (as lscpu prints it) and its logical CPUs."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical CPUs on the host, "\
+           f"{len(os.sched_getaffinity(0))} available to this process)"
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -324,7 +338,7 @@ def bench_single(a):
             reps += 1
         cpu_s = first_s + (time.perf_counter() - t1)
         cpu = {"value": reps * nrhs / cpu_s, "unit": "RHS/s", "cores": blas_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{reps} sequential numpy/scipy FP64 series solves of the same "
                          f"workload ({nrhs} RHS each) in {cpu_s:.1f} s; oracle H build "
                          f"{oracle_build_s:.1f} s not included"}
@@ -493,9 +507,8 @@ def bench_single(a):
         "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
         "autotune": None if tune is None else {"choice": tune[0], "ms": tune[1]},
     }
-    print(json.dumps(out), flush=True)
     h.close()
-    return 0
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -619,7 +632,7 @@ def bench_batched(a):
             rel["refine_f32_vs_xstar"] = max(rel["refine_f32_vs_xstar"],
                                              series.rel_err(xr[o0:o1], xs))
         cpu = {"value": cpu_rhs / cpu_t, "unit": "RHS/s", "cores": blas_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"numpy/scipy FP64 series of {len(sample)} sampled instances "
                          f"(N = {[int(sizes[i]) for i in sample]}, {nrhs} RHS each) in "
                          f"{cpu_t:.1f} s; oracle builds not included"}
@@ -656,9 +669,8 @@ def bench_batched(a):
         "latency_ms": latr, "roofline": roof, "kernels": kernels, "build_s": build_s,
         "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
     }
-    print(json.dumps(out), flush=True)
     h.close()
-    return 0
+    return out
 
 
 def bench_served(a):
@@ -813,8 +825,11 @@ def bench_served(a):
             b = bank[k][:, c0:c0 + rq.nrhs]
             log(f"oracle request {i}: kind {rq.kind} N {wl.problem.n} nrhs {rq.nrhs}")
             H = hmatrix.HMatrix(wl.problem, wl.leaf_max, 1.0, wl.aca_tol)
+            # the CPU baseline solves the same request to x* as the server
+            # does: the oracle's GMRES (D^{-1}-preconditioned) to the same
+            # relative residual
             t1 = time.perf_counter()
-            ref = series.series(H, b, wl.K)
+            series.solve_gmres(H, b, tol=GMRES_TOL)
             cpu_t += time.perf_counter() - t1
             cpu_rhs += rq.nrhs
             if rq.kind == W.SURFACE:
@@ -828,9 +843,10 @@ def bench_served(a):
                                                    series.rel_err(mixed_x[i], xs_))
             checked.append({"request": i, "kind": int(rq.kind), "N": int(wl.problem.n), "nrhs": rq.nrhs})
         if cpu_rhs:
-            cpu = {"value": cpu_rhs / cpu_t, "unit": "RHS/s", "cores": blas_threads(), "kind": "oracle",
-                   "sample": f"numpy/scipy FP64 series of {len(checked)} sampled requests "
-                             f"({cpu_rhs} RHS) in {cpu_t:.1f} s; oracle builds not included"}
+            cpu = {"value": cpu_rhs / cpu_t, "unit": "RHS/s", "cores": blas_threads(), "kind": "oracle", "cpu_model": cpu_model(),
+                   "sample": f"numpy/scipy FP64 GMRES to x* (relative residual {GMRES_TOL:g}) of "
+                             f"{len(checked)} sampled requests ({cpu_rhs} RHS, N <= 6000) in "
+                             f"{cpu_t:.1f} s; oracle builds not included"}
         log(f"rel.err on the sample: {rel}")
     ok = (not a.no_oracle) and rel["surface_gmres_vs_xstar"] <= SOLVED_TOL and \
         rel["volume_gmres_vs_xstar"] <= SOLVED_TOL
@@ -854,8 +870,7 @@ def bench_served(a):
         "extras": {"mixed": results["mixed"], "plain_f64": results["f64"],
                    "oracle_checked_requests": checked},
     }
-    print(json.dumps(out), flush=True)
-    return 0
+    return out
 
 
 def main(argv=None):
@@ -876,6 +891,8 @@ def main(argv=None):
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the side measurements (H-matvec, other precision, refinement)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload only: skip the 32^3 cube and 256-instance legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed region, copy a MIB-MiB device buffer 3 times (a plain "
                          "copy kernel of known size to scale HBM byte counters)")
@@ -891,12 +908,30 @@ def main(argv=None):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     if a.workload == "served":
-        return bench_served(a)
-    if a.workload.startswith("batched"):
+        out = bench_served(a)
+    elif a.workload.startswith("batched"):
         if "_" in a.workload:
             a.instances = int(a.workload.split("_")[1])
-        return bench_batched(a)
-    return bench_single(a)
+        out = bench_batched(a)
+    else:
+        out = bench_single(a)
+        if a.workload == "sphere_24576" and not (a.no_legs or a.no_extras):
+            # the volume (64 RHS, matrix cores) and batched configurations,
+            # each with its own oracle check, roofline and CPU baseline
+            legs = {}
+            for name, steps in (("cube_32768", 10), ("batched_256", 10)):
+                la = argparse.Namespace(**vars(a))
+                la.workload, la.steps, la.warmup = name, min(a.steps, steps), 2
+                la.cpu_seconds = min(a.cpu_seconds, 10.0)
+                la.instances = 256
+                log(f"leg {name}")
+                t0 = time.perf_counter()
+                legs[name] = bench_batched(la) if name.startswith("batched") else bench_single(la)
+                legs[name]["leg_wall_s"] = time.perf_counter() - t0
+                torch.cuda.empty_cache()
+            out["extras"]["legs"] = legs
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 if __name__ == "__main__":

@@ -126,12 +126,16 @@ __global__ void k_kstart(KrylovState S, const double2* __restrict__ rn2,
                          const double2* __restrict__ bn2, double tol, int nrhs) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= nrhs) return;
-  const double rn = sqrt(fmax(rn2[c].x, 0.0)), bn = sqrt(fmax(bn2[c].x, 0.0));
+  // a NaN norm stays NaN (fmax would turn it into 0, i.e. b = 0)
+  const double rq = rn2[c].x, bq = bn2[c].x;
+  const double rn = rq > 0.0 ? sqrt(rq) : (rq <= 0.0 ? 0.0 : rq);
+  const double bn = bq > 0.0 ? sqrt(bq) : (bq <= 0.0 ? 0.0 : bq);
   double2* g = S.g + (int64_t)c * (S.m + 1);
   g[0] = make_double2(rn, 0.0);
   for (int i = 1; i <= S.m; ++i) g[i] = kzero();
-  // b = 0 has the solution x = 0: nothing to do
-  const double rel = bn > 0 ? rn / bn : 0.0;
+  // b = 0 has the solution x = 0: nothing to do; a non-finite b or r gives
+  // a NaN or infinite estimate (inactive, reported as not converged)
+  const double rel = bn > 0 ? rn / bn : (bn == 0.0 ? 0.0 : bn);
   const bool go = bn > 0 && rn > 0 && rel > tol && isfinite(rel);
   S.bnorm[c] = bn;
   S.resid[c] = rel;

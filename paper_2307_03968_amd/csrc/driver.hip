@@ -731,11 +731,11 @@ int scaled_refine_pass(hm_matrix* h, int li, bool f32, int K, bool check, hipStr
 
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
-                bool want_norms, hipStream_t st) {
+                bool want_norms, hipStream_t st, bool allow_half = true) {
   const int64_t N = h->N, ldin = h->N + h->T;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
-  if (use_half(h, li, nrhs)) {
+  if (allow_half && use_half(h, li, nrhs)) {
     // scaled series (see build_half): yhat_0 = C^{-1} b, yhat_k =
     // -S yhat_{k-1} with the half-storage product, x = C^{-T} sum_k yhat_k
     double2* xh = h->zbuf;
@@ -997,8 +997,8 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
     HIPCHK(block_pass(h, chat_set(h, false), h->dt, N, false, nullptr, 0, h->bt, 0, nullptr, 0, st));
     double bn2 = 0.0;
     STCHK(host_norm2(h->dt, &bn2));
-    bn_true = std::sqrt(std::max(bn2, 0.0));
-    rel_true[0] = bn_true > 0 ? 1.0 : 0.0;
+    bn_true = bn2 > 0.0 ? std::sqrt(bn2) : (bn2 <= 0.0 ? 0.0 : bn2);  // NaN stays NaN
+    rel_true[0] = bn_true > 0 ? 1.0 : (bn_true == 0.0 ? 0.0 : NAN);
     HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));  // ||bhat||^2 for the scaled estimates
   } else {
     // b in tree order, ||b||^2; x = 0; the first residual is b
@@ -1069,7 +1069,7 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
       STCHK(apply_core(h, li, false, 1, -1.0, 1.0, h->dt, h->rt, nullptr, 0, st));
       double rn2 = 0.0;
       STCHK(host_norm2(h->rt, &rn2));
-      rel_true[0] = bn_true > 0 ? std::sqrt(std::max(rn2, 0.0)) / bn_true : 0.0;
+      rel_true[0] = bn_true > 0 ? (rn2 >= 0.0 ? std::sqrt(rn2) : NAN) / bn_true : 0.0;
       if (!(rel_true[0] == rel_true[0])) break;  // not finite: stop, reported as such
     } else {
       // true residual r = b - Z x into V_0 (it starts the next cycle)
@@ -1298,8 +1298,14 @@ inline double2 cdiv(double2 a, double2 b) {
 
 // D = C C^T for a complex symmetric leaf block D (m x m, column-major)
 // without pivoting (C lower triangular), and Chat = C^{-1} (lower, column-
-// major, ld m).  False when a pivot is not well away from zero relative to
-// the block's diagonal.
+// major, ld m).  False, and the handle keeps the pivoted LU's
+// premultiplied panels, when the factorisation is not backward stable for
+// this block: a pivot not well away from zero relative to the block's
+// diagonal, an entry of C with |C_ij|^2 above kCsymGrowth max|D| (element
+// growth), ||C C^T - D||_F above kCsymBackward ||D||_F, or a non-finite
+// entry of C^{-1}.
+constexpr double kCsymGrowth = 1e2;
+constexpr double kCsymBackward = 1e-14;
 bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat) {
   std::vector<double2> C((size_t)m * m, make_double2(0.0, 0.0));
   double dmax = 0.0;
@@ -1327,6 +1333,23 @@ bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat) {
       C[i + (size_t)j * m] = cdiv(v, cjj);
     }
   }
+  // element growth and backward error of the factorisation
+  double amax = 0.0, cmax = 0.0, dnorm2 = 0.0, rnorm2 = 0.0;
+  for (int j = 0; j < m; ++j)
+    for (int i = 0; i < m; ++i) {
+      const double a = std::abs(D[i + (size_t)j * m]);
+      amax = std::max(amax, a);
+      dnorm2 += a * a;
+      if (i >= j) cmax = std::max(cmax, std::hypot(C[i + (size_t)j * m].x, C[i + (size_t)j * m].y));
+    }
+  if (!(cmax * cmax <= kCsymGrowth * amax)) return false;
+  for (int j = 0; j < m; ++j)
+    for (int i = j; i < m; ++i) {  // (C C^T)_ij = sum_{k <= j} C_ik C_jk, symmetric
+      double2 acc = make_double2(-D[i + (size_t)j * m].real(), -D[i + (size_t)j * m].imag());
+      for (int k = 0; k <= j; ++k) cmacc(acc, C[i + (size_t)k * m], C[j + (size_t)k * m]);
+      rnorm2 += (i == j ? 1.0 : 2.0) * (acc.x * acc.x + acc.y * acc.y);
+    }
+  if (!(rnorm2 <= kCsymBackward * kCsymBackward * dnorm2)) return false;
   // Chat = C^{-1}, column by column (forward substitution)
   Chat.assign((size_t)m * m, make_double2(0.0, 0.0));
   for (int j = 0; j < m; ++j) {
@@ -2470,7 +2493,9 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
     for (int g = 0; g < ns; ++g) {
       const double a = std::sqrt(h->norms_host[(int64_t)c * ns + g]);
       const double b = std::sqrt(h->norms_host[(int64_t)(nrhs + c) * ns + g]);
-      const double q = (a > 0) ? b / a : (b > 0 ? INFINITY : 0.0);
+      // a non-finite norm (NaN or inf in the column) makes the ratio NaN
+      const double q = !(std::isfinite(a) && std::isfinite(b)) ? NAN
+                       : (a > 0) ? b / a : (b > 0 ? INFINITY : 0.0);
       if (!(q <= r)) r = q;  // keeps NaN / inf
     }
     return r;
@@ -2522,10 +2547,27 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
     }
     if (adaptive && all) break;
   }
-  if (scaled)  // x = C^{-T} xhat, in original order
+  if (scaled) {  // x = C^{-T} xhat, in original order
     HIPCHK(block_pass(h, chat_set(h, true), h->zbuf, N, false, nullptr, 0, h->xt, 0,
                       (double2*)x_dev, ldx, st));
-  else if (refine)
+    if (want) {
+      // check of the scaled basis from the unscaled operator: the next
+      // correction P_K (b - Z_l x) with the FP64 H-matvec and the pivoted
+      // LU's panels; its size relative to x joins the reported correction
+      HIPCHK(launch_permute_in((const double2*)b_dev, ldb, h->perm, h->rt, N, N, nrhs, st));
+      HIPCHK(launch_axpy(1.0, h->xt, N, h->xin0, ldin, N, nrhs, 0, st));
+      STCHK(apply_core(h, li, false, nrhs, -1.0, 1.0, h->rt, h->bt, nullptr, 0, st));
+      STCHK(series_core(h, li, f32, o->K, h->bt, N, false, h->dt, nullptr, 0, nrhs, false, st,
+                        false));
+      HIPCHK(norms_into(h, h->xt, N, nrhs, 0, st));
+      HIPCHK(norms_into(h, h->dt, N, nrhs, 1, st));
+      STCHK(read_norms());
+      for (int c = 0; c < nrhs; ++c) {
+        const double rel = ratio(c);
+        if (!(rel <= resid[c])) resid[c] = rel;
+      }
+    }
+  } else if (refine)
     HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
   int status = HM_OK;
   if (per_rhs) {

@@ -14,9 +14,14 @@
 // (host part, then device part on the worker's stream) and kept resident.
 // Before a device part is built, least recently used geometries with no
 // queued or running request are freed until the resident bytes (blocks and
-// workspaces) plus the new geometry's estimate fit the budget; if they
-// cannot fit while other work runs, the build waits for it; a geometry that
-// does not fit an idle device fails its requests with HM_ENOMEM.
+// workspaces) plus the new geometry's estimate fit the budget.  If they do
+// not fit yet: while a resident geometry has queued requests that no
+// worker runs, the cold build steps aside (its host part kept) and the
+// worker serves those requests first, since they release that geometry;
+// while other batches or builds run, the build waits for them; a geometry
+// that does not fit an idle device fails its requests with HM_ENOMEM.
+// Handles freed to make room are released after the server lock is
+// dropped (a free synchronises the device).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,6 +60,8 @@ struct Geometry {
   bool building = false;
   bool reserved = false; // building, with its device bytes counted
   bool busy = false;     // a worker runs a batch on it
+  bool wait_room = false;  // a cold build stepped aside until room frees up
+  hm_matrix_t staged = nullptr;  // its host part, kept meanwhile
   int pending = 0;       // queued + running requests
   clk::time_point last_used;
   int64_t builds = 0;
@@ -103,12 +110,28 @@ struct hm_server {
     return r;
   }
   void worker(int slot);
-  // with mu held: free idle geometries (LRU first) until need more bytes fit
-  bool make_room(int64_t need, uint64_t except);
+  // with mu held: drop idle geometries (LRU first) until need more bytes
+  // fit; their handles go to `freed`, to be released without the lock
+  bool make_room(int64_t need, uint64_t except, std::vector<hm_matrix_t>& freed);
+  // with mu held: a resident geometry other than `except` with queued
+  // requests and no worker on it
+  bool runnable_elsewhere(uint64_t except) const {
+    for (auto& kv : geoms)
+      if (kv.first != except && kv.second.h && !kv.second.busy && !kv.second.building &&
+          kv.second.pending > 0)
+        return true;
+    return false;
+  }
+  // with mu held: batches or builds (with their room) running elsewhere
+  bool running_elsewhere(uint64_t except) const {
+    for (auto& kv : geoms)
+      if (kv.first != except && (kv.second.busy || kv.second.reserved)) return true;
+    return false;
+  }
   void finish(std::vector<Request*>& batch, int status, const std::string& err);
 };
 
-bool hm_server::make_room(int64_t need, uint64_t except) {
+bool hm_server::make_room(int64_t need, uint64_t except, std::vector<hm_matrix_t>& freed) {
   while (resident() + need > budget) {
     uint64_t victim = 0;
     bool found = false;
@@ -124,7 +147,7 @@ bool hm_server::make_room(int64_t need, uint64_t except) {
     }
     if (!found) return false;
     Geometry& g = geoms[victim];
-    hmat_free(g.h);
+    freed.push_back(g.h);
     g.h = nullptr;
     g.bytes = 0;
     st.evictions++;
@@ -137,6 +160,11 @@ void hm_server::finish(std::vector<Request*>& batch, int status, const std::stri
   for (Request* r : batch) {
     r->state = (status == HM_OK || status == HM_EDIVERGED) ? PS_DONE : PS_FAILED;
     r->status = status;
+    if (r->state == PS_DONE) {  // a request's own columns decide its status
+      r->status = HM_OK;
+      for (const auto& q : r->stats)
+        if (q.diverged) r->status = HM_EDIVERGED;
+    }
     r->err = err;
     r->t_done = now;
     const double ms = std::chrono::duration<double, std::milli>(now - r->t_submit).count();
@@ -159,8 +187,11 @@ void hm_server::worker(int slot) {
   size_t cap = 0;
   void *db = nullptr, *dx = nullptr;
   cplx *hb = nullptr, *hx = nullptr;
-  auto grow = [&](size_t elems) -> int {
-    if (elems <= cap) return HM_OK;
+  // grown geometrically, so a stream of growing batches reallocates (and
+  // synchronises the device in the frees) only a few times
+  auto grow = [&](size_t want) -> int {
+    if (want <= cap) return HM_OK;
+    const size_t elems = std::max(want, 2 * cap);
     const size_t bytes = elems * sizeof(cplx);
     if (db) (void)hipFree(db);
     if (dx) (void)hipFree(dx);
@@ -187,14 +218,16 @@ void hm_server::worker(int slot) {
 
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    // ---- pick: oldest request whose geometry is free (or buildable)
+    // ---- pick: oldest request whose geometry is free (or buildable);
+    // builds that stepped aside for room come last
     Request* head = nullptr;
-    for (Request* r : queue) {
-      Geometry& g = geoms[r->key];
-      if (g.busy || g.building) continue;
-      head = r;
-      break;
-    }
+    for (int pass = 0; pass < 2 && !head; ++pass)
+      for (Request* r : queue) {
+        Geometry& g = geoms[r->key];
+        if (g.busy || g.building || (pass == 0 && g.wait_room)) continue;
+        head = r;
+        break;
+      }
     if (!head) {
       if (stop) break;
       cv.wait(lk);
@@ -207,19 +240,29 @@ void hm_server::worker(int slot) {
       // ---- cold geometry: host part, room under the budget, device part
       auto spec = specs[key];
       g.building = true;
+      hm_matrix_t h = g.staged;  // host part of an earlier attempt, if any
+      g.staged = nullptr;
       lk.unlock();
-      hm_matrix_t h = nullptr;
-      int s = hm::build_host_phase(&spec->prob, &spec->opts, &h);
-      std::string err = s == HM_OK ? "" : hm_last_error();
+      int s = HM_OK;
+      std::string err;
+      if (!h) {
+        s = hm::build_host_phase(&spec->prob, &spec->opts, &h);
+        if (s != HM_OK) err = hm_last_error();
+      }
       const int64_t need = s == HM_OK ? hm::device_bytes_estimate(h, head->nrhs) : 0;
       lk.lock();
-      while (s == HM_OK && !make_room(need, key)) {
-        // wait only for work that will end without this worker: running
-        // batches and builds that already hold their room
-        bool others = false;
-        for (auto& kv : geoms)
-          if (kv.first != key && (kv.second.busy || kv.second.reserved)) others = true;
-        if (!others) {
+      std::vector<hm_matrix_t> freed;
+      bool aside = false;
+      while (s == HM_OK && !make_room(need, key, freed)) {
+        // queued requests of a resident geometry that no worker runs hold
+        // it in place: serve them first (they release it), keep the host part
+        if (runnable_elsewhere(key)) {
+          aside = true;
+          break;
+        }
+        // else wait only for work that will end without this worker:
+        // running batches and builds that already hold their room
+        if (!running_elsewhere(key)) {
           s = HM_ENOMEM;
           err = "geometry needs about " + std::to_string(need) +
                 " device bytes, more than the budget allows";
@@ -227,10 +270,23 @@ void hm_server::worker(int slot) {
         }
         cv.wait(lk);
       }
+      if (aside) {
+        g.staged = h;
+        g.wait_room = true;
+        g.building = false;
+        lk.unlock();
+        for (hm_matrix_t f : freed) hmat_free(f);
+        lk.lock();
+        cv.notify_all();
+        continue;
+      }
+      g.wait_room = false;
       if (s == HM_OK) {
         g.bytes = need;  // reserved until the real size is known
         g.reserved = true;
         lk.unlock();
+        for (hm_matrix_t f : freed) hmat_free(f);
+        freed.clear();
         s = hm::build_device_phase(h, &spec->opts, stream);
         if (s == HM_OK && hipStreamSynchronize(stream) != hipSuccess) s = HM_EHIP;
         if (s != HM_OK) err = hm_last_error();
@@ -238,6 +294,12 @@ void hm_server::worker(int slot) {
       }
       g.building = false;
       g.reserved = false;
+      if (!freed.empty()) {
+        lk.unlock();
+        for (hm_matrix_t f : freed) hmat_free(f);
+        freed.clear();
+        lk.lock();
+      }
       if (s != HM_OK) {
         if (h) hmat_free(h);
         g.bytes = 0;
@@ -287,13 +349,11 @@ void hm_server::worker(int slot) {
     // a wider batch than before grows the geometry's workspace: room first
     int s = HM_OK;
     std::string err;
+    std::vector<hm_matrix_t> freed;
     if (cols > hm::workspace_rhs(h)) {
       const int64_t extra = hm::workspace_bytes(h, cols, 0) - hm::workspace_bytes(h, hm::workspace_rhs(h), 0);
-      while (!make_room(extra, key)) {
-        bool others = false;
-        for (auto& kv : geoms)
-          if (kv.first != key && (kv.second.busy || kv.second.reserved)) others = true;
-        if (!others) {
+      while (!make_room(extra, key, freed)) {
+        if (!running_elsewhere(key)) {
           s = HM_ENOMEM;
           err = "workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
           break;
@@ -305,11 +365,8 @@ void hm_server::worker(int slot) {
     // GMRES keeps its basis on the handle: room for its growth too
     if (s == HM_OK && o.kind == PS_GMRES) {
       const int64_t extra = hm::gmres_growth_bytes(h, hm::gmres_restart(o), cols);
-      while (extra > 0 && !make_room(extra, key)) {
-        bool others = false;
-        for (auto& kv : geoms)
-          if (kv.first != key && (kv.second.busy || kv.second.reserved)) others = true;
-        if (!others) {
+      while (extra > 0 && !make_room(extra, key, freed)) {
+        if (!running_elsewhere(key)) {
           s = HM_ENOMEM;
           err = "GMRES workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
           break;
@@ -319,6 +376,7 @@ void hm_server::worker(int slot) {
       if (s == HM_OK) g.bytes += extra;
     }
     lk.unlock();
+    for (hm_matrix_t f : freed) hmat_free(f);
 
     // ---- run: pack b, copy in, solve, copy out
     if (s == HM_OK) {
@@ -493,8 +551,10 @@ int ps_server_destroy(hm_server_t s) {
   }
   s->cv.notify_all();
   for (auto& w : s->workers) w.join();
-  for (auto& kv : s->geoms)
+  for (auto& kv : s->geoms) {
     if (kv.second.h) hmat_free(kv.second.h);
+    if (kv.second.staged) hmat_free(kv.second.staged);
+  }
   delete s;
   return HM_OK;
 }

@@ -188,3 +188,76 @@ def test_server_gmres_where_the_series_diverges(oracles):
         _submit(srv, 2, bs[0], seen, K=0, kind=hmps.PS_GMRES, max_passes=10, refine_tol=1e-9,
                 restart=65)
     srv.close()
+
+
+def test_server_cold_build_steps_aside_for_queued_resident_work(oracles):
+    """One slot and a budget for one geometry: a cold request (geometry 3)
+    followed at once by a request for the resident geometry 1.  Geometry 1
+    cannot be evicted while its request is queued, so the cold build steps
+    aside, the worker serves geometry 1 first, then evicts it and builds
+    geometry 3; both requests finish and match the oracle."""
+    probe = hmps.Server(slots=1)
+    sizes = {}
+    seen = set()
+    for key in (1, 3):
+        b = W.plane_waves(GEOMS[key][0].xyz, W.Z_HAT)
+        probe.wait(_submit(probe, key, b, seen, K=2))
+        sizes[key] = probe.info()["resident_bytes"] - sum(sizes.values())
+    probe.close()
+    budget = int(max(sizes.values()) + 0.5 * min(sizes.values()))
+    srv = hmps.Server(budget_bytes=budget, slots=1)
+    seen = set()
+    b1 = W.plane_waves(GEOMS[1][0].xyz, W.directions(2, 3, instance=40))
+    srv.wait(_submit(srv, 1, b1, seen, K=2))           # geometry 1 resident
+    b3 = W.plane_waves(GEOMS[3][0].xyz, W.directions(3, 3, instance=41))
+    b1b = W.plane_waves(GEOMS[1][0].xyz, W.directions(1, 3, instance=42))
+    _say("server cold request then a resident one, one slot")
+    t3 = _submit(srv, 3, b3, seen, K=2)
+    t1 = _submit(srv, 1, b1b, seen, K=2)
+    x1, _ = srv.wait(t1)
+    x3, st3 = srv.wait(t3)
+    assert_close(x1, series.series(oracles[1], b1b, 2), 1e-10)
+    assert_close(x3, series.series(oracles[3], b3, 2), 1e-10)
+    assert st3[0]["built"] == 1
+    info = srv.info()
+    assert info["requests_failed"] == 0 and info["evictions"] >= 1
+    assert info["resident_bytes"] <= budget
+    srv.close()
+
+
+def test_non_finite_rhs_reported():
+    """A right-hand side with a NaN entry: the series and refinement report
+    the column as diverged (HM_EDIVERGED with statistics) and leave the
+    other columns exact; through the server, the request with the NaN is
+    reported diverged and a clean request of the same batch is not."""
+    wl = W.sphere_small()
+    H = hmatrix.HMatrix(wl.problem, 64, 1.0, 1e-4)
+    b = W.plane_waves(wl.problem.xyz, W.directions(3, 3))
+    bad = b.copy()
+    bad[17, 1] = np.nan
+    h = hmps.HMatrix(wl.problem, 64, 1.0, 1e-4)
+    for kw in (dict(kind=hmps.PS_SERIES), dict(kind=hmps.PS_REFINE, max_passes=50, refine_tol=1e-10),
+               dict(kind=hmps.PS_GMRES, max_passes=40, refine_tol=1e-10)):
+        for cols in ([1], [0, 1, 2]):
+            _say(f"NaN right-hand side {kw} columns {cols}")
+            x, st = h.solve(torch.from_numpy(np.ascontiguousarray(bad[:, cols])).to("cuda"), K=4,
+                            stats=True, **kw)
+            x = x.cpu().numpy().reshape(wl.problem.n, -1)
+            for j, c in enumerate(cols):
+                if c == 1:
+                    assert st[j]["diverged"] == 1, (kw, st[j])
+                else:
+                    assert st[j]["diverged"] == 0, (kw, st[j])
+                    assert np.all(np.isfinite(x[:, j]))
+    h.close()
+    srv = hmps.Server(slots=1)
+    ok = b[:, [0, 2]]
+    t_bad = srv.submit(5, bad[:, [1]], K=4, prob=wl.problem, leaf_max=64, aca_tol=1e-4)
+    t_ok = srv.submit(5, ok, K=4)
+    _, st_ok = srv.wait(t_ok)
+    assert all(s_["diverged"] == 0 for s_ in st_ok)
+    state, x_bad, st_bad = srv.poll(t_bad)
+    while st_bad is None:
+        state, x_bad, st_bad = srv.poll(t_bad)
+    assert state == hmps.PS_DONE and st_bad[0]["diverged"] == 1
+    srv.close()
