@@ -99,11 +99,18 @@ struct TermArgs {
   double2* out;              // may be null: out[out_perm[q]] = new x (or y)
   int64_t ldo;
   const int64_t* out_perm;
-  // FP32 shadows for the FP32 matrix-core kernels (ld ldx / ldy): inputs
-  // [y | t] read by them, and the FP32 copy of y the epilogue writes for
-  // the next term (may be null)
-  const float2* xin32;
-  float2* yout32;
+  // Matrix-core (many right-hand sides) kernels read [y | t] in ROW
+  // layout: entry (p, c) at p * ldr + c, right-hand sides contiguous, ldr a
+  // multiple of 16; FP64 (xr) or FP32 (xr32, the values the FP32 products
+  // would round the FP64 ones to).  Their partial sums use the same layout
+  // (partial[(prow + i) * ldr + c]).  The epilogue writes the new y in row
+  // layout for the next term when yrow / yrow32 are set.
+  const double2* xr;
+  const float2* xr32;
+  int64_t ldr;
+  int32_t zrow;              // a row of xr / xr32 that holds zeros
+  double2* yrow;
+  float2* yrow32;
 };
 
 // Epilogue of one entry (row i of the leaf at tree offset off, right-hand
@@ -117,7 +124,8 @@ __device__ __forceinline__ void finish_entry(const TermArgs& A, int64_t off, int
     y.y = fma(A.beta, v.y, y.y);
   }
   if (A.yout) A.yout[off + i + (int64_t)c * A.ldy] = y;
-  if (A.yout32) A.yout32[off + i + (int64_t)c * A.ldy] = make_float2((float)y.x, (float)y.y);
+  if (A.yrow) A.yrow[(off + i) * A.ldr + c] = y;
+  if (A.yrow32) A.yrow32[(off + i) * A.ldr + c] = make_float2((float)y.x, (float)y.y);
   double2 res = y;
   if (A.xacc) {
     const int64_t q = off + i + (int64_t)c * A.ldxa;
@@ -190,16 +198,29 @@ hipError_t launch_permute_in(const double2* b, int64_t ldb, const int64_t* perm,
                              int64_t ldo, int64_t n, int nrhs, hipStream_t st);
 hipError_t launch_permute_out(const double2* in, int64_t ldi, const int64_t* perm, double2* x,
                               int64_t ldx, int64_t n, int nrhs, hipStream_t st);
-// many-RHS variants on MFMA (FP32 3M, FP64 4M), right-hand sides in tiles
-// of `tile` = 16/32/64 per workgroup (0: by nrhs)
-hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
+// many-RHS variants on MFMA (FP32 3M, FP64 4M), inputs and partial sums
+// in row layout (TermArgs::xr / xr32, ldr), right-hand sides in tiles of
+// `tile` = 16/32/64 (0: by nrhs).  Leaves of at most kMmWaveLeaf rows run
+// one piece per wave (wave mode: nunits = waves, pieces grouped by wave);
+// larger leaves (up to 256 rows) one piece per workgroup, wave w taking
+// rows [w R, (w + 1) R) of the leaf, R = 32 or 64 (nunits = workgroups).
+hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nunits, int nrhs, int tile,
                           hipStream_t st);
+constexpr int kMmWaveLeaf = 64;
+// zeroed bytes after every panel set the matrix-core kernels read (their row
+// tiles run up to 15 rows past a leaf's last column)
+constexpr size_t kPanelPad = 4096;
+inline bool mm_wave_mode(int max_m) { return max_m <= kMmWaveLeaf; }
+// t rows of the listed group tiles (64 rows each) in row layout:
+// x[(N + t0 + q) ldr + c] = sum_j W_g[q, j] x[(s_off + j) ldr + c]
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, float2* xin32, int64_t ldx, int64_t N,
-                            int nrhs, int tile, hipStream_t st);
-// out[q + c ldo] = (float) in[q + c ldi], q < n, c < nrhs
-hipError_t launch_cast2d(const double2* in, int64_t ldi, float2* out, int64_t ldo, int64_t n,
-                         int nrhs, hipStream_t st);
+                            int nitems, double2* xr, float2* xr32, int64_t ldr, int64_t N,
+                            int zrow, int nrhs, int tile, hipStream_t st);
+// column layout -> row layout: out[p ldr + c] = in[(perm ? perm[p] : p) + c ldi]
+// for p < n, c < nrhs, zero for nrhs <= c < ldr; FP64 (out) and/or FP32 (out32)
+hipError_t launch_rows(const double2* in, int64_t ldi, const int64_t* perm, int64_t n, int nrhs,
+                       double2* out, float2* out32, int64_t ldr, hipStream_t st);
+inline int64_t row_ld(int nrhs) { return ((int64_t)nrhs + 15) / 16 * 16; }
 // nwg persistent workgroups; grid.y covers the right-hand sides
 hipError_t launch_term(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs,
                        hipStream_t st);

@@ -432,16 +432,6 @@ __global__ __launch_bounds__(kThreads) void k_premul(const double2* __restrict__
   }
 }
 
-__global__ void k_cast2d(const double2* __restrict__ in, int64_t ldi, float2* __restrict__ out,
-                         int64_t ldo, int64_t n) {
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int c = blockIdx.y;
-  if (q < n) {
-    const double2 v = in[q + c * ldi];
-    out[q + c * ldo] = make_float2((float)v.x, (float)v.y);
-  }
-}
-
 __global__ void k_cast(const double2* __restrict__ in, float2* __restrict__ out, int64_t n) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
        q += (int64_t)gridDim.x * blockDim.x)
@@ -715,13 +705,6 @@ hipError_t launch_norm2(const double2* v, int64_t ld, const NormItem* items, int
   return hipGetLastError();
 }
 
-hipError_t launch_cast2d(const double2* in, int64_t ldi, float2* out, int64_t ldo, int64_t n,
-                         int nrhs, hipStream_t st) {
-  if (n <= 0 || nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cast2d, dim3(blocks_for(n, 256), nrhs), dim3(256), 0, st, in, ldi, out, ldo,
-                     n);
-  return hipGetLastError();
-}
 
 hipError_t launch_axpy(double alpha, const double2* x, int64_t ldx, double2* y, int64_t ldy,
                        int64_t n, int nrhs, int accumulate, hipStream_t st) {

@@ -9,9 +9,18 @@
 // B[k][j] with k = l / 16, j = l % 16.  Result element v of lane l is
 // D[4 (l / 16) + v][l % 16] for the FP32 instruction and D[l / 16 + 4 v][l % 16]
 // for the FP64 one (both measured on gfx950).
-// A workgroup of four waves covers up to 128 (or 256) panel rows: wave w owns
-// the 16-row tiles w, w + 4, ...; the inputs of a column chunk are staged in
-// LDS (converted to the compute precision) and shared by the waves.
+//
+// Every wave works on its own: the inputs are kept in row layout (the
+// right-hand sides of one source point contiguous), so the B operand of a
+// k-step (4 panel columns x 16 right-hand sides) is four 128- or 256-byte
+// rows read straight from L2 with one load per lane, and no LDS staging or
+// workgroup barrier is needed.  A piece (panel columns [c0, c1) of a leaf)
+// streams D k-steps ahead of the products through a ring of registers (the
+// source index of a column one more ring ahead, since the B address depends
+// on it).  Leaves of at most 64 rows: one wave takes a whole leaf (up to
+// four 16-row tiles, only the tiles the leaf has); larger leaves: the four
+// waves of a workgroup take the same piece, each its own block of rows, so
+// the B rows they share are read from L2 by one workgroup at a time.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -21,6 +30,13 @@
 namespace hm {
 
 namespace {
+
+#ifndef HM_MM_D32
+#define HM_MM_D32 8  // k-steps of 4 columns in flight per wave, FP32 blocks
+#endif
+#ifndef HM_MM_D64
+#define HM_MM_D64 4  // the same, FP64 blocks
+#endif
 
 constexpr int kThreads = 256;
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -37,47 +53,54 @@ struct Prec;
 
 template <>
 struct Prec<true> {                      // FP32 blocks, 3M
-  using X = float2;                      // staged input element
+  using A = float2;                      // panel element
+  using X = float2;                      // input element (row layout)
   using Acc = f4v;
   static constexpr int NACC = 3;
-  __device__ static __forceinline__ float2 load_a(const void* P, uint32_t idx) {
-    const fvec2 v = __builtin_nontemporal_load(reinterpret_cast<const fvec2*>(P) + idx);
+  static constexpr int D = HM_MM_D32;    // k-steps in flight
+  __device__ static __forceinline__ A load_a(const void* P, uint32_t byte_off) {
+    const fvec2 v = __builtin_nontemporal_load(
+        reinterpret_cast<const fvec2*>(reinterpret_cast<const char*>(P) + byte_off));
     return make_float2(v.x, v.y);
   }
-  __device__ static __forceinline__ X cvt(double2 v) { return make_float2((float)v.x, (float)v.y); }
-  __device__ static __forceinline__ X cvt(float2 v) { return v; }
-  __device__ static __forceinline__ void mac(Acc (&acc)[3], float2 a, X b) {
+  __device__ static __forceinline__ void mac(Acc (&acc)[3], float2 a, float as, X b, float bs) {
     acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc[0], 0, 0, 0);
     acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc[1], 0, 0, 0);
-    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, acc[2], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(as, bs, acc[2], 0, 0, 0);
   }
+  __device__ static __forceinline__ float sum(float2 v) { return v.x + v.y; }
   __device__ static __forceinline__ double2 result(const Acc (&acc)[3], int v) {
     const double t1 = acc[0][v], t2 = acc[1][v], t3 = acc[2][v];
     return make_double2(t1 - t2, t3 - t1 - t2);
   }
+  __device__ static __forceinline__ X from(double2 z) { return make_float2((float)z.x, (float)z.y); }
   // row of result element v within the 16 x 16 tile (kq = lane / 16)
   __device__ static __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
 template <>
 struct Prec<false> {                     // FP64 blocks, four real products
+  using A = double2;
   using X = double2;
   using Acc = d4v;
   static constexpr int NACC = 2;
-  __device__ static __forceinline__ double2 load_a(const void* P, uint32_t idx) {
-    const dvec2 v = __builtin_nontemporal_load(reinterpret_cast<const dvec2*>(P) + idx);
+  static constexpr int D = HM_MM_D64;
+  __device__ static __forceinline__ A load_a(const void* P, uint32_t byte_off) {
+    const dvec2 v = __builtin_nontemporal_load(
+        reinterpret_cast<const dvec2*>(reinterpret_cast<const char*>(P) + byte_off));
     return make_double2(v.x, v.y);
   }
-  __device__ static __forceinline__ X cvt(double2 v) { return v; }
-  __device__ static __forceinline__ void mac(Acc (&acc)[2], double2 a, X b) {
+  __device__ static __forceinline__ void mac(Acc (&acc)[2], double2 a, double, X b, double) {
     acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, acc[0], 0, 0, 0);
     acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, acc[0], 0, 0, 0);
     acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acc[1], 0, 0, 0);
     acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acc[1], 0, 0, 0);
   }
+  __device__ static __forceinline__ double sum(double2) { return 0.0; }
   __device__ static __forceinline__ double2 result(const Acc (&acc)[2], int v) {
     return make_double2(acc[0][v], acc[1][v]);
   }
+  __device__ static __forceinline__ X from(double2 z) { return z; }
   __device__ static __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
 };
 
@@ -94,124 +117,112 @@ struct MMAcc {
   }
 };
 
-// acc += P[rows of this wave's tiles, c0:c1) * X[c0:c1, tile].  colp(c)
-// points (XT: double2, or float2 for FP32 shadows of the inputs) at input
-// column c's value for the tile's first right-hand side (right-hand side n
-// at colp(c)[n * ldx]); nv right-hand sides of the tile are valid.
-// Software pipelined one chunk of NG groups of 16 columns ahead: the inputs
-// of chunk j + 1 are loaded into registers while chunk j is multiplied (two
-// LDS buffers, one barrier per chunk), and each group's panel registers are
-// refilled with the same group of the next chunk right after their
-// products (NG register sets, no copies).  Every load is issued
-// unconditionally at a clamped address (values past c1 or past the last
-// right-hand side are replaced by zero), so the memory-counter waits before
-// each group cover only the loads that group needs.
-template <bool F32, int RT>
-struct Groups {  // groups of 16 columns per staged chunk (4 measured no faster)
-  static constexpr int NG = 2;
-};
-
-template <bool F32, int RT, int NT, typename XT, typename COLP>
-__device__ __forceinline__ void mm_core(const void* __restrict__ P, uint32_t ld, int row0,
-                                        int c0, int c1, const COLP& colp, int64_t ldx, int nv,
-                                        MMAcc<F32, RT, NT>& acc, int w, int lane) {
+// acc[r][t] += P[row0 + 16 r + (0..15), c0 : c1) X[src(c0 : c1), rhs0 + 16 t + (0..15)]
+// for the RTL row tiles r < RTL of this wave.  P is column-major with
+// leading dimension ld (its allocation extends at least 16 rows past the
+// last column, so the row tiles need no clamp: rows past ld read the next
+// column, and rows past m are never stored); srcf(c) is the X row holding
+// column c's input, and X row zrow is all zero.
+// The sources travel 64 columns (16 k-steps) at a time: lane l loads the
+// source of column c0 + 64 j + l (zrow past c1) one block early and parks it
+// in a per-wave ring of three blocks in LDS, from which a k-step reads its
+// lane's value; so the loads of a k-step depend on no vector load issued
+// after the ring slot was written.  Panel loads past c1 are issued at the
+// clamped column c1 - 1 and read the zero row of X, so every k-step runs the same
+// instructions; right-hand sides past the row length are read at the
+// clamped column ldr - 1 (their products land in result columns that are
+// never stored).  One loop iteration covers one block of 16 k-steps, so the
+// code inside the loop is the same in every iteration.
+template <bool F32, int RT, int NT, int RTL, typename SRCF>
+__device__ __forceinline__ void mm_wave(const void* __restrict__ P, uint32_t ld, int row0, int c0,
+                                        int c1, const SRCF& srcf,
+                                        const typename Prec<F32>::X* __restrict__ xr, int64_t ldr,
+                                        int zrow, int rhs0, MMAcc<F32, RT, NT>& acc, int lane,
+                                        int* __restrict__ ring) {
   using PR = Prec<F32>;
-  using AV = typename std::conditional<F32, float2, double2>::type;
-  constexpr int NRT = 16 * NT;
-  constexpr int NG = Groups<F32, RT>::NG;
-  constexpr int CH = 16 * NG;                  // columns per staged chunk
-  constexpr int NPT = kThreads / CH;           // right-hand sides apart per thread
-  constexpr int XPT = CH * NRT / kThreads;     // staged inputs per thread
-  __shared__ typename PR::X xs[2][CH][NRT + 1];  // +1: spreads the banks of column writes
+  using AV = typename PR::A;
+  using XV = typename PR::X;
+  constexpr int D = PR::D;
+  static_assert(D <= 16, "the loads of a k-step lie at most one block ahead");
   if (c1 <= c0) return;
   const int l16 = lane & 15, kq = lane >> 4;
-  const int xk = threadIdx.x % CH, xn = threadIdx.x / CH;
-  uint32_t ri[RT];
+  // byte offsets: panel entry (row0 + l16, column c) and the input rows stay
+  // 32-bit (a panel set and a row-layout vector are below 2^32 bytes)
+  constexpr uint32_t esz = sizeof(AV);
+  const uint32_t a_first = (uint32_t)(row0 + l16 + (c0 + kq) * ld) * esz;
+  const uint32_t a_last = (uint32_t)(row0 + l16 + (c1 - 1) * ld) * esz;
+  const uint32_t a_step = 4u * ld * esz;
+  uint32_t cx[NT];
 #pragma unroll
-  for (int r = 0; r < RT; ++r) ri[r] = min<uint32_t>(row0 + (w + 4 * r) * 16 + l16, ld - 1);
-  XT xr[XPT];
-  bool xok[XPT];
-  auto load_x = [&](int cb) {
-    const bool col_ok = cb + xk < c1;
-    const XT* base = colp(min(cb + xk, c1 - 1));
-#pragma unroll
-    for (int i = 0; i < XPT; ++i) {
-      const int n = xn + i * NPT;
-      xr[i] = base[(int64_t)min(n, nv - 1) * ldx];
-      xok[i] = col_ok && n < nv;
-    }
+  for (int t = 0; t < NT; ++t) cx[t] = (uint32_t)min<int64_t>(rhs0 + 16 * t + l16, ldr - 1);
+  const uint32_t ldr32 = (uint32_t)ldr;
+  const int nsteps = (c1 - c0 + 3) >> 2;
+  auto block = [&](int j) -> int {
+    const int c = c0 + 64 * j + lane;
+    const int v = srcf(min(c, c1 - 1));
+    return c < c1 ? v : zrow;
   };
-  auto store_x = [&](int buf) {
+  AV ab[D][RTL];
+  XV bb[D][NT];
+  auto load = [&](int s, AV (&a)[RTL], XV (&b)[NT]) {
+    const uint32_t ao = min(a_first + (uint32_t)s * a_step, a_last);
 #pragma unroll
-    for (int i = 0; i < XPT; ++i) xs[buf][xk][xn + i * NPT] = PR::cvt(xok[i] ? xr[i] : XT{});
+    for (int r = 0; r < RTL; ++r) a[r] = PR::load_a(P, ao + r * 16 * esz);
+    const int srow = ring[((s >> 4) % 3) * 64 + 4 * (s & 15) + kq];
+    const uint32_t rb = (uint32_t)srow * ldr32;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) b[t] = xr[rb + cx[t]];
   };
-  AV a[NG][4][RT];
-  auto load_a = [&](int cg, AV (&dst)[4][RT]) {
+  ring[lane] = block(0);
+  ring[64 + lane] = block(1);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int col = min(cg + 4 * s + kq, c1 - 1);
+  for (int d = 0; d < D; ++d) load(d, ab[d], bb[d]);
+  for (int k = 0; k < nsteps; k += 16) {
+    const int nxt = block((k >> 4) + 2);  // parked at the end of the block
 #pragma unroll
-      for (int r = 0; r < RT; ++r) dst[s][r] = PR::load_a(P, ri[r] + (uint32_t)col * ld);
-    }
-  };
-  // columns past c1 hold zero inputs (and clamped panel columns), so every
-  // chunk runs all its groups of four k-steps without branches
-  auto group = [&](const AV (&av)[4][RT], int buf, int kk) {
+    for (int d = 0; d < 16; ++d) {
+      const int slot = d % D;
+      decltype(PR::sum(XV{})) bs[NT];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+      for (int t = 0; t < NT; ++t) bs[t] = PR::sum(bb[slot][t]);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const typename PR::X b = xs[buf][kk + 4 * s + kq][t * 16 + l16];
+      for (int r = 0; r < RTL; ++r) {
+        const auto as = PR::sum(ab[slot][r]);
 #pragma unroll
-        for (int r = 0; r < RT; ++r) PR::mac(acc.a[r][t], av[s][r], b);
+        for (int t = 0; t < NT; ++t) PR::mac(acc.a[r][t], ab[slot][r], as, bb[slot][t], bs[t]);
       }
+      load(k + d + D, ab[slot], bb[slot]);
+      // keep this k-step's products and the refill of its ring slot where
+      // they are: otherwise the scheduler gathers the products of many
+      // k-steps first and issues the loads after them, leaving no time
+      // between a load and its use
+      __builtin_amdgcn_sched_barrier(0);
     }
-  };
-  const int nchunks = (c1 - c0 + CH - 1) / CH;
-  load_x(c0);
-  store_x(0);
-#pragma unroll
-  for (int g = 0; g < NG; ++g) load_a(c0 + 16 * g, a[g]);
-  __syncthreads();
-  for (int j = 0; j < nchunks; ++j) {
-    const int cb = c0 + j * CH;
-    const int buf = j & 1;
-    load_x(cb + CH);  // past the last chunk: zeros, never read
-#pragma unroll
-    for (int g = 0; g < NG; ++g) {
-      group(a[g], buf, 16 * g);
-      load_a(cb + CH + 16 * g, a[g]);
-    }
-    store_x(buf ^ 1);
-    __syncthreads();
+    ring[(((k >> 4) + 2) % 3) * 64 + lane] = nxt;
   }
 }
 
-// ---------------------------------------------------------------- epilogue
-// Partial-sum rows of the leaf's pieces come from LDS (STAGED, up to
-// kThreads pieces) or straight from global memory.
-template <int NRT, bool STAGED>
-__device__ void epilogue_loop(const TermArgs& A, int a, int rhs0, int nrhs, const int* s_prow) {
-  const int m = A.ps.leaf_m[a];
+// ---------------------------------------------------------------- term
+// Sum of the partial rows of one leaf's pieces for rows [row0, row0 + nrow)
+// and one tile of right-hand sides, then the term epilogue; one wave, the
+// right-hand sides of a row on consecutive lanes.
+template <int NRT>
+__device__ void mm_epilogue(const TermArgs& A, int a, int row0, int nrow, int rhs0, int nrhs,
+                            int lane) {
   const int64_t off = A.leaf_off[a];
   const int q0 = A.lptr[a], np = A.lptr[a + 1] - q0;
-  for (int idx = threadIdx.x; idx < m * NRT; idx += kThreads) {
-    const int i = idx % m;
-    const int c = rhs0 + idx / m;
+  for (int idx = lane; idx < nrow * NRT; idx += 64) {
+    const int i = row0 + idx / NRT;
+    const int c = rhs0 + idx % NRT;
     if (c >= nrhs) continue;
-    const double* pc = reinterpret_cast<const double*>(A.partial + i + (int64_t)c * A.ldp);
     double zr = 0.0, zi = 0.0;
     for (int p = 0; p < np; p += 8) {  // fixed order; loads in flight together
       double vr[8], vi[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (p + u < np) {
-          int prow;
-          if constexpr (STAGED)
-            prow = s_prow[p + u];
-          else
-            prow = A.lprow[q0 + p + u];
-          const double* q = pc + 2 * (int64_t)prow;
+          const double* q =
+              reinterpret_cast<const double*>(A.partial + ((int64_t)A.lprow[q0 + p + u] + i) * A.ldr + c);
           vr[u] = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           vi[u] = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
@@ -229,231 +240,258 @@ __device__ void epilogue_loop(const TermArgs& A, int a, int rhs0, int nrhs, cons
   }
 }
 
-template <int NRT>
-__device__ void term_epilogue_mm(const TermArgs& A, int a, int rhs0, int nrhs) {
-  __shared__ int s_prow[kThreads];
-  const int q0 = A.lptr[a], np = A.lptr[a + 1] - q0;
-  if (np <= kThreads) {
-    __syncthreads();
-    if ((int)threadIdx.x < np) s_prow[threadIdx.x] = A.lprow[q0 + threadIdx.x];
-    __syncthreads();
-    epilogue_loop<NRT, true>(A, a, rhs0, nrhs, s_prow);
-  } else {
-    epilogue_loop<NRT, false>(A, a, rhs0, nrhs, nullptr);
-  }
-}
-
-// ---------------------------------------------------------------- term
-// Persistent workgroup over its run of (dense) pieces; same publication and
-// last-workgroup epilogue as the one-RHS term kernel.
-template <bool F32, int RT, int NT>
-__global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs) {
+// One piece on one wave: the products of its rows (RTL tiles), then either
+// the epilogue straight from the registers (the leaf's only piece) or the
+// partial sums published with agent-scope stores and the wave that brings
+// the (leaf, row block) counter to the piece count sums them.
+template <bool F32, int RT, int NT, int RTL>
+__device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it, int m, int rb,
+                                           int row0, int rhs0, int nrhs, int lane, int* ring) {
   using PR = Prec<F32>;
+  using XV = typename PR::X;
   constexpr int NRT = 16 * NT;
-  __shared__ int s_last;
-  const int rhs0 = blockIdx.y * NRT;
-  const int w = wave_id();
-  const int lane = threadIdx.x & 63;
+  const int a = it.leaf;
+  const uint32_t ld = (uint32_t)(m + (m & 1));
+  const int64_t poff = __builtin_amdgcn_readfirstlane((int)(A.ps.panel_off[a] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(A.ps.panel_off[a] >> 32)) << 32);
+  const int64_t coff = __builtin_amdgcn_readfirstlane((int)(A.ps.col_off[a] & 0xffffffff)) |
+                       ((int64_t)__builtin_amdgcn_readfirstlane((int)(A.ps.col_off[a] >> 32)) << 32);
+  const void* P = F32 ? (const void*)(reinterpret_cast<const float2*>(A.ps.data) + poff)
+                      : (const void*)(reinterpret_cast<const double2*>(A.ps.data) + poff);
+  const int32_t* __restrict__ src = A.ps.src + coff;
+  const XV* xr = F32 ? reinterpret_cast<const XV*>(A.xr32) : reinterpret_cast<const XV*>(A.xr);
+  MMAcc<F32, RT, NT> acc;
+  acc.zero();
+  auto srcf = [&](int c) -> int { return src[c]; };
+  mm_wave<F32, RT, NT, RTL>(P, ld, row0, it.c0, it.c1, srcf, xr, A.ldr, A.zrow, rhs0, acc, lane,
+                            ring);
   const int l16 = lane & 15, kq = lane >> 4;
-  const int pe = A.wptr[blockIdx.x + 1];
-  for (int p = A.wptr[blockIdx.x]; p < pe; ++p) {
-    const TermItem it = A.items[p];
-    const int a = it.leaf;
-    const int m = A.ps.leaf_m[a];
-    const uint32_t ld = (uint32_t)(m + (m & 1));
-    const void* P = F32 ? (const void*)(reinterpret_cast<const float2*>(A.ps.data) + A.ps.panel_off[a])
-                        : (const void*)(reinterpret_cast<const double2*>(A.ps.data) + A.ps.panel_off[a]);
-    const int32_t* __restrict__ src = A.ps.src + A.ps.col_off[a];
-    MMAcc<F32, RT, NT> acc;
-    acc.zero();
-    const int64_t* inp = A.in_perm;
-    if constexpr (F32) {
-      // FP32 blocks take FP32 inputs: read the shadow copy (the values the
-      // products would round the FP64 inputs to anyway)
-      const float2* xbase = A.xin32 + (int64_t)rhs0 * A.ldx;
-      auto colp = [&](int c) -> const float2* { return xbase + src[c]; };
-      mm_core<F32, RT, NT, float2>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
-    } else {
-      const double2* xbase = A.xin + (int64_t)rhs0 * A.ldx;
-      auto colp = [&](int c) -> const double2* {
-        int64_t s = src[c];
-        if (inp) s = inp[s];
-        return xbase + s;
-      };
-      mm_core<F32, RT, NT, double2>(P, ld, 0, it.c0, it.c1, colp, A.ldx, nrhs - rhs0, acc, w, lane);
-    }
-    if constexpr (RT == 1) {
-      // small leaves: a leaf's only piece finishes its rows straight from the
-      // registers (no partial sums, no counter); larger tiles keep the
-      // register budget of the partial-sum path below
-      if (A.lptr[a + 1] - A.lptr[a] == 1) {
-        const int64_t off = A.leaf_off[a];
+  const int np = __builtin_amdgcn_readfirstlane(A.lptr[a + 1] - A.lptr[a]);
+  if (np == 1) {
+    const int64_t off = A.leaf_off[a];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = w * 16 + PR::row(kq, v);
-            const int c = rhs0 + t * 16 + l16;
-            if (i < m && c < nrhs) finish_entry(A, off, i, c, PR::result(acc.a[0][t], v));
-          }
-        continue;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < RT; ++r)
+    for (int r = 0; r < RTL; ++r)
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int i = (w + 4 * r) * 16 + PR::row(kq, v);
-          const int c = rhs0 + t * 16 + l16;
-          if (i < m && c < nrhs) {
-            const double2 z = PR::result(acc.a[r][t], v);
-            double* q = reinterpret_cast<double*>(A.partial + it.prow + i + (int64_t)c * A.ldp);
-            __hip_atomic_store(q, z.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(q + 1, z.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          }
+          const int i = row0 + 16 * r + PR::row(kq, v);
+          const int c = rhs0 + 16 * t + l16;
+          if (i < m && c < nrhs) finish_entry(A, off, i, c, PR::result(acc.a[r][t], v));
         }
-    __builtin_amdgcn_s_waitcnt(0);
-    if (A.lptr[a + 1] - A.lptr[a] == 1) {
-      // the leaf's only piece: its epilogue needs no counter
-      __syncthreads();
-      term_epilogue_mm<NRT>(A, a, rhs0, nrhs);
-      __syncthreads();
-      continue;
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < RTL; ++r)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = row0 + 16 * r + PR::row(kq, v);
+        const int c = rhs0 + 16 * t + l16;
+        if (i < m && c < nrhs) {
+          const double2 z = PR::result(acc.a[r][t], v);
+          double* q = reinterpret_cast<double*>(A.partial + ((int64_t)it.prow + i) * A.ldr + c);
+          __hip_atomic_store(q, z.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(q + 1, z.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+  // the stores have completed at the device's coherence point before the
+  // counter moves, so the wave that finishes the count reads them all
+  __builtin_amdgcn_s_waitcnt(0);
+  int32_t* cnt = A.counters + ((int64_t)a * 4 + rb) * gridDim.y + blockIdx.y;
+  int old = 0;
+  if (lane == 0) old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  old = __shfl(old, 0);
+  if (old == np - 1) {
+    mm_epilogue<NRT>(A, a, row0, min(16 * RTL, m - row0), rhs0, nrhs, lane);
+    if (lane == 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// Persistent term kernel.  WAVE: unit = wave (pieces grouped by wave), the
+// wave takes all rows of its leaves (m <= 16 RT).  Otherwise unit =
+// workgroup, wave w takes rows [16 RT w, 16 RT (w + 1)) of every piece of
+// its workgroup.
+template <bool F32, int RT, int NT, bool WAVE>
+__global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs, int nunits) {
+  const int lane = threadIdx.x & 63;
+  const int w = wave_id();
+  const int unit = WAVE ? (int)blockIdx.x * 4 + w : (int)blockIdx.x;
+  if (unit >= nunits) return;
+  const int rb = WAVE ? 0 : w;
+  const int rhs0 = blockIdx.y * 16 * NT;
+  __shared__ int rings[4][3 * 64];  // per wave: sources of three 64-column blocks
+  int* ring = rings[w];
+  const int pe = A.wptr[unit + 1];
+  for (int p = A.wptr[unit]; p < pe; ++p) {
+    // the piece is the same for the whole wave: keep it in scalar registers
+    // (uniform branches, scalar base addresses)
+    TermItem it = A.items[p];
+    it.leaf = __builtin_amdgcn_readfirstlane(it.leaf);
+    it.c0 = __builtin_amdgcn_readfirstlane(it.c0);
+    it.c1 = __builtin_amdgcn_readfirstlane(it.c1);
+    it.prow = __builtin_amdgcn_readfirstlane(it.prow);
+    const int m = __builtin_amdgcn_readfirstlane(A.ps.leaf_m[it.leaf]);
+    const int row0 = rb * 16 * RT;
+    if (row0 >= m) continue;
+    const int rtl = min(RT, (m - row0 + 15) >> 4);
+    if constexpr (RT >= 4) {
+      if (rtl == 4) { term_piece<F32, RT, NT, 4>(A, it, m, rb, row0, rhs0, nrhs, lane, ring); continue; }
+      if (rtl == 3) { term_piece<F32, RT, NT, 3>(A, it, m, rb, row0, rhs0, nrhs, lane, ring); continue; }
     }
-    int32_t* cnt = A.counters + (int64_t)a * gridDim.y + blockIdx.y;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const int old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_last = (old == A.lptr[a + 1] - A.lptr[a] - 1);
+    if constexpr (RT >= 2) {
+      if (rtl == 2) { term_piece<F32, RT, NT, 2>(A, it, m, rb, row0, rhs0, nrhs, lane, ring); continue; }
     }
-    __syncthreads();
-    if (s_last) {
-      term_epilogue_mm<NRT>(A, a, rhs0, nrhs);
-      if (threadIdx.x == 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
+    term_piece<F32, RT, NT, 1>(A, it, m, rb, row0, rhs0, nrhs, lane, ring);
   }
 }
 
 // ---------------------------------------------------------------- stage A
-// One workgroup = a 64-row tile of a source group (one 16-row tile per
-// wave): t rows = W_g Y[s_off .. s_off + n), written to the t part of xin.
+// One workgroup = a 64-row tile of a source group, wave w its rows
+// [16 w, 16 w + 16): t rows = W_g X[s_off .. s_off + n), written to the t
+// rows of the same row-layout vector.
 template <bool F32, int NT>
 __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__ W,
                                                         const Group* __restrict__ groups,
                                                         const GroupItem* __restrict__ items,
-                                                        double2* __restrict__ xin,
-                                                        float2* __restrict__ xin32, int64_t ldx,
-                                                        int64_t N, int nrhs) {
+                                                        typename Prec<F32>::X* __restrict__ xr,
+                                                        int64_t ldr, int64_t N, int zrow, int nrhs) {
   using PR = Prec<F32>;
-  constexpr int NRT = 16 * NT;
   const GroupItem it = items[blockIdx.x];
   const Group g = groups[it.group];
-  const void* Wg = F32 ? (const void*)(reinterpret_cast<const float2*>(W) + g.w_off)
-                       : (const void*)(reinterpret_cast<const double2*>(W) + g.w_off);
-  const int rhs0 = blockIdx.y * NRT;
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
-  const int l16 = lane & 15, kq = lane >> 4;
+  const int row0 = it.row0 + 16 * w;
+  if (row0 >= it.rows) return;
+  const void* Wg = F32 ? (const void*)(reinterpret_cast<const float2*>(W) + g.w_off)
+                       : (const void*)(reinterpret_cast<const double2*>(W) + g.w_off);
+  const int rhs0 = blockIdx.y * 16 * NT;
   MMAcc<F32, 1, NT> acc;
   acc.zero();
-  // FP32: inputs and the t coefficients live in the FP32 shadow [y | t]
-  if constexpr (F32) {
-    const float2* xbase = xin32 + g.s_off + (int64_t)rhs0 * ldx;
-    auto colp = [&](int c) -> const float2* { return xbase + c; };
-    mm_core<F32, 1, NT, float2>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc,
-                                w, lane);
-  } else {
-    const double2* xbase = xin + g.s_off + (int64_t)rhs0 * ldx;
-    auto colp = [&](int c) -> const double2* { return xbase + c; };
-    mm_core<F32, 1, NT, double2>(Wg, (uint32_t)g.ld, it.row0, 0, g.n, colp, ldx, nrhs - rhs0, acc,
-                                 w, lane);
-  }
+  const int s_off = g.s_off;
+  auto srcf = [&](int c) -> int { return s_off + c; };
+  __shared__ int rings[4][3 * 64];
+  mm_wave<F32, 1, NT, 1>(Wg, (uint32_t)g.ld, row0, 0, g.n, srcf, xr, ldr, zrow, rhs0, acc, lane,
+                         rings[w]);
+  const int l16 = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int q = it.row0 + w * 16 + PR::row(kq, v);
-      const int c = rhs0 + t * 16 + l16;
-      if (q < it.rows && c < nrhs) {
-        const double2 z = PR::result(acc.a[0][t], v);
-        const int64_t o = N + g.t0 + q + (int64_t)c * ldx;
-        if constexpr (F32)
-          xin32[o] = make_float2((float)z.x, (float)z.y);
-        else
-          xin[o] = z;
-      }
+      const int q = row0 + PR::row(kq, v);
+      const int c = rhs0 + 16 * t + l16;
+      if (q < it.rows && c < nrhs) xr[(N + g.t0 + q) * ldr + c] = PR::from(PR::result(acc.a[0][t], v));
     }
 }
 
-// 16-column RHS tiles per workgroup: the requested tile (16, 32 or 64), or
-// by nrhs when 0
-inline int pick_nt(int nrhs, int tile) {
-  if (tile == 16 || tile == 32 || tile == 64) return tile / 16;
-  return nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4);
+// ---------------------------------------------------------------- layout
+// Column layout (n x nrhs, ld ldi, rows through perm when set) to row
+// layout through a 64 x 16 LDS tile: reads coalesced along the rows, writes
+// along the right-hand sides.
+__global__ __launch_bounds__(kThreads) void k_rows(const double2* __restrict__ in, int64_t ldi,
+                                                   const int64_t* __restrict__ perm, int64_t n,
+                                                   int nrhs, double2* __restrict__ out,
+                                                   float2* __restrict__ out32, int64_t ldr) {
+  __shared__ double2 tile[16][65];
+  const int64_t p0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 16;
+  {
+    const int pl = threadIdx.x & 63;
+    const int64_t p = p0 + pl;
+    const int64_t srow = (p < n) ? (perm ? perm[p] : p) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int cl = (threadIdx.x >> 6) + 4 * j;
+      const int c = c0 + cl;
+      tile[cl][pl] = (p < n && c < nrhs) ? in[srow + (int64_t)c * ldi] : make_double2(0.0, 0.0);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int cl = threadIdx.x & 15;
+    const int pl = (threadIdx.x >> 4) + 16 * j;
+    const int64_t p = p0 + pl;
+    if (p >= n || c0 + cl >= ldr) continue;
+    const double2 v = tile[cl][pl];
+    if (out) out[p * ldr + c0 + cl] = v;
+    if (out32) out32[p * ldr + c0 + cl] = make_float2((float)v.x, (float)v.y);
+  }
 }
 
-template <bool F32, int RT>
-hipError_t term_mm_rt(const TermArgs& a, int nwg, int nrhs, int tile, hipStream_t st) {
-  // four row tiles per wave: at most 32 right-hand sides per workgroup (the
-  // 64-wide tile does not fit the register file)
-  const int nt = (RT == 4) ? min(2, pick_nt(nrhs, tile)) : pick_nt(nrhs, tile);
+// 16-column right-hand-side tiles per unit: the requested tile (16, 32 or
+// 64), or by nrhs when 0; at most cap
+inline int pick_nt(int nrhs, int tile, int cap) {
+  int nt = (tile == 16 || tile == 32 || tile == 64) ? tile / 16 : (nrhs <= 16 ? 1 : (nrhs <= 32 ? 2 : 4));
+  return nt < cap ? nt : cap;
+}
+
+template <bool F32, int RT, bool WAVE>
+hipError_t term_mm_launch(const TermArgs& a, int nunits, int nrhs, int tile, hipStream_t st) {
+  // accumulator registers: RT x NT tiles (at most 8 per wave)
+  const int nt = pick_nt(nrhs, tile, RT >= 4 ? 2 : 4);
+  const int nwg = WAVE ? (nunits + 3) / 4 : nunits;
   const dim3 grid(nwg, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
-    hipLaunchKernelGGL((k_term_mm<F32, RT, 1>), grid, dim3(kThreads), 0, st, a, nrhs);
-  else if (nt == 2 || RT == 4)
-    hipLaunchKernelGGL((k_term_mm<F32, RT, 2>), grid, dim3(kThreads), 0, st, a, nrhs);
-  else
-    hipLaunchKernelGGL((k_term_mm<F32, RT, RT == 4 ? 2 : 4>), grid, dim3(kThreads), 0, st, a,
-                       nrhs);
+    hipLaunchKernelGGL((k_term_mm<F32, RT, 1, WAVE>), grid, dim3(kThreads), 0, st, a, nrhs, nunits);
+  else if (nt == 2)
+    hipLaunchKernelGGL((k_term_mm<F32, RT, 2, WAVE>), grid, dim3(kThreads), 0, st, a, nrhs, nunits);
+  else if constexpr (RT <= 2)
+    hipLaunchKernelGGL((k_term_mm<F32, RT, 4, WAVE>), grid, dim3(kThreads), 0, st, a, nrhs, nunits);
   return hipGetLastError();
 }
 
 template <bool F32>
 hipError_t stageA_mm_p(const void* W, const Group* groups, const GroupItem* items, int nitems,
-                       double2* xin, float2* xin32, int64_t ldx, int64_t N, int nrhs, int tile,
-                       hipStream_t st) {
-  const int nt = pick_nt(nrhs, tile);
+                       typename Prec<F32>::X* xr, int64_t ldr, int64_t N, int zrow, int nrhs,
+                       int tile, hipStream_t st) {
+  const int nt = pick_nt(nrhs, tile, 4);
   const dim3 grid(nitems, (nrhs + 16 * nt - 1) / (16 * nt));
   if (nt == 1)
-    hipLaunchKernelGGL((k_stageA_mm<F32, 1>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       xin32, ldx, N, nrhs);
+    hipLaunchKernelGGL((k_stageA_mm<F32, 1>), grid, dim3(kThreads), 0, st, W, groups, items, xr, ldr,
+                       N, zrow, nrhs);
   else if (nt == 2)
-    hipLaunchKernelGGL((k_stageA_mm<F32, 2>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       xin32, ldx, N, nrhs);
+    hipLaunchKernelGGL((k_stageA_mm<F32, 2>), grid, dim3(kThreads), 0, st, W, groups, items, xr, ldr,
+                       N, zrow, nrhs);
   else
-    hipLaunchKernelGGL((k_stageA_mm<F32, 4>), grid, dim3(kThreads), 0, st, W, groups, items, xin,
-                       xin32, ldx, N, nrhs);
+    hipLaunchKernelGGL((k_stageA_mm<F32, 4>), grid, dim3(kThreads), 0, st, W, groups, items, xr, ldr,
+                       N, zrow, nrhs);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nwg, int nrhs, int tile,
+hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nunits, int nrhs, int tile,
                           hipStream_t st) {
-  if (nwg <= 0 || nrhs <= 0) return hipSuccess;
-  if (f32 && (!a.xin32 || a.in_perm)) return hipErrorInvalidValue;  // FP32 reads the shadow
-  if (max_m > 256) return hipErrorInvalidValue;
-  const int rt = (max_m + 63) / 64;  // 16-row tiles per wave
-  if (f32) {
-    if (rt <= 1) return term_mm_rt<true, 1>(a, nwg, nrhs, tile, st);
-    if (rt <= 2) return term_mm_rt<true, 2>(a, nwg, nrhs, tile, st);
-    return term_mm_rt<true, 4>(a, nwg, nrhs, tile, st);
-  }
-  if (rt <= 1) return term_mm_rt<false, 1>(a, nwg, nrhs, tile, st);
-  if (rt <= 2) return term_mm_rt<false, 2>(a, nwg, nrhs, tile, st);
-  return term_mm_rt<false, 4>(a, nwg, nrhs, tile, st);
+  if (nunits <= 0 || nrhs <= 0) return hipSuccess;
+  if (max_m > 256 || a.ldr < row_ld(nrhs) || (f32 ? !a.xr32 : !a.xr)) return hipErrorInvalidValue;
+  if (mm_wave_mode(max_m))
+    return f32 ? term_mm_launch<true, 4, true>(a, nunits, nrhs, tile, st)
+               : term_mm_launch<false, 4, true>(a, nunits, nrhs, tile, st);
+  if (max_m <= 128)
+    return f32 ? term_mm_launch<true, 2, false>(a, nunits, nrhs, tile, st)
+               : term_mm_launch<false, 2, false>(a, nunits, nrhs, tile, st);
+  return f32 ? term_mm_launch<true, 4, false>(a, nunits, nrhs, tile, st)
+             : term_mm_launch<false, 4, false>(a, nunits, nrhs, tile, st);
 }
 
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
-                            int nitems, double2* xin, float2* xin32, int64_t ldx, int64_t N,
-                            int nrhs, int tile, hipStream_t st) {
+                            int nitems, double2* xr, float2* xr32, int64_t ldr, int64_t N,
+                            int zrow, int nrhs, int tile, hipStream_t st) {
   if (nitems <= 0 || nrhs <= 0) return hipSuccess;
-  if (f32 && !xin32) return hipErrorInvalidValue;
-  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xin, xin32, ldx, N, nrhs, tile, st)
-             : stageA_mm_p<false>(W, groups, items, nitems, xin, xin32, ldx, N, nrhs, tile, st);
+  if (ldr < row_ld(nrhs) || (f32 ? !xr32 : !xr)) return hipErrorInvalidValue;
+  return f32 ? stageA_mm_p<true>(W, groups, items, nitems, xr32, ldr, N, zrow, nrhs, tile, st)
+             : stageA_mm_p<false>(W, groups, items, nitems, xr, ldr, N, zrow, nrhs, tile, st);
+}
+
+hipError_t launch_rows(const double2* in, int64_t ldi, const int64_t* perm, int64_t n, int nrhs,
+                       double2* out, float2* out32, int64_t ldr, hipStream_t st) {
+  if (n <= 0 || nrhs <= 0) return hipSuccess;
+  if (ldr < row_ld(nrhs)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)(ldr / 16));
+  hipLaunchKernelGGL(k_rows, grid, dim3(kThreads), 0, st, in, ldi, perm, n, nrhs, out, out32, ldr);
+  return hipGetLastError();
 }
 
 }  // namespace hm

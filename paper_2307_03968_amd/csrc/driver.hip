@@ -114,6 +114,7 @@ struct hm_matrix {
   float2* Wmm32 = nullptr;
   hm::Group* groups_mm = nullptr;
   std::vector<hm::TermList> tl_apply_mm, tl_series_mm;
+  hm::TermList tl_dinv_mm;  // D^{-1} panels on the matrix-core kernels
   // half-storage product (symmetric problems, one right-hand side): per
   // row leaf t its near blocks (t, s > t) side by side (half panels), the
   // source row and v slot of every half-panel column, and per-level lists
@@ -156,6 +157,7 @@ struct hm_matrix {
   int64_t partial_rows = 0;
   int term_wgs = 1024;          // persistent workgroups of a term kernel
   int term_wgs_auto = 1024;
+  int num_cus = 256;            // compute units of the device
   int half_wgs_auto = 512;      // resident round of the half-storage kernel
   int32_t* counters = nullptr;  // workspace
   // workspace
@@ -163,7 +165,11 @@ struct hm_matrix {
   int64_t ws_bytes = 0;
   double2 *xin0 = nullptr, *xin1 = nullptr, *xt = nullptr, *bt = nullptr, *rt = nullptr,
           *dt = nullptr, *partial = nullptr;
-  float2 *xin32_0 = nullptr, *xin32_1 = nullptr;  // FP32 shadows of [y | t]
+  // [y | t] in row layout for the matrix-core kernels (ld ws_ldr): FP64 and
+  // FP32 copies, two of each (term input and output)
+  double2 *xr64_0 = nullptr, *xr64_1 = nullptr;
+  float2 *xr32_0 = nullptr, *xr32_1 = nullptr;
+  int64_t ws_ldr = 0;
   double *nscratch = nullptr, *norms = nullptr;
   double* norms_host = nullptr;  // pinned
   // norm segments (one per instance) and their row items
@@ -221,10 +227,14 @@ int dalloc(hm_matrix* h, void** p, size_t bytes, bool lists = false) {
   return HM_OK;
 }
 
+// pad: zeroed bytes after the data (panels the matrix-core kernels read
+// past their last column, kPanelPad)
 template <typename T, typename A>
-int upload(hm_matrix* h, T** dst, const std::vector<T, A>& v, hipStream_t st, bool lists = false) {
-  STCHK(dalloc(h, (void**)dst, v.size() * sizeof(T), lists));
+int upload(hm_matrix* h, T** dst, const std::vector<T, A>& v, hipStream_t st, bool lists = false,
+           size_t pad = 0) {
+  STCHK(dalloc(h, (void**)dst, v.size() * sizeof(T) + pad, lists));
   if (!v.empty()) HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  if (pad) HIPCHK(hipMemsetAsync(reinterpret_cast<char*>(*dst) + v.size() * sizeof(T), 0, pad, st));
   HIPCHK(hipStreamSynchronize(st));  // host vectors may be freed after return
   return HM_OK;
 }
@@ -252,7 +262,7 @@ int level_index(const hm_matrix* h, int level, int* li) {
 int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t, int64_t>>>& dense,
                   const std::vector<int64_t>& inrow_rows, const std::vector<int64_t>& inrow_col,
                   const std::vector<int32_t>& inrow_ncol, TermList& tl, hipStream_t st,
-                  hm_matrix::HalfList* hl = nullptr) {
+                  hm_matrix::HalfList* hl = nullptr, int units = 0, bool whole = false) {
   struct Seg { int leaf, kind; int64_t u0, u1, col0, cost; };
   std::vector<Seg> segs;
   int64_t total = 0;
@@ -269,7 +279,9 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     for (size_t k = first; k < segs.size(); ++k) total += (segs[k].u1 - segs[k].u0) * segs[k].cost;
   }
   // the half-storage kernel's own resident round unless a count was set
-  const int G = std::max(1, hl && h->term_wgs == h->term_wgs_auto ? h->half_wgs_auto : h->term_wgs);
+  const int G = units > 0 ? units
+                          : std::max(1, hl && h->term_wgs == h->term_wgs_auto ? h->half_wgs_auto
+                                                                               : h->term_wgs);
   std::vector<TermItem> items;
   std::vector<int32_t> wg_of, vleaf, lcnt(hl ? h->nl : 0, 0);
   int64_t rows = 0, done = 0;
@@ -332,9 +344,38 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   auto wg_at = [&](int64_t cost) {
     return total > 0 ? (int)std::min<int64_t>(G - 1, (cost * G) / total) : 0;
   };
+  if (whole && !hl) {
+    // whole leaves: every segment of a leaf is one piece of the same unit
+    // (no partial sums for a single-segment leaf); leaves go to the least
+    // loaded unit, largest first (LPT), and each unit runs its pieces in
+    // tree order
+    std::vector<int64_t> lcost(h->nl, 0);
+    for (const Seg& sg : segs) lcost[sg.leaf] += (sg.u1 - sg.u0) * sg.cost + 1;
+    std::vector<int> order(h->nl);
+    for (int a = 0; a < h->nl; ++a) order[a] = a;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return lcost[x] > lcost[y]; });
+    std::vector<std::pair<int64_t, int>> heap;  // (load, unit), min-heap
+    for (int g = 0; g < G; ++g) heap.push_back({0, g});
+    auto gt = [](const std::pair<int64_t, int>& x, const std::pair<int64_t, int>& y) { return x > y; };
+    std::make_heap(heap.begin(), heap.end(), gt);
+    std::vector<int> unit_of(h->nl, 0);
+    for (int a : order) {
+      std::pop_heap(heap.begin(), heap.end(), gt);
+      unit_of[a] = heap.back().second;
+      heap.back().first += lcost[a];
+      std::push_heap(heap.begin(), heap.end(), gt);
+    }
+    for (const Seg& sg : segs) {
+      const int m = h->H.leaf_size[sg.leaf];
+      TermItem it{sg.leaf, 0, (int32_t)sg.u0, (int32_t)sg.u1, 0, 0, (int32_t)rows, 0};
+      items.push_back(it);
+      wg_of.push_back(unit_of[sg.leaf]);
+      rows += m;
+    }
+  }
   // other lists: pieces split evenly over the G workgroups by cost, each
   // workgroup taking a contiguous run
-  for (size_t si = 0; si < (hl ? 0 : segs.size()); ++si) {
+  for (size_t si = 0; si < (hl || whole ? 0 : segs.size()); ++si) {
     const Seg& sg = segs[si];
     const int m = h->H.leaf_size[sg.leaf];
     int64_t u = sg.u0;
@@ -428,6 +469,12 @@ int upload_groups(hm_matrix* h, const std::vector<GroupItem>& v, GroupList& gl, 
   return upload(h, &gl.items, v, st);
 }
 
+// Split-K counters: per (leaf, right-hand-side tile) for the streaming
+// kernels, per (leaf, block of rows < 4, 16-RHS tile) for the matrix cores.
+int64_t counter_count(const hm_matrix* h, int nrhs) {
+  return (int64_t)h->nl * std::max<int64_t>(nrhs, 4 * ((nrhs + 15) / 16));
+}
+
 int ensure_workspace(hm_matrix* h, int nrhs) {
   if (nrhs <= h->ws_nrhs) return HM_OK;
   for (void* p : h->ws_allocs) (void)hipFree(p);
@@ -446,19 +493,28 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
     h->ws_bytes += (int64_t)std::max<size_t>(bytes, 16);
     return HM_OK;
   };
+  const int64_t ldr = row_ld(nrhs);
   STCHK(al((void**)&h->xin0, sizeof(double2) * ldin * nrhs));
   STCHK(al((void**)&h->xin1, sizeof(double2) * ldin * nrhs));
-  STCHK(al((void**)&h->xin32_0, sizeof(float2) * ldin * nrhs));
-  STCHK(al((void**)&h->xin32_1, sizeof(float2) * ldin * nrhs));
+  // row-layout vectors: rows [y | t] plus one row of zeros (zrow = N + T)
+  STCHK(al((void**)&h->xr64_0, sizeof(double2) * (ldin + 1) * ldr));
+  STCHK(al((void**)&h->xr64_1, sizeof(double2) * (ldin + 1) * ldr));
+  STCHK(al((void**)&h->xr32_0, sizeof(float2) * (ldin + 1) * ldr));
+  STCHK(al((void**)&h->xr32_1, sizeof(float2) * (ldin + 1) * ldr));
+  HIPCHK(hipMemset(h->xr64_0 + ldin * ldr, 0, sizeof(double2) * ldr));
+  HIPCHK(hipMemset(h->xr64_1 + ldin * ldr, 0, sizeof(double2) * ldr));
+  HIPCHK(hipMemset(h->xr32_0 + ldin * ldr, 0, sizeof(float2) * ldr));
+  HIPCHK(hipMemset(h->xr32_1 + ldin * ldr, 0, sizeof(float2) * ldr));
   STCHK(al((void**)&h->xt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->bt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->rt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->dt, sizeof(double2) * h->N * nrhs));
-  STCHK(al((void**)&h->partial, sizeof(double2) * h->partial_rows * nrhs));
+  STCHK(al((void**)&h->partial, sizeof(double2) * h->partial_rows * ldr));
   STCHK(al((void**)&h->nscratch, sizeof(double) * h->n_norm_items * nrhs * 2));
   STCHK(al((void**)&h->norms, sizeof(double) * h->nseg * nrhs * 2));
-  STCHK(al((void**)&h->counters, sizeof(int32_t) * h->nl * nrhs));
-  HIPCHK(hipMemset(h->counters, 0, sizeof(int32_t) * h->nl * nrhs));
+  STCHK(al((void**)&h->counters, sizeof(int32_t) * counter_count(h, nrhs)));
+  HIPCHK(hipMemset(h->counters, 0, sizeof(int32_t) * counter_count(h, nrhs)));
+  h->ws_ldr = ldr;
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   h->norms_host = nullptr;
   HIPCHK(hipHostMalloc((void**)&h->norms_host, sizeof(double) * h->nseg * nrhs * 2,
@@ -495,6 +551,8 @@ TermArgs term_args(const hm_matrix* h, const PanelSet& ps, const TermList& tl, b
   t.partial = h->partial;
   t.ldp = h->partial_rows;
   t.counters = h->counters;
+  t.ldr = h->ws_ldr;
+  t.zrow = (int32_t)(h->N + h->T);
   t.alpha = 1.0;
   t.beta = 0.0;
   return t;
@@ -566,7 +624,9 @@ struct Path {
 };
 
 Path pick_path(const hm_matrix* h, bool f32, int nrhs) {
-  if (nrhs >= h->mm_min_rhs)
+  // the matrix-core kernels index the row-layout vectors with 32-bit offsets
+  const bool fits = (h->N + h->T + 1) * row_ld(nrhs) * (int64_t)sizeof(double2) < ((int64_t)1 << 32);
+  if (nrhs >= h->mm_min_rhs && fits)
     return Path{true, f32 ? (const void*)h->Wmm32 : (const void*)h->Wmm64, h->groups_mm,
                 &h->sa_mm, &h->tl_series_mm, &h->tl_apply_mm, h->src_mm};
   return Path{false, f32 ? (const void*)h->W32 : (const void*)h->W64, h->groups, &h->sa,
@@ -579,10 +639,13 @@ hipError_t run_term(const hm_matrix* h, const Path& P, bool f32, const TermArgs&
               : launch_term(f32, h->max_m, t, tl.nwg, nrhs, st);
 }
 
+// Stage A: streaming kernels on [y | t] in column layout (xin, ld ldx), the
+// matrix-core ones on the row-layout vectors (xr64 or xr32, ld ws_ldr).
 hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupList& sa,
-                      double2* xin, float2* xin32, int64_t ldx, int nrhs, hipStream_t st) {
-  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xin, xin32, ldx, h->N, nrhs,
-                                 h->rhs_tile, st)
+                      double2* xin, int64_t ldx, double2* xr64, float2* xr32, int nrhs,
+                      hipStream_t st) {
+  return P.mm ? launch_stageA_mm(f32, P.W, P.groups, sa.items, sa.n, xr64, xr32, h->ws_ldr, h->N,
+                                 (int)(h->N + h->T), nrhs, h->rhs_tile, st)
               : launch_stageA(f32, P.W, P.groups, sa.items, sa.n, xin, ldx, h->N, nrhs, st);
 }
 
@@ -779,15 +842,56 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     return HM_OK;
   }
   const Path P = pick_path(h, f32, nrhs);
-  // the FP32 matrix-core kernels read FP32 shadows of [y | t]
-  const bool shadow = P.mm && f32;
-  float2* y32_cur = shadow ? h->xin32_0 : nullptr;
-  float2* y32_nxt = shadow ? h->xin32_1 : nullptr;
+  const TermList& tl = (*P.tl_series)[li];
+  const GroupList& sa = (*P.sa)[li];
+  if (P.mm) {
+    // matrix cores: [y | t] in row layout, FP64 (r64) or FP32 (r32) by the
+    // block precision; the column-layout y is written only for the norms
+    double2* r64[2] = {h->xr64_0, h->xr64_1};
+    float2* r32[2] = {h->xr32_0, h->xr32_1};
+    HIPCHK(launch_rows(rhs, ldr, rhs_perm ? h->perm : nullptr, N, nrhs, r64[1], nullptr, h->ws_ldr,
+                       st));
+    {
+      TermArgs t = term_args(h, dinv_set(h), h->tl_dinv_mm, false, nullptr, 0);
+      t.xr = r64[1];
+      t.yrow = f32 ? nullptr : r64[0];
+      t.yrow32 = f32 ? r32[0] : nullptr;
+      t.yout = want_norms ? y_cur : nullptr;
+      t.ldy = ldin;
+      t.xacc = x_tree;
+      t.ldxa = N;
+      t.accumulate = 0;
+      if (K == 0 && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+      TIMED(HM_K_TERM_DINV, run_term(h, P, false, t, h->tl_dinv_mm, nrhs, st));
+    }
+    if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
+    int cur = 0;
+    for (int k = 1; k <= K; ++k) {
+      if (sa.n > 0)
+        TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, nullptr, 0, r64[cur], r32[cur], nrhs, st));
+      TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, nullptr, 0);
+      t.xr = r64[cur];
+      t.xr32 = r32[cur];
+      t.alpha = -1.0;
+      t.yrow = f32 ? nullptr : r64[cur ^ 1];
+      t.yrow32 = f32 ? r32[cur ^ 1] : nullptr;
+      t.yout = (want_norms && k == K) ? y_nxt : nullptr;
+      t.ldy = ldin;
+      t.xacc = x_tree;
+      t.ldxa = N;
+      t.accumulate = 1;
+      if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
+      TIMED(HM_K_TERM_SERIES, run_term(h, P, f32, t, tl, nrhs, st));
+      cur ^= 1;
+      if (k == K) std::swap(y_cur, y_nxt);
+    }
+    if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
+    return HM_OK;
+  }
   {
     TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, rhs, ldr);
     t.in_perm = rhs_perm ? h->perm : nullptr;
     t.yout = y_cur;
-    t.yout32 = y32_cur;
     t.ldy = ldin;
     t.xacc = x_tree;
     t.ldxa = N;
@@ -796,15 +900,12 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     TIMED(HM_K_TERM_DINV, run_term(h, P, false, t, h->tl_dinv, nrhs, st));
   }
   if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
-  const TermList& tl = (*P.tl_series)[li];
-  const GroupList& sa = (*P.sa)[li];
   for (int k = 1; k <= K; ++k) {
-    if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, y32_cur, ldin, nrhs, st));
+    if (sa.n > 0)
+      TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, y_cur, ldin, nullptr, nullptr, nrhs, st));
     TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, y_cur, ldin);
-    t.xin32 = y32_cur;
     t.alpha = -1.0;
     t.yout = y_nxt;
-    t.yout32 = y32_nxt;
     t.ldy = ldin;
     t.xacc = x_tree;
     t.ldxa = N;
@@ -812,7 +913,6 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
     if (k == K && out) { t.out = out; t.ldo = ldo; t.out_perm = h->perm; }
     TIMED(HM_K_TERM_SERIES, run_term(h, P, f32, t, tl, nrhs, st));
     std::swap(y_cur, y_nxt);
-    std::swap(y32_cur, y32_nxt);
   }
   if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
   return HM_OK;
@@ -824,14 +924,16 @@ int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double be
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
   const Path P = pick_path(h, f32, nrhs);
-  const bool shadow = P.mm && f32;
-  if (shadow) HIPCHK(launch_cast2d(h->xin0, ldin, h->xin32_0, ldin, N, nrhs, st));
-  float2* x32 = shadow ? h->xin32_0 : nullptr;
+  // matrix cores: x into row layout, FP64 or FP32 by the block precision
+  double2* r64 = (P.mm && !f32) ? h->xr64_0 : nullptr;
+  float2* r32 = (P.mm && f32) ? h->xr32_0 : nullptr;
+  if (P.mm) HIPCHK(launch_rows(h->xin0, ldin, nullptr, N, nrhs, r64, r32, h->ws_ldr, st));
   const GroupList& sa = (*P.sa)[li];
-  if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, h->xin0, x32, ldin, nrhs, st));
+  if (sa.n > 0) TIMED(HM_K_STAGEA, run_stageA(h, P, f32, sa, h->xin0, ldin, r64, r32, nrhs, st));
   const TermList& tl = (*P.tl_apply)[li];
   TermArgs t = term_args(h, apply_set(h, f32, P.src), tl, f32, h->xin0, ldin);
-  t.xin32 = x32;
+  t.xr = r64;
+  t.xr32 = r32;
   t.alpha = alpha;
   t.beta = beta;
   t.v = v;
@@ -1091,14 +1193,20 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
 hipError_t dinv_pass(hm_matrix* h, const double2* in, const double2* v, double beta, double2* out,
                      int nrhs, hipStream_t st) {
   const Path P = pick_path(h, false, nrhs);
-  TermArgs t = term_args(h, dinv_set(h), h->tl_dinv, false, in, h->N);
+  const TermList& tl = P.mm ? h->tl_dinv_mm : h->tl_dinv;
+  TermArgs t = term_args(h, dinv_set(h), tl, false, in, h->N);
+  if (P.mm) {
+    const hipError_t e = launch_rows(in, h->N, nullptr, h->N, nrhs, h->xr64_0, nullptr, h->ws_ldr, st);
+    if (e != hipSuccess) return e;
+    t.xr = h->xr64_0;
+  }
   t.beta = beta;
   t.v = v;
   t.ldv = h->N;
   t.xacc = out;
   t.ldxa = h->N;
   t.accumulate = 0;
-  return run_term(h, P, false, t, h->tl_dinv, nrhs, st);
+  return run_term(h, P, false, t, tl, nrhs, st);
 }
 
 constexpr int64_t kMaxNestedProducts = 100000;  // level products per nested solve, at most
@@ -1222,6 +1330,18 @@ bool check_arch(std::string* arch) {
   return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
 }
 
+// Work units of the matrix-core term lists: waves when one wave takes a
+// whole leaf, else workgroups.
+int mm_units(const hm_matrix* h) {
+  return mm_wave_mode(h->max_m) ? 4 * h->term_wgs : h->term_wgs;
+}
+
+// One wave per whole leaf (no partial sums) when there are enough leaves
+// for the waves to even out: small leaves and at least two per unit.
+bool mm_whole(const hm_matrix* h) {
+  return mm_wave_mode(h->max_m) && h->nl >= 2 * mm_units(h);
+}
+
 // Term-kernel work lists for every level (one resident round of h->term_wgs
 // persistent workgroups): one-RHS lists (dense column ranges + in-row stack
 // rows), many-RHS lists (dense column ranges only: in-row U columns read t
@@ -1270,7 +1390,8 @@ int build_lists(hm_matrix* h, hipStream_t st) {
       }
       TermList& tl = mm ? (series ? h->tl_series_mm[li] : h->tl_apply_mm[li])
                         : (series ? h->tl_series[li] : h->tl_apply[li]);
-      STCHK(make_termlist(h, dense, mm ? zero : irr, irc, h->ir_ncol_h, tl, st));
+      STCHK(make_termlist(h, dense, mm ? zero : irr, irc, h->ir_ncol_h, tl, st, nullptr,
+                          mm ? mm_units(h) : 0, mm && mm_whole(h)));
     }
   }
   for (int a = 0; a < nl; ++a) {
@@ -1278,6 +1399,8 @@ int build_lists(hm_matrix* h, hipStream_t st) {
     dense[a].push_back({0, H.leaf_size[a]});
   }
   STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv, st));
+  STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv_mm, st, nullptr, mm_units(h),
+                      true));
   HIPCHK(hipStreamSynchronize(st));
   if (h->partial_rows > old_rows) h->ws_nrhs = 0;  // workspace is sized by partial_rows
   return HM_OK;
@@ -1897,7 +2020,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->perm, H.tree.perm, st));
   STCHK(upload(h, &h->leaf_off, loff, st));
   STCHK(upload(h, &h->leaf_m, lm, st));
-  STCHK(upload(h, &h->R64, R, st));
+  STCHK(upload(h, &h->R64, R, st, false, kPanelPad));
   bigvec<double2>().swap(R);
   STCHK(upload(h, &h->src, src, st));
   STCHK(upload(h, &h->R_off, R_off, st));
@@ -1915,7 +2038,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->groups_mm, gsm.groups, st));
   STCHK(upload(h, &h->src_mm, src_mm, st));
   fill_W(gsm, W);
-  STCHK(upload(h, &h->Wmm64, W, st));
+  STCHK(upload(h, &h->Wmm64, W, st, false, kPanelPad));
   bigvec<double2>().swap(W);
   STCHK(upload(h, &h->IR64, IR, st));
   bigvec<double2>().swap(IR);
@@ -1925,10 +2048,11 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->ir_row0, ir_row0, st));
   STCHK(upload(h, &h->ir_soff, ir_soff, st));
   STCHK(upload(h, &h->ir_n, ir_n, st));
-  STCHK(dalloc(h, (void**)&h->Dinv, sizeof(double2) * std::max<int64_t>(ditot, 1)));
+  STCHK(dalloc(h, (void**)&h->Dinv, sizeof(double2) * std::max<int64_t>(ditot, 1) + kPanelPad));
+  HIPCHK(hipMemsetAsync(h->Dinv, 0, sizeof(double2) * std::max<int64_t>(ditot, 1) + kPanelPad, st));
   STCHK(dalloc(h, (void**)&h->piv, sizeof(int32_t) * ptot));
-  STCHK(dalloc(h, (void**)&h->M64, sizeof(double2) * std::max<int64_t>(mtot, 1)));
-  HIPCHK(hipMemsetAsync(h->M64, 0, sizeof(double2) * std::max<int64_t>(mtot, 1), st));
+  STCHK(dalloc(h, (void**)&h->M64, sizeof(double2) * std::max<int64_t>(mtot, 1) + kPanelPad));
+  HIPCHK(hipMemsetAsync(h->M64, 0, sizeof(double2) * std::max<int64_t>(mtot, 1) + kPanelPad, st));
 
   // ---- leaf LU with partial pivoting, then D^{-1} (eq. 12's near inverse)
   int* info = nullptr;
@@ -1959,11 +2083,15 @@ int build_device(hm_matrix* h, hipStream_t st) {
 
   // ---- FP32 copies (same layout, pad rows stay zero)
   if (h->has_f32) {
-    STCHK(dalloc(h, (void**)&h->R32, sizeof(float2) * std::max<int64_t>(rtot, 1)));
-    STCHK(dalloc(h, (void**)&h->M32, sizeof(float2) * std::max<int64_t>(mtot, 1)));
+    STCHK(dalloc(h, (void**)&h->R32, sizeof(float2) * std::max<int64_t>(rtot, 1) + kPanelPad));
+    STCHK(dalloc(h, (void**)&h->M32, sizeof(float2) * std::max<int64_t>(mtot, 1) + kPanelPad));
     STCHK(dalloc(h, (void**)&h->W32, sizeof(float2) * std::max<int64_t>(wtot, 1)));
     STCHK(dalloc(h, (void**)&h->IR32, sizeof(float2) * std::max<int64_t>(irtot, 1)));
-    STCHK(dalloc(h, (void**)&h->Wmm32, sizeof(float2) * std::max<int64_t>(wtot_mm, 1)));
+    STCHK(dalloc(h, (void**)&h->Wmm32, sizeof(float2) * std::max<int64_t>(wtot_mm, 1) + kPanelPad));
+    HIPCHK(hipMemsetAsync(reinterpret_cast<char*>(h->R32) + sizeof(float2) * rtot, 0, kPanelPad, st));
+    HIPCHK(hipMemsetAsync(reinterpret_cast<char*>(h->M32) + sizeof(float2) * mtot, 0, kPanelPad, st));
+    HIPCHK(hipMemsetAsync(reinterpret_cast<char*>(h->Wmm32) + sizeof(float2) * wtot_mm, 0, kPanelPad,
+                          st));
     HIPCHK(launch_cast(h->R64, h->R32, rtot, st));
     HIPCHK(launch_cast(h->M64, h->M32, mtot, st));
     HIPCHK(launch_cast(h->W64, h->W32, wtot, st));
@@ -2009,6 +2137,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
     HIPCHK(hipGetDeviceProperties(&prop, h->device));
     const int occ = std::min(term_occupancy(false, h->max_m), term_occupancy(true, h->max_m));
     h->term_wgs_auto = std::max(1, prop.multiProcessorCount * occ);
+    h->num_cus = std::max(1, prop.multiProcessorCount);
     h->term_wgs = h->term_wgs_auto;
     if (h->max_m <= kHalfMaxLeaf) {
       const int hocc = std::min(half_occupancy(false, h->max_m), half_occupancy(true, h->max_m));
@@ -2153,9 +2282,10 @@ int scratch_address(int dev, unsigned char** out) {
 
 // The workspace buffers a series or fixed-pass refinement reads and writes.
 struct WsView {
-  double2 *xin0, *xin1, *xt, *bt, *rt, *dt, *partial;
-  float2 *xin32_0, *xin32_1;
+  double2 *xin0, *xin1, *xt, *bt, *rt, *dt, *partial, *xr64_0, *xr64_1;
+  float2 *xr32_0, *xr32_1;
   int32_t* counters;
+  int64_t ldr;
 };
 
 // Lays the workspace for nrhs right-hand sides out from base in 256-byte
@@ -2167,18 +2297,21 @@ int64_t carve_workspace(const hm_matrix* h, int nrhs, unsigned char* base, WsVie
     off += (std::max<int64_t>(bytes, 16) + 255) / 256 * 256;
     return q;
   };
-  const int64_t ldin = h->N + h->T;
+  const int64_t ldin = h->N + h->T, ldr = row_ld(nrhs);
   WsView w{};
   w.xin0 = (double2*)take(16 * ldin * nrhs);
   w.xin1 = (double2*)take(16 * ldin * nrhs);
-  w.xin32_0 = (float2*)take(8 * ldin * nrhs);
-  w.xin32_1 = (float2*)take(8 * ldin * nrhs);
+  w.xr64_0 = (double2*)take(16 * (ldin + 1) * ldr);
+  w.xr64_1 = (double2*)take(16 * (ldin + 1) * ldr);
+  w.xr32_0 = (float2*)take(8 * (ldin + 1) * ldr);
+  w.xr32_1 = (float2*)take(8 * (ldin + 1) * ldr);
   w.xt = (double2*)take(16 * h->N * nrhs);
   w.bt = (double2*)take(16 * h->N * nrhs);
   w.rt = (double2*)take(16 * h->N * nrhs);
   w.dt = (double2*)take(16 * h->N * nrhs);
-  w.partial = (double2*)take(16 * h->partial_rows * nrhs);
-  w.counters = (int32_t*)take(4 * (int64_t)h->nl * nrhs);
+  w.partial = (double2*)take(16 * h->partial_rows * ldr);
+  w.counters = (int32_t*)take(4 * counter_count(h, nrhs));
+  w.ldr = ldr;
   if (v) *v = w;
   return off;
 }
@@ -2189,14 +2322,14 @@ struct WsSwap {
   hm_matrix* h;
   WsView saved;
   WsSwap(hm_matrix* h_, const WsView& w) : h(h_) {
-    saved = WsView{h->xin0, h->xin1, h->xt, h->bt, h->rt, h->dt, h->partial,
-                   h->xin32_0, h->xin32_1, h->counters};
+    saved = WsView{h->xin0, h->xin1, h->xt, h->bt, h->rt, h->dt, h->partial, h->xr64_0,
+                   h->xr64_1, h->xr32_0, h->xr32_1, h->counters, h->ws_ldr};
     set(w);
   }
   void set(const WsView& w) {
     h->xin0 = w.xin0; h->xin1 = w.xin1; h->xt = w.xt; h->bt = w.bt; h->rt = w.rt; h->dt = w.dt;
-    h->partial = w.partial; h->xin32_0 = w.xin32_0; h->xin32_1 = w.xin32_1;
-    h->counters = w.counters;
+    h->partial = w.partial; h->xr64_0 = w.xr64_0; h->xr64_1 = w.xr64_1; h->xr32_0 = w.xr32_0;
+    h->xr32_1 = w.xr32_1; h->counters = w.counters; h->ws_ldr = w.ldr;
   }
   ~WsSwap() { set(saved); }
 };
@@ -2697,6 +2830,10 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
   };
   const int autow = h->term_wgs_auto;
   std::vector<int> wgs = {autow, std::max(1, autow / 2), 2 * autow, 4 * autow};
+  // the matrix-core kernels hold one or two workgroups per compute unit
+  if (nrhs >= 2)
+    for (int w : {h->num_cus, 2 * h->num_cus})
+      if (std::find(wgs.begin(), wgs.end(), w) == wgs.end()) wgs.push_back(w);
   // in-row weights matter only for the streaming kernels' work split
   std::vector<int> pcts = {100, 150, 200};
   struct Cand { int mm_min, tile; };
@@ -2801,9 +2938,16 @@ int ps_solve_noalloc(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t
   hipStream_t st = (hipStream_t)hip_stream;
   // the split-K counters must start at zero (the array keeps the last call's
   // contents); a fill kernel, not a memset node, so the call stays capturable
-  const int64_t nc = (int64_t)h->nl * nrhs;
+  const int64_t nc = counter_count(h, nrhs);
   hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 1024)),
                      dim3(256), 0, st, w.counters, nc);
+  HIPCHK(hipGetLastError());
+  // the zero rows of the row-layout vectors (as 32-bit words)
+  const int64_t ldin = h->N + h->T;
+  for (void* zr : {(void*)(w.xr64_0 + ldin * w.ldr), (void*)(w.xr64_1 + ldin * w.ldr)})
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, (int32_t*)zr, 4 * w.ldr);
+  for (void* zr : {(void*)(w.xr32_0 + ldin * w.ldr), (void*)(w.xr32_1 + ldin * w.ldr)})
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, (int32_t*)zr, 2 * w.ldr);
   HIPCHK(hipGetLastError());
   WsSwap swap(h, w);
   return ps_solve_impl(h, o, b_dev, ldb, x_dev, ldx, nrhs, nullptr, hip_stream, false);
@@ -2892,8 +3036,9 @@ int64_t workspace_bytes(hm_matrix_t h, int nrhs, int64_t T) {
   const int64_t partial = h->partial_rows > 0 ? h->partial_rows
                                               : 2 * h->N + (int64_t)h->term_wgs * h->max_m;
   const int64_t items = h->n_norm_items > 0 ? h->n_norm_items : h->N / kNormRows + 1;
-  return (int64_t)nrhs * (24 * (2 * (h->N + T)) + 16 * (4 * h->N + partial) + 16 * (items + h->nseg) +
-                          4 * (int64_t)h->nl);
+  const int64_t ldr = row_ld(nrhs);
+  return (int64_t)nrhs * (16 * 2 * (h->N + T) + 16 * 4 * h->N + 16 * (items + h->nseg)) +
+         ldr * (24 * 2 * (h->N + T) + 16 * partial) + 4 * counter_count(h, nrhs);
 }
 
 int workspace_rhs(hm_matrix_t h) { return h->ws_nrhs; }
