@@ -158,25 +158,37 @@ def recorded_traffic(workload_name, prec, kernel):
     return None
 
 
-def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T, workload_name=None, half=False):
+def terms_per_launch(K, reps, kern):
+    """Series terms one term-kernel launch ran: 1, or K where the K terms
+    run as one launch (half storage, far blocks all between two leaves)."""
+    n = kern["term_series"]["launches"]
+    return max(1, round(K * reps / n)) if n else 1
+
+
+def term_roofline(info, level, n, nrhs, prec, mm, avg_us, T, workload_name=None, half=False,
+                  terms=1):
     """Roofline of one series-term launch.  Algorithmic bytes: the level's
-    series panel entries (D^{-1}[near | U]), or with half storage the
-    entries of the scaled operator S it reads (near blocks s > t once, far
-    U columns); on the one-RHS kernels also the W rows of the far blocks
-    read in the same launch; plus the vectors (y_{k-1} with its t part
-    read, y_k written, x read and written).  Flops (matrix-core kernels):
+    series panel entries (D^{-1}[near | U]) plus, on the one-RHS kernels,
+    the W rows of the far blocks read in the same launch; or with half
+    storage the entries of the scaled operator S it reads (near blocks
+    s > t once, far blocks between two leaves once as U' and W', U' and W'
+    of the other far blocks per orientation); plus the vectors (y_{k-1} with its t part
+    read, y_k written, x read and written), times the terms one launch
+    runs.  Flops (matrix-core kernels):
     executed real flops, 6 per complex multiply-add in FP32 (3M), 8 in
     FP64 (4M)."""
     elem = 16 if prec == "f64" else 8
     ent = info["half_entries" if half else "series_entries"][level]
-    went = 0 if mm else info["stageA_entries"][level]
+    went = 0 if (mm or half) else info["stageA_entries"][level]
     vec = 16 * nrhs * ((n + (T if mm else 0)) + 3 * n)
-    nbytes = elem * (ent + went) + vec
+    nbytes = terms * (elem * (ent + went) + vec)
     gbps = nbytes / (avg_us * 1e-6) / 1e9
     kname = "k_term_mm" if mm else ("k_half" if half else "k_term")
     traffic = recorded_traffic(workload_name, prec, kname)
     label = {"k_term_mm": "k_term_mm (one series term)", "k_term": "k_term (one series term)",
              "k_half": "k_half (one scaled series term, half storage)"}[kname]
+    if terms > 1:
+        label = f"k_half (the {terms} scaled series terms in one launch, half storage)"
     out = {"bound": "hbm", "kernel": label,
            "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
            "traffic": traffic, "bytes_per_launch": nbytes, "avg_launch_us": avg_us,
@@ -303,14 +315,14 @@ def bench_single(a):
     x_np = x.cpu().numpy()
     T = info["coeffs"][level]
     roof = term_roofline(info, level, n, nrhs, pname, mm, kernels["term_series"]["avg_us"], T,
-                         wl.name, half)
+                         wl.name, half, terms_per_launch(wl.K, a.steps, kernels))
     if not mm:
         assert kernels["stageA"]["launches"] == 0, "the leaf-level one-RHS path has no stage A"
     elem = 16 if prec == hmps.HM_F64 else 8
     # K terms, then the block-diagonal steps: D^{-1} b, or C^{-1} b and
     # C^{-T} x on the scaled series
-    per_solve_bytes = (wl.K * elem * (info["half_entries" if half else "series_entries"][level]
-                                      + info["stageA_entries"][level])
+    per_solve_bytes = (wl.K * elem * (info["half_entries"][level] if half else
+                                      info["series_entries"][level] + info["stageA_entries"][level])
                        + (2 if half else 1) * 16 * info["diag_entries"])
 
     rel = cpu = None
@@ -384,7 +396,8 @@ def bench_single(a):
         extras[f"series_{oname}"] = {"ms_per_solve": o_ms, "RHS_per_s": nrhs * 1e3 / o_ms}
         _, ko = profiled(h, lambda: solve(other), 5)
         extras[f"series_{oname}"]["roofline"] = term_roofline(
-            info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T, wl.name, half)
+            info, level, n, nrhs, oname, mm, ko["term_series"]["avg_us"], T, wl.name, half,
+            terms_per_launch(wl.K, 5, ko))
         extras[f"series_{oname}"]["kernels"] = ko
         if H is not None:
             from oracle import series
@@ -409,8 +422,9 @@ def bench_single(a):
                     nt = max(1, kl["term_series"]["launches"])
                     us = (kl["term_series"]["avg_us"] * nt
                           + kl["stageA"]["avg_us"] * kl["stageA"]["launches"]) / nt
-                    ent = info["half_entries" if half else "series_entries"][lev]
-                    nb = 16 * (ent + info["stageA_entries"][lev]) + 16 * (
+                    ent = (info["half_entries"][lev] if half else
+                           info["series_entries"][lev] + info["stageA_entries"][lev])
+                    nb = 16 * ent + 16 * (
                         n + info["coeffs"][lev] + 3 * n)
                     per_level[str(lev)]["term_and_stageA"] = {
                         "us": us, "bytes": nb, "GBps": nb / (us * 1e-6) / 1e9,

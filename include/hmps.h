@@ -200,10 +200,12 @@ typedef struct {
   int64_t stageA_entries[HM_MAX_LEVELS];
   int64_t coeffs[HM_MAX_LEVELS];
   int32_t num_instances;            /* 1, or the count of a batched handle  */
-  int64_t half_entries[HM_MAX_LEVELS]; /* panel entries the half-storage
+  int64_t half_entries[HM_MAX_LEVELS]; /* entries the half-storage
                                         product reads per term: near
-                                        blocks (t, s > t) once, plus the
-                                        far U columns (0: not symmetric) */
+                                        blocks (t, s > t) once, far blocks
+                                        between two leaves once (U and W),
+                                        U and W of the other far blocks per
+                                        orientation (0: not symmetric) */
 } hm_info;
 
 /* Kernel classes timed by hm_profile_enable. */
@@ -313,10 +315,14 @@ typedef struct {
                          of one right-hand side on a symmetric (surface)
                          problem (below mm_min_rhs) run in the scaled basis
                          D = C C^T, S = C^{-1} R C^{-T} on half storage:
-                         each off-diagonal near block S_ts, s > t, is read
+                         each off-diagonal near block S_ts, s > t, and
+                         each far block between two leaves t < s is read
                          once and applied in both orientations
-                         (S_st = S_ts^T); 2: the D^{-1}-premultiplied
-                         panels.  hmat_apply reads the panels either way */
+                         (S_st = S_ts^T), and where every far block of the
+                         level lies between two leaves the K terms run as
+                         one launch; 3: half storage with one launch per
+                         term; 2: the D^{-1}-premultiplied panels.
+                         hmat_apply reads the panels either way */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);

@@ -149,17 +149,23 @@ struct NormItem {
 // even(m_t), unpremultiplied).  Streaming a half-panel column j (row jj of
 // source leaf s) gives both u_t += Z[:, j] y_s[jj] and v_j = Z[:, j]^T y_t,
 // which is row jj of Z_st y_t: v_j goes to slot j of the vector vb and the
-// epilogue of leaf s adds it in.  Far blocks keep their per-orientation
-// form (in-row W stacks and the U columns of the apply panels).  The
+// epilogue of leaf s adds it in.  A far block between two leaves t < s is
+// stored once too, as the pair of factors (U' of t's rows, W' of s's rows,
+// S_ts = U' W'^T); one pass over the pair forms U'^T y_t and W'^T y_s and
+// from them z_t += U' (W'^T y_s) and z_s += W' (U'^T y_t), the second into
+// partial rows of its own that the epilogue of s adds.  Other far blocks
+// (a row or column cluster above the leaves) keep their per-orientation
+// form (in-row W stacks and the U columns of the far panels).  The
 // workgroup that completes a leaf writes z = alpha R y + beta v through the
-// TermArgs epilogue; the diagonal block (D or D^{-1}) is a second,
-// block-diagonal launch of the ordinary term kernel.
-// Pieces are TermItems with the apply panels as the panel set, taken by the
+// TermArgs epilogue.
+// Pieces are TermItems with the far panels as the panel set, taken by the
 // persistent workgroups one at a time from a queue (a device counter):
-//  kind 0: apply-panel columns [c0, c1) through src (global far U slices)
-//  kind 1: in-row far rows [r0, r1) of the W stack, apply-panel columns c0..
+//  kind 0: far-panel columns [c0, c1) through src (global far U slices)
+//  kind 1: in-row far rows [r0, r1) of the W stack, far-panel columns c0..
 //  kind 2: half-panel columns [c0, c1) of the leaf; its v values go to the
 //          leaves vleaf[r0, r1) (the blocks the columns cover)
+//  kind 3: far pairs [c0, c1) of the leaf (global pair indices); pair
+//          c0 + k goes to leaf vleaf[r0 + k]
 struct HalfArgs {
   TermArgs t;                // ps = scaled far panels; lptr/lprow: the leaf's
                              // u partial rows, then its v slots
@@ -172,10 +178,35 @@ struct HalfArgs {
   const int32_t* vleaf;      // target leaves of the kind-2 pieces
   int npieces;               // pieces in t.items, taken in order from a queue
   int32_t* queue;            // [next piece, workgroups done]; zero between launches
+  // far pairs: pair p is U' (even(m_t) x r) then W' (even(m_s) x r), both
+  // column-major, at element offset fp_off[p]; its z_s rows are partial
+  // rows frow + fp_slot[p] ..
+  const void* fp;            // double2 (FP64) or float2 (FP32) elements
+  const int64_t* fp_off;
+  const int32_t* fp_rank;
+  const int32_t* fp_slot;
+  int64_t frow;
+};
+// All K terms of the scaled series in one launch of the half-storage kernel
+// (lists whose far blocks are all pairs): term k reads y_{k-1} from
+// y[(k - 1) & 1] (y_0 given) and writes y_k = alpha z to y[k & 1] and
+// x += y_k, leaf by leaf; a piece of term k > 1 starts once the leaves it
+// reads and writes are done with term k - 1.  done (nl entries) and the
+// queue are zero between launches; err is set (and the launch still ends)
+// if a wait gives up, which a consistent list never makes it do.
+struct MultiArgs {
+  int K;
+  int nl;
+  double2* y[2];
+  double2* xacc;
+  int32_t* done;
+  int32_t* err;
 };
 hipError_t launch_half(bool f32, int max_m, const HalfArgs& a, int nwg, hipStream_t st);
-int half_occupancy(bool f32, int max_m);
-constexpr int kMaxVLeaves = 8;  // target leaves (blocks) per kind-2 piece
+hipError_t launch_half_multi(bool f32, int max_m, const HalfArgs& a, const MultiArgs& m, int nwg,
+                             hipStream_t st);
+int half_occupancy(bool f32, int max_m, bool multi = false);
+constexpr int kMaxVLeaves = 8;  // target leaves (blocks) per kind-2 or kind-3 piece
 constexpr int kHalfMaxLeaf = 128;  // largest leaf the half-storage product serves
 constexpr int kHalfChunk = 1024;   // input columns of a kind-0 half-list piece (at most)
 constexpr int kHalfPieceCols = 256;  // half-panel columns of a kind-2 piece (at most)

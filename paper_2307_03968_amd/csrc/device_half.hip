@@ -16,13 +16,15 @@
 // the set of columns (ten exchanges for eight sums) and stored to slot j of
 // vb.  v_j is row jj of Z_st y_t when column j is row jj of leaf s, so the
 // epilogue of leaf s adds the vb slots of its blocks (t, s) to its partial
-// sums.  Far blocks are unchanged (in-row W stacks and the U columns of the
-// apply panels, unpremultiplied).
+// sums.  A far block between two leaves t < s is stored once as its pair of
+// factors and applied in both orientations from one read (far_pairs); the
+// other far blocks keep one copy per orientation (in-row W stacks and the
+// U columns of the far panels).
 //
 // Completion: each piece counts once for its own leaf and once for every
-// leaf its v values go to; the workgroup that brings a leaf's counter to
-// its total sums the leaf's u partials and vb slots in a fixed order and
-// writes z.  The diagonal block is applied by a separate block-diagonal
+// leaf its v values or pair rows go to; the workgroup that brings a leaf's
+// counter to its total sums the leaf's u partials, vb slots and pair rows
+// in a fixed order and writes z.  The diagonal block is applied by a separate block-diagonal
 // launch of the term kernel (D^{-1} z for a series term, D x + z for the
 // H-matvec).  Relative to the D^{-1}-premultiplied panels this reads the
 // off-diagonal near blocks once instead of twice.
@@ -63,6 +65,20 @@ __device__ __forceinline__ void store_agent(double2* q, double2 z) {
   double* d = reinterpret_cast<double*>(q);
   __hip_atomic_store(d, z.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(d + 1, z.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double2 load_agent(const double2* q) {
+  const double* d = reinterpret_cast<const double*>(q);
+  return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// y entry of the term's input: a plain load within one term, a
+// device-coherent load where an earlier term of the same launch wrote it.
+template <bool MT>
+__device__ __forceinline__ double2 ld_y(const double2* q) {
+  if constexpr (MT) return load_agent(q);
+  else return *q;
 }
 
 // acc += a * x (complex) with nxy = -x.y given: the negation sits on the
@@ -161,13 +177,130 @@ __device__ __forceinline__ void half_tile(const void* __restrict__ P, uint32_t l
   }
 }
 
+// Far pairs [c0, c1) of leaf a (kind 3), pair c0 + k going to leaf
+// vleaf[r0 + k]: wave w takes the pairs k = w, w + kWaves, ...  Pair p holds
+// U' (rows of a, leading dimension lda) and W' (rows of its leaf s,
+// leading dimension even(m_s)), r columns each, one after the other.  Each
+// four-column step reads columns q of both factors with the half_tile lane
+// layout and forms, per column,
+//   sv = U'[:, q]^T y_a,  tv = W'[:, q]^T y_s   (sums over the 16 row lanes)
+//   za += U'[:, q] tv,    zs += W'[:, q] sv,
+// so za gathers S_as y_s = U' W'^T y_s and zs = W' U'^T y_a = S_sa y_a.
+// Two steps are loaded before either is used.  zs is summed over the four
+// column lanes and stored to the pair's partial rows when its pair is done;
+// za stays in registers over the wave's pairs (summed by the caller).
+// Columns past r re-read column r - 1 and are given sv = tv = 0; rows past
+// a leaf meet y = 0 and their z is never stored.  y_a is read from LDS (ys)
+// and y_s from the wave's own LDS rows yw (16 E RG entries).
+template <int E, int RG, bool MT>
+__device__ __forceinline__ void far_pairs(const HalfArgs& A, const TermItem& it,
+                                          const double2* xin, int lda, int w, int lane,
+                                          const double2* ys, double2* yw, double2 (&za)[RG][E]) {
+  using T = typename Elem<E>::T;
+  constexpr uint32_t kES = E == 1 ? 16 : 8;  // bytes per complex element
+  constexpr int NS = E * RG <= 4 ? 2 : 1;     // four-column steps in flight
+  const TermArgs& Tm = A.t;
+  const int r = lane & 15, c = lane >> 4;
+  const uint32_t lane_off = (uint32_t)(E * r) * kES;
+  const double2* ya = ys + E * r;  // y_a of the lane's rows (LDS): ya[16 E g + e]
+  const int c0 = __builtin_amdgcn_readfirstlane(it.c0);
+  const int np = __builtin_amdgcn_readfirstlane(it.c1) - c0;
+  const int v0 = __builtin_amdgcn_readfirstlane(it.r0);
+  for (int k = w; k < np; k += kWaves) {
+    const int p = c0 + k;
+    const int s = __builtin_amdgcn_readfirstlane(A.vleaf[v0 + k]);
+    const int rk = __builtin_amdgcn_readfirstlane(A.fp_rank[p]);
+    const int ms = __builtin_amdgcn_readfirstlane(Tm.ps.leaf_m[s]);
+    const int lds = ms + (ms & 1);
+    // the wave's y_s rows are rewritten once its previous pair is done
+    __builtin_amdgcn_wave_barrier();
+    const int offs = __builtin_amdgcn_readfirstlane(Tm.leaf_off[s]);
+    const int64_t eoff = A.fp_off[p];
+    const uint64_t pa = reinterpret_cast<uint64_t>(A.fp) + (uint64_t)eoff * kES;
+    const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
+    const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
+    void* pu = reinterpret_cast<void*>(((uint64_t)phi << 32) | plo);
+    const uint32_t nbytes = (uint32_t)(lda + lds) * (uint32_t)rk * kES;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        pu, 0, (int)__builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
+    const uint32_t wb = (uint32_t)lda * (uint32_t)rk * kES;  // W' after U'
+    double2 zs[RG][E];
+    for (int row = lane; row < 16 * E * RG; row += 64)
+      yw[row] = row < ms ? ld_y<MT>(xin + offs + row) : zero2();
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+      for (int e = 0; e < E; ++e) zs[g][e] = zero2();
+    const double2* yv = yw + E * r;  // y_s of the lane's rows: yv[16 E g + e]
+    for (int q0 = 0; q0 < rk; q0 += 4 * NS) {
+      T au[NS][RG], aw[NS][RG];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        const uint32_t q = (uint32_t)min(q0 + 4 * st + c, rk - 1);
+#pragma unroll
+        for (int g = 0; g < RG; ++g) {
+          au[st][g] = bload<E>(rs, lane_off + q * (uint32_t)lda * kES + g * 16 * E * kES);
+          aw[st][g] = bload<E>(rs, wb + lane_off + q * (uint32_t)lds * kES + g * 16 * E * kES);
+        }
+      }
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        double2 sv = zero2(), tv = zero2();
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            cmac(sv, Elem<E>::get(au[st][g], e), ya[16 * E * g + e]);
+            cmac(tv, Elem<E>::get(aw[st][g], e), yv[16 * E * g + e]);
+          }
+        sv.x = sum16_lanes(sv.x);
+        sv.y = sum16_lanes(sv.y);
+        tv.x = sum16_lanes(tv.x);
+        tv.y = sum16_lanes(tv.y);
+        if (q0 + 4 * st + c >= rk) {
+          sv = zero2();
+          tv = zero2();
+        }
+#pragma unroll
+        for (int g = 0; g < RG; ++g)
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            cmac(za[g][e], Elem<E>::get(au[st][g], e), tv);
+            cmac(zs[g][e], Elem<E>::get(aw[st][g], e), sv);
+          }
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g)
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int sh = 16; sh < 64; sh <<= 1) {
+          zs[g][e].x += __shfl_xor(zs[g][e].x, sh);
+          zs[g][e].y += __shfl_xor(zs[g][e].y, sh);
+        }
+    if (c == 0) {
+      double2* zp = Tm.partial + A.frow + A.fp_slot[p];
+#pragma unroll
+      for (int g = 0; g < RG; ++g)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int row = 16 * E * g + E * r + e;
+          if (row < ms) store_agent(zp + row, zs[g][e]);
+        }
+    }
+  }
+}
+
 // Epilogue of leaf a: z = the sum of its u partials and v slots (one list
 // of partial rows), then y = alpha z + beta v and the stores of the TermArgs
 // epilogue; the leaf's counter is cleared for the next launch.  P threads
 // share a row (P = 256 / 128 or 256 / 64): thread (i, p) sums the list
 // entries p, p + P, ... with all its loads in flight at once, and the P
 // sums are added in a fixed order, so the result does not depend on timing.
-__device__ void half_epilogue(const HalfArgs& A, int a, int* s_off, double2* s_z) {
+template <bool MT>
+__device__ void half_epilogue(const HalfArgs& A, const MultiArgs& M, int a, int term, int* s_off,
+                              double2* s_z) {
   constexpr int kInFlight = 16;
   const int m = A.t.ps.leaf_m[a];
   const int P = m <= 64 ? 4 : 2;
@@ -211,21 +344,79 @@ __device__ void half_epilogue(const HalfArgs& A, int a, int* s_off, double2* s_z
       z.x += s_z[r * 128 + threadIdx.x].x;
       z.y += s_z[r * 128 + threadIdx.x].y;
     }
-    finish_entry(A.t, A.t.leaf_off[a], threadIdx.x, 0, z);
+    if constexpr (MT) {
+      // y_k = alpha z for the next term and x += y_k, read by other
+      // workgroups of this launch: device-coherent stores and loads
+      const int64_t q = A.t.leaf_off[a] + threadIdx.x;
+      const double2 y = make_double2(A.t.alpha * z.x, A.t.alpha * z.y);
+      store_agent(M.y[term & 1] + q, y);
+      double2 x = load_agent(M.xacc + q);
+      x.x += y.x;
+      x.y += y.y;
+      store_agent(M.xacc + q, x);
+    } else {
+      finish_entry(A.t, A.t.leaf_off[a], threadIdx.x, 0, z);
+    }
   }
   if (threadIdx.x == 0)
     __hip_atomic_store(A.t.counters + a, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if constexpr (MT) {
+    // every store of the epilogue (y, x, the counter) is complete before
+    // the leaf is marked done with this term
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(M.done + a, term, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();  // s_z and s_off are free again
 }
+
+// Waits until leaf has finished term need (M.done[leaf] >= need).  The
+// wait is bounded: past kSpinLimit polls, or once another wait has given
+// up, it sets M.err and returns, so a launch always ends.
+constexpr int kSpinLimit = 1 << 21;
+__device__ void wait_done(const MultiArgs& M, int leaf, int need) {
+  for (int spins = 0;
+       __hip_atomic_load(M.done + leaf, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need;
+       ++spins) {
+    if (spins >= kSpinLimit ||
+        __hip_atomic_load(M.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+      __hip_atomic_store(M.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 
 // Persistent workgroup over its run of pieces (see the file comment).
 // Half-panel pieces use the row-group tiles of half_tile (RG groups of 16E
 // rows); the far pieces use the lane-per-row GEMV of the term kernel (G
 // groups of 64E rows).
-template <int E, int G, int RG, int NC>
-__global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
+//
+// MT (multi-term): one launch runs the M.K terms of the scaled series.
+// The queue holds the pieces of term 1, then those of term 2, ...; term k
+// reads y_{k-1} from M.y[(k - 1) & 1] and the epilogue of each leaf writes
+// y_k = alpha z to M.y[k & 1], adds it to M.xacc and then marks the leaf
+// done with term k (M.done).  A piece of term k > 1 waits until its own
+// leaf and the leaves of its columns or pairs are done with term k - 1.
+// That orders every reuse of memory within the launch: (a) a piece writes
+// partial rows only of those leaves, whose term k - 1 epilogues have read
+// them; (b) every term k - 1 reader of y_{k-2} of a leaf L (the buffer L's
+// term k epilogue overwrites) is L's own piece or writes v or pair rows of
+// L, so it counts toward L's term k - 1 epilogue, which precedes L's term k
+// pieces and so its term k epilogue; (c) L's epilogues, the only writers of
+// its x rows, run in term order.  Data published by an epilogue (y, x, the
+// leaf counter) is stored device-coherently and complete (s_waitcnt) before
+// the mark, and the y of a later term is read device-coherently after the
+// mark was seen.  Waits end: a piece waits only on pieces earlier in the
+// queue, each taken by a running workgroup.  Only lists whose far blocks
+// are all pairs (no kind 0 columns, no kind 1 rows) run this way.
+template <int E, int G, int RG, int NC, bool MT>
+__global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
   constexpr int UNR = 8;
   constexpr int MR = 16 * E * RG;  // rows a half-panel piece covers
+  static_assert(MR <= kHalfChunk / kWaves, "a wave's y_s rows of a far pair live in xs");
   const TermArgs& T = A.t;
   const int w = wave_id();
   const int lane = threadIdx.x & 63;
@@ -240,39 +431,54 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
   __shared__ int s_off[kThreads];
   __shared__ double2 s_z[4 * 128];
   __shared__ int s_last[kMaxVLeaves + 1];
-  __shared__ int s_nlast, s_next;
-  // Pieces come from a queue: a workgroup takes the next ticket as it
-  // starts a piece (the atomic's result is needed only when the piece is
-  // done), so faster workgroups take more pieces and no static split has
-  // to predict how long each piece takes.
+  __shared__ int s_nlast, s_next, s_reset;
+  // Pieces come from a queue: a workgroup takes the next ticket once its
+  // current piece's loads are done (the atomic completes with the piece's
+  // stores), so faster workgroups take more pieces, no static split has to
+  // predict how long each piece takes, and a workgroup holds one piece at
+  // a time (no piece waits, unstarted, behind another).
   if (threadIdx.x == 0)
     s_next = __hip_atomic_fetch_add(A.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __syncthreads();
+  const int total = MT ? M.K * A.npieces : A.npieces;
   int p = s_next;
-  while (p < A.npieces) {
-    int ticket = 0;
-    if (threadIdx.x == 0)
-      ticket = __hip_atomic_fetch_add(A.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const TermItem it = T.items[p];
+  while (p < total) {
+    const int term = MT ? p / A.npieces + 1 : 1;
+    const TermItem it = T.items[MT ? p - (term - 1) * A.npieces : p];
+    const double2* xin = MT ? M.y[(term - 1) & 1] : T.xin;
     const int a = it.leaf;
     const int m = T.ps.leaf_m[a];
     const int64_t ld = m + (m & 1);
     const int nc = it.c1 - it.c0;  // at most kHalfChunk for kinds 0 and 2
-    if (it.kind == 2) {
+    if constexpr (MT) {
+      if (term > 1) {
+        const int nd = (it.kind >= 2 ? it.r1 - it.r0 : 0) + 1;
+        if ((int)threadIdx.x < nd)
+          wait_done(M, threadIdx.x == 0 ? a : A.vleaf[it.r0 + threadIdx.x - 1], term - 1);
+        __syncthreads();
+      }
+    }
+    if (it.kind == 2 || it.kind == 3) {
       const int64_t off = T.leaf_off[a];
-      const int32_t* __restrict__ hsrc = A.hsrc + A.hp_col[a];
-      for (int i = threadIdx.x; i < MR; i += kThreads) ys[i] = i < m ? T.xin[off + i] : zero2();
-      for (int k = threadIdx.x; k < nc; k += kThreads) xs[k] = T.xin[hsrc[it.c0 + k]];
+      for (int i = threadIdx.x; i < MR; i += kThreads) ys[i] = i < m ? ld_y<MT>(xin + off + i) : zero2();
+      if (it.kind == 2) {
+        const int32_t* __restrict__ hsrc = A.hsrc + A.hp_col[a];
+        for (int k = threadIdx.x; k < nc; k += kThreads) xs[k] = ld_y<MT>(xin + hsrc[it.c0 + k]);
+      }
       __syncthreads();
-      const void* HP = Elem<E>::offset(A.hp, A.hp_off[a]);
-      const uint32_t nbytes =
-          (uint32_t)(ld * (A.hp_col[a + 1] - A.hp_col[a]) * (E == 1 ? 16 : 8));
       double2 u[RG][E];
 #pragma unroll
       for (int g = 0; g < RG; ++g)
 #pragma unroll
         for (int e = 0; e < E; ++e) u[g][e] = zero2();
-      half_tile<E, RG, NC>(HP, (uint32_t)ld, nbytes, it.c0, it.c1, w, lane, xs, ys, u, vl);
+      if (it.kind == 2) {
+        const void* HP = Elem<E>::offset(A.hp, A.hp_off[a]);
+        const uint32_t nbytes =
+            (uint32_t)(ld * (A.hp_col[a + 1] - A.hp_col[a]) * (E == 1 ? 16 : 8));
+        half_tile<E, RG, NC>(HP, (uint32_t)ld, nbytes, it.c0, it.c1, w, lane, xs, ys, u, vl);
+      } else {
+        far_pairs<E, RG, MT>(A, it, xin, (int)ld, w, lane, ys, xs + w * (kHalfChunk / kWaves), u);
+      }
       // u over the four column lanes of each row (lane bits 4, 5), then
       // over the waves in a fixed order
 #pragma unroll
@@ -300,11 +506,16 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
         }
         store_agent(T.partial + it.prow + i, z);
       }
-      double2* vb = T.partial + A.vrow + A.hp_col[a] + it.c0;
-      for (int k = threadIdx.x; k < nc; k += kThreads) store_agent(vb + k, vl[k]);
+      if (it.kind == 2) {
+        double2* vb = T.partial + A.vrow + A.hp_col[a] + it.c0;
+        for (int k = threadIdx.x; k < nc; k += kThreads) store_agent(vb + k, vl[k]);
+      }
+    } else if constexpr (MT) {
+      // a leaf with no work of its own publishes zeros
+      for (int i = threadIdx.x; i < m; i += kThreads) store_agent(T.partial + it.prow + i, zero2());
     } else {
       // far pieces (kind 0, 1) and pieces of leaves with no work of their
-      // own (which publish zeros): lane-per-row GEMV on the apply panel
+      // own (which publish zeros): lane-per-row GEMV on the far panel
       double2 acc[G][E][1];
       zero_acc(acc);
       if (it.kind == 0) {
@@ -346,12 +557,15 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
           }
       }
     }
+    int ticket = 0;
+    if (threadIdx.x == 0)
+      ticket = __hip_atomic_fetch_add(A.queue, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // every store of the piece is complete before it is counted
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) s_nlast = 0;
     __syncthreads();
-    const int nv = it.kind == 2 ? it.r1 - it.r0 : 0;
+    const int nv = it.kind >= 2 ? it.r1 - it.r0 : 0;
     if ((int)threadIdx.x <= nv) {
       const int leaf = threadIdx.x == 0 ? a : A.vleaf[it.r0 + threadIdx.x - 1];
       const int old = __hip_atomic_fetch_add(T.counters + leaf, 1, __ATOMIC_RELAXED,
@@ -360,27 +574,35 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A) {
     }
     __syncthreads();
     const int nlast = s_nlast;
-    for (int k = 0; k < nlast; ++k) half_epilogue(A, s_last[k], s_off, s_z);
+    for (int k = 0; k < nlast; ++k) half_epilogue<MT>(A, M, s_last[k], term, s_off, s_z);
     if (threadIdx.x == 0) s_next = ticket;
     __syncthreads();
     p = s_next;
   }
-  // the last workgroup out clears the queue for the next launch (every
-  // workgroup has taken its last ticket before it counts itself out)
+  // the last workgroup out clears the queue (and the done marks) for the
+  // next launch: every workgroup has taken its last ticket, and finished
+  // its pieces and epilogues, before it counts itself out
   if (threadIdx.x == 0) {
     const int done = __hip_atomic_fetch_add(A.queue + 1, 1, __ATOMIC_RELAXED,
                                             __HIP_MEMORY_SCOPE_AGENT);
-    if (done == (int)gridDim.x - 1) {
+    s_reset = done == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (s_reset) {
+    if constexpr (MT)
+      for (int i = threadIdx.x; i < M.nl; i += kThreads)
+        __hip_atomic_store(M.done + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
       __hip_atomic_store(A.queue, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(A.queue + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
 
-template <int E, int G, int RG, int NC>
+template <int E, int G, int RG, int NC, bool MT>
 int occ_half() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_half<E, G, RG, NC>, kThreads, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_half<E, G, RG, NC, MT>, kThreads, 0) !=
       hipSuccess)
     return 1;
   return n > 0 ? n : 1;
@@ -398,9 +620,11 @@ int occ_half() {
 hipError_t launch_half(bool f32, int max_m, const HalfArgs& a, int nwg, hipStream_t st) {
   if (nwg <= 0) return hipSuccess;
   if (max_m > kHalfMaxLeaf) return hipErrorInvalidValue;
+  const MultiArgs none{};
 #define X(F, MM, E, G, RG, NC)                                                                \
   if (f32 == F && max_m <= MM) {                                                             \
-    hipLaunchKernelGGL((k_half<E, G, RG, NC>), dim3(nwg), dim3(kThreads), 0, st, a);         \
+    hipLaunchKernelGGL((k_half<E, G, RG, NC, false>), dim3(nwg), dim3(kThreads), 0, st, a,   \
+                       none);                                                                \
     return hipGetLastError();                                                                \
   }
   HALF_VARIANTS(X)
@@ -408,9 +632,25 @@ hipError_t launch_half(bool f32, int max_m, const HalfArgs& a, int nwg, hipStrea
   return hipErrorInvalidValue;
 }
 
-int half_occupancy(bool f32, int max_m) {
-#define X(F, MM, E, G, RG, NC) \
-  if (f32 == F && max_m <= MM) return occ_half<E, G, RG, NC>();
+hipError_t launch_half_multi(bool f32, int max_m, const HalfArgs& a, const MultiArgs& m, int nwg,
+                             hipStream_t st) {
+  if (nwg <= 0 || m.K <= 0) return hipSuccess;
+  if (max_m > kHalfMaxLeaf || (int64_t)m.K * a.npieces >= ((int64_t)1 << 31))
+    return hipErrorInvalidValue;
+#define X(F, MM, E, G, RG, NC)                                                                \
+  if (f32 == F && max_m <= MM) {                                                             \
+    hipLaunchKernelGGL((k_half<E, G, RG, NC, true>), dim3(nwg), dim3(kThreads), 0, st, a, m); \
+    return hipGetLastError();                                                                \
+  }
+  HALF_VARIANTS(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+int half_occupancy(bool f32, int max_m, bool multi) {
+#define X(F, MM, E, G, RG, NC)                                                         \
+  if (f32 == F && max_m <= MM)                                                        \
+    return multi ? occ_half<E, G, RG, NC, true>() : occ_half<E, G, RG, NC, false>();
   HALF_VARIANTS(X)
 #undef X
   return 1;

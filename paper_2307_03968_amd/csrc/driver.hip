@@ -48,6 +48,7 @@ struct TermList {
   int npieces = 0;
   int64_t rows = 0;            // partial rows
   int64_t vrow = 0;            // half lists: first partial row of the v slots
+  int64_t frow = 0;            // half lists: first partial row of the far-pair slots
 };
 
 struct GroupList {
@@ -139,10 +140,31 @@ struct hm_matrix {
   struct HalfList {
     hm::TermList tl;
     int32_t *lcnt = nullptr, *vleaf = nullptr;
+    bool multi = false;  // every far block of the level is a pair: all K terms in one launch
   };
   std::vector<HalfList> half;
+  // far blocks between two leaves in the scaled basis, stored once per pair
+  // (t < s): U' then W' per pair; the remaining far blocks keep in-row
+  // stacks (hir_*) and far-panel columns [in-row U' | global U'] (HF*)
+  double2* FP64 = nullptr;
+  float2* FP32 = nullptr;
+  int64_t* fp_off = nullptr;
+  int32_t *fp_rank = nullptr, *fp_slot = nullptr;
+  std::vector<int32_t> fp_first_h;              // per leaf (+ end): first pair
+  std::vector<int32_t> fp_rank_h, fp_tgt_h, fp_slot_h;  // per pair
+  std::vector<std::vector<int32_t>> fp_end;     // per level, per leaf: pairs of level >= l
+  int64_t fp_rows = 0;                          // partial rows of all pairs' z_s
+  int64_t* hir_off = nullptr;
+  int32_t *hir_ld = nullptr, *hir_ncol = nullptr, *hir_row0 = nullptr, *hir_soff = nullptr,
+          *hir_n = nullptr;
+  std::vector<int64_t> hir_cols;                // per leaf: in-row stack rows
+  std::vector<int32_t> hir_ncol_h;
+  std::vector<std::vector<int64_t>> hir_end;    // per level, per leaf
   std::vector<int64_t> ent_half;  // entries read per half-storage product, per level
-  int use_half = 1;               // 1: half storage where available, 2: panels
+  int use_half = 1;               // 1: half storage where available (K terms per launch
+                                  // where the level allows), 3: one launch per term, 2: panels
+  int32_t* hdone = nullptr;       // multi-term launch: per leaf, last finished term
+  int32_t* herr = nullptr;        // multi-term launch: a dependency wait gave up
   int half_pct = 100;             // cost weight (%) of half-panel columns in the work split
   std::vector<hm::GroupList> sa_mm;
   int mm_min_rhs = hm::kMmMinRhsDefault;  // right-hand sides from which the MFMA kernels run
@@ -262,7 +284,8 @@ int level_index(const hm_matrix* h, int level, int* li) {
 int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t, int64_t>>>& dense,
                   const std::vector<int64_t>& inrow_rows, const std::vector<int64_t>& inrow_col,
                   const std::vector<int32_t>& inrow_ncol, TermList& tl, hipStream_t st,
-                  hm_matrix::HalfList* hl = nullptr, int units = 0, bool whole = false) {
+                  hm_matrix::HalfList* hl = nullptr, int units = 0, bool whole = false,
+                  const std::vector<int32_t>* npairs = nullptr) {
   struct Seg { int leaf, kind; int64_t u0, u1, col0, cost; };
   std::vector<Seg> segs;
   int64_t total = 0;
@@ -275,6 +298,13 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
     if (inrow_rows[a] > 0)
       segs.push_back({a, 1, 0, inrow_rows[a], inrow_col[a],
                       ((int64_t)inrow_ncol[a] + m) * h->inrow_pct / 100});
+    if (hl && npairs && (*npairs)[a] > 0) {  // far pairs: cost of the leaf's average pair
+      const int32_t p0 = h->fp_first_h[a], np = (*npairs)[a];
+      int64_t c = 0;
+      for (int32_t p = p0; p < p0 + np; ++p)
+        c += (int64_t)h->fp_rank_h[p] * (m + h->H.leaf_size[h->fp_tgt_h[p]]);
+      segs.push_back({a, 3, 0, np, 0, std::max<int64_t>(1, c / np)});
+    }
     if (segs.size() == first) segs.push_back({a, 0, 0, 0, 0, 0});  // epilogue only
     for (size_t k = first; k < segs.size(); ++k) total += (segs[k].u1 - segs[k].u0) * segs[k].cost;
   }
@@ -307,12 +337,26 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
           k = std::min<int64_t>(k, bc[lim] - u);
           b1 = std::upper_bound(bc.begin(), bc.end(), (int32_t)(u + k - 1));
         }
+        if (sg.kind == 3) k = std::min<int64_t>(k, kMaxVLeaves);
         TermItem it{sg.leaf, sg.kind, 0, 0, 0, 0, (int32_t)rows, 0};
+        int64_t cost = k * sg.cost;
         if (sg.kind == 1) {
           it.r0 = (int32_t)u;
           it.r1 = (int32_t)(u + k);
           it.c0 = (int32_t)(sg.col0 + u);
           it.c1 = (int32_t)(sg.col0 + u + k);
+        } else if (sg.kind == 3) {
+          it.c0 = (int32_t)(h->fp_first_h[sg.leaf] + u);
+          it.c1 = (int32_t)(it.c0 + k);
+          it.r0 = (int32_t)vleaf.size();
+          cost = 0;
+          for (int32_t p = it.c0; p < it.c1; ++p) {
+            const int s = h->fp_tgt_h[p];
+            vleaf.push_back(s);
+            lcnt[s]++;
+            cost += (int64_t)h->fp_rank_h[p] * (m + h->H.leaf_size[s]);
+          }
+          it.r1 = (int32_t)vleaf.size();
         } else {
           it.c0 = (int32_t)u;
           it.c1 = (int32_t)(u + k);
@@ -327,15 +371,53 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
           }
           it.r1 = (int32_t)vleaf.size();
         }
-        pcs.push_back({k * sg.cost, it});
+        pcs.push_back({cost, it});
         rows += m;
         u += k;
       } while (u < sg.u1);
     }
-    std::stable_sort(pcs.begin(), pcs.end(),
-                     [](const std::pair<int64_t, TermItem>& x, const std::pair<int64_t, TermItem>& y) {
-                       return x.first > y.first;
-                     });
+    // Queue order.  Pieces whose leaves (its own and those its columns or
+    // pairs read) all lie in the first part of the tree order come first,
+    // those whose leaves all lie in the last part come last, the rest in
+    // between, each part about a third of the pieces.  When the K terms
+    // run as one launch, the pieces still running at the end of a term then
+    // touch only the last leaves, and the first pieces of the next term
+    // read only the first ones, which are done: the terms overlap instead
+    // of waiting for each other.  Within a part, far pairs (the slowest per
+    // byte) first, then the largest estimated cost first, so that the last
+    // pieces taken are small.
+    std::vector<int32_t> lo(pcs.size()), hi(pcs.size());
+    for (size_t q = 0; q < pcs.size(); ++q) {
+      const TermItem& it = pcs[q].second;
+      lo[q] = hi[q] = it.leaf;
+      if (it.kind >= 2)
+        for (int32_t r = it.r0; r < it.r1; ++r) {
+          lo[q] = std::min(lo[q], vleaf[r]);
+          hi[q] = std::max(hi[q], vleaf[r]);
+        }
+    }
+    // first leaf bound h1 with a third of the pieces below it, last bound h2
+    // with a third at or above it
+    const int64_t third = (int64_t)pcs.size() / 3;
+    std::vector<int32_t> sh(hi), sl(lo);
+    std::sort(sh.begin(), sh.end());
+    std::sort(sl.begin(), sl.end());
+    const int32_t h1 = sh.empty() ? 0 : sh[(size_t)third];
+    const int32_t h2 = sl.empty() ? 0 : sl[sl.size() - 1 - (size_t)third];
+    std::vector<int> part(pcs.size());
+    for (size_t q = 0; q < pcs.size(); ++q)
+      part[q] = hi[q] < h1 ? 0 : (lo[q] > h2 ? 2 : 1);
+    std::vector<size_t> ord(pcs.size());
+    for (size_t q = 0; q < ord.size(); ++q) ord[q] = q;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+      if (part[x] != part[y]) return part[x] < part[y];
+      const bool px = pcs[x].second.kind == 3, py = pcs[y].second.kind == 3;
+      if (px != py) return px;
+      return pcs[x].first > pcs[y].first;
+    });
+    std::vector<std::pair<int64_t, TermItem>> sorted;
+    for (size_t q : ord) sorted.push_back(pcs[q]);
+    pcs.swap(sorted);
     for (auto& pc : pcs) {
       items.push_back(pc.second);
       wg_of.push_back(0);
@@ -412,7 +494,8 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   }
   for (const TermItem& it : items)
     if ((it.kind == 1 && ((it.r0 & 1) || it.r1 - it.r0 > (hl ? kHalfInRowTile : kInRowTile))) ||
-        (it.kind == 2 && (it.r1 - it.r0 < 1 || it.r1 - it.r0 > kMaxVLeaves)) ||
+        ((it.kind == 2 || it.kind == 3) && (it.r1 - it.r0 < 1 || it.r1 - it.r0 > kMaxVLeaves)) ||
+        (it.kind == 3 && (!hl || it.c1 - it.c0 != it.r1 - it.r0)) ||
         (hl && it.c1 - it.c0 > kHalfChunk && it.kind != 1)) {
       set_error("internal: bad term piece");
       return HM_EINVAL;
@@ -427,11 +510,21 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   for (size_t q = 0; q < items.size(); ++q) by_wg[fill[wg_of[q]]++] = items[q];
   // per leaf: the partial rows of its pieces, in piece order (half lists:
   // then the v slots of the blocks (t, leaf), t < leaf, which follow the
-  // pieces' rows in the partial buffer)
-  std::vector<int32_t> lptr(h->nl + 1, 0), lprow;
-  for (auto& it : items) lptr[it.leaf + 1]++;
+  // pieces' rows in the partial buffer, then the z rows of the far pairs
+  // (t, leaf) of the list, in pair order)
+  std::vector<int32_t> lptr(h->nl + 1, 0), lprow, own(h->nl, 0);
+  std::vector<std::vector<int32_t>> pair_in(hl ? h->nl : 0);
+  for (auto& it : items) {
+    lptr[it.leaf + 1]++;
+    own[it.leaf]++;
+    if (it.kind == 3)
+      for (int32_t p = it.c0; p < it.c1; ++p) pair_in[h->fp_tgt_h[p]].push_back(p);
+  }
   if (hl)
-    for (int a = 0; a < h->nl; ++a) lptr[a + 1] += h->vptr_h[a + 1] - h->vptr_h[a];
+    for (int a = 0; a < h->nl; ++a) {
+      std::sort(pair_in[a].begin(), pair_in[a].end());
+      lptr[a + 1] += h->vptr_h[a + 1] - h->vptr_h[a] + (int32_t)pair_in[a].size();
+    }
   for (int a = 0; a < h->nl; ++a) lptr[a + 1] += lptr[a];
   lprow.assign(lptr[h->nl], 0);
   std::vector<int32_t> lf(lptr.begin(), lptr.end() - 1);
@@ -446,6 +539,14 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
       for (int q = h->vptr_h[a]; q < h->vptr_h[a + 1]; ++q)
         lprow[lf[a]++] = (int32_t)(rows + h->vstart_h[q]);
     rows += h->hp_cols;
+    tl.frow = rows;
+    if (rows + h->fp_rows >= ((int64_t)1 << 31)) {
+      set_error("term partial rows exceed 2^31");
+      return HM_EINVAL;
+    }
+    for (int a = 0; a < h->nl; ++a)
+      for (int32_t p : pair_in[a]) lprow[lf[a]++] = (int32_t)(rows + h->fp_slot_h[p]);
+    rows += h->fp_rows;
   }
   tl.nwg = G;
   tl.npieces = (int)items.size();
@@ -455,8 +556,10 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   STCHK(upload(h, &tl.lptr, lptr, st, true));
   STCHK(upload(h, &tl.lprow, lprow, st, true));
   if (hl) {
-    for (int a = 0; a < h->nl; ++a)
-      lcnt[a] += lptr[a + 1] - lptr[a] - (h->vptr_h[a + 1] - h->vptr_h[a]);
+    hl->multi = true;
+    for (const TermItem& it : items)
+      if (it.kind == 1 || (it.kind == 0 && it.c1 > it.c0)) hl->multi = false;
+    for (int a = 0; a < h->nl; ++a) lcnt[a] += own[a];
     STCHK(upload(h, &hl->lcnt, lcnt, st, true));
     STCHK(upload(h, &hl->vleaf, vleaf, st, true));
   }
@@ -652,7 +755,7 @@ hipError_t run_stageA(const hm_matrix* h, const Path& P, bool f32, const GroupLi
 // The half-storage series serves one right-hand side of a symmetric
 // problem, when the tuning allows it.
 bool use_half(const hm_matrix* h, int li, int nrhs) {
-  return nrhs == 1 && nrhs < h->mm_min_rhs && h->use_half == 1 && h->half_ok &&
+  return nrhs == 1 && nrhs < h->mm_min_rhs && (h->use_half == 1 || h->use_half == 3) && h->half_ok &&
          li < (int)h->half.size();
 }
 
@@ -663,7 +766,8 @@ HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int
   a.t = term_args(h, PanelSet{f32 ? (const void*)h->HF32 : (const void*)h->HF64, h->hf_off, h->src,
                               h->hf_col, h->leaf_m},
                   L.tl, f32, xin, ldx);
-  a.t.ir.W = f32 ? (const void*)h->IRT32 : (const void*)h->IRT64;
+  a.t.ir = InRow{f32 ? (const void*)h->IRT32 : (const void*)h->IRT64, h->hir_off, h->hir_ld,
+                 h->hir_ncol, h->hir_row0, h->hir_soff, h->hir_n};
   a.hp = f32 ? (const void*)h->H32 : (const void*)h->H64;
   a.hp_off = h->hp_off;
   a.hp_col = h->hp_col;
@@ -673,6 +777,11 @@ HalfArgs half_args(const hm_matrix* h, int li, bool f32, const double2* xin, int
   a.vleaf = L.vleaf;
   a.npieces = L.tl.npieces;
   a.queue = h->hq;
+  a.fp = f32 ? (const void*)h->FP32 : (const void*)h->FP64;
+  a.fp_off = h->fp_off;
+  a.fp_rank = h->fp_rank;
+  a.fp_slot = h->fp_slot;
+  a.frow = L.tl.frow;
   return a;
 }
 
@@ -713,6 +822,15 @@ int scaled_terms(hm_matrix* h, int li, bool f32, int K, double2* xh, double2** l
   const int64_t N = h->N, ldin = h->N + h->T;
   double2* y_cur = h->xin0;
   double2* y_nxt = h->xin1;
+  if (K > 0 && h->use_half == 1 && h->half[li].multi) {
+    // all K terms in one launch (pieces gated by per-leaf term marks)
+    HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
+    ha.t.alpha = -1.0;
+    const MultiArgs m{K, h->nl, {y_cur, y_nxt}, xh, h->hdone, h->herr};
+    TIMED(HM_K_TERM_SERIES, launch_half_multi(f32, h->max_m, ha, m, h->half[li].tl.nwg, st));
+    *last = (K & 1) ? y_nxt : y_cur;
+    return HM_OK;
+  }
   const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
   const void* W1 = f32 ? (const void*)h->WT32 : (const void*)h->WT64;
   for (int k = 1; k <= K; ++k) {
@@ -819,21 +937,8 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
       HIPCHK(block_diag(dinv_set(h), rhs, ldr, rhs_perm, y_nxt, ldin, nullptr, nullptr));
       HIPCHK(norms_into(h, y_nxt, ldin, nrhs, 0, st));
     }
-    const GroupList& sa1 = h->sa[li];  // the one-RHS stage-A groups (global far only)
-    const void* W1 = f32 ? (const void*)h->WT32 : (const void*)h->WT64;
-    for (int k = 1; k <= K; ++k) {
-      if (sa1.n > 0)
-        TIMED(HM_K_STAGEA, launch_stageA(f32, W1, h->groups, sa1.items, sa1.n, y_cur, ldin, N, 1, st));
-      HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
-      ha.t.alpha = -1.0;
-      ha.t.yout = y_nxt;
-      ha.t.ldy = ldin;
-      ha.t.xacc = xh;
-      ha.t.ldxa = N;
-      ha.t.accumulate = 1;
-      TIMED(HM_K_TERM_SERIES, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
-      std::swap(y_cur, y_nxt);
-    }
+    STCHK(scaled_terms(h, li, f32, K, xh, &y_cur, st));
+    y_nxt = y_cur == h->xin0 ? h->xin1 : h->xin0;
     if (want_norms) {  // ||y_K||, y_K = C^{-T} yhat_K
       HIPCHK(block_diag(chat_set(h, true), y_cur, ldin, false, y_nxt, ldin, nullptr, nullptr));
       HIPCHK(norms_into(h, y_nxt, ldin, nrhs, 1, st));
@@ -1364,16 +1469,18 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   std::vector<std::vector<std::pair<int64_t, int64_t>>> dense(nl);
   std::vector<int64_t> irr(nl), irc(nl), zero(nl, 0);
   for (int li = 0; li < h->nlev && h->half_ok; ++li) {
-    // half storage: half-panel columns, then the scaled far panels
-    // [in-row U' | global U']
+    // half storage: half-panel columns, the scaled far panels
+    // [in-row U' | global U'] of the far blocks not stored as pairs, and
+    // the far pairs
     for (int a = 0; a < nl; ++a) {
-      const int64_t gstart = h->ir_cols[a];
+      const int64_t gstart = h->hir_cols[a];
       dense[a].clear();
       if (h->gl_end[li][a] > 0) dense[a].push_back({gstart, gstart + h->gl_end[li][a]});
-      irr[a] = h->ir_end[li][a];
+      irr[a] = h->hir_end[li][a];
       irc[a] = 0;
     }
-    STCHK(make_termlist(h, dense, irr, irc, h->ir_ncol_h, h->half[li].tl, st, &h->half[li]));
+    STCHK(make_termlist(h, dense, irr, irc, h->hir_ncol_h, h->half[li].tl, st, &h->half[li], 0,
+                        false, &h->fp_end[li]));
   }
   for (int li = 0; li < h->nlev; ++li) {
     for (int pass = 0; pass < 4; ++pass) {  // apply, series, apply MM, series MM
@@ -1524,6 +1631,7 @@ struct HalfSrc {
   const std::vector<int64_t>* ir_cols;
   const bigvec<double2>* W;                  // one-RHS stage-A groups
   const std::vector<Group>* groups;
+  const std::vector<std::vector<int>>* inrow;  // per leaf: in-row far blocks, in order
 };
 
 // Half-storage data (symmetric problems only: every instance a surface
@@ -1629,52 +1737,163 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
       for (int i = 0; i < mt; ++i) right_chatT(Ch[nb.s_leaf].data(), ms, dst + i, ld);
     }
   }
-  // ---- far part: U' = Chat_t U (far columns of the apply panels), and
-  // W' = W Chat_s^T per source leaf (in-row stacks, stage-A groups)
-  std::vector<int64_t> hf_off(nl);
-  int64_t ftot = 0;
+  // ---- far part.  A far block whose row and column clusters are both
+  // leaves (t, s) is a pair, stored once by its lower leaf t < s: U' =
+  // Chat_t U (even(m_t) x r) and W' = Chat_s W (even(m_s) x r) with
+  // S_ts = U' W'^T and S_st = W' U'^T.  Every other far block keeps U' =
+  // Chat_t U as far-panel columns ([in-row U' | global U'] per leaf) and
+  // W' = W Chat_s^T as rows of the in-row stacks or the one-RHS stage-A
+  // groups (row segments per source leaf).  Blocks stay finest level first.
+  auto lev_of = [&](int li) { return (h->lmin < 0) ? h->L + 1 : h->lmin + li; };
+  auto rank = [&](int b) { return H.lowrank[H.far[b].src].r; };
+  auto col_leaf = [&](int b) -> int {  // column leaf of a block onto one leaf, else -1
+    const FarBlock& fb = H.far[b];
+    const int s = H.tree.leaf_of[fb.s_off];
+    return (H.leaf_off[s] == fb.s_off && H.leaf_size[s] == fb.n) ? s : -1;
+  };
+  struct Blk { int b; int64_t ucol, srow; };  // in-row block, its U' column and stack row
+  std::vector<std::vector<Blk>> own_pairs(nl), rest(nl);
+  for (int a = 0; a < nl; ++a) {
+    int64_t ucol = 0;
+    for (int b : (*hs.inrow)[a]) {
+      const int s = col_leaf(b);
+      if (s < 0) rest[a].push_back({b, ucol, ucol});
+      else if (a < s) own_pairs[a].push_back({b, ucol, ucol});
+      ucol += rank(b);  // in-row U' columns and stack rows share the order
+    }
+  }
+  // pair index, data offsets and z_s slots
+  std::vector<int32_t> fp_first(nl + 1, 0), fp_rank, fp_tgt, fp_slot;
+  std::vector<int64_t> fp_off;
+  int64_t fptot = 0, fprows = 0;
+  for (int a = 0; a < nl; ++a) {
+    fp_first[a] = (int32_t)fp_rank.size();
+    for (const Blk& k : own_pairs[a]) {
+      const int s = col_leaf(k.b), r = rank(k.b);
+      fp_off.push_back(fptot);
+      fp_rank.push_back(r);
+      fp_tgt.push_back(s);
+      fp_slot.push_back((int32_t)fprows);
+      fptot += (int64_t)(even_ld(H.leaf_size[a]) + even_ld(H.leaf_size[s])) * r;
+      fprows += H.leaf_size[s];
+    }
+  }
+  const int npair = (int)fp_rank.size();
+  fp_first[nl] = npair;
+  // in-row stacks and far panels of the remaining blocks
+  std::vector<int64_t> hir_off(nl), hir_cols(nl, 0), hf_off(nl);
+  std::vector<int32_t> hir_ld(nl), hir_ncol(nl, 0), hir_row0(nl), hir_soff, hir_n;
+  std::vector<int64_t> gl_cols(nl), hf_col(nl);
+  int64_t irtot = 0, ftot = 0;
   for (int a = 0; a < nl; ++a) {
     const int m = H.leaf_size[a];
+    for (const Blk& k : rest[a]) {
+      hir_cols[a] += rank(k.b);
+      hir_ncol[a] = std::max(hir_ncol[a], H.far[k.b].n);
+      for (int q = 0; q < rank(k.b); ++q) {
+        hir_soff.push_back(H.far[k.b].s_off);
+        hir_n.push_back(H.far[k.b].n);
+      }
+    }
+    hir_row0[a] = (int32_t)(hir_soff.size() - hir_cols[a]);
+    hir_ld[a] = even_ld((int)hir_cols[a]);
+    hir_off[a] = irtot;
+    irtot += (int64_t)hir_ld[a] * hir_ncol[a];
+    gl_cols[a] = (*hs.ncols)[a] - m - h->near_cols[a] - (*hs.ir_cols)[a];
     hf_off[a] = ftot;
-    ftot += (int64_t)even_ld(m) * ((*hs.ncols)[a] - m - h->near_cols[a]);
+    ftot += (int64_t)even_ld(m) * (hir_cols[a] + gl_cols[a]);
+    if ((int64_t)hir_ld[a] * hir_ncol[a] >= ((int64_t)1 << 31) ||
+        (int64_t)even_ld(m) * (hir_cols[a] + gl_cols[a]) >= ((int64_t)1 << 31)) {
+      set_error("a leaf's far data exceeds 2^31 elements");
+      return HM_EINVAL;
+    }
   }
-  std::vector<int64_t> R_col_h(nl);  // src index of each leaf's first far column
+  // src index of far-panel column c of leaf a: global columns keep the
+  // sources of the apply panel's global columns
   {
     int64_t ctot = 0;
     for (int a = 0; a < nl; ++a) {
-      R_col_h[a] = ctot + H.leaf_size[a] + h->near_cols[a];
+      const int64_t far0 = ctot + H.leaf_size[a] + h->near_cols[a];
+      hf_col[a] = far0 + (*hs.ir_cols)[a] - hir_cols[a];
       ctot += (*hs.ncols)[a];
     }
   }
-  bigvec<double2> HF((size_t)std::max<int64_t>(ftot, 1));
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int a = 0; a < nl; ++a) {
-    const int m = H.leaf_size[a];
-    const int64_t ld = even_ld(m);
-    const int64_t c0 = m + h->near_cols[a], nf = (*hs.ncols)[a] - c0;
-    const double2* srcp = hs.R->data() + (*hs.R_off)[a] + c0 * ld;
-    double2* dst = HF.data() + hf_off[a];
-    for (int64_t c = 0; c < nf; ++c) {
-      for (int i = 0; i < m; ++i) dst[i + c * ld] = srcp[i + c * ld];
-      left_chat(Ch[a].data(), m, dst + c * ld);
-    }
-  }
+  if (hir_soff.empty()) { hir_soff.push_back(0); hir_n.push_back(0); }
   // row segments of a source range [s0, s0 + n) by leaf
   auto by_leaf = [&](int64_t s0, int64_t n, double2* w, int64_t inc) {
     for (int s = H.tree.leaf_of[s0]; s < nl && H.leaf_off[s] < s0 + n; ++s)
       right_chatT(Ch[s].data(), H.leaf_size[s], w + (H.leaf_off[s] - s0) * inc, inc);
   };
-  bigvec<double2> IRT(hs.IR->size());
+  bigvec<double2> HF((size_t)std::max<int64_t>(ftot, 1));     // zeroed (pad rows stay 0)
+  bigvec<double2> IRT((size_t)std::max<int64_t>(irtot, 1));
+  bigvec<double2> FP((size_t)std::max<int64_t>(fptot, 1));
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
-    const int64_t ld = (*hs.ir_ld)[a], base = (*hs.ir_off)[a];
-    const int64_t rows = (*hs.ir_cols)[a];
-    const int64_t ncol = h->ir_ncol_h[a];
-    for (int64_t e = 0; e < ld * ncol; ++e) IRT[base + e] = (*hs.IR)[base + e];
-    for (int64_t r = 0; r < rows; ++r) {
-      const int32_t k = (*hs.ir_row0)[a] + (int32_t)r;
-      by_leaf((*hs.ir_soff)[k], (*hs.ir_n)[k], IRT.data() + base + r, ld);
+    const int m = H.leaf_size[a];
+    const int64_t ld = even_ld(m);
+    const int64_t far0 = m + h->near_cols[a];  // first far column of the apply panel
+    const double2* R = hs.R->data() + (*hs.R_off)[a];
+    const double2* IR = hs.IR->data() + (*hs.ir_off)[a];
+    const int64_t irld = (*hs.ir_ld)[a];
+    auto u_col = [&](int64_t src_col, double2* dst) {  // dst = Chat_a R[:, src_col]
+      for (int i = 0; i < m; ++i) dst[i] = R[i + src_col * ld];
+      left_chat(Ch[a].data(), m, dst);
+    };
+    // far panel: [in-row U' of the remaining blocks | global U']
+    double2* F = HF.data() + hf_off[a];
+    int64_t c = 0;
+    int64_t row = 0;
+    double2* S = IRT.data() + hir_off[a];
+    for (const Blk& k : rest[a]) {
+      const FarBlock& fb = H.far[k.b];
+      for (int q = 0; q < rank(k.b); ++q, ++c, ++row) {
+        u_col(far0 + k.ucol + q, F + c * ld);
+        for (int j = 0; j < fb.n; ++j) S[row + j * hir_ld[a]] = IR[k.srow + q + j * irld];
+        by_leaf(fb.s_off, fb.n, S + row, hir_ld[a]);
+      }
     }
+    for (int64_t g = 0; g < gl_cols[a]; ++g, ++c) u_col(far0 + (*hs.ir_cols)[a] + g, F + c * ld);
+    // pairs: U' then W' = Chat_s (row q of the stack)^T
+    for (size_t kk = 0; kk < own_pairs[a].size(); ++kk) {
+      const Blk& k = own_pairs[a][kk];
+      const int p = fp_first[a] + (int)kk;
+      const int s = fp_tgt[p], r = fp_rank[p], ms = H.leaf_size[s];
+      const int64_t lds = even_ld(ms);
+      double2* U = FP.data() + fp_off[p];
+      double2* W = U + ld * r;
+      for (int q = 0; q < r; ++q) {
+        u_col(far0 + k.ucol + q, U + q * ld);
+        for (int j = 0; j < ms; ++j) W[j + q * lds] = IR[k.srow + q + j * irld];
+        left_chat(Ch[s].data(), ms, W + q * lds);
+      }
+    }
+  }
+  // per level: pairs and in-row rows of the far blocks of level >= l, and
+  // the entries one half-storage term reads (near blocks s > t, pairs once,
+  // U' and W' of the other far blocks)
+  h->fp_end.assign(h->nlev, std::vector<int32_t>(nl, 0));
+  h->hir_end.assign(h->nlev, std::vector<int64_t>(nl, 0));
+  for (int li = 0; li < h->nlev; ++li) {
+    int64_t e = 0;
+    for (int a = 0; a < nl; ++a) {
+      const int m = H.leaf_size[a];
+      e += (int64_t)m * h->hp_ncol[a];
+      for (const Blk& k : own_pairs[a]) {
+        if (H.far[k.b].level < lev_of(li)) break;
+        h->fp_end[li][a]++;
+        e += (int64_t)rank(k.b) * (m + H.far[k.b].n);
+      }
+      for (const Blk& k : rest[a]) {
+        if (H.far[k.b].level < lev_of(li)) break;
+        h->hir_end[li][a] += rank(k.b);
+        e += (int64_t)rank(k.b) * (m + H.far[k.b].n);
+      }
+    }
+    for (const FarBlock& fb : H.far)  // global blocks: U' slices and stage-A W'
+      if (fb.level >= lev_of(li) && !(H.leaf_off[H.tree.leaf_of[fb.t_off]] == fb.t_off &&
+                                      H.leaf_size[H.tree.leaf_of[fb.t_off]] == fb.m))
+        e += (int64_t)H.lowrank[fb.src].r * (fb.m + fb.n);
+    h->ent_half[li] = e;
   }
   bigvec<double2> WT(hs.W->size());
   const int ng = (int)hs.groups->size();
@@ -1708,19 +1927,24 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   bigvec<double2>().swap(HF);
   STCHK(upload(h, &h->IRT64, IRT, st));
   bigvec<double2>().swap(IRT);
+  STCHK(upload(h, &h->FP64, FP, st));
+  bigvec<double2>().swap(FP);
   STCHK(upload(h, &h->WT64, WT, st));
   bigvec<double2>().swap(WT);
   STCHK(upload(h, &h->CH, CH, st));
   STCHK(upload(h, &h->CHT, CHT, st));
   if (h->has_f32) {
-    const int64_t n_ir = (int64_t)hs.IR->size(), n_w = (int64_t)hs.W->size();
+    const int64_t n_ir = std::max<int64_t>(irtot, 1), n_w = (int64_t)hs.W->size();
+    const int64_t n_fp = std::max<int64_t>(fptot, 1);
     STCHK(dalloc(h, (void**)&h->H32, sizeof(float2) * std::max<int64_t>(tot, 1)));
     STCHK(dalloc(h, (void**)&h->HF32, sizeof(float2) * std::max<int64_t>(ftot, 1)));
-    STCHK(dalloc(h, (void**)&h->IRT32, sizeof(float2) * std::max<int64_t>(n_ir, 1)));
+    STCHK(dalloc(h, (void**)&h->IRT32, sizeof(float2) * n_ir));
+    STCHK(dalloc(h, (void**)&h->FP32, sizeof(float2) * n_fp));
     STCHK(dalloc(h, (void**)&h->WT32, sizeof(float2) * std::max<int64_t>(n_w, 1)));
     HIPCHK(launch_cast(h->H64, h->H32, tot, st));
     HIPCHK(launch_cast(h->HF64, h->HF32, ftot, st));
     HIPCHK(launch_cast(h->IRT64, h->IRT32, n_ir, st));
+    HIPCHK(launch_cast(h->FP64, h->FP32, n_fp, st));
     HIPCHK(launch_cast(h->WT64, h->WT32, n_w, st));
   }
   hp_off.pop_back();
@@ -1731,17 +1955,37 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   h->vstart_h = vstart;
   h->hp_cols = cols;
   STCHK(upload(h, &h->hf_off, hf_off, st));
-  STCHK(upload(h, &h->hf_col, R_col_h, st));
+  STCHK(upload(h, &h->hf_col, hf_col, st));
   STCHK(upload(h, &h->ch_off, ch_off, st));
+  STCHK(upload(h, &h->hir_off, hir_off, st));
+  STCHK(upload(h, &h->hir_ld, hir_ld, st));
+  STCHK(upload(h, &h->hir_ncol, hir_ncol, st));
+  STCHK(upload(h, &h->hir_row0, hir_row0, st));
+  STCHK(upload(h, &h->hir_soff, hir_soff, st));
+  STCHK(upload(h, &h->hir_n, hir_n, st));
+  h->hir_cols = hir_cols;
+  h->hir_ncol_h = hir_ncol;
+  if (fp_off.empty()) {  // device arrays of at least one entry
+    fp_off.push_back(0);
+    fp_rank.push_back(0);
+    fp_slot.push_back(0);
+  }
+  STCHK(upload(h, &h->fp_off, fp_off, st));
+  STCHK(upload(h, &h->fp_rank, fp_rank, st));
+  STCHK(upload(h, &h->fp_slot, fp_slot, st));
+  fp_rank.resize(npair);
+  fp_slot.resize(npair);
+  h->fp_first_h = fp_first;
+  h->fp_rank_h = fp_rank;
+  h->fp_tgt_h = fp_tgt;
+  h->fp_slot_h = fp_slot;
+  h->fp_rows = fprows;
   STCHK(dalloc(h, (void**)&h->zbuf, sizeof(double2) * h->N));
   STCHK(dalloc(h, (void**)&h->hq, 2 * sizeof(int32_t)));
   HIPCHK(hipMemsetAsync(h->hq, 0, 2 * sizeof(int32_t), st));
-  for (int li = 0; li < h->nlev; ++li) {
-    int64_t e = 0;
-    for (int a = 0; a < nl; ++a)
-      e += (int64_t)H.leaf_size[a] * (h->hp_ncol[a] + h->ir_end[li][a] + h->gl_end[li][a]);
-    h->ent_half[li] = e;
-  }
+  STCHK(dalloc(h, (void**)&h->hdone, sizeof(int32_t) * (nl + 1)));
+  HIPCHK(hipMemsetAsync(h->hdone, 0, sizeof(int32_t) * (nl + 1), st));
+  h->herr = h->hdone + nl;
   h->half_ok = true;
   return HM_OK;
 }
@@ -2011,7 +2255,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   h->gl_end = gl_end;
   {
     const HalfSrc hs{&R, &R_off, &ncols, &IR, &ir_off, &ir_ld, &ir_row0, &ir_soff, &ir_n,
-                     &ir_cols, &W, &gs1.groups};
+                     &ir_cols, &W, &gs1.groups, &inrow};
     STCHK(build_half(h, hs, st));
   }
 
@@ -2557,6 +2801,19 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
   }
+  // a multi-term half-storage launch that gave up a dependency wait (a
+  // list inconsistent with its data; never expected) is reported by the
+  // calls that synchronise
+  auto multi_ok = [&]() -> int {
+    if (!h->herr) return HM_OK;
+    int32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, h->herr, sizeof(e), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (e == 0) return HM_OK;
+    HIPCHK(hipMemsetAsync(h->herr, 0, sizeof(e), st));
+    set_error("multi-term half-storage launch: a dependency wait gave up");
+    return HM_EHIP;
+  };
   if (o->kind == PS_NESTED) {
     STCHK(nested_solve(h, o->level, f32, o->K, (const double2*)b_dev, ldb, (double2*)x_dev, ldx,
                        nrhs, st));
@@ -2577,6 +2834,7 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
     std::vector<double> rr;
     STCHK(gmres_solve(h, li, f32, o->K, m, o->max_passes, o->refine_tol, (const double2*)b_dev,
                       ldb, (double2*)x_dev, ldx, nrhs, it, rr, st));
+    STCHK(multi_ok());
     int status = HM_OK;
     float ms = 0;
     if (per_rhs) {
@@ -2703,6 +2961,7 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
   } else if (refine)
     HIPCHK(launch_permute_out(h->xt, N, h->perm, (double2*)x_dev, ldx, N, nrhs, st));
   int status = HM_OK;
+  if (want) STCHK(multi_ok());
   if (per_rhs) {
     HIPCHK(hipEventRecord(ev1, st));
     HIPCHK(hipEventSynchronize(ev1));
@@ -2753,7 +3012,7 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
     set_error("bad tuning values");
     return HM_EINVAL;
   }
-  if (t->half_storage < -1 || t->half_storage > 2) {
+  if (t->half_storage < -1 || t->half_storage > 3) {
     set_error("bad tuning values");
     return HM_EINVAL;
   }

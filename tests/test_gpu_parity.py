@@ -557,6 +557,58 @@ def test_half_storage_deterministic_and_refine(sphere):
     assert_close(x2, xs, TOL_REFINE)
 
 
+def _term_launches(h, fn):
+    """Series-term launches the handle's profiler counts while fn runs."""
+    lib = hmps._lib()
+    assert lib.hm_profile_enable(h.handle, 1) == 0
+    torch.cuda.synchronize()
+    fn()
+    torch.cuda.synchronize()
+    kt = (hmps.hm_kernel_time * hmps.HM_K_COUNT)()
+    assert lib.hm_profile_read(h.handle, kt) == 0
+    lib.hm_profile_enable(h.handle, 0)
+    return kt[hmps.HM_K_TERM_SERIES].launches
+
+
+def test_half_multi_term_launch_matches_per_term(sphere, ragged_depth):
+    """Where every far block of the level lies between two leaves, the K
+    terms of the scaled series run as one launch whose pieces wait for the
+    leaves they read (half_storage 1); the result equals the one launch per
+    term path (half_storage 3) bit for bit: series of K = 1, 2, 5 terms in
+    FP64 and FP32, and fixed-pass refinement, at every level (levels with
+    other far blocks take the per-term launches either way)."""
+    K_all = (1, 2, 5)
+    for c in (sphere, ragged_depth):
+        b = _dev(c.b)
+        for lev in [-1] + list(reversed(c.H.far_levels)):
+            for prec in (hmps.HM_F64, hmps.HM_F32_APPLY):
+                for K in K_all:
+                    _say(f"multi-term {c.name} level={lev} precision={prec} K={K}")
+                    c.h.tune(half_storage=3)
+                    try:
+                        x3 = _host(c.h.solve(b, K=K, level=lev, precision=prec))
+                    finally:
+                        c.h.tune(half_storage=-1)
+                    x1 = _host(c.h.solve(b, K=K, level=lev, precision=prec))
+                    assert np.array_equal(x1, x3), (c.name, lev, prec, K)
+        kw = dict(K=4, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE_FIXED, max_passes=5)
+        _say(f"multi-term {c.name} fixed refinement")
+        c.h.tune(half_storage=3)
+        try:
+            x3 = _host(c.h.solve(b, **kw))
+        finally:
+            c.h.tune(half_storage=-1)
+        assert np.array_equal(_host(c.h.solve(b, **kw)), x3)
+    # the sphere's leaf level runs its four terms as one launch
+    b = _dev(sphere.b)
+    assert _term_launches(sphere.h, lambda: sphere.h.solve(b, K=4)) == 1
+    sphere.h.tune(half_storage=3)
+    try:
+        assert _term_launches(sphere.h, lambda: sphere.h.solve(b, K=4)) == 4
+    finally:
+        sphere.h.tune(half_storage=-1)
+
+
 def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
     """Leaves of at most 64 rows (one 16-row tile per wave) with 16-RHS
     tiles on the matrix cores: against the oracle at every level, FP64 (4M)
