@@ -364,7 +364,14 @@ def bench_single(a):
         for _ in range(3):
             h.apply(xr, level=wl.level)
         mv_ms = timed(lambda: h.apply(xr, level=wl.level), reps, stream)
-        mv_bytes = 16 * (info["apply_entries"][level] + info["stageA_entries"][level]) + 32 * n
+        if half:
+            # Z x = C (xhat + S xhat) with xhat = C^T x: the entries of S the
+            # half storage reads, the two triangular factors C and C^T, and
+            # the vectors (x, xhat written and read twice, (I + S) xhat
+            # written and read, y)
+            mv_bytes = 16 * (info["half_entries"][level] + info["diag_entries"] + n) + 16 * 7 * n
+        else:
+            mv_bytes = 16 * (info["apply_entries"][level] + info["stageA_entries"][level]) + 32 * n
         extras["hmatvec_1rhs_f64"] = {"ms": mv_ms, "bytes": mv_bytes,
                                       "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
                                       "frac_hbm_peak": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS}

@@ -322,7 +322,9 @@ typedef struct {
                          level lies between two leaves the K terms run as
                          one launch; 3: half storage with one launch per
                          term; 2: the D^{-1}-premultiplied panels.
-                         hmat_apply reads the panels either way */
+                         With 1 or 3, hmat_apply of one right-hand side
+                         on such a problem reads the half storage too,
+                         as Z x = C (I + S) C^T x                          */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);

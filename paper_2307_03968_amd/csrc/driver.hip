@@ -127,6 +127,8 @@ struct hm_matrix {
   float2 *HF32 = nullptr, *IRT32 = nullptr, *WT32 = nullptr;
   int64_t *hf_off = nullptr, *hf_col = nullptr;
   double2 *CH = nullptr, *CHT = nullptr;  // C_a^{-1}, C_a^{-T} panels (ld even m)
+  double2 *CF = nullptr, *CFT = nullptr;  // C_a, C_a^T panels (ld even m)
+  double2* hwork = nullptr;               // half-storage H-matvec: (I + S) C^T x (N)
   int64_t* ch_off = nullptr;
   int64_t* hp_off = nullptr;
   int32_t *hp_col = nullptr, *hsrc = nullptr;
@@ -791,6 +793,12 @@ PanelSet chat_set(const hm_matrix* h, bool transposed) {
                   h->R_col, h->leaf_m};
 }
 
+// Block-diagonal product with the C_a (or C_a^T) panels.
+PanelSet cf_set(const hm_matrix* h, bool transposed) {
+  return PanelSet{transposed ? (const void*)h->CFT : (const void*)h->CF, h->ch_off, h->src,
+                  h->R_col, h->leaf_m};
+}
+
 // One right-hand side through block-diagonal panels: one workgroup per leaf
 // where the leaves fit it, else the term kernel on the D^{-1} work list.
 hipError_t block_launch(const hm_matrix* h, const TermArgs& t, hipStream_t st) {
@@ -1028,6 +1036,38 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
 int apply_core(hm_matrix* h, int li, bool f32, int nrhs, double alpha, double beta,
                const double2* v, double2* out_tree, double2* out, int64_t ldo, hipStream_t st) {
   const int64_t N = h->N, ldin = h->N + h->T;
+  if (use_half(h, li, nrhs)) {
+    // half storage (symmetric problems, one right-hand side): with
+    // D = C C^T and S = C^{-1} R C^{-T}, Z x = C (xhat + S xhat) for
+    // xhat = C^T x, so the product reads S once (near blocks s > t and far
+    // pairs once) plus the two block-diagonal factors
+    TermArgs t0 = term_args(h, cf_set(h, true), h->tl_dinv, false, h->xin0, ldin);
+    t0.yout = h->xin1;  // xhat (tree order, with the t rows of stage A after N)
+    t0.ldy = ldin;
+    HIPCHK(block_launch(h, t0, st));
+    const GroupList& sa1 = h->sa[li];
+    if (sa1.n > 0)
+      TIMED(HM_K_STAGEA, launch_stageA(f32, f32 ? (const void*)h->WT32 : (const void*)h->WT64,
+                                       h->groups, sa1.items, sa1.n, h->xin1, ldin, N, 1, st));
+    HalfArgs ha = half_args(h, li, f32, h->xin1, ldin);
+    ha.t.alpha = 1.0;
+    ha.t.beta = 1.0;
+    ha.t.v = h->xin1;
+    ha.t.ldv = ldin;
+    ha.t.yout = h->hwork;
+    ha.t.ldy = N;
+    TIMED(HM_K_TERM_APPLY, launch_half(f32, h->max_m, ha, h->half[li].tl.nwg, st));
+    TermArgs t1 = term_args(h, cf_set(h, false), h->tl_dinv, false, h->hwork, N);
+    t1.alpha = alpha;
+    t1.beta = beta;
+    t1.v = v;
+    t1.ldv = N;
+    t1.yout = out_tree;
+    t1.ldy = N;
+    if (out) { t1.out = out; t1.ldo = ldo; t1.out_perm = h->perm; }
+    HIPCHK(block_launch(h, t1, st));
+    return HM_OK;
+  }
   const Path P = pick_path(h, f32, nrhs);
   // matrix cores: x into row layout, FP64 or FP32 by the block precision
   double2* r64 = (P.mm && !f32) ? h->xr64_0 : nullptr;
@@ -1527,8 +1567,8 @@ inline double2 cdiv(double2 a, double2 b) {
 }
 
 // D = C C^T for a complex symmetric leaf block D (m x m, column-major)
-// without pivoting (C lower triangular), and Chat = C^{-1} (lower, column-
-// major, ld m).  False, and the handle keeps the pivoted LU's
+// without pivoting (C lower triangular, returned in Cf), and Chat = C^{-1}
+// (lower, column-major, ld m).  False, and the handle keeps the pivoted LU's
 // premultiplied panels, when the factorisation is not backward stable for
 // this block: a pivot not well away from zero relative to the block's
 // diagonal, an entry of C with |C_ij|^2 above kCsymGrowth max|D| (element
@@ -1536,8 +1576,9 @@ inline double2 cdiv(double2 a, double2 b) {
 // entry of C^{-1}.
 constexpr double kCsymGrowth = 1e2;
 constexpr double kCsymBackward = 1e-14;
-bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat) {
-  std::vector<double2> C((size_t)m * m, make_double2(0.0, 0.0));
+bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat, std::vector<double2>& Cf) {
+  std::vector<double2>& C = Cf;
+  C.assign((size_t)m * m, make_double2(0.0, 0.0));
   double dmax = 0.0;
   for (int j = 0; j < m; ++j) dmax = std::max(dmax, std::abs(D[j + (size_t)j * m]));
   if (!(dmax > 0.0)) return false;
@@ -1667,11 +1708,12 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     if (nb.t_leaf < nb.s_leaf) blk[nb.t_leaf].push_back(q);
   }
   // ---- C_a^{-1} per leaf
-  std::vector<std::vector<double2>> Ch(nl);
+  std::vector<std::vector<double2>> Ch(nl), Cf(nl);
   std::vector<char> ok(nl, 1);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a)
-    ok[a] = diag[a] >= 0 && csym_factor(H.near_data.data() + H.near[diag[a]].data, H.leaf_size[a], Ch[a]);
+    ok[a] = diag[a] >= 0 && csym_factor(H.near_data.data() + H.near[diag[a]].data, H.leaf_size[a],
+                                        Ch[a], Cf[a]);
   for (int a = 0; a < nl; ++a)
     if (!ok[a]) return HM_OK;  // not safely factorable: the panels serve
   // ---- half-panel layout
@@ -1910,7 +1952,8 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     ch_off[a] = chtot;
     chtot += (int64_t)even_ld(H.leaf_size[a]) * H.leaf_size[a];
   }
-  bigvec<double2> CH((size_t)chtot), CHT((size_t)chtot);
+  // and C, C^T (the half-storage H-matvec Z x = C (I + S) C^T x)
+  bigvec<double2> CH((size_t)chtot), CHT((size_t)chtot), CF((size_t)chtot), CFT((size_t)chtot);
   for (int a = 0; a < nl; ++a) {
     const int m = H.leaf_size[a];
     const int64_t ld = even_ld(m);
@@ -1918,6 +1961,8 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
       for (int i = 0; i < m; ++i) {
         CH[ch_off[a] + i + j * ld] = Ch[a][i + (size_t)j * m];
         CHT[ch_off[a] + i + j * ld] = Ch[a][j + (size_t)i * m];
+        CF[ch_off[a] + i + j * ld] = Cf[a][i + (size_t)j * m];
+        CFT[ch_off[a] + i + j * ld] = Cf[a][j + (size_t)i * m];
       }
   }
   // ---- upload
@@ -1933,6 +1978,9 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   bigvec<double2>().swap(WT);
   STCHK(upload(h, &h->CH, CH, st));
   STCHK(upload(h, &h->CHT, CHT, st));
+  STCHK(upload(h, &h->CF, CF, st));
+  STCHK(upload(h, &h->CFT, CFT, st));
+  STCHK(dalloc(h, (void**)&h->hwork, sizeof(double2) * h->N));
   if (h->has_f32) {
     const int64_t n_ir = std::max<int64_t>(irtot, 1), n_w = (int64_t)hs.W->size();
     const int64_t n_fp = std::max<int64_t>(fptot, 1);
@@ -3281,10 +3329,10 @@ int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
   const int64_t f32 = h->has_f32 ? 1 : 0;
   const int64_t bytes =
       16 * (P + (P - Dm)) + 32 * Dm + 2 * 16 * Wn + f32 * (8 * (2 * P - Dm) + 2 * 8 * Wn);
-  // half panels, their sources and v slots, the scaled far data and the
-  // C^{-1} / C^{-T} panels
+  // half panels, their sources and v slots, the scaled far data, the
+  // C^{-1}, C^{-T}, C and C^T panels and two N-vectors
   const int64_t half =
-      Hn > 0 ? (16 + 8 * f32) * (Hn + Pf + Wn) + 20 * Hc + 16 * h->N + 32 * Dm : 0;
+      Hn > 0 ? (16 + 8 * f32) * (Hn + Pf + Wn) + 20 * Hc + 32 * h->N + 64 * Dm : 0;
   return bytes + half + workspace_bytes(h, nrhs, T);
 }
 

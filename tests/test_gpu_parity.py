@@ -501,8 +501,9 @@ def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels):
     S = C^{-1} R C^{-T} read once) against the oracle and against the
     premultiplied panels, at every level (levels above the leaf level add
     stage A on the scaled W and the global far columns), FP64 and FP32
-    blocks, and over several workgroup counts.  The H-matvec keeps the
-    panels whatever the setting."""
+    blocks, and over several workgroup counts.  The one-RHS H-matvec on
+    half storage (Z x = C (I + S) C^T x) against the oracle's Z x and the
+    panels' H-matvec."""
     for c in (ragged_depth, sphere_levels):
         b = c.b[:, 0]
         c.h.tune(half_storage=-1)
