@@ -186,12 +186,12 @@ __device__ __forceinline__ void half_tile(const void* __restrict__ P, uint32_t l
 //   sv = U'[:, q]^T y_a,  tv = W'[:, q]^T y_s   (sums over the 16 row lanes)
 //   za += U'[:, q] tv,    zs += W'[:, q] sv,
 // so za gathers S_as y_s = U' W'^T y_s and zs = W' U'^T y_a = S_sa y_a.
-// Two steps are loaded before either is used.  zs is summed over the four
-// column lanes and stored to the pair's partial rows when its pair is done;
-// za stays in registers over the wave's pairs (summed by the caller).
+// Small tiles load two steps before using either.  zs is summed over the
+// four column lanes and stored to the pair's partial rows when its pair is
+// done; za stays in registers over the wave's pairs (summed by the caller).
 // Columns past r re-read column r - 1 and are given sv = tv = 0; rows past
 // a leaf meet y = 0 and their z is never stored.  y_a is read from LDS (ys)
-// and y_s from the wave's own LDS rows yw (16 E RG entries).
+// and y_s from the wave's own LDS rows yw (128 entries per pair, two pairs).
 template <int E, int RG, bool MT>
 __device__ __forceinline__ void far_pairs(const HalfArgs& A, const TermItem& it,
                                           const double2* xin, int lda, int w, int lane,
@@ -206,17 +206,42 @@ __device__ __forceinline__ void far_pairs(const HalfArgs& A, const TermItem& it,
   const int c0 = __builtin_amdgcn_readfirstlane(it.c0);
   const int np = __builtin_amdgcn_readfirstlane(it.c1) - c0;
   const int v0 = __builtin_amdgcn_readfirstlane(it.r0);
-  for (int k = w; k < np; k += kWaves) {
+  static_assert(kMaxVLeaves <= 2 * kWaves, "a wave takes at most two pairs of a piece");
+  static_assert(16 * E * RG <= 128, "the y_s rows of a wave's two pairs fit its 256 LDS entries");
+  // the metadata of every pair of the piece at once (lane k: pair c0 + k),
+  // then the y_s rows of the wave's (at most two) pairs, so that the
+  // latencies of these loads overlap instead of adding up pair by pair
+  int s_l = 0, rk_l = 0, slot_l = 0, ms_l = 0, off_l = 0;
+  int64_t eoff_l = 0;
+  if (lane < np) {
+    s_l = A.vleaf[v0 + lane];
+    rk_l = A.fp_rank[c0 + lane];
+    slot_l = A.fp_slot[c0 + lane];
+    eoff_l = A.fp_off[c0 + lane];
+    ms_l = Tm.ps.leaf_m[s_l];
+    off_l = Tm.leaf_off[s_l];
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int k = w + j * kWaves;
+    if (k < np) {
+      const int ms = __builtin_amdgcn_readlane(ms_l, k);
+      const int offs = __builtin_amdgcn_readlane(off_l, k);
+      for (int row = lane; row < 16 * E * RG; row += 64)
+        yw[128 * j + row] = row < ms ? ld_y<MT>(xin + offs + row) : zero2();
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int k = w, j = 0; k < np; k += kWaves, ++j) {
     const int p = c0 + k;
-    const int s = __builtin_amdgcn_readfirstlane(A.vleaf[v0 + k]);
-    const int rk = __builtin_amdgcn_readfirstlane(A.fp_rank[p]);
-    const int ms = __builtin_amdgcn_readfirstlane(Tm.ps.leaf_m[s]);
+    const int rk = __builtin_amdgcn_readlane(rk_l, k);
+    const int ms = __builtin_amdgcn_readlane(ms_l, k);
     const int lds = ms + (ms & 1);
-    // the wave's y_s rows are rewritten once its previous pair is done
-    __builtin_amdgcn_wave_barrier();
-    const int offs = __builtin_amdgcn_readfirstlane(Tm.leaf_off[s]);
-    const int64_t eoff = A.fp_off[p];
-    const uint64_t pa = reinterpret_cast<uint64_t>(A.fp) + (uint64_t)eoff * kES;
+    const int slot = __builtin_amdgcn_readlane(slot_l, k);
+    const uint32_t elo = __builtin_amdgcn_readlane((uint32_t)eoff_l, k);
+    const uint32_t ehi = __builtin_amdgcn_readlane((uint32_t)((uint64_t)eoff_l >> 32), k);
+    const uint64_t eoff = ((uint64_t)ehi << 32) | elo;
+    const uint64_t pa = reinterpret_cast<uint64_t>(A.fp) + eoff * kES;
     const uint32_t plo = __builtin_amdgcn_readfirstlane((uint32_t)pa);
     const uint32_t phi = __builtin_amdgcn_readfirstlane((uint32_t)(pa >> 32));
     void* pu = reinterpret_cast<void*>(((uint64_t)phi << 32) | plo);
@@ -225,13 +250,12 @@ __device__ __forceinline__ void far_pairs(const HalfArgs& A, const TermItem& it,
         pu, 0, (int)__builtin_amdgcn_readfirstlane(nbytes), 0x00020000);
     const uint32_t wb = (uint32_t)lda * (uint32_t)rk * kES;  // W' after U'
     double2 zs[RG][E];
-    for (int row = lane; row < 16 * E * RG; row += 64)
-      yw[row] = row < ms ? ld_y<MT>(xin + offs + row) : zero2();
 #pragma unroll
     for (int g = 0; g < RG; ++g)
 #pragma unroll
       for (int e = 0; e < E; ++e) zs[g][e] = zero2();
-    const double2* yv = yw + E * r;  // y_s of the lane's rows: yv[16 E g + e]
+    const double2* yw_k = yw + 128 * j;
+    const double2* yv = yw_k + E * r;  // y_s of the lane's rows: yv[16 E g + e]
     for (int q0 = 0; q0 < rk; q0 += 4 * NS) {
       T au[NS][RG], aw[NS][RG];
 #pragma unroll
@@ -280,7 +304,7 @@ __device__ __forceinline__ void far_pairs(const HalfArgs& A, const TermItem& it,
           zs[g][e].y += __shfl_xor(zs[g][e].y, sh);
         }
     if (c == 0) {
-      double2* zp = Tm.partial + A.frow + A.fp_slot[p];
+      double2* zp = Tm.partial + A.frow + slot;
 #pragma unroll
       for (int g = 0; g < RG; ++g)
 #pragma unroll
@@ -432,6 +456,9 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
   __shared__ double2 s_z[4 * 128];
   __shared__ int s_last[kMaxVLeaves + 1];
   __shared__ int s_nlast, s_next, s_reset;
+  __shared__ TermItem s_it;  // the piece about to start, and of its leaf:
+  __shared__ int s_meta[4];  // rows, tree offset, first and end half-panel column
+  __shared__ int64_t s_hpo;  // element offset of the half panel
   // Pieces come from a queue: a workgroup takes the next ticket once its
   // current piece's loads are done (the atomic completes with the piece's
   // stores), so faster workgroups take more pieces, no static split has to
@@ -442,12 +469,35 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
   __syncthreads();
   const int total = MT ? M.K * A.npieces : A.npieces;
   int p = s_next;
+  // A piece's item and its leaf's metadata are loaded into LDS before the
+  // piece starts: the next piece's item along with the current piece's
+  // counter updates, the metadata along with its epilogues.
+  auto item_word = [&](int q) -> int32_t {  // threads 0..7
+    return reinterpret_cast<const int32_t*>(T.items + (MT ? q % A.npieces : q))[threadIdx.x];
+  };
+  auto meta_value = [&](int na) -> int64_t {  // threads 0..4
+    switch (threadIdx.x) {
+      case 0: return T.ps.leaf_m[na];
+      case 1: return T.leaf_off[na];
+      case 2: return A.hp_col[na];
+      case 3: return A.hp_col[na + 1];
+      default: return A.hp_off[na];
+    }
+  };
+  auto put_meta = [&](int64_t v) {
+    if (threadIdx.x < 4) s_meta[threadIdx.x] = (int)v;
+    else s_hpo = v;
+  };
+  if (p < total && threadIdx.x < 8) reinterpret_cast<int32_t*>(&s_it)[threadIdx.x] = item_word(p);
+  __syncthreads();
+  if (p < total && threadIdx.x < 5) put_meta(meta_value(s_it.leaf));
+  __syncthreads();
   while (p < total) {
     const int term = MT ? p / A.npieces + 1 : 1;
-    const TermItem it = T.items[MT ? p - (term - 1) * A.npieces : p];
+    const TermItem it = s_it;
     const double2* xin = MT ? M.y[(term - 1) & 1] : T.xin;
     const int a = it.leaf;
-    const int m = T.ps.leaf_m[a];
+    const int m = s_meta[0];
     const int64_t ld = m + (m & 1);
     const int nc = it.c1 - it.c0;  // at most kHalfChunk for kinds 0 and 2
     if constexpr (MT) {
@@ -459,10 +509,10 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
       }
     }
     if (it.kind == 2 || it.kind == 3) {
-      const int64_t off = T.leaf_off[a];
+      const int64_t off = s_meta[1];
       for (int i = threadIdx.x; i < MR; i += kThreads) ys[i] = i < m ? ld_y<MT>(xin + off + i) : zero2();
       if (it.kind == 2) {
-        const int32_t* __restrict__ hsrc = A.hsrc + A.hp_col[a];
+        const int32_t* __restrict__ hsrc = A.hsrc + s_meta[2];
         for (int k = threadIdx.x; k < nc; k += kThreads) xs[k] = ld_y<MT>(xin + hsrc[it.c0 + k]);
       }
       __syncthreads();
@@ -472,9 +522,8 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
 #pragma unroll
         for (int e = 0; e < E; ++e) u[g][e] = zero2();
       if (it.kind == 2) {
-        const void* HP = Elem<E>::offset(A.hp, A.hp_off[a]);
-        const uint32_t nbytes =
-            (uint32_t)(ld * (A.hp_col[a + 1] - A.hp_col[a]) * (E == 1 ? 16 : 8));
+        const void* HP = Elem<E>::offset(A.hp, s_hpo);
+        const uint32_t nbytes = (uint32_t)(ld * (s_meta[3] - s_meta[2]) * (E == 1 ? 16 : 8));
         half_tile<E, RG, NC>(HP, (uint32_t)ld, nbytes, it.c0, it.c1, w, lane, xs, ys, u, vl);
       } else {
         far_pairs<E, RG, MT>(A, it, xin, (int)ld, w, lane, ys, xs + w * (kHalfChunk / kWaves), u);
@@ -563,8 +612,13 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
     // every store of the piece is complete before it is counted
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) s_nlast = 0;
+    if (threadIdx.x == 0) {
+      s_nlast = 0;
+      s_next = ticket;
+    }
     __syncthreads();
+    const int pn = s_next;
+    const int32_t iw = pn < total && threadIdx.x < 8 ? item_word(pn) : 0;
     const int nv = it.kind >= 2 ? it.r1 - it.r0 : 0;
     if ((int)threadIdx.x <= nv) {
       const int leaf = threadIdx.x == 0 ? a : A.vleaf[it.r0 + threadIdx.x - 1];
@@ -572,12 +626,14 @@ __global__ __launch_bounds__(kThreads) void k_half(HalfArgs A, MultiArgs M) {
                                              __HIP_MEMORY_SCOPE_AGENT);
       if (old == A.lcnt[leaf] - 1) s_last[atomicAdd(&s_nlast, 1)] = leaf;
     }
+    if (pn < total && threadIdx.x < 8) reinterpret_cast<int32_t*>(&s_it)[threadIdx.x] = iw;
     __syncthreads();
+    const int64_t mv = pn < total && threadIdx.x < 5 ? meta_value(s_it.leaf) : 0;
     const int nlast = s_nlast;
     for (int k = 0; k < nlast; ++k) half_epilogue<MT>(A, M, s_last[k], term, s_off, s_z);
-    if (threadIdx.x == 0) s_next = ticket;
+    if (pn < total && threadIdx.x < 5) put_meta(mv);
     __syncthreads();
-    p = s_next;
+    p = pn;
   }
   // the last workgroup out clears the queue (and the done marks) for the
   // next launch: every workgroup has taken its last ticket, and finished
