@@ -9,12 +9,14 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
 
+#include "build_dev.h"
 #include "dev.h"
 #include "hm_internal.h"
 #include "krylov.h"
@@ -1553,130 +1555,71 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   return HM_OK;
 }
 
-// ---- symmetric scaling of the series (host arithmetic on double2)
-inline double2 cm(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-inline void cmacc(double2& acc, double2 a, double2 b) {
-  acc.x += a.x * b.x - a.y * b.y;
-  acc.y += a.x * b.y + a.y * b.x;
-}
-inline double2 cdiv(double2 a, double2 b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
-}
-
-// D = C C^T for a complex symmetric leaf block D (m x m, column-major)
-// without pivoting (C lower triangular, returned in Cf), and Chat = C^{-1}
-// (lower, column-major, ld m).  False, and the handle keeps the pivoted LU's
-// premultiplied panels, when the factorisation is not backward stable for
-// this block: a pivot not well away from zero relative to the block's
-// diagonal, an entry of C with |C_ij|^2 above kCsymGrowth max|D| (element
-// growth), ||C C^T - D||_F above kCsymBackward ||D||_F, or a non-finite
-// entry of C^{-1}.
-constexpr double kCsymGrowth = 1e2;
-constexpr double kCsymBackward = 1e-14;
-bool csym_factor(const cplx* D, int m, std::vector<double2>& Chat, std::vector<double2>& Cf) {
-  std::vector<double2>& C = Cf;
-  C.assign((size_t)m * m, make_double2(0.0, 0.0));
-  double dmax = 0.0;
-  for (int j = 0; j < m; ++j) dmax = std::max(dmax, std::abs(D[j + (size_t)j * m]));
-  if (!(dmax > 0.0)) return false;
-  for (int j = 0; j < m; ++j) {
-    double2 sj = make_double2(D[j + (size_t)j * m].real(), D[j + (size_t)j * m].imag());
-    for (int k = 0; k < j; ++k) {
-      const double2 c = C[j + (size_t)k * m];
-      sj.x -= c.x * c.x - c.y * c.y;
-      sj.y -= 2.0 * c.x * c.y;
-    }
-    const double mag = std::hypot(sj.x, sj.y);
-    if (!(mag > 1e-10 * dmax)) return false;
-    const cplx r = std::sqrt(cplx(sj.x, sj.y));
-    const double2 cjj = make_double2(r.real(), r.imag());
-    C[j + (size_t)j * m] = cjj;
-    for (int i = j + 1; i < m; ++i) {
-      double2 v = make_double2(D[i + (size_t)j * m].real(), D[i + (size_t)j * m].imag());
-      for (int k = 0; k < j; ++k) {
-        const double2 p = cm(C[i + (size_t)k * m], C[j + (size_t)k * m]);
-        v.x -= p.x;
-        v.y -= p.y;
-      }
-      C[i + (size_t)j * m] = cdiv(v, cjj);
-    }
-  }
-  // element growth and backward error of the factorisation
-  double amax = 0.0, cmax = 0.0, dnorm2 = 0.0, rnorm2 = 0.0;
-  for (int j = 0; j < m; ++j)
-    for (int i = 0; i < m; ++i) {
-      const double a = std::abs(D[i + (size_t)j * m]);
-      amax = std::max(amax, a);
-      dnorm2 += a * a;
-      if (i >= j) cmax = std::max(cmax, std::hypot(C[i + (size_t)j * m].x, C[i + (size_t)j * m].y));
-    }
-  if (!(cmax * cmax <= kCsymGrowth * amax)) return false;
-  for (int j = 0; j < m; ++j)
-    for (int i = j; i < m; ++i) {  // (C C^T)_ij = sum_{k <= j} C_ik C_jk, symmetric
-      double2 acc = make_double2(-D[i + (size_t)j * m].real(), -D[i + (size_t)j * m].imag());
-      for (int k = 0; k <= j; ++k) cmacc(acc, C[i + (size_t)k * m], C[j + (size_t)k * m]);
-      rnorm2 += (i == j ? 1.0 : 2.0) * (acc.x * acc.x + acc.y * acc.y);
-    }
-  if (!(rnorm2 <= kCsymBackward * kCsymBackward * dnorm2)) return false;
-  // Chat = C^{-1}, column by column (forward substitution)
-  Chat.assign((size_t)m * m, make_double2(0.0, 0.0));
-  for (int j = 0; j < m; ++j) {
-    double2* x = Chat.data() + (size_t)j * m;
-    x[j] = cdiv(make_double2(1.0, 0.0), C[j + (size_t)j * m]);
-    for (int i = j + 1; i < m; ++i) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int k = j; k < i; ++k) cmacc(acc, C[i + (size_t)k * m], x[k]);
-      x[i] = cdiv(make_double2(-acc.x, -acc.y), C[i + (size_t)i * m]);
-    }
-  }
-  for (double2 v : Chat)
-    if (!std::isfinite(v.x) || !std::isfinite(v.y)) return false;
-  return true;
-}
-
-// x := Chat x for one column of m entries with stride 1 (Chat lower, ld m);
-// in place from the last row up.
-inline void left_chat(const double2* Ch, int m, double2* x) {
-  for (int i = m - 1; i >= 0; --i) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (int l = 0; l <= i; ++l) cmacc(acc, Ch[i + (size_t)l * m], x[l]);
-    x[i] = acc;
-  }
-}
-
-// w := w Chat^T for one row segment of m entries with stride inc; in place
-// from the last entry down.
-inline void right_chatT(const double2* Ch, int m, double2* w, int64_t inc) {
-  for (int j = m - 1; j >= 0; --j) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (int l = 0; l <= j; ++l) cmacc(acc, w[l * inc], Ch[j + (size_t)l * m]);
-    w[j * inc] = acc;
-  }
-}
-
-// Host copies of the far-field device arrays the half-storage data is
-// derived from (built by build_device before upload).
+// Host layout of the far-field device arrays the half-storage data is
+// derived from (the device arrays themselves are on the handle: apply
+// panels R64, in-row stacks IR64, one-RHS stage-A groups W64).
 struct HalfSrc {
-  const bigvec<double2>* R;                  // apply panels
   const std::vector<int64_t>* R_off;
   const std::vector<int64_t>* ncols;
-  const bigvec<double2>* IR;                 // in-row W stacks
   const std::vector<int64_t>* ir_off;
   const std::vector<int32_t>* ir_ld;
-  const std::vector<int32_t>* ir_row0;
-  const std::vector<int32_t>* ir_soff;
-  const std::vector<int32_t>* ir_n;
   const std::vector<int64_t>* ir_cols;
-  const bigvec<double2>* W;                  // one-RHS stage-A groups
   const std::vector<Group>* groups;
   const std::vector<std::vector<int>>* inrow;  // per leaf: in-row far blocks, in order
 };
 
+// A temporary device buffer of the build (freed with the object).
+template <typename T>
+struct DevTmp {
+  T* p = nullptr;
+  DevTmp() = default;
+  DevTmp(const DevTmp&) = delete;
+  DevTmp& operator=(const DevTmp&) = delete;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+  int alloc(size_t n) {
+    if (hipMalloc((void**)&p, sizeof(T) * std::max<size_t>(n, 1)) != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      set_error("hipMalloc of a build buffer failed");
+      return HM_ENOMEM;
+    }
+    return HM_OK;
+  }
+};
+
+// Runs a batch of complex products C = op(A) op(B) (one launch over the
+// items' 64 x 64 output tiles) and waits for it.
+int run_gemms(const double2* A, const double2* B, double2* C, const std::vector<GemmItem>& items,
+              hipStream_t st) {
+  if (items.empty()) return HM_OK;
+  std::vector<GemmTile> tiles;
+  for (int32_t q = 0; q < (int32_t)items.size(); ++q)
+    for (int32_t i0 = 0; i0 < items[q].m; i0 += kGemmTile)
+      for (int32_t j0 = 0; j0 < items[q].n; j0 += kGemmTile) tiles.push_back({q, i0, j0, 0});
+  DevTmp<GemmItem> di;
+  DevTmp<GemmTile> dt;
+  STCHK(di.alloc(items.size()));
+  STCHK(dt.alloc(tiles.size()));
+  HIPCHK(hipMemcpyAsync(di.p, items.data(), sizeof(GemmItem) * items.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dt.p, tiles.data(), sizeof(GemmTile) * tiles.size(), hipMemcpyHostToDevice, st));
+  for (size_t t0 = 0; t0 < tiles.size(); t0 += (size_t)1 << 30)
+    HIPCHK(launch_cgemm(A, B, C, di.p, dt.p + t0,
+                        (int)std::min<size_t>(tiles.size() - t0, (size_t)1 << 30), st));
+  HIPCHK(hipStreamSynchronize(st));  // the item and tile buffers are freed on return
+  return HM_OK;
+}
+
+// Device buffer of the handle, zeroed.
+int dzero(hm_matrix* h, double2** p, int64_t n, hipStream_t st) {
+  STCHK(dalloc(h, (void**)p, sizeof(double2) * std::max<int64_t>(n, 1)));
+  HIPCHK(hipMemsetAsync(*p, 0, sizeof(double2) * std::max<int64_t>(n, 1), st));
+  return HM_OK;
+}
+
 // Half-storage data (symmetric problems only: every instance a surface
-// problem, leaves of at most kHalfMaxLeaf rows).
+// problem, leaves of at most kHalfMaxLeaf rows), computed on the device.
 //
 // Symmetric scaling: each leaf block factors as D_a = C_a C_a^T (complex
 // symmetric, C_a lower triangular, Chat_a = C_a^{-1}).  With yhat = C^T y
@@ -1685,12 +1628,14 @@ struct HalfSrc {
 // x = Chat^T sum_k yhat_k.  So a term is one product with S and no
 // block-diagonal step.  The half panels hold S_ts = Chat_t Z_ts Chat_s^T for
 // the near blocks s > t of row leaf t, side by side (ld = even m_t); the far
-// part of S is U' = Chat_t U (copied from the apply panels' far columns)
-// and W' = W Chat_s^T (the in-row stacks and the one-RHS stage-A groups,
-// row segments per source leaf).  Column j of the half panel of t is row jj
-// of its block's leaf s: it reads yhat[off_s + jj] (hsrc) and its v value
-// goes to vb slot hp_col[t] + j, which the epilogue of s adds (vstart,
-// blocks ordered by t).
+// part of S is U' = Chat_t U (from the apply panels' far columns) and
+// W' = W Chat_s^T (the in-row stacks and the one-RHS stage-A groups, row
+// segments per source leaf).  Column j of the half panel of t is row jj of
+// its block's leaf s: it reads yhat[off_s + jj] (hsrc) and its v value goes
+// to vb slot hp_col[t] + j, which the epilogue of s adds (vstart, blocks
+// ordered by t).  The factors (launch_csym) and every scaled block
+// (launch_cgemm) are formed on the device from the handle's apply panels,
+// in-row stacks and stage-A groups; the host lays out the arrays.
 int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   const HostH& H = h->H;
   const int nl = h->nl;
@@ -1699,34 +1644,66 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   h->hp_bcol.assign(nl, std::vector<int32_t>());
   h->hp_bleaf.assign(nl, std::vector<int32_t>());
   h->ent_half.assign(h->nlev, 0);
-  if (!H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf) return HM_OK;
+  if (!H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf ||
+      h->max_m > kCsymMaxLeaf)
+    return HM_OK;
   std::vector<int> diag(nl, -1);
   std::vector<std::vector<int>> blk(nl);
-  for (int q = 0; q < (int)H.near.size(); ++q) {
-    const NearBlock& nb = H.near[q];
-    if (nb.t_leaf == nb.s_leaf) diag[nb.t_leaf] = q;
-    if (nb.t_leaf < nb.s_leaf) blk[nb.t_leaf].push_back(q);
+  std::vector<std::vector<std::pair<int, int64_t>>> near_col(nl);  // (s, apply-panel column)
+  {
+    std::vector<int64_t> c(nl);
+    for (int a = 0; a < nl; ++a) c[a] = H.leaf_size[a];  // after D
+    for (int q = 0; q < (int)H.near.size(); ++q) {  // H.near is sorted by (t, s)
+      const NearBlock& nb = H.near[q];
+      if (nb.t_leaf == nb.s_leaf) {
+        diag[nb.t_leaf] = q;
+        continue;
+      }
+      if (nb.t_leaf < nb.s_leaf) {
+        blk[nb.t_leaf].push_back(q);
+        near_col[nb.t_leaf].push_back({nb.s_leaf, c[nb.t_leaf]});
+      }
+      c[nb.t_leaf] += H.leaf_size[nb.s_leaf];
+    }
   }
-  // ---- C_a^{-1} per leaf
-  std::vector<std::vector<double2>> Ch(nl), Cf(nl);
-  std::vector<char> ok(nl, 1);
-#pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a)
-    ok[a] = diag[a] >= 0 && csym_factor(H.near_data.data() + H.near[diag[a]].data, H.leaf_size[a],
-                                        Ch[a], Cf[a]);
-  for (int a = 0; a < nl; ++a)
-    if (!ok[a]) return HM_OK;  // not safely factorable: the panels serve
+    if (diag[a] < 0) return HM_OK;
+  const std::vector<int64_t>& R_off = *hs.R_off;
+  // ---- C_a, C_a^T, C_a^{-1}, C_a^{-T} as block-diagonal panels (ld even m)
+  std::vector<int64_t> ch_off(nl);
+  int64_t chtot = 0;
+  for (int a = 0; a < nl; ++a) {
+    ch_off[a] = chtot;
+    chtot += (int64_t)even_ld(H.leaf_size[a]) * H.leaf_size[a];
+  }
+  DevTmp<int64_t> d_choff;
+  DevTmp<int32_t> d_ok;
+  STCHK(d_choff.alloc(nl));
+  STCHK(d_ok.alloc(nl));
+  HIPCHK(hipMemcpyAsync(d_choff.p, ch_off.data(), sizeof(int64_t) * nl, hipMemcpyHostToDevice, st));
+  DevTmp<double2> cf, cft, ch, cht;
+  for (DevTmp<double2>* b : {&cf, &cft, &ch, &cht}) {
+    STCHK(b->alloc(chtot));
+    HIPCHK(hipMemsetAsync(b->p, 0, sizeof(double2) * std::max<int64_t>(chtot, 1), st));
+  }
+  HIPCHK(launch_csym(h->R64, h->R_off, h->leaf_m, nl, h->max_m, cf.p, cft.p, ch.p, cht.p,
+                     d_choff.p, d_ok.p, st));
+  {
+    std::vector<int32_t> ok(nl, 0);
+    HIPCHK(hipMemcpyAsync(ok.data(), d_ok.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int a = 0; a < nl; ++a)
+      if (!ok[a]) return HM_OK;  // not safely factorable: the panels serve
+  }
   // ---- half-panel layout
   std::vector<int64_t> hp_off(nl + 1, 0);
   std::vector<int32_t> hp_col(nl + 1, 0);
   int64_t cols = 0, tot = 0;
   for (int t = 0; t < nl; ++t) {
-    std::sort(blk[t].begin(), blk[t].end(),
-              [&](int x, int y) { return H.near[x].s_leaf < H.near[y].s_leaf; });
     std::vector<int32_t>& bc = h->hp_bcol[t];
     std::vector<int32_t>& bl = h->hp_bleaf[t];
     int64_t c = 0;
-    for (int q : blk[t]) {
+    for (int q : blk[t]) {  // increasing s
       bc.push_back((int32_t)c);
       bl.push_back(H.near[q].s_leaf);
       c += H.leaf_size[H.near[q].s_leaf];
@@ -1758,26 +1735,27 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     vptr[s + 1] = vptr[s] + (int32_t)vs[s].size();
     vstart.insert(vstart.end(), vs[s].begin(), vs[s].end());
   }
-  // ---- half panels S_ts = Chat_t Z_ts Chat_s^T
-  bigvec<double2> HD((size_t)std::max<int64_t>(tot, 1));  // zeroed (pad rows stay 0)
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int t = 0; t < nl; ++t) {
-    const int mt = H.leaf_size[t];
-    const int64_t ld = even_ld(mt);
-    for (size_t b = 0; b < blk[t].size(); ++b) {
-      const NearBlock& nb = H.near[blk[t][b]];
-      const int ms = H.leaf_size[nb.s_leaf];
-      const cplx* z = H.near_data.data() + nb.data;
-      double2* dst = HD.data() + hp_off[t] + (int64_t)h->hp_bcol[t][b] * ld;
-      for (int j = 0; j < ms; ++j) {
-        for (int i = 0; i < mt; ++i) {
-          const cplx v = z[i + (size_t)j * mt];
-          dst[i + j * ld] = make_double2(v.real(), v.imag());
-        }
-        left_chat(Ch[t].data(), mt, dst + j * ld);
+  // ---- half panels S_ts = Chat_t Z_ts Chat_s^T: T = Chat_t Z_ts (Z_ts the
+  // block's columns of the apply panel of t), then S = T Chat_s^T
+  {
+    DevTmp<double2> tmp;
+    STCHK(tmp.alloc(tot));
+    STCHK(dzero(h, &h->H64, tot, st));
+    std::vector<GemmItem> g1, g2;
+    for (int t = 0; t < nl; ++t) {
+      const int mt = H.leaf_size[t];
+      const int32_t ldt = even_ld(mt);
+      for (size_t b = 0; b < near_col[t].size(); ++b) {
+        const int s = near_col[t][b].first;
+        const int ms = H.leaf_size[s];
+        const int64_t c_off = hp_off[t] + (int64_t)h->hp_bcol[t][b] * ldt;
+        g1.push_back({ch_off[t], R_off[t] + near_col[t][b].second * ldt, c_off, ldt, ldt, ldt, mt,
+                      ms, mt, 0, 0});
+        g2.push_back({c_off, ch_off[s], c_off, ldt, even_ld(ms), ldt, mt, ms, ms, 0, 0});
       }
-      for (int i = 0; i < mt; ++i) right_chatT(Ch[nb.s_leaf].data(), ms, dst + i, ld);
     }
+    STCHK(run_gemms(ch.p, h->R64, tmp.p, g1, st));
+    STCHK(run_gemms(tmp.p, cht.p, h->H64, g2, st));
   }
   // ---- far part.  A far block whose row and column clusters are both
   // leaves (t, s) is a pair, stored once by its lower leaf t < s: U' =
@@ -1861,54 +1839,64 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     }
   }
   if (hir_soff.empty()) { hir_soff.push_back(0); hir_n.push_back(0); }
-  // row segments of a source range [s0, s0 + n) by leaf
-  auto by_leaf = [&](int64_t s0, int64_t n, double2* w, int64_t inc) {
-    for (int s = H.tree.leaf_of[s0]; s < nl && H.leaf_off[s] < s0 + n; ++s)
-      right_chatT(Ch[s].data(), H.leaf_size[s], w + (H.leaf_off[s] - s0) * inc, inc);
-  };
-  bigvec<double2> HF((size_t)std::max<int64_t>(ftot, 1));     // zeroed (pad rows stay 0)
-  bigvec<double2> IRT((size_t)std::max<int64_t>(irtot, 1));
-  bigvec<double2> FP((size_t)std::max<int64_t>(fptot, 1));
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int a = 0; a < nl; ++a) {
-    const int m = H.leaf_size[a];
-    const int64_t ld = even_ld(m);
-    const int64_t far0 = m + h->near_cols[a];  // first far column of the apply panel
-    const double2* R = hs.R->data() + (*hs.R_off)[a];
-    const double2* IR = hs.IR->data() + (*hs.ir_off)[a];
-    const int64_t irld = (*hs.ir_ld)[a];
-    auto u_col = [&](int64_t src_col, double2* dst) {  // dst = Chat_a R[:, src_col]
-      for (int i = 0; i < m; ++i) dst[i] = R[i + src_col * ld];
-      left_chat(Ch[a].data(), m, dst);
+  // ---- scaled far data on the device: U' = Chat_a U for the far-panel
+  // columns and the pairs, W' = Chat_s W for the pairs (W the block's rows
+  // of the stack, transposed), W' = W Chat_s^T per source-leaf segment for
+  // the remaining in-row stack rows and the one-RHS stage-A groups
+  STCHK(dzero(h, &h->HF64, ftot, st));
+  STCHK(dzero(h, &h->IRT64, irtot, st));
+  STCHK(dzero(h, &h->FP64, fptot, st));
+  int64_t wtot = 0;
+  for (const Group& G : *hs.groups) wtot = std::max<int64_t>(wtot, G.w_off + (int64_t)G.ld * G.n);
+  STCHK(dzero(h, &h->WT64, wtot, st));
+  {
+    std::vector<GemmItem> uf, up, wp, wi, wg;
+    // segments of a source range [s0, s0 + n) by leaf: (leaf, column in range)
+    auto segs = [&](int64_t s0, int64_t n, const std::function<void(int, int64_t)>& f) {
+      for (int s = H.tree.leaf_of[s0]; s < nl && H.leaf_off[s] < s0 + n; ++s) f(s, H.leaf_off[s] - s0);
     };
-    // far panel: [in-row U' of the remaining blocks | global U']
-    double2* F = HF.data() + hf_off[a];
-    int64_t c = 0;
-    int64_t row = 0;
-    double2* S = IRT.data() + hir_off[a];
-    for (const Blk& k : rest[a]) {
-      const FarBlock& fb = H.far[k.b];
-      for (int q = 0; q < rank(k.b); ++q, ++c, ++row) {
-        u_col(far0 + k.ucol + q, F + c * ld);
-        for (int j = 0; j < fb.n; ++j) S[row + j * hir_ld[a]] = IR[k.srow + q + j * irld];
-        by_leaf(fb.s_off, fb.n, S + row, hir_ld[a]);
+    for (int a = 0; a < nl; ++a) {
+      const int m = H.leaf_size[a];
+      const int32_t ld = even_ld(m);
+      const int64_t far0 = m + h->near_cols[a];  // first far column of the apply panel
+      const int64_t rb = R_off[a] + far0 * ld;
+      const int64_t irb = (*hs.ir_off)[a];
+      const int32_t irld = (*hs.ir_ld)[a];
+      int64_t c = 0;
+      for (const Blk& k : rest[a]) {
+        const FarBlock& fb = H.far[k.b];
+        const int r = rank(k.b);
+        uf.push_back({ch_off[a], rb + k.ucol * ld, hf_off[a] + c * ld, ld, ld, ld, m, r, m, 0, 0});
+        segs(fb.s_off, fb.n, [&](int s, int64_t j0) {
+          const int ms = H.leaf_size[s];
+          wi.push_back({irb + k.srow + j0 * irld, ch_off[s], hir_off[a] + c + j0 * hir_ld[a], irld,
+                        even_ld(ms), hir_ld[a], r, ms, ms, 0, 0});
+        });
+        c += r;
+      }
+      if (gl_cols[a] > 0)
+        uf.push_back({ch_off[a], rb + (*hs.ir_cols)[a] * ld, hf_off[a] + c * ld, ld, ld, ld, m,
+                      (int32_t)gl_cols[a], m, 0, 0});
+      for (size_t kk = 0; kk < own_pairs[a].size(); ++kk) {
+        const Blk& k = own_pairs[a][kk];
+        const int p = fp_first[a] + (int)kk;
+        const int s = fp_tgt[p], r = fp_rank[p], ms = H.leaf_size[s];
+        up.push_back({ch_off[a], rb + k.ucol * ld, fp_off[p], ld, ld, ld, m, r, m, 0, 0});
+        wp.push_back({ch_off[s], irb + k.srow, fp_off[p] + (int64_t)ld * r, even_ld(ms), irld,
+                      even_ld(ms), ms, r, ms, 0, 1});
       }
     }
-    for (int64_t g = 0; g < gl_cols[a]; ++g, ++c) u_col(far0 + (*hs.ir_cols)[a] + g, F + c * ld);
-    // pairs: U' then W' = Chat_s (row q of the stack)^T
-    for (size_t kk = 0; kk < own_pairs[a].size(); ++kk) {
-      const Blk& k = own_pairs[a][kk];
-      const int p = fp_first[a] + (int)kk;
-      const int s = fp_tgt[p], r = fp_rank[p], ms = H.leaf_size[s];
-      const int64_t lds = even_ld(ms);
-      double2* U = FP.data() + fp_off[p];
-      double2* W = U + ld * r;
-      for (int q = 0; q < r; ++q) {
-        u_col(far0 + k.ucol + q, U + q * ld);
-        for (int j = 0; j < ms; ++j) W[j + q * lds] = IR[k.srow + q + j * irld];
-        left_chat(Ch[s].data(), ms, W + q * lds);
-      }
-    }
+    for (const Group& G : *hs.groups)
+      segs(G.s_off, G.n, [&](int s, int64_t j0) {
+        const int ms = H.leaf_size[s];
+        wg.push_back({G.w_off + j0 * G.ld, ch_off[s], G.w_off + j0 * G.ld, G.ld, even_ld(ms), G.ld,
+                      G.ld, ms, ms, 0, 0});
+      });
+    STCHK(run_gemms(ch.p, h->R64, h->HF64, uf, st));
+    STCHK(run_gemms(ch.p, h->R64, h->FP64, up, st));
+    STCHK(run_gemms(ch.p, h->IR64, h->FP64, wp, st));
+    STCHK(run_gemms(h->IR64, cht.p, h->IRT64, wi, st));
+    STCHK(run_gemms(h->W64, cht.p, h->WT64, wg, st));
   }
   // per level: pairs and in-row rows of the far blocks of level >= l, and
   // the entries one half-storage term reads (near blocks s > t, pairs once,
@@ -1937,52 +1925,17 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
         e += (int64_t)H.lowrank[fb.src].r * (fb.m + fb.n);
     h->ent_half[li] = e;
   }
-  bigvec<double2> WT(hs.W->size());
-  const int ng = (int)hs.groups->size();
-#pragma omp parallel for schedule(dynamic, 1)
-  for (int g = 0; g < ng; ++g) {
-    const Group& G = (*hs.groups)[g];
-    for (int64_t e = 0; e < (int64_t)G.ld * G.n; ++e) WT[G.w_off + e] = (*hs.W)[G.w_off + e];
-    for (int r = 0; r < G.ld; ++r) by_leaf(G.s_off, G.n, WT.data() + G.w_off + r, G.ld);
+  // ---- the factor panels move to the handle
+  for (auto pr : {std::make_pair(&ch, &h->CH), std::make_pair(&cht, &h->CHT),
+                  std::make_pair(&cf, &h->CF), std::make_pair(&cft, &h->CFT)}) {
+    *pr.second = pr.first->p;
+    pr.first->p = nullptr;
+    h->allocs.push_back(*pr.second);
+    h->bytes += (int64_t)sizeof(double2) * std::max<int64_t>(chtot, 1);
   }
-  // ---- Chat and Chat^T as block-diagonal panels (ld = even m)
-  std::vector<int64_t> ch_off(nl);
-  int64_t chtot = 0;
-  for (int a = 0; a < nl; ++a) {
-    ch_off[a] = chtot;
-    chtot += (int64_t)even_ld(H.leaf_size[a]) * H.leaf_size[a];
-  }
-  // and C, C^T (the half-storage H-matvec Z x = C (I + S) C^T x)
-  bigvec<double2> CH((size_t)chtot), CHT((size_t)chtot), CF((size_t)chtot), CFT((size_t)chtot);
-  for (int a = 0; a < nl; ++a) {
-    const int m = H.leaf_size[a];
-    const int64_t ld = even_ld(m);
-    for (int j = 0; j < m; ++j)
-      for (int i = 0; i < m; ++i) {
-        CH[ch_off[a] + i + j * ld] = Ch[a][i + (size_t)j * m];
-        CHT[ch_off[a] + i + j * ld] = Ch[a][j + (size_t)i * m];
-        CF[ch_off[a] + i + j * ld] = Cf[a][i + (size_t)j * m];
-        CFT[ch_off[a] + i + j * ld] = Cf[a][j + (size_t)i * m];
-      }
-  }
-  // ---- upload
-  STCHK(upload(h, &h->H64, HD, st));
-  bigvec<double2>().swap(HD);
-  STCHK(upload(h, &h->HF64, HF, st));
-  bigvec<double2>().swap(HF);
-  STCHK(upload(h, &h->IRT64, IRT, st));
-  bigvec<double2>().swap(IRT);
-  STCHK(upload(h, &h->FP64, FP, st));
-  bigvec<double2>().swap(FP);
-  STCHK(upload(h, &h->WT64, WT, st));
-  bigvec<double2>().swap(WT);
-  STCHK(upload(h, &h->CH, CH, st));
-  STCHK(upload(h, &h->CHT, CHT, st));
-  STCHK(upload(h, &h->CF, CF, st));
-  STCHK(upload(h, &h->CFT, CFT, st));
   STCHK(dalloc(h, (void**)&h->hwork, sizeof(double2) * h->N));
   if (h->has_f32) {
-    const int64_t n_ir = std::max<int64_t>(irtot, 1), n_w = (int64_t)hs.W->size();
+    const int64_t n_ir = std::max<int64_t>(irtot, 1), n_w = std::max<int64_t>(wtot, 1);
     const int64_t n_fp = std::max<int64_t>(fptot, 1);
     STCHK(dalloc(h, (void**)&h->H32, sizeof(float2) * std::max<int64_t>(tot, 1)));
     STCHK(dalloc(h, (void**)&h->HF32, sizeof(float2) * std::max<int64_t>(ftot, 1)));
@@ -2301,11 +2254,6 @@ int build_device(hm_matrix* h, hipStream_t st) {
   h->ir_ncol_h = ir_ncol;
   h->ir_end = ir_end;
   h->gl_end = gl_end;
-  {
-    const HalfSrc hs{&R, &R_off, &ncols, &IR, &ir_off, &ir_ld, &ir_row0, &ir_soff, &ir_n,
-                     &ir_cols, &W, &gs1.groups, &inrow};
-    STCHK(build_half(h, hs, st));
-  }
 
   // ---- upload
   std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
@@ -2452,6 +2400,11 @@ int build_device(hm_matrix* h, hipStream_t st) {
     h->n_norm_items = (int)items.size();
     STCHK(upload(h, &h->norm_items, items, st));
     STCHK(upload(h, &h->norm_seg, seg, st));
+  }
+  {
+    // half storage from the uploaded apply panels, stacks and groups
+    const HalfSrc hs{&R_off, &ncols, &ir_off, &ir_ld, &ir_cols, &gs1.groups, &inrow};
+    STCHK(build_half(h, hs, st));
   }
   STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
