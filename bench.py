@@ -119,6 +119,22 @@ def profiled(h, fn, reps):
                   for i, nm in enumerate(names)}
 
 
+def copy_calibration(a):
+    """With --copy-calibration MIB: three device copies of a MIB-MiB buffer
+    (a plain copy kernel of known size that scales the HBM byte counters)."""
+    import torch
+    if a.copy_calibration <= 0:
+        return
+    nbytes = a.copy_calibration << 20
+    src_buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst_buf = torch.empty_like(src_buf)
+    for _ in range(3):
+        dst_buf.copy_(src_buf)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes")
+    del src_buf, dst_buf
+
+
 def latency(fn, reps):
     """Per-request latency: each call issued and waited for on its own."""
     import torch
@@ -302,15 +318,7 @@ def bench_single(a):
     if use_graph:
         wall = wall_graph
     lat = latency(solve, a.steps)
-    if a.copy_calibration > 0:
-        nbytes = a.copy_calibration << 20
-        src_buf = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
-        dst_buf = torch.empty_like(src_buf)
-        for _ in range(3):
-            dst_buf.copy_(src_buf)
-        torch.cuda.synchronize()
-        log(f"copy calibration: 3 copies of {nbytes} bytes")
-        del src_buf, dst_buf
+    copy_calibration(a)
     ms_per_step = wall * 1e3 / a.steps
     x_np = x.cpu().numpy()
     T = info["coeffs"][level]
@@ -588,10 +596,13 @@ def bench_batched(a):
     wall32 = time.perf_counter() - t0
     x32 = out32.t().cpu().numpy()
     lat32 = latency(g32.replay, a.steps)
+    copy_calibration(a)
     # kernel durations from eager solves (same kernels as in the graph)
     _, kernels = profiled(h, lambda: h.solve(b, K=K, precision=F32), 5)
     T = info["coeffs"][level]
-    roof = term_roofline(info, level, n, nrhs, "f32", mm, kernels["term_series"]["avg_us"], T)
+    wname = f"batched_{a.instances}"
+    roof = term_roofline(info, level, n, nrhs, "f32", mm, kernels["term_series"]["avg_us"], T,
+                         wname)
 
     # ---- plain FP64 series on the same handle (same tuning), graph replay
     g64, out64 = graph_of(K=K, precision=F64)
@@ -670,7 +681,7 @@ def bench_batched(a):
                              "solved_RHS_per_s": (tot * a.steps / wall64) if ok("series_f64", 1e-10) else 0.0,
                              "latency_ms": lat64, "kernels": k64,
                              "roofline": term_roofline(info, level, n, nrhs, "f64", mm,
-                                                       k64["term_series"]["avg_us"], T)},
+                                                       k64["term_series"]["avg_us"], T, wname)},
         "refine_f32_graph": {"passes": passes, "ms_per_solve": 1e3 * wallr / rsteps,
                              "rel_err_vs_oracle_xstar_sample": rel["refine_f32_vs_xstar"]},
         "autotune": {"choice": best, "ms": best_ms},
