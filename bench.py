@@ -555,7 +555,9 @@ def bench_batched(a):
     K, nrhs = wls[0].K, wls[0].nrhs
     log(f"library build of {count} instances, total N = {int(sizes.sum())}")
     t0 = time.perf_counter()
-    h = hmps.HMatrix([w.problem for w in wls], 64, 1.0, 1e-4, progress=log)
+    # 16 right-hand sides per instance: the one-RHS half-storage data is not built
+    h = hmps.HMatrix([w.problem for w in wls], 64, 1.0, 1e-4, progress=log,
+                     flags=hmps.HM_BUILD_NO_HALF)
     build_s = time.perf_counter() - t0
     info = h.info()
     n = h.n
@@ -783,8 +785,26 @@ def bench_served(a):
                 time.sleep(min(max(nxt, 0.0), 0.0005) if pending else max(nxt, 0.0))
         return recs, out, time.perf_counter() - t0
 
+    def split(stream, recs, sel):
+        """p50 / p99 (ms) and count of the requests with sel(request, record)."""
+        v = np.array([recs[i]["ms"] for i, rq in enumerate(stream) if sel(rq, recs[i])])
+        if not len(v):
+            return None
+        return {"requests": int(len(v)), "p50": float(np.percentile(v, 50)),
+                "p99": float(np.percentile(v, 99))}
+
     def summary(stream, recs, wall):
         lat = np.array([recs[i]["ms"] for i in range(len(stream))])
+        nof = lambda rq: pool[(rq.kind, rq.geom)].problem.n  # noqa: E731
+        by = {}
+        for kname, kind in (("surface", W.SURFACE), ("volume", W.VOLUME)):
+            by[kname] = split(stream, recs, lambda rq, r: rq.kind == kind)
+            for lo, hi in ((0, 4096), (4096, 16384), (16384, 1 << 30)):
+                by[f"{kname}_N_{lo}_{hi}" if hi < (1 << 30) else f"{kname}_N_above_{lo}"] = split(
+                    stream, recs, lambda rq, r: rq.kind == kind and lo < nof(rq) <= hi)
+        for lo, hi in ((0, 16), (16, 64)):
+            by[f"nrhs_{lo + 1}_{hi}"] = split(stream, recs, lambda rq, r: lo < rq.nrhs <= hi)
+        by["cold_build"] = split(stream, recs, lambda rq, r: bool(r["built"]))
         warm = np.array([recs[i]["ms"] for i in range(len(stream)) if not recs[i]["built"]])
         rhs = sum(rq.nrhs for rq in stream)
         surf_ok = sum(rq.nrhs for i, rq in enumerate(stream)
@@ -804,18 +824,29 @@ def bench_served(a):
                                                      if rq.kind == W.SURFACE and recs[i]["diverged"])),
                 "unconverged_volume_requests": int(sum(1 for i, rq in enumerate(stream)
                                                        if rq.kind == W.VOLUME and recs[i]["diverged"])),
-                "max_gmres_steps": int(max(recs[i]["passes"] for i in range(len(stream))))}
+                "max_gmres_steps": int(max(recs[i]["passes"] for i in range(len(stream)))),
+                "latency_ms_by": by}
 
     results = {}
     srv_info = {}
-    for mixed in (True, False):
-        tag = "mixed" if mixed else "f64"
-        srv = hmps.Server(budget_bytes=a.budget_gb << 30 if a.budget_gb else 0, slots=a.slots)
+    resident_all = 0
+    runs = [("mixed", True), ("f64", False)]
+    if a.evict_frac > 0:
+        runs.append(("mixed_evicting", True))
+    for tag, mixed in runs:
+        budget = a.budget_gb << 30 if a.budget_gb else 0
+        if tag == "mixed_evicting":
+            # a budget below what the pool keeps resident: the timed stream
+            # evicts and rebuilds geometries
+            budget = int(a.evict_frac * resident_all)
+        srv = hmps.Server(budget_bytes=budget, slots=a.slots)
         seen = set()
         log(f"[{tag}] cold pass: one request per geometry")
         cold_stream = [W.Request(0.0, kind, gi, 8) for (kind, gi) in sorted(pool)]
         cold, _, cold_wall = run(srv, cold_stream, mixed, seen)
         log(f"[{tag}] cold pass {cold_wall:.1f} s; {srv.info()}")
+        if tag == "mixed":
+            resident_all = srv.info()["resident_bytes"]
         log(f"[{tag}] closed-loop burst for the saturated rate")
         burst = W.request_stream(a.calib_requests, 1.0, seed=6)
         brec, _, bwall = run(srv, burst, mixed, seen)
@@ -824,9 +855,13 @@ def bench_served(a):
         log(f"[{tag}] saturated {sat:.2f} req/s; open loop at {rate:.2f} req/s")
         stream = W.request_stream(a.requests, rate)
         small = [i for i, rq in enumerate(stream) if pool[(rq.kind, rq.geom)].problem.n <= 6000]
-        keep = set(small[:40]) if mixed else set()
+        keep = set(small[:40]) if tag == "mixed" else set()
+        before = srv.info()
         recs, xs, wall = run(srv, stream, mixed, seen, rate=rate, keep=keep)
+        after = srv.info()
         results[tag] = summary(stream, recs, wall)
+        results[tag]["timed_stream_builds"] = after["builds"] - before["builds"]
+        results[tag]["timed_stream_evictions"] = after["evictions"] - before["evictions"]
         results[tag]["saturated_req_per_s"] = sat
         results[tag]["offered_req_per_s"] = rate
         results[tag]["cold_pass"] = {"wall_s": cold_wall,
@@ -834,7 +869,7 @@ def bench_served(a):
         srv_info[tag] = srv.info()
         results[tag]["server"] = srv_info[tag]
         log(f"[{tag}] {results[tag]}")
-        if mixed:
+        if tag == "mixed":
             mixed_stream, mixed_x, mixed_recs = stream, xs, recs
         srv.close()
 
@@ -900,6 +935,7 @@ def bench_served(a):
         "rel_err_vs_oracle": rel if not a.no_oracle else None,
         "latency_ms": m["latency_ms"], "roofline": None, "cpu_baseline": cpu,
         "extras": {"mixed": results["mixed"], "plain_f64": results["f64"],
+                   "mixed_evicting": results.get("mixed_evicting"),
                    "oracle_checked_requests": checked},
     }
     return out
@@ -918,6 +954,9 @@ def main(argv=None):
                     help="served: closed-loop burst for the saturated rate")
     ap.add_argument("--slots", type=int, default=4, help="served: server workers")
     ap.add_argument("--budget-gb", type=int, default=0, help="served: HBM budget (0: 90%% free)")
+    ap.add_argument("--evict-frac", type=float, default=0.0,
+                    help="served: also serve the mixed stream under a budget of this fraction of "
+                         "the bytes the pool keeps resident (evictions in the timed stream)")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle check and CPU baseline (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",

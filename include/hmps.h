@@ -110,6 +110,11 @@ enum { PS_SERIES = 0, PS_REFINE = 1, PS_REFINE_FIXED = 2, PS_GMRES = 3, PS_NESTE
 #define HM_BUILD_KEEP_HOST 0x4u /* keep the host copy of the blocks after the
                                    upload so that hmat_export works on a
                                    device-built handle */
+#define HM_BUILD_NO_HALF   0x8u /* do not build the half-storage data of a
+                                   symmetric problem (it serves one right-
+                                   hand side: the scaled series and the one-
+                                   RHS H-matvec); saves its device memory and
+                                   build time on handles for many RHS */
 
 /* ---- problem and options -------------------------------------------------- */
 /* Entries of Z (synthetic point-kernel stand-in for the MoM matrix of eq. 5,

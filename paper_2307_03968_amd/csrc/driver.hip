@@ -64,6 +64,7 @@ struct hm_matrix {
   hm::HostH H;
   bool host_only = false;
   bool has_f32 = false;
+  bool want_half = true;  // build the half-storage data where the problem allows it
   bool host_kept = true;
   int device = -1;
   int64_t N = 0, T = 0;
@@ -1644,7 +1645,7 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   h->hp_bcol.assign(nl, std::vector<int32_t>());
   h->hp_bleaf.assign(nl, std::vector<int32_t>());
   h->ent_half.assign(h->nlev, 0);
-  if (!H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf ||
+  if (!h->want_half || !H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf ||
       h->max_m > kCsymMaxLeaf)
     return HM_OK;
   std::vector<int> diag(nl, -1);
@@ -2625,6 +2626,7 @@ static void prepare_fields(hm_matrix* h, const hm_build_opts* opts) {
   h->lmin = h->H.min_far_level;
   h->host_only = (opts->flags & HM_BUILD_HOST_ONLY) != 0;
   h->has_f32 = (opts->flags & HM_BUILD_NO_F32) == 0;
+  h->want_half = (opts->flags & HM_BUILD_NO_HALF) == 0;
 }
 
 static int device_part(hm_matrix* h, const hm_build_opts* opts, void* hip_stream) {
@@ -3103,11 +3105,13 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
     if (nrhs > 16) paths.push_back({1, 32});
     if (nrhs > 32) paths.push_back({1, 64});
   }
-  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct, 2};
-  double bms = INFINITY;
-  // one right-hand side of a symmetric problem: the half-storage product too
-  std::vector<int> halves = {2};
+  // one right-hand side of a symmetric problem: the half-storage product
+  // too; with more right-hand sides the setting does not enter the timed
+  // solves and keeps its value (it serves later one-RHS calls)
+  std::vector<int> halves = {nrhs == 1 ? 2 : h->use_half};
   if (nrhs == 1 && h->half_ok) halves.push_back(1);
+  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct, halves[0]};
+  double bms = INFINITY;
   for (int w : wgs) {
     for (int pct : pcts) {
       if (w != h->term_wgs || pct != h->inrow_pct) {
@@ -3119,7 +3123,7 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
         h->use_half = hs;
         for (const Cand& c : paths) {
           if (pct != 100 && c.mm_min == 1) continue;  // MFMA lists have no in-row rows
-          if (hs == 1 && c.mm_min == 1) continue;     // the half product is one-RHS only
+          if (nrhs == 1 && hs == 1 && c.mm_min == 1) continue;  // the half product is one-RHS only
           h->mm_min_rhs = c.mm_min;
           h->rhs_tile = c.tile;
           double ms = 0;
@@ -3261,7 +3265,7 @@ int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_strea
 int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
   const HostH& H = h->H;
   int64_t P = 0, Dm = 0, Wn = 0, T = 0, Hn = 0, Hc = 0;
-  const bool sym = H.chi_tree.empty();  // half panels are built for symmetric problems
+  const bool sym = H.chi_tree.empty() && h->want_half;  // half panels: symmetric problems
   for (const NearBlock& nb : H.near) {
     const int64_t m = even_ld(H.leaf_size[nb.t_leaf]);
     P += m * H.leaf_size[nb.s_leaf];

@@ -26,7 +26,7 @@ HM_EINVAL, HM_ENOMEM, HM_EHIP, HM_EBUSY, HM_ESTATE = -1, -2, -3, -4, -5
 HM_SURFACE, HM_VOLUME = 0, 1
 HM_F64, HM_F32_APPLY = 0, 1
 PS_SERIES, PS_REFINE, PS_REFINE_FIXED, PS_GMRES, PS_NESTED = 0, 1, 2, 3, 4
-HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST = 0x1, 0x2, 0x4
+HM_BUILD_HOST_ONLY, HM_BUILD_NO_F32, HM_BUILD_KEEP_HOST, HM_BUILD_NO_HALF = 0x1, 0x2, 0x4, 0x8
 HM_MAX_LEVELS = 32
 HM_NOALLOC_SCRATCH_BYTES = 64 << 20
 

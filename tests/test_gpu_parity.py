@@ -556,6 +556,14 @@ def test_half_storage_deterministic_and_refine(sphere):
         sphere.h.tune(half_storage=-1)
     assert_close(x1, xs, TOL_REFINE)
     assert_close(x2, xs, TOL_REFINE)
+    # autotuning for many right-hand sides leaves the one-RHS setting alone
+    _say("autotune nrhs=8 keeps half storage")
+    try:
+        best, _ = sphere.h.autotune(8, K=2)
+        assert best["half_storage"] == 1 and sphere.h.tuning()["half_storage"] == 1
+        assert np.array_equal(_host(sphere.h.solve(b, K=4)), x0)
+    finally:
+        sphere.h.tune(mm_min_rhs=-1, term_wgs=-1, rhs_tile=-1, inrow_pct=-1, half_storage=-1)
 
 
 def _term_launches(h, fn):
@@ -631,6 +639,28 @@ def test_mfma_small_leaves_16rhs_tiles(ragged, cube):
                     assert_close(y, series.apply_Z(c.H, b, lev), 1e-12)
         finally:
             c.h.tune(mm_min_rhs=-1, rhs_tile=-1)
+
+
+def test_build_without_half_storage(sphere):
+    """HM_BUILD_NO_HALF: a surface handle without the half-storage data (for
+    many right-hand sides) takes less device memory and solves one
+    right-hand side on the premultiplied panels, as a handle with the data
+    does when told to use the panels."""
+    _say("build without half storage")
+    h = hmps.HMatrix(sphere.prob, 64, 1.0, 1e-4, flags=hmps.HM_BUILD_NO_HALF)
+    try:
+        assert max(h.info()["half_entries"]) == 0
+        assert h.info()["device_bytes"] < sphere.h.info()["device_bytes"]
+        b = _dev(sphere.b)
+        x = _host(h.solve(b, K=4))
+        assert_close(x, series.series(sphere.H, sphere.b, 4, -1), TOL_F64)
+        sphere.h.tune(half_storage=2)
+        try:
+            assert_close(x, _host(sphere.h.solve(b, K=4)), 1e-13)
+        finally:
+            sphere.h.tune(half_storage=-1)
+    finally:
+        h.close()
 
 
 def test_half_storage_batched_surfaces_one_rhs():
