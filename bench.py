@@ -269,8 +269,10 @@ def bench_single(a):
     mm = nrhs >= h.tuning()["mm_min_rhs"]
     # one right-hand side of a symmetric problem: the scaled series on half
     # storage when the tuning keeps it
-    half = (not mm and nrhs == 1 and not cube and h.tuning()["half_storage"] == 1
-            and info["half_entries"][level] > 0)
+    # one right-hand side runs on half storage where the handle has it
+    # (surface problems, and volume ones through their symmetric part)
+    half1 = h.tuning()["half_storage"] in (1, 3) and info["half_entries"][level] > 0
+    half = half1 and not mm and nrhs == 1
     solve = lambda p=prec: h.solve(b, K=wl.K, level=wl.level, precision=p)  # noqa: E731
 
     for _ in range(a.warmup):
@@ -372,7 +374,7 @@ def bench_single(a):
         for _ in range(3):
             h.apply(xr, level=wl.level)
         mv_ms = timed(lambda: h.apply(xr, level=wl.level), reps, stream)
-        if half:
+        if half1:
             # Z x = C (xhat + S xhat) with xhat = C^T x: the entries of S the
             # half storage reads, the two triangular factors C and C^T, and
             # the vectors (x, xhat written and read twice, (I + S) xhat
@@ -396,7 +398,8 @@ def bench_single(a):
             extras["series_1rhs_f64"] = {
                 "ms_per_solve": ms1, "RHS_per_s": 1e3 / ms1,
                 "roofline": term_roofline(info, level, n, 1, "f64", False,
-                                          k1["term_series"]["avg_us"], T)}
+                                          k1["term_series"]["avg_us"], T, wl.name, half1,
+                                          terms_per_launch(wl.K, reps, k1))}
             if ref is not None:
                 extras["series_1rhs_f64"]["rel_err_vs_oracle_xK"] = series.rel_err(
                     x1.cpu().numpy(), ref[:, :1])
@@ -825,6 +828,10 @@ def bench_served(a):
                 "unconverged_volume_requests": int(sum(1 for i, rq in enumerate(stream)
                                                        if rq.kind == W.VOLUME and recs[i]["diverged"])),
                 "max_gmres_steps": int(max(recs[i]["passes"] for i in range(len(stream)))),
+                "unconverged": [{"kind": "surface" if rq.kind == W.SURFACE else "volume",
+                                 "N": int(nof(rq)), "nrhs": int(rq.nrhs),
+                                 "built": int(recs[i]["built"]), "steps": int(recs[i]["passes"])}
+                                for i, rq in enumerate(stream) if recs[i]["diverged"]][:20],
                 "latency_ms_by": by}
 
     results = {}

@@ -317,9 +317,11 @@ typedef struct {
                          column in the even split of the work (default 100;
                          changing it rebuilds the work lists)              */
   int32_t half_storage; /* 1 (default): the series, refinement and GMRES
-                         of one right-hand side on a symmetric (surface)
-                         problem (below mm_min_rhs) run in the scaled basis
-                         D = C C^T, S = C^{-1} R C^{-T} on half storage:
+                         of one right-hand side (below mm_min_rhs) run in
+                         the scaled basis D = C C^T, S = C^{-1} R C^{-T} on
+                         half storage (a surface problem is symmetric; a
+                         volume problem Z = A diag(chi) runs on its
+                         symmetric A, x = diag(1/chi) x_A):
                          each off-diagonal near block S_ts, s > t, and
                          each far block between two leaves t < s is read
                          once and applied in both orientations

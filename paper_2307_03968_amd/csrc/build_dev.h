@@ -12,7 +12,9 @@ namespace hm {
 
 // Per leaf a (m_a <= kCsymMaxLeaf rows): the diagonal block D_a is the
 // first m_a columns of the leaf's apply panel (column-major, leading
-// dimension even(m_a), at element offset d_off[a] of d).  The kernel
+// dimension even(m_a), at element offset d_off[a] of d), with column k
+// divided by chi[leaf_off[a] + k] when chi is not null (the volume
+// operator's contrasts: D diag(1/chi) is symmetric).  The kernel
 // factors D_a = C_a C_a^T without pivoting (C_a lower triangular, complex
 // symmetric: no conjugation), forms C_a^{-1}, and writes C_a, C_a^T,
 // C_a^{-1} and C_a^{-T} as m_a x m_a panels (leading dimension even(m_a),
@@ -22,9 +24,18 @@ namespace hm {
 // 1e2 max |D_ij| (element growth), ||C C^T - D||_F at most
 // 1e-14 ||D||_F (backward error) and a finite inverse; else 0.
 constexpr int kCsymMaxLeaf = 128;
-hipError_t launch_csym(const double2* d, const int64_t* d_off, const int32_t* leaf_m, int nl,
-                       int max_m, double2* cf, double2* cft, double2* ch, double2* cht,
-                       const int64_t* c_off, int32_t* ok, hipStream_t st);
+hipError_t launch_csym(const double2* d, const int64_t* d_off, const int32_t* leaf_m,
+                       const int32_t* leaf_off, const double* chi, int nl, int max_m, double2* cf,
+                       double2* cft, double2* ch, double2* cht, const int64_t* c_off, int32_t* ok,
+                       hipStream_t st);
+
+// Block-diagonal m_a x m_a panels (leading dimension even(m_a), element
+// offset c_off[a]) scaled by the contrasts of the leaf's points:
+// out = diag(chi)^p in, p = -1 (mode 0), or out = in diag(chi)^p, p = -1
+// (mode 1) or +1 (mode 2).  in and out may be the same panels.
+hipError_t launch_panel_scale(const double2* in, double2* out, const int64_t* c_off,
+                              const int32_t* leaf_m, const int32_t* leaf_off, const double* chi,
+                              int nl, int mode, hipStream_t st);
 
 // One product of a batch: C = op(A) op(B) with complex FP64 column-major
 // operands (op(X) = X, or X^T when the flag is set; no conjugation); C is

@@ -76,7 +76,9 @@ __device__ double wg_sum(double v, double* red) {
 // inverse of the trailing block already in place.
 __global__ __launch_bounds__(kT) void k_csym(const double2* __restrict__ d,
                                              const int64_t* __restrict__ d_off,
-                                             const int32_t* __restrict__ leaf_m, double2* cf,
+                                             const int32_t* __restrict__ leaf_m,
+                                             const int32_t* __restrict__ leaf_off,
+                                             const double* __restrict__ chi, double2* cf,
                                              double2* cft, double2* ch, double2* cht,
                                              const int64_t* __restrict__ c_off, int32_t* ok) {
   extern __shared__ double2 P[];
@@ -89,6 +91,14 @@ __global__ __launch_bounds__(kT) void k_csym(const double2* __restrict__ d,
   const int64_t ld = m + (m & 1);
   const int tid = threadIdx.x;
   const double2* D = d + d_off[a];
+  const double* ch_a = chi ? chi + leaf_off[a] : nullptr;
+  // entry (i, k) of the block to factor: D, or D diag(1/chi)
+  auto dval = [&](int i, int k) {
+    const double2 v = D[i + k * ld];
+    if (!ch_a) return v;
+    const double s = 1.0 / ch_a[k];
+    return make_double2(v.x * s, v.y * s);
+  };
   auto at = [m](int i, int k) { return k * m - (k * (k - 1)) / 2 + (i - k); };
   const int npk = m * (m + 1) / 2;
   // lower triangle of D into LDS; max |D_jj|, max |D_ij| and ||D||_F^2
@@ -97,7 +107,7 @@ __global__ __launch_bounds__(kT) void k_csym(const double2* __restrict__ d,
   for (int e = tid; e < m * m; e += kT) {
     const int i = e % m, k = e / m;
     if (i < k) continue;
-    const double2 v = D[i + k * ld];
+    const double2 v = dval(i, k);
     P[at(i, k)] = v;
     const double av = cabs(v);
     amax = fmax(amax, av);
@@ -153,7 +163,7 @@ __global__ __launch_bounds__(kT) void k_csym(const double2* __restrict__ d,
     int k = 0;
     while (at(m - 1, k) < e) ++k;
     const int i = k + (e - at(k, k));  // entry (i, k) of C C^T, i >= k
-    const double2 dv = D[i + k * ld];
+    const double2 dv = dval(i, k);
     double2 acc = make_double2(-dv.x, -dv.y);
     for (int q = 0; q <= k; ++q) cfma(acc, P[at(i, q)], P[at(k, q)]);
     rn2 += (i == k ? 1.0 : 2.0) * (acc.x * acc.x + acc.y * acc.y);
@@ -251,19 +261,47 @@ __global__ __launch_bounds__(kT) void k_cgemm(const double2* __restrict__ A,
     }
 }
 
+// Contrast scaling of block-diagonal panels (one workgroup per leaf).
+__global__ __launch_bounds__(kT) void k_panel_scale(const double2* in, double2* out,
+                                                    const int64_t* __restrict__ c_off,
+                                                    const int32_t* __restrict__ leaf_m,
+                                                    const int32_t* __restrict__ leaf_off,
+                                                    const double* __restrict__ chi, int mode) {
+  const int a = blockIdx.x;
+  const int m = leaf_m[a];
+  const int64_t ld = m + (m & 1), co = c_off[a];
+  const double* c = chi + leaf_off[a];
+  for (int e = threadIdx.x; e < m * m; e += kT) {
+    const int i = e % m, k = e / m;
+    const double s = mode == 0 ? 1.0 / c[i] : (mode == 1 ? 1.0 / c[k] : c[k]);
+    const double2 v = in[co + i + k * ld];
+    out[co + i + k * ld] = make_double2(v.x * s, v.y * s);
+  }
+}
+
 }  // namespace
 
-hipError_t launch_csym(const double2* d, const int64_t* d_off, const int32_t* leaf_m, int nl,
-                       int max_m, double2* cf, double2* cft, double2* ch, double2* cht,
-                       const int64_t* c_off, int32_t* ok, hipStream_t st) {
+hipError_t launch_panel_scale(const double2* in, double2* out, const int64_t* c_off,
+                              const int32_t* leaf_m, const int32_t* leaf_off, const double* chi,
+                              int nl, int mode, hipStream_t st) {
+  if (nl <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_panel_scale, dim3(nl), dim3(kT), 0, st, in, out, c_off, leaf_m, leaf_off,
+                     chi, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_csym(const double2* d, const int64_t* d_off, const int32_t* leaf_m,
+                       const int32_t* leaf_off, const double* chi, int nl, int max_m, double2* cf,
+                       double2* cft, double2* ch, double2* cht, const int64_t* c_off, int32_t* ok,
+                       hipStream_t st) {
   if (nl <= 0) return hipSuccess;
   if (max_m > kCsymMaxLeaf) return hipErrorInvalidValue;
   const size_t lds = sizeof(double2) * (size_t)max_m * (max_m + 1) / 2;
   hipError_t e = hipFuncSetAttribute((const void*)k_csym,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_csym, dim3(nl), dim3(kT), lds, st, d, d_off, leaf_m, cf, cft, ch, cht,
-                     c_off, ok);
+  hipLaunchKernelGGL(k_csym, dim3(nl), dim3(kT), lds, st, d, d_off, leaf_m, leaf_off, chi, cf, cft,
+                     ch, cht, c_off, ok);
   return hipGetLastError();
 }
 

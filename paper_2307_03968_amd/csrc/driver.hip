@@ -583,7 +583,25 @@ int64_t counter_count(const hm_matrix* h, int nrhs) {
   return (int64_t)h->nl * std::max<int64_t>(nrhs, 4 * ((nrhs + 15) / 16));
 }
 
-int ensure_workspace(hm_matrix* h, int nrhs) {
+__global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// n 32-bit words at p set to zero on stream st: a fill kernel, ordered with
+// the stream's later work (a memset on the null stream is not ordered with
+// a non-blocking stream), and no memset node when the caller captures
+hipError_t zero_words(void* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 1024)), dim3(256),
+                     0, st, (int32_t*)p, n);
+  return hipGetLastError();
+}
+
+// The row-layout and counter workspace for nrhs right-hand sides; the
+// counters and the zero rows are cleared on st, ahead of the solve's work.
+int ensure_workspace(hm_matrix* h, int nrhs, hipStream_t st) {
   if (nrhs <= h->ws_nrhs) return HM_OK;
   for (void* p : h->ws_allocs) (void)hipFree(p);
   h->ws_allocs.clear();
@@ -609,10 +627,10 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   STCHK(al((void**)&h->xr64_1, sizeof(double2) * (ldin + 1) * ldr));
   STCHK(al((void**)&h->xr32_0, sizeof(float2) * (ldin + 1) * ldr));
   STCHK(al((void**)&h->xr32_1, sizeof(float2) * (ldin + 1) * ldr));
-  HIPCHK(hipMemset(h->xr64_0 + ldin * ldr, 0, sizeof(double2) * ldr));
-  HIPCHK(hipMemset(h->xr64_1 + ldin * ldr, 0, sizeof(double2) * ldr));
-  HIPCHK(hipMemset(h->xr32_0 + ldin * ldr, 0, sizeof(float2) * ldr));
-  HIPCHK(hipMemset(h->xr32_1 + ldin * ldr, 0, sizeof(float2) * ldr));
+  HIPCHK(zero_words(h->xr64_0 + ldin * ldr, 4 * ldr, st));
+  HIPCHK(zero_words(h->xr64_1 + ldin * ldr, 4 * ldr, st));
+  HIPCHK(zero_words(h->xr32_0 + ldin * ldr, 2 * ldr, st));
+  HIPCHK(zero_words(h->xr32_1 + ldin * ldr, 2 * ldr, st));
   STCHK(al((void**)&h->xt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->bt, sizeof(double2) * h->N * nrhs));
   STCHK(al((void**)&h->rt, sizeof(double2) * h->N * nrhs));
@@ -621,7 +639,7 @@ int ensure_workspace(hm_matrix* h, int nrhs) {
   STCHK(al((void**)&h->nscratch, sizeof(double) * h->n_norm_items * nrhs * 2));
   STCHK(al((void**)&h->norms, sizeof(double) * h->nseg * nrhs * 2));
   STCHK(al((void**)&h->counters, sizeof(int32_t) * counter_count(h, nrhs)));
-  HIPCHK(hipMemset(h->counters, 0, sizeof(int32_t) * counter_count(h, nrhs)));
+  HIPCHK(zero_words(h->counters, counter_count(h, nrhs), st));
   h->ws_ldr = ldr;
   if (h->norms_host) (void)hipHostFree(h->norms_host);
   h->norms_host = nullptr;
@@ -1619,8 +1637,9 @@ int dzero(hm_matrix* h, double2** p, int64_t n, hipStream_t st) {
   return HM_OK;
 }
 
-// Half-storage data (symmetric problems only: every instance a surface
-// problem, leaves of at most kHalfMaxLeaf rows), computed on the device.
+// Half-storage data (leaves of at most kHalfMaxLeaf rows), computed on the
+// device.  Surface problems are symmetric; a volume problem Z = A diag(chi)
+// runs on its symmetric A (x = diag(1/chi) x_A term by term).
 //
 // Symmetric scaling: each leaf block factors as D_a = C_a C_a^T (complex
 // symmetric, C_a lower triangular, Chat_a = C_a^{-1}).  With yhat = C^T y
@@ -1645,8 +1664,7 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   h->hp_bcol.assign(nl, std::vector<int32_t>());
   h->hp_bleaf.assign(nl, std::vector<int32_t>());
   h->ent_half.assign(h->nlev, 0);
-  if (!h->want_half || !H.chi_tree.empty() || H.near_data.empty() || h->max_m > kHalfMaxLeaf ||
-      h->max_m > kCsymMaxLeaf)
+  if (!h->want_half || H.near_data.empty() || h->max_m > kHalfMaxLeaf || h->max_m > kCsymMaxLeaf)
     return HM_OK;
   std::vector<int> diag(nl, -1);
   std::vector<std::vector<int>> blk(nl);
@@ -1687,8 +1705,19 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     STCHK(b->alloc(chtot));
     HIPCHK(hipMemsetAsync(b->p, 0, sizeof(double2) * std::max<int64_t>(chtot, 1), st));
   }
-  HIPCHK(launch_csym(h->R64, h->R_off, h->leaf_m, nl, h->max_m, cf.p, cft.p, ch.p, cht.p,
-                     d_choff.p, d_ok.p, st));
+  // volume: Z = A diag(chi) with A symmetric (the kernel part G and the
+  // diagonal terms), so the scaled series runs on A: its blocks are the
+  // panels' blocks with column j divided by chi_j (W' folds 1/chi into the
+  // C^{-1} or C^{-T} factor it meets), and x = diag(1/chi) x_A
+  DevTmp<double> d_chi;
+  const bool vol = !H.chi_tree.empty();
+  if (vol) {
+    STCHK(d_chi.alloc(h->N));
+    HIPCHK(hipMemcpyAsync(d_chi.p, H.chi_tree.data(), sizeof(double) * h->N,
+                          hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(launch_csym(h->R64, h->R_off, h->leaf_m, h->leaf_off, d_chi.p, nl, h->max_m, cf.p, cft.p,
+                     ch.p, cht.p, d_choff.p, d_ok.p, st));
   {
     std::vector<int32_t> ok(nl, 0);
     HIPCHK(hipMemcpyAsync(ok.data(), d_ok.p, sizeof(int32_t) * nl, hipMemcpyDeviceToHost, st));
@@ -1696,6 +1725,18 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
     for (int a = 0; a < nl; ++a)
       if (!ok[a]) return HM_OK;  // not safely factorable: the panels serve
   }
+  // volume: C^{-T} with rows divided by chi (every use maps back to the
+  // unknowns x = diag(1/chi) x_A, or meets a column divided by chi in the
+  // scaled blocks), C^{-1} with columns divided by chi (the pairs' W'), and
+  // C^T with columns multiplied by chi (the H-matvec's C^T diag(chi) x)
+  DevTmp<double2> chx;
+  if (vol) {
+    STCHK(chx.alloc(chtot));
+    HIPCHK(launch_panel_scale(cht.p, cht.p, d_choff.p, h->leaf_m, h->leaf_off, d_chi.p, nl, 0, st));
+    HIPCHK(launch_panel_scale(ch.p, chx.p, d_choff.p, h->leaf_m, h->leaf_off, d_chi.p, nl, 1, st));
+    HIPCHK(launch_panel_scale(cft.p, cft.p, d_choff.p, h->leaf_m, h->leaf_off, d_chi.p, nl, 2, st));
+  }
+  const double2* ch_w = vol ? chx.p : ch.p;  // C^{-1} the pairs' W' meet
   // ---- half-panel layout
   std::vector<int64_t> hp_off(nl + 1, 0);
   std::vector<int32_t> hp_col(nl + 1, 0);
@@ -1895,7 +1936,7 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
       });
     STCHK(run_gemms(ch.p, h->R64, h->HF64, uf, st));
     STCHK(run_gemms(ch.p, h->R64, h->FP64, up, st));
-    STCHK(run_gemms(ch.p, h->IR64, h->FP64, wp, st));
+    STCHK(run_gemms(ch_w, h->IR64, h->FP64, wp, st));
     STCHK(run_gemms(h->IR64, cht.p, h->IRT64, wi, st));
     STCHK(run_gemms(h->W64, cht.p, h->WT64, wg, st));
   }
@@ -2499,12 +2540,6 @@ static __device__ __align__(256) unsigned char scratch[HM_NOALLOC_SCRATCH_BYTES]
 namespace hm {
 namespace {
 
-__global__ void k_zero_i32(int32_t* __restrict__ p, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = 0;
-}
-
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 unsigned char* g_scratch[kMaxDevices] = {};
@@ -2739,8 +2774,8 @@ int hmat_apply(hm_matrix_t h, int32_t level, int32_t precision, const void* x_de
   int li = 0;
   STCHK(level_index(h, level, &li));
   HIPCHK(hipSetDevice(h->device));
-  STCHK(ensure_workspace(h, nrhs));
   hipStream_t st = (hipStream_t)hip_stream;
+  STCHK(ensure_workspace(h, nrhs, st));
   const int64_t ldin = h->N + h->T;
   HIPCHK(launch_permute_in((const double2*)x_dev, ldx, h->perm, h->xin0, ldin, h->N, nrhs, st));
   STCHK(apply_core(h, li, f32, nrhs, 1.0, 0.0, nullptr, nullptr, (double2*)y_dev, ldy, st));
@@ -2791,8 +2826,8 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
   int li = 0;
   STCHK(level_index(h, o->level, &li));
   HIPCHK(hipSetDevice(h->device));
-  if (own_ws) STCHK(ensure_workspace(h, nrhs));
   hipStream_t st = (hipStream_t)hip_stream;
+  if (own_ws) STCHK(ensure_workspace(h, nrhs, st));
   const int64_t N = h->N, ldin = h->N + h->T;
   const int ns = h->nseg;
   // host reads of norms happen only with stats or adaptive refinement;
@@ -3202,17 +3237,13 @@ int ps_solve_noalloc(hm_matrix_t h, const ps_opts* o, const void* b_dev, int64_t
   hipStream_t st = (hipStream_t)hip_stream;
   // the split-K counters must start at zero (the array keeps the last call's
   // contents); a fill kernel, not a memset node, so the call stays capturable
-  const int64_t nc = counter_count(h, nrhs);
-  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)std::min<int64_t>((nc + 255) / 256, 1024)),
-                     dim3(256), 0, st, w.counters, nc);
-  HIPCHK(hipGetLastError());
+  HIPCHK(zero_words(w.counters, counter_count(h, nrhs), st));
   // the zero rows of the row-layout vectors (as 32-bit words)
   const int64_t ldin = h->N + h->T;
   for (void* zr : {(void*)(w.xr64_0 + ldin * w.ldr), (void*)(w.xr64_1 + ldin * w.ldr)})
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, (int32_t*)zr, 4 * w.ldr);
+    HIPCHK(zero_words(zr, 4 * w.ldr, st));
   for (void* zr : {(void*)(w.xr32_0 + ldin * w.ldr), (void*)(w.xr32_1 + ldin * w.ldr)})
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(256), 0, st, (int32_t*)zr, 2 * w.ldr);
-  HIPCHK(hipGetLastError());
+    HIPCHK(zero_words(zr, 2 * w.ldr, st));
   WsSwap swap(h, w);
   return ps_solve_impl(h, o, b_dev, ldb, x_dev, ldx, nrhs, nullptr, hip_stream, false);
 }
@@ -3265,7 +3296,7 @@ int build_device_phase(hm_matrix_t h, const hm_build_opts* opts, void* hip_strea
 int64_t device_bytes_estimate(hm_matrix_t h, int nrhs) {
   const HostH& H = h->H;
   int64_t P = 0, Dm = 0, Wn = 0, T = 0, Hn = 0, Hc = 0;
-  const bool sym = H.chi_tree.empty() && h->want_half;  // half panels: symmetric problems
+  const bool sym = h->want_half;  // half panels (surface, and volume on Z diag(1/chi))
   for (const NearBlock& nb : H.near) {
     const int64_t m = even_ld(H.leaf_size[nb.t_leaf]);
     P += m * H.leaf_size[nb.s_leaf];

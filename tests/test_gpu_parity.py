@@ -495,16 +495,17 @@ def test_refine_stops_when_the_series_does_not_contract(cube):
 
 
 # ---------------------------------------------------------------- half storage
-def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels):
-    """Symmetric (surface) problems, one right-hand side: the scaled series
-    on half storage (D = C C^T, each off-diagonal near block of
+def test_half_storage_matches_oracle_and_panels(ragged_depth, sphere_levels, cube):
+    """One right-hand side on half storage: surface problems (symmetric) and
+    a volume problem (through its symmetric part A, Z = A diag(chi)): the
+    scaled series (D = C C^T, each off-diagonal near block of
     S = C^{-1} R C^{-T} read once) against the oracle and against the
     premultiplied panels, at every level (levels above the leaf level add
     stage A on the scaled W and the global far columns), FP64 and FP32
     blocks, and over several workgroup counts.  The one-RHS H-matvec on
     half storage (Z x = C (I + S) C^T x) against the oracle's Z x and the
     panels' H-matvec."""
-    for c in (ragged_depth, sphere_levels):
+    for c in (ragged_depth, sphere_levels, cube):
         b = c.b[:, 0]
         c.h.tune(half_storage=-1)
         assert c.h.tuning()["half_storage"] == 1
@@ -579,7 +580,7 @@ def _term_launches(h, fn):
     return kt[hmps.HM_K_TERM_SERIES].launches
 
 
-def test_half_multi_term_launch_matches_per_term(sphere, ragged_depth):
+def test_half_multi_term_launch_matches_per_term(sphere, ragged_depth, cube):
     """Where every far block of the level lies between two leaves, the K
     terms of the scaled series run as one launch whose pieces wait for the
     leaves they read (half_storage 1); the result equals the one launch per
@@ -587,8 +588,8 @@ def test_half_multi_term_launch_matches_per_term(sphere, ragged_depth):
     FP64 and FP32, and fixed-pass refinement, at every level (levels with
     other far blocks take the per-term launches either way)."""
     K_all = (1, 2, 5)
-    for c in (sphere, ragged_depth):
-        b = _dev(c.b)
+    for c in (sphere, ragged_depth, cube):
+        b = _dev(c.b if c.b.ndim == 1 or c.b.shape[1] == 1 else c.b[:, 0])
         for lev in [-1] + list(reversed(c.H.far_levels)):
             for prec in (hmps.HM_F64, hmps.HM_F32_APPLY):
                 for K in K_all:

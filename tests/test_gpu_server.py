@@ -110,6 +110,61 @@ def test_server_budget_evicts_idle_geometries(oracles):
     srv.close()
 
 
+def test_server_rebuilds_under_load_stay_exact(oracles):
+    """Four workers, a budget for about two of the three geometries and a
+    rotating stream of series and GMRES requests kept four deep: geometries
+    are evicted and rebuilt while other workers solve, and every result
+    still equals the oracle (the series) or x* (GMRES, with the FP32 series
+    preconditioner on the spheres and D^{-1} on the cube)."""
+    probe = hmps.Server(slots=1)
+    seen = set()
+    for key in (1, 2, 3):
+        b = W.plane_waves(GEOMS[key][0].xyz, W.Z_HAT)
+        probe.wait(_submit(probe, key, b, seen, K=0 if key == 2 else 4, kind=hmps.PS_GMRES,
+                           max_passes=300, refine_tol=1e-10))
+    total = probe.info()["resident_bytes"]
+    probe.close()
+    budget = int(0.7 * total)
+    _say(f"server under load: budget {budget} of {total} bytes, four workers")
+    srv = hmps.Server(budget_bytes=budget, slots=4)
+    seen = set()
+    g = np.random.default_rng(5)
+    inflight, checks = [], []
+
+    def drain(n):
+        while len(inflight) > n:
+            t, key, b, gm = inflight.pop(0)
+            x, st = srv.wait(t)
+            if gm:
+                assert all(s["diverged"] == 0 and s["resid_rel"] <= 1e-10 and s["passes"] < 300
+                           for s in st), (key, st)
+                assert_close(x, series.solve_exact(oracles[key], b), 1e-8)
+            else:
+                assert_close(x, series.series(oracles[key], b, 3), 1e-10)
+            checks.append(key)
+
+    for i in range(36):
+        key = (1, 2, 3)[i % 3]
+        p = GEOMS[key][0]
+        b = W.plane_waves(p.xyz, W.directions(int(g.integers(1, 6)), 3, instance=300 + i))
+        gm = i % 2 == 1
+        if gm:
+            kw = dict(K=0, kind=hmps.PS_GMRES) if key == 2 else dict(
+                K=4, kind=hmps.PS_GMRES, precision=hmps.HM_F32_APPLY)
+            t = _submit(srv, key, b, seen, max_passes=300, refine_tol=1e-10, **kw)
+        else:
+            t = _submit(srv, key, b, seen, K=3)
+        inflight.append((t, key, b, gm))
+        drain(4)
+    drain(0)
+    info = srv.info()
+    _say(f"server info {info}")
+    assert len(checks) == 36 and info["requests_failed"] == 0
+    assert info["evictions"] >= 3 and info["builds"] >= 6
+    assert info["resident_bytes"] <= budget
+    srv.close()
+
+
 def test_server_rejects_geometry_over_budget():
     srv = hmps.Server(budget_bytes=1 << 20, slots=1)
     p, leaf, tol = GEOMS[1]
