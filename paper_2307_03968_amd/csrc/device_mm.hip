@@ -309,6 +309,15 @@ __device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it
   }
 }
 
+// Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD
+// b mod 8), each XCD with its own L2.  Workgroup b runs list position
+// (b mod 8) G/8 + b/8, so XCD x runs positions [x G/8, (x + 1) G/8): a
+// contiguous range of the tree order, whose leaves read overlapping input
+// rows from one L2.  The identity when G is not a multiple of 8.
+__device__ __forceinline__ int xcd_order(int b, int G) {
+  return (G & 7) ? b : (b & 7) * (G >> 3) + (b >> 3);
+}
+
 // Persistent term kernel.  WAVE: unit = wave (pieces grouped by wave), the
 // wave takes all rows of its leaves (m <= 16 RT).  Otherwise unit =
 // workgroup, wave w takes rows [16 RT w, 16 RT (w + 1)) of every piece of
@@ -317,7 +326,8 @@ template <bool F32, int RT, int NT, bool WAVE>
 __global__ __launch_bounds__(kThreads) void k_term_mm(TermArgs A, int nrhs, int nunits) {
   const int lane = threadIdx.x & 63;
   const int w = wave_id();
-  const int unit = WAVE ? (int)blockIdx.x * 4 + w : (int)blockIdx.x;
+  const int b = xcd_order((int)blockIdx.x, (int)gridDim.x);
+  const int unit = WAVE ? b * 4 + w : b;
   if (unit >= nunits) return;
   const int rb = WAVE ? 0 : w;
   const int rhs0 = blockIdx.y * 16 * NT;
