@@ -840,6 +840,17 @@ def bench_served(a):
     runs = [("mixed", True), ("f64", False)]
     if a.evict_frac > 0:
         runs.append(("mixed_evicting", True))
+    if a.served_runs:
+        want = a.served_runs.split(",")
+        runs = [r for r in runs if r[0] in want]
+    if any(t == "mixed_evicting" for t, _ in runs) and runs[0][0] != "mixed":
+        # the evicting budget is a fraction of what the pool keeps resident
+        srv = hmps.Server(budget_bytes=a.budget_gb << 30 if a.budget_gb else 0, slots=a.slots)
+        seen = set()
+        run(srv, [W.Request(0.0, kind, gi, 8) for (kind, gi) in sorted(pool)], True, seen)
+        resident_all = srv.info()["resident_bytes"]
+        srv.close()
+        log(f"pool resident bytes {resident_all}")
     for tag, mixed in runs:
         budget = a.budget_gb << 30 if a.budget_gb else 0
         if tag == "mixed_evicting":
@@ -880,6 +891,11 @@ def bench_served(a):
             mixed_stream, mixed_x, mixed_recs = stream, xs, recs
         srv.close()
 
+    if "mixed" not in results:
+        # a partial set of runs (--served-runs): their records only, no value
+        return {"metric": METRIC + " (served stream, GMRES to x*)", "value": None, "unit": "RHS/s",
+                "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+                "config": {"workload": "served", "runs": sorted(results)}, "extras": results}
     # ---- oracle on a sample of the mixed-stream requests (small geometries)
     rel = {"surface_gmres_vs_xstar": 0.0, "volume_gmres_vs_xstar": 0.0}
     cpu = None
@@ -941,7 +957,7 @@ def bench_served(a):
                    "budget_bytes": srv_info["mixed"]["budget_bytes"]},
         "rel_err_vs_oracle": rel if not a.no_oracle else None,
         "latency_ms": m["latency_ms"], "roofline": None, "cpu_baseline": cpu,
-        "extras": {"mixed": results["mixed"], "plain_f64": results["f64"],
+        "extras": {"mixed": results["mixed"], "plain_f64": results.get("f64"),
                    "mixed_evicting": results.get("mixed_evicting"),
                    "oracle_checked_requests": checked},
     }
@@ -964,6 +980,8 @@ def main(argv=None):
     ap.add_argument("--evict-frac", type=float, default=0.0,
                     help="served: also serve the mixed stream under a budget of this fraction of "
                          "the bytes the pool keeps resident (evictions in the timed stream)")
+    ap.add_argument("--served-runs", default="",
+                    help="served: comma list of the runs to make (mixed, f64, mixed_evicting)")
     ap.add_argument("--no-oracle", action="store_true",
                     help="skip the oracle check and CPU baseline (profiling runs)")
     ap.add_argument("--no-extras", action="store_true",

@@ -57,4 +57,34 @@ hipError_t launch_cgemm(const double2* a, const double2* b, double2* c, const Ge
                         const GemmTile* tiles, int n_tiles, hipStream_t st);
 constexpr int kGemmTile = 64;
 
+// Kernel parameters of one instance: kind 0 (surface) or 1 (volume), wave
+// number k and spacing h.
+struct EntryInst {
+  int32_t kind, pad;
+  double k, h;
+};
+// One near block of the entry fill: rows are the points of leaf t, columns
+// the points of leaf s (both in tree order); entry (i, j) goes to
+// out[dst + i + j ld], and rows m_t .. ld - 1 of each column are set to zero.
+struct FillItem {
+  int64_t dst;
+  int32_t ld, t, s, pad;
+};
+// Computes every item's entries from the points (xyz: 3 doubles per point,
+// tree order) with the formulas of the problem (Sec. II's integral
+// equations on the synthetic point kernels): off the diagonal
+// scale e^{-jkR} / (4 pi R), R the distance, scale h^2 (surface) or
+// k^2 h^3 chi_j (volume, chi in tree order); on the diagonal 2h(1 + 0.1j)
+// (surface) or 1/chi_i + 0.5 (volume).  Parameters per leaf through
+// leaf_inst and inst.  *bad is set to 1 (never cleared here) when two
+// distinct points of a block lie closer than 1e-12.
+hipError_t launch_fill_near(const FillItem* items, int n_items, const double* xyz,
+                            const double* chi, const int32_t* leaf_off, const int32_t* leaf_m,
+                            const int32_t* leaf_inst, const EntryInst* inst, double2* out,
+                            int32_t* bad, hipStream_t st);
+// Segments (src_off, dst_off, len), three int64 each: len elements copied
+// from src + src_off to dst + dst_off.
+hipError_t launch_seg_copy(const double2* src, double2* dst, const int64_t* seg, int n_seg,
+                           hipStream_t st);
+
 }  // namespace hm

@@ -279,6 +279,56 @@ __global__ __launch_bounds__(kT) void k_panel_scale(const double2* in, double2* 
   }
 }
 
+// One workgroup per near block; consecutive threads take consecutive rows
+// of a column, so the stores of a wave are contiguous.
+__global__ __launch_bounds__(kT) void k_fill_near(const FillItem* __restrict__ items,
+                                                  const double* __restrict__ xyz,
+                                                  const double* __restrict__ chi,
+                                                  const int32_t* __restrict__ leaf_off,
+                                                  const int32_t* __restrict__ leaf_m,
+                                                  const int32_t* __restrict__ leaf_inst,
+                                                  const EntryInst* __restrict__ inst,
+                                                  double2* __restrict__ out, int32_t* bad) {
+  const FillItem it = items[blockIdx.x];
+  const int m = leaf_m[it.t], n = leaf_m[it.s], ld = it.ld;
+  const int t0 = leaf_off[it.t], s0 = leaf_off[it.s];
+  const EntryInst P = inst[leaf_inst[it.t]];
+  const bool surface = P.kind == 0;
+  const double scale = surface ? P.h * P.h : P.k * P.k * P.h * P.h * P.h;
+  double2* dst = out + it.dst;
+  int close = 0;
+  for (int e = threadIdx.x; e < ld * n; e += kT) {
+    const int j = e / ld, i = e - j * ld;
+    double2 v = cz();
+    if (i < m) {
+      const int gi = t0 + i, gj = s0 + j;
+      if (gi == gj) {
+        v = surface ? make_double2(2.0 * P.h, 0.2 * P.h) : make_double2(1.0 / chi[gi] + 0.5, 0.0);
+      } else {
+        const double dx = xyz[3 * gi] - xyz[3 * gj], dy = xyz[3 * gi + 1] - xyz[3 * gj + 1],
+                     dz = xyz[3 * gi + 2] - xyz[3 * gj + 2];
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < 1e-24) close = 1;
+        const double r = sqrt(r2);
+        double sn, cs;
+        sincos(P.k * r, &sn, &cs);
+        double a = scale / (4.0 * M_PI * r);
+        if (!surface) a *= chi[gj];
+        v = make_double2(a * cs, -a * sn);
+      }
+    }
+    dst[e] = v;
+  }
+  if (close) atomicOr(bad, 1);
+}
+
+__global__ __launch_bounds__(kT) void k_seg_copy(const double2* __restrict__ src,
+                                                 double2* __restrict__ dst,
+                                                 const int64_t* __restrict__ seg) {
+  const int64_t so = seg[3 * blockIdx.x], d0 = seg[3 * blockIdx.x + 1], len = seg[3 * blockIdx.x + 2];
+  for (int64_t e = threadIdx.x; e < len; e += kT) dst[d0 + e] = src[so + e];
+}
+
 }  // namespace
 
 hipError_t launch_panel_scale(const double2* in, double2* out, const int64_t* c_off,
@@ -302,6 +352,23 @@ hipError_t launch_csym(const double2* d, const int64_t* d_off, const int32_t* le
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_csym, dim3(nl), dim3(kT), lds, st, d, d_off, leaf_m, leaf_off, chi, cf, cft,
                      ch, cht, c_off, ok);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_near(const FillItem* items, int n_items, const double* xyz,
+                            const double* chi, const int32_t* leaf_off, const int32_t* leaf_m,
+                            const int32_t* leaf_inst, const EntryInst* inst, double2* out,
+                            int32_t* bad, hipStream_t st) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_near, dim3(n_items), dim3(kT), 0, st, items, xyz, chi, leaf_off, leaf_m,
+                     leaf_inst, inst, out, bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_copy(const double2* src, double2* dst, const int64_t* seg, int n_seg,
+                           hipStream_t st) {
+  if (n_seg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_copy, dim3(n_seg), dim3(kT), 0, st, src, dst, seg);
   return hipGetLastError();
 }
 

@@ -1630,6 +1630,91 @@ int run_gemms(const double2* A, const double2* B, double2* C, const std::vector<
   return HM_OK;
 }
 
+// The apply panels and the LU blocks with the near entries computed on the
+// device: R64 (rtot elements and the zeroed pad) gets the near blocks of
+// every leaf (fills, as the panel assembly listed them) and the packed
+// far-factor columns (upack, leaf a at u_off[a], placed after the leaf's
+// diagonal and near columns); LU (lutot) gets each leaf's diagonal block
+// with leading dimension m_a.  Two distinct points closer than 1e-12 in a
+// near block are refused as on the host.
+int fill_near_device(hm_matrix* h, const std::vector<std::vector<FillItem>>& fills,
+                     const bigvec<double2>& upack, const std::vector<int64_t>& u_off,
+                     const std::vector<int64_t>& near_cols, const std::vector<int64_t>& R_off,
+                     int64_t rtot, const std::vector<int64_t>& LU_off, int64_t lutot,
+                     hipStream_t st) {
+  const HostH& H = h->H;
+  const int nl = (int)H.leaf_size.size();
+  const size_t rbytes = sizeof(double2) * std::max<int64_t>(rtot, 1) + kPanelPad;
+  STCHK(dalloc(h, (void**)&h->R64, rbytes));
+  HIPCHK(hipMemsetAsync(h->R64, 0, rbytes, st));
+  STCHK(dalloc(h, (void**)&h->LU, sizeof(double2) * std::max<int64_t>(lutot, 1)));
+  // far-factor columns: one upload, then one segment per leaf
+  std::vector<int64_t> seg;
+  for (int a = 0; a < nl; ++a) {
+    const int64_t end = a + 1 < nl ? u_off[a + 1] : (int64_t)upack.size();
+    const int64_t ld = even_ld(H.leaf_size[a]);
+    if (end > u_off[a]) {
+      seg.push_back(u_off[a]);
+      seg.push_back(R_off[a] + (H.leaf_size[a] + near_cols[a]) * ld);
+      seg.push_back(end - u_off[a]);
+    }
+  }
+  std::vector<FillItem> items, lu_items;
+  for (int a = 0; a < nl; ++a) {
+    items.insert(items.end(), fills[a].begin(), fills[a].end());
+    lu_items.push_back({LU_off[a], H.leaf_size[a], a, a, 0});
+  }
+  std::vector<EntryInst> inst;
+  for (const EntryParams& e : H.inst) inst.push_back({e.kind, 0, e.k, e.h});
+  std::vector<int32_t> loff(H.leaf_off), lm(H.leaf_size);
+  DevTmp<double2> du;
+  DevTmp<int64_t> dseg;
+  DevTmp<FillItem> ditems, dlu;
+  DevTmp<double> dxyz, dchi;
+  DevTmp<int32_t> dloff, dlm, dli, dbad;
+  DevTmp<EntryInst> dinst;
+  STCHK(du.alloc(upack.size()));
+  STCHK(dseg.alloc(seg.size()));
+  STCHK(ditems.alloc(items.size()));
+  STCHK(dlu.alloc(lu_items.size()));
+  STCHK(dxyz.alloc(H.xyz_tree.size()));
+  STCHK(dchi.alloc(H.chi_tree.size()));
+  STCHK(dloff.alloc(loff.size()));
+  STCHK(dlm.alloc(lm.size()));
+  STCHK(dli.alloc(H.leaf_inst.size()));
+  STCHK(dbad.alloc(1));
+  STCHK(dinst.alloc(inst.size()));
+  auto put = [&](void* d, const void* s_, size_t bytes) {
+    return bytes ? hipMemcpyAsync(d, s_, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+  };
+  HIPCHK(put(du.p, upack.data(), sizeof(double2) * upack.size()));
+  HIPCHK(put(dseg.p, seg.data(), sizeof(int64_t) * seg.size()));
+  HIPCHK(put(ditems.p, items.data(), sizeof(FillItem) * items.size()));
+  HIPCHK(put(dlu.p, lu_items.data(), sizeof(FillItem) * lu_items.size()));
+  HIPCHK(put(dxyz.p, H.xyz_tree.data(), sizeof(double) * H.xyz_tree.size()));
+  HIPCHK(put(dchi.p, H.chi_tree.data(), sizeof(double) * H.chi_tree.size()));
+  HIPCHK(put(dloff.p, loff.data(), sizeof(int32_t) * loff.size()));
+  HIPCHK(put(dlm.p, lm.data(), sizeof(int32_t) * lm.size()));
+  HIPCHK(put(dli.p, H.leaf_inst.data(), sizeof(int32_t) * H.leaf_inst.size()));
+  HIPCHK(put(dinst.p, inst.data(), sizeof(EntryInst) * inst.size()));
+  HIPCHK(hipMemsetAsync(dbad.p, 0, sizeof(int32_t), st));
+  HIPCHK(launch_seg_copy(du.p, h->R64, dseg.p, (int)(seg.size() / 3), st));
+  const double* chi = H.chi_tree.empty() ? nullptr : dchi.p;
+  for (size_t i0 = 0; i0 < items.size(); i0 += (size_t)1 << 30)
+    HIPCHK(launch_fill_near(ditems.p + i0, (int)std::min<size_t>(items.size() - i0, (size_t)1 << 30),
+                            dxyz.p, chi, dloff.p, dlm.p, dli.p, dinst.p, h->R64, dbad.p, st));
+  HIPCHK(launch_fill_near(dlu.p, (int)lu_items.size(), dxyz.p, chi, dloff.p, dlm.p, dli.p, dinst.p,
+                          h->LU, dbad.p, st));
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, dbad.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));  // the temporaries are freed on return
+  if (bad) {
+    set_error("coincident points off the diagonal (R < 1e-12)");
+    return HM_EINVAL;
+  }
+  return HM_OK;
+}
+
 // Device buffer of the handle, zeroed.
 int dzero(hm_matrix* h, double2** p, int64_t n, hipStream_t st) {
   STCHK(dalloc(h, (void**)p, sizeof(double2) * std::max<int64_t>(n, 1)));
@@ -1664,7 +1749,7 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
   h->hp_bcol.assign(nl, std::vector<int32_t>());
   h->hp_bleaf.assign(nl, std::vector<int32_t>());
   h->ent_half.assign(h->nlev, 0);
-  if (!h->want_half || H.near_data.empty() || h->max_m > kHalfMaxLeaf || h->max_m > kCsymMaxLeaf)
+  if (!h->want_half || H.near.empty() || h->max_m > kHalfMaxLeaf || h->max_m > kCsymMaxLeaf)
     return HM_OK;
   std::vector<int> diag(nl, -1);
   std::vector<std::vector<int>> blk(nl);
@@ -2227,26 +2312,40 @@ int build_device(hm_matrix* h, hipStream_t st) {
     piv_off[a] = ptot;
     ptot += m;
   }
-  bigvec<double2> R((size_t)std::max<int64_t>(rtot, 1));  // zeroed (pad rows stay 0)
+  // Near entries computed on the device (the handle keeps no host blocks):
+  // the host packs only the far-factor columns of each panel, contiguous per
+  // leaf (u_off), and lists the near blocks for the device fill.
+  const bool dev_near = H.near_on_device;
+  std::vector<int64_t> u_off(nl, 0);
+  int64_t utot = 0;
+  for (int a = 0; a < nl; ++a) {
+    u_off[a] = utot;
+    utot += (int64_t)even_ld(H.leaf_size[a]) * (ir_cols[a] + gl_cols[a]);
+  }
+  bigvec<double2> R((size_t)std::max<int64_t>(dev_near ? utot : rtot, 1));  // zeroed (pad rows stay 0)
   std::vector<int32_t> src((size_t)std::max<int64_t>(ctot, 1)), src_mm(src.size());
-  bigvec<double2> D((size_t)lutot);
+  bigvec<double2> D((size_t)(dev_near ? 0 : lutot));
+  std::vector<std::vector<FillItem>> fills(nl);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int a = 0; a < nl; ++a) {
     const int m = H.leaf_size[a];
-    const int64_t ld = even_ld(m);
-    double2* P = R.data() + R_off[a];
+    const int64_t ld = even_ld(m), c_u = m + near_cols[a];
+    // column c of the panel (near columns are not packed on the device path)
+    auto col = [&](int64_t c) {
+      return dev_near ? R.data() + u_off[a] + (c - c_u) * ld : R.data() + R_off[a] + c * ld;
+    };
     int32_t* S = src.data() + R_col[a];
     int32_t* S2 = src_mm.data() + R_col[a];
     int64_t c = 0;
     auto put_block = [&](const NearBlock& nb) {
       const int n = H.leaf_size[nb.s_leaf];
-      const cplx* z = H.near_data.data() + nb.data;
+      if (dev_near) fills[a].push_back({R_off[a] + c * ld, (int32_t)ld, a, nb.s_leaf, 0});
       for (int j = 0; j < n; ++j, ++c) {
         S[c] = S2[c] = H.leaf_off[nb.s_leaf] + j;
-        for (int i = 0; i < m; ++i) {
-          const cplx v = z[i + (size_t)j * m];
-          P[i + c * ld] = make_double2(v.real(), v.imag());
-        }
+        if (dev_near) continue;
+        const cplx* z = H.near_data.data() + nb.data + (size_t)j * m;
+        double2* P = col(c);
+        for (int i = 0; i < m; ++i) P[i] = make_double2(z[i].real(), z[i].imag());
       }
     };
     auto put_u = [&](int b, int row_in_block, int32_t src_base) {
@@ -2257,14 +2356,15 @@ int build_device(hm_matrix* h, hipStream_t st) {
       for (int q = 0; q < lr.r; ++q, ++c) {
         S[c] = src_base < 0 ? 0 : (int32_t)(src_base + q);
         S2[c] = src_mm_base + q;
+        double2* P = col(c);
         for (int i = 0; i < m; ++i) {
           const cplx v = U[row_in_block + i + (size_t)q * fb.m];
-          P[i + c * ld] = make_double2(v.real(), v.imag());
+          P[i] = make_double2(v.real(), v.imag());
         }
       }
     };
     put_block(H.near[diag_of[a]]);
-    {
+    if (!dev_near) {
       const cplx* z = H.near_data.data() + H.near[diag_of[a]].data;
       for (int64_t e = 0; e < (int64_t)m * m; ++e) D[LU_off[a] + e] = make_double2(z[e].real(), z[e].imag());
     }
@@ -2302,7 +2402,11 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->perm, H.tree.perm, st));
   STCHK(upload(h, &h->leaf_off, loff, st));
   STCHK(upload(h, &h->leaf_m, lm, st));
-  STCHK(upload(h, &h->R64, R, st, false, kPanelPad));
+  if (dev_near) {
+    STCHK(fill_near_device(h, fills, R, u_off, near_cols, R_off, rtot, LU_off, lutot, st));
+  } else {
+    STCHK(upload(h, &h->R64, R, st, false, kPanelPad));
+  }
   bigvec<double2>().swap(R);
   STCHK(upload(h, &h->src, src, st));
   STCHK(upload(h, &h->R_off, R_off, st));
@@ -2312,7 +2416,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(upload(h, &h->LU_off, LU_off, st));
   STCHK(upload(h, &h->Dinv_off, Dinv_off, st));
   STCHK(upload(h, &h->piv_off, piv_off, st));
-  STCHK(upload(h, &h->LU, D, st));
+  if (!dev_near) STCHK(upload(h, &h->LU, D, st));
   bigvec<double2>().swap(D);
   STCHK(upload(h, &h->W64, W, st));
   bigvec<double2>().swap(W);

@@ -146,6 +146,12 @@ struct NearBlock {
   int64_t data;      // offset into HostH::near_data (column-major m x n)
 };
 
+// Kernel parameters of one instance (the entry formulas of include/hmps.h).
+struct EntryParams {
+  int32_t kind = HM_SURFACE, pad = 0;
+  double k = 0, h = 0;
+};
+
 // Host-side H-matrix in tree order.
 struct HostH {
   Problem prob;
@@ -158,6 +164,10 @@ struct HostH {
   std::vector<LowRank> lowrank;                  // compressed (t before s) blocks
   std::vector<FarBlock> far;                     // both orientations
   std::vector<double> chi_tree;                  // volume: chi in tree order
+  std::vector<double> xyz_tree;                  // points in tree order (3 per point)
+  std::vector<EntryParams> inst;                 // kernel parameters per instance
+  std::vector<int32_t> leaf_inst;                // instance of each leaf
+  bool near_on_device = false;                   // near entries are left to the device build
   int32_t min_far_level = -1;
   int32_t max_leaf = 0;
 };

@@ -35,6 +35,14 @@ int build_host(const Problem& p, const hm_build_opts& o, HostH& H) {
     H.chi_tree.resize(p.n);
     for (int64_t q = 0; q < p.n; ++q) H.chi_tree[q] = p.chi[tr.perm[q]];
   }
+  H.xyz_tree.resize(3 * (size_t)p.n);
+  for (int64_t q = 0; q < p.n; ++q)
+    for (int c = 0; c < 3; ++c) H.xyz_tree[3 * q + c] = p.xyz[3 * tr.perm[q] + c];
+  H.inst.assign(1, EntryParams{p.kind, 0, p.k, p.h});
+  H.leaf_inst.assign(nl, 0);
+  // a handle that keeps no host blocks has its near entries computed by the
+  // device build straight into the panels
+  H.near_on_device = (o.flags & (HM_BUILD_HOST_ONLY | HM_BUILD_KEEP_HOST)) == 0;
 
   std::vector<BlockPair> near, far;
   build_partition(tr, o.eta, near, far);
@@ -50,11 +58,14 @@ int build_host(const Problem& p, const hm_build_opts& o, HostH& H) {
     nb.data = tot;
     tot += (int64_t)H.leaf_size[nb.t_leaf] * H.leaf_size[nb.s_leaf];
   }
-  H.near_data = bigvec<cplx>((size_t)tot);  // zeroed; every block is written below
   std::atomic<int> bad{0};
   const int nthreads = o.num_threads > 0 ? o.num_threads : omp_get_max_threads();
+  // host entries (every block is written below), or none when the device
+  // build computes them (it also rejects coincident points there)
+  const int64_t nfill = H.near_on_device ? 0 : (int64_t)H.near.size();
+  if (nfill) H.near_data = bigvec<cplx>((size_t)tot);
 #pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
-  for (int64_t q = 0; q < (int64_t)H.near.size(); ++q) {
+  for (int64_t q = 0; q < nfill; ++q) {
     const NearBlock& nb = H.near[q];
     const int m = H.leaf_size[nb.t_leaf], n = H.leaf_size[nb.s_leaf];
     const int t0 = H.leaf_off[nb.t_leaf], s0 = H.leaf_off[nb.s_leaf];
@@ -139,6 +150,8 @@ void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst
   for (auto& P : parts) any_volume = any_volume || P.prob.kind == HM_VOLUME;
   inst_off.assign(parts.size() + 1, 0);
   H.prob.kind = parts.empty() ? HM_SURFACE : parts[0].prob.kind;
+  H.near_on_device = !parts.empty();
+  for (auto& P : parts) H.near_on_device = H.near_on_device && P.near_on_device;
   H.tree.depth = kTopLevel;
   H.min_far_level = -1;
   size_t near_total = 0;
@@ -152,10 +165,14 @@ void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst
       H.tree.perm.push_back(P.tree.perm[q] + n);
       H.tree.leaf_of.push_back(P.tree.leaf_of[q] + nleaf);
     }
+    const int32_t ibase = (int32_t)H.inst.size();
     for (size_t a = 0; a < P.leaf_off.size(); ++a) {
       H.leaf_off.push_back((int32_t)(P.leaf_off[a] + n));
       H.leaf_size.push_back(P.leaf_size[a]);
+      H.leaf_inst.push_back(P.leaf_inst[a] + ibase);
     }
+    H.inst.insert(H.inst.end(), P.inst.begin(), P.inst.end());
+    H.xyz_tree.insert(H.xyz_tree.end(), P.xyz_tree.begin(), P.xyz_tree.end());
     for (const NearBlock& b : P.near) H.near.push_back({b.t_leaf + nleaf, b.s_leaf + nleaf, b.data + nd});
     H.near_data.insert(H.near_data.end(), P.near_data.begin(), P.near_data.end());
     for (const FarBlock& f : P.far) {

@@ -122,9 +122,17 @@ int main(int argc, char** argv) {
     o.aca_tol = c.tol;
     o.max_rank = 0;
     o.num_threads = 4;
+    o.flags = HM_BUILD_KEEP_HOST;  // the host computes the near entries
     HostH H;
     CHECK(build_host(c.p, o, H) == HM_OK);
     check(H, c.p.n, c.leaf, (double)c.p.n * (double)c.p.n);
+    CHECK(!H.near_on_device && !H.near_data.empty());
+    // the same build leaving the near entries to the device
+    o.flags = 0;
+    HostH Hd;
+    CHECK(build_host(c.p, o, Hd) == HM_OK);
+    CHECK(Hd.near_on_device && Hd.near_data.empty() && Hd.near.size() == H.near.size());
+    CHECK((int64_t)Hd.xyz_tree.size() == 3 * c.p.n && Hd.leaf_inst.size() == Hd.leaf_size.size());
     std::printf("built n=%lld leaf=%d: %zu near, %zu far blocks\n", (long long)c.p.n, c.leaf,
                 H.near.size(), H.far.size());
     parts.push_back(std::move(H));

@@ -234,6 +234,34 @@ def test_export_lu_factors_reconstruct_diagonal(tmp_path):
         assert np.linalg.norm(L @ U - A) <= 1e-13 * np.linalg.norm(D)
 
 
+def test_device_entry_fill_matches_host_fill():
+    """Near entries computed on the device (the default build) give the
+    operator of the host's entries (HM_BUILD_KEEP_HOST): H-matvec and series
+    agree to rounding on a surface, a volume and a batched (surface + volume)
+    handle; the device fill refuses coincident points as the host does."""
+    cases = [("sphere_1200", W.sphere_problem(1200, math.sqrt(1200 / 1536)), 1e-6),
+             ("cube_1000", W.cube_problem(10, 10 / 16), 1e-5),
+             ("batched", [W.sphere_problem(700, math.sqrt(700 / 1536), instance=3),
+                          W.cube_problem(8, 8 / 16, instance=2)], 1e-5)]
+    for name, prob, tol in cases:
+        _say(f"device vs host entry fill: {name}")
+        parts = prob if isinstance(prob, list) else [prob]
+        b = np.vstack([W.plane_waves(p.xyz, W.directions(3, 3, instance=40 + i))
+                       for i, p in enumerate(parts)])
+        hd = hmps.HMatrix(prob, 32, 1.0, tol)
+        hh = hmps.HMatrix(prob, 32, 1.0, tol, flags=hmps.HM_BUILD_KEEP_HOST)
+        assert_close(_host(hd.apply(_dev(b))), _host(hh.apply(_dev(b))), 1e-14, name)
+        assert_close(_host(hd.solve(_dev(b), K=3)), _host(hh.solve(_dev(b), K=3)), 1e-13, name)
+        hd.close()
+        hh.close()
+    p = W.sphere_problem(300, 0.5)
+    p.xyz[5] = p.xyz[6]
+    _say("device entry fill: coincident points")
+    with pytest.raises(hmps.HmpsError) as e:
+        hmps.HMatrix(p, 40)
+    assert e.value.status == hmps.HM_EINVAL
+
+
 @pytest.mark.timeout(900)
 def test_full_size_sphere_24576():
     """The 24,576-point sphere (leaf <= 128, tol 1e-4, K = 4) at the leaf
