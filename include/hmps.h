@@ -396,6 +396,9 @@ typedef struct {
   int64_t batches, batch_rhs;        /* solves issued and their columns     */
   int64_t requests_submitted, requests_done, requests_failed, rhs_done;
   int64_t queued;
+  int64_t split_batches;             /* batches solved in pieces of the
+                                        existing workspace's width (no room
+                                        for a wider one)                   */
 } ps_server_stats;
 int ps_server_create(size_t hbm_budget_bytes, int32_t max_slots, hm_server_t* out);
 int ps_submit(hm_server_t s, uint64_t geom_key, const hm_problem* prob,

@@ -82,6 +82,46 @@ hipError_t launch_fill_near(const FillItem* items, int n_items, const double* xy
                             const double* chi, const int32_t* leaf_off, const int32_t* leaf_m,
                             const int32_t* leaf_inst, const EntryInst* inst, double2* out,
                             int32_t* bad, hipStream_t st);
+// One far block for the device compression (adaptive cross approximation
+// with partial pivoting, then recompression; Sec. III): rows are the points
+// t_off .. t_off + m - 1, columns s_off .. s_off + n - 1 (tree order), kernel
+// part only (e^{-jkR} / (4 pi R) times h^2 or k^2 h^3; no contrast).
+// Scratch (double2, offsets from the launch's base): U at u_off (m x rcap),
+// V at v_off (n x rcap), four rcap x rcap matrices at w_off, and the output
+// U' (m x rcap) then V' (n x rcap) at o_off.
+struct AcaItem {
+  int32_t t_off, m, s_off, n;
+  int32_t inst, r_max, rcap, pad;
+  int64_t u_off, v_off, w_off, o_off;
+};
+// k: rank of the cross approximation (0: no pivot above 1e-300 anywhere);
+// rank: after recompression; status 1 when k reached rcap below r_max
+// without meeting the stopping test (the block needs more columns).
+struct AcaOut {
+  int32_t k, rank, status, pad;
+};
+constexpr int kAcaMaxCols = 128;  // rcap limit of the device compression
+// Cross approximation of every item (one workgroup each), rules:
+//   start at row 0; residual row = A[i,:] - sum_l u_l[i] v_l;
+//   if max|row| <= 1e-300 mark row i used and take the next unused row in
+//   index order (stop when none is left);
+//   pivot j = first index of max|row|; v = row / row[j];
+//   u = A[:,j] - sum_l v_l[j] u_l;
+//   ||S||_F^2 of S = sum_l u_l v_l^T updated with 2 Re(sum_l (u_l^H u)(v_l^H v))
+//   + (||u|| ||v||)^2; stop after the step where ||u|| ||v|| <= eps ||S||_F
+//   or the rank reaches r_max; next row = first index of max|u| over unused
+//   rows.  max_m: largest m of the launch (its row marks live in LDS).
+hipError_t launch_aca(const AcaItem* items, int n_items, int max_m, const double* xyz,
+                      const EntryInst* inst, double eps, double2* ws, AcaOut* out,
+                      hipStream_t st);
+// Recompression of every item with status 0 and k >= 1: U = Qu Ru and
+// V = Qv Rv (Gram-Schmidt with one reorthogonalisation), Ru Rv^T = Phi S Psi^H
+// by one-sided Jacobi, and the smallest rank >= 1 whose discarded singular
+// values have 2-norm <= eps times the 2-norm of all of them;
+// U' = Qu Phi_r S_r and V' = Qv conj(Psi_r) written at o_off; rank set.
+hipError_t launch_recompress(const AcaItem* items, int n_items, double eps, double2* ws,
+                             AcaOut* out, hipStream_t st);
+
 // Segments (src_off, dst_off, len), three int64 each: len elements copied
 // from src + src_off to dst + dst_off.
 hipError_t launch_seg_copy(const double2* src, double2* dst, const int64_t* seg, int n_seg,

@@ -13,6 +13,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -1715,6 +1716,130 @@ int fill_near_device(hm_matrix* h, const std::vector<std::vector<FillItem>>& fil
   return HM_OK;
 }
 
+// Compression of the far blocks the host build left to the device
+// (H.aca): cross approximation and recompression on the GPU in chunks of at
+// most kAcaChunkBytes of scratch, first with 32 columns per block, then with
+// kAcaMaxCols for the blocks that needed more; a block still short of
+// columns is compressed on the host by the same rules.
+constexpr int64_t kAcaChunkBytes = (int64_t)512 << 20;
+
+int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
+  if (!H.aca_pending) return HM_OK;
+  const int nb = (int)H.aca.size();
+  std::vector<EntryInst> inst;
+  for (const EntryParams& e : H.inst) inst.push_back({e.kind, 0, e.k, e.h});
+  DevTmp<double> dxyz;
+  DevTmp<EntryInst> dinst;
+  STCHK(dxyz.alloc(H.xyz_tree.size()));
+  STCHK(dinst.alloc(inst.size()));
+  HIPCHK(hipMemcpyAsync(dxyz.p, H.xyz_tree.data(), sizeof(double) * H.xyz_tree.size(),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(dinst.p, inst.data(), sizeof(EntryInst) * inst.size(), hipMemcpyHostToDevice, st));
+  std::vector<int> todo(nb);
+  std::iota(todo.begin(), todo.end(), 0);
+  for (int pass = 0; pass < 2 && !todo.empty(); ++pass) {
+    const int cols = pass == 0 ? 32 : kAcaMaxCols;
+    std::vector<int> retry;
+    size_t b0 = 0;
+    while (b0 < todo.size()) {
+      std::vector<AcaItem> items;
+      int64_t off = 0;
+      int max_m = 1;
+      size_t b1 = b0;
+      for (; b1 < todo.size(); ++b1) {
+        const HostH::AcaBlock& d = H.aca[todo[b1]];
+        const int r_max = o.max_rank <= 0 ? std::min(d.m, d.n) : std::min({o.max_rank, d.m, d.n});
+        const int rc = std::min(cols, r_max);
+        const int64_t mn = (int64_t)d.m + d.n, need = 2 * mn * rc + 4 * (int64_t)rc * rc;
+        if (!items.empty() && (off + need) * (int64_t)sizeof(double2) > kAcaChunkBytes) break;
+        items.push_back({d.t_off, d.m, d.s_off, d.n, d.inst, r_max, rc, 0, off, off + (int64_t)d.m * rc,
+                         off + mn * rc, off + mn * rc + 4 * (int64_t)rc * rc});
+        off += need;
+        max_m = std::max(max_m, d.m);
+      }
+      const int ni = (int)items.size();
+      DevTmp<double2> ws, packed;
+      DevTmp<AcaItem> ditems;
+      DevTmp<AcaOut> dout;
+      DevTmp<int64_t> dseg;
+      STCHK(ws.alloc(off));
+      STCHK(ditems.alloc(ni));
+      STCHK(dout.alloc(ni));
+      HIPCHK(hipMemcpyAsync(ditems.p, items.data(), sizeof(AcaItem) * ni, hipMemcpyHostToDevice, st));
+      HIPCHK(launch_aca(ditems.p, ni, max_m, dxyz.p, dinst.p, o.aca_tol, ws.p, dout.p, st));
+      HIPCHK(launch_recompress(ditems.p, ni, o.aca_tol, ws.p, dout.p, st));
+      std::vector<AcaOut> res(ni);
+      HIPCHK(hipMemcpyAsync(res.data(), dout.p, sizeof(AcaOut) * ni, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      // the kept factors, packed U' then V' per block, in one download
+      std::vector<int64_t> seg, pos(ni, -1);
+      int64_t ptot = 0;
+      for (int q = 0; q < ni; ++q) {
+        if (res[q].status != 0) {
+          retry.push_back(todo[b0 + q]);
+          continue;
+        }
+        if (res[q].k < 1) continue;
+        const AcaItem& a = items[q];
+        const int r = res[q].rank;
+        if (r < 1 || r > a.rcap) {
+          set_error("internal: device compression returned rank " + std::to_string(r));
+          return HM_EINVAL;
+        }
+        pos[q] = ptot;
+        seg.insert(seg.end(), {a.o_off, ptot, (int64_t)a.m * r});
+        seg.insert(seg.end(), {a.o_off + (int64_t)a.m * a.rcap, ptot + (int64_t)a.m * r, (int64_t)a.n * r});
+        ptot += (int64_t)(a.m + a.n) * r;
+      }
+      STCHK(packed.alloc(ptot));
+      STCHK(dseg.alloc(seg.size()));
+      std::vector<cplx> host((size_t)ptot);
+      if (ptot > 0) {
+        HIPCHK(hipMemcpyAsync(dseg.p, seg.data(), sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(launch_seg_copy(ws.p, packed.p, dseg.p, (int)(seg.size() / 3), st));
+        HIPCHK(hipMemcpyAsync(host.data(), packed.p, sizeof(double2) * ptot, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+      }
+      for (int q = 0; q < ni; ++q) {
+        if (res[q].status != 0) continue;
+        const AcaItem& a = items[q];
+        LowRank& lr = H.lowrank[todo[b0 + q]];
+        lr.m = a.m;
+        lr.n = a.n;
+        if (res[q].k < 1) {  // no pivot anywhere: a zero block of rank 1
+          lr.r = 1;
+          lr.U.assign(a.m, cplx(0));
+          lr.V.assign(a.n, cplx(0));
+          continue;
+        }
+        lr.r = res[q].rank;
+        const cplx* src = host.data() + pos[q];
+        lr.U.assign(src, src + (size_t)a.m * lr.r);
+        lr.V.assign(src + (size_t)a.m * lr.r, src + (size_t)(a.m + a.n) * lr.r);
+      }
+      b0 = b1;
+    }
+    todo.swap(retry);
+  }
+  // blocks beyond the device's column limit
+  for (const int q : todo) {
+    const HostH::AcaBlock& d = H.aca[q];
+    Problem pt;
+    pt.n = (int64_t)H.xyz_tree.size() / 3;
+    pt.kind = H.inst[d.inst].kind;
+    pt.k = H.inst[d.inst].k;
+    pt.h = H.inst[d.inst].h;
+    pt.xyz = H.xyz_tree;
+    std::vector<int64_t> rows(d.m), cols(d.n);
+    std::iota(rows.begin(), rows.end(), (int64_t)d.t_off);
+    std::iota(cols.begin(), cols.end(), (int64_t)d.s_off);
+    H.lowrank[q] = compress_block(pt, rows.data(), d.m, cols.data(), d.n, o.aca_tol, o.max_rank);
+  }
+  H.aca_pending = false;
+  std::vector<HostH::AcaBlock>().swap(H.aca);
+  return HM_OK;
+}
+
 // Device buffer of the handle, zeroed.
 int dzero(hm_matrix* h, double2** p, int64_t n, hipStream_t st) {
   STCHK(dalloc(h, (void**)p, sizeof(double2) * std::max<int64_t>(n, 1)));
@@ -2775,7 +2900,11 @@ static int device_part(hm_matrix* h, const hm_build_opts* opts, void* hip_stream
     return HM_EHIP;
   }
   HIPCHK(hipGetDevice(&h->device));
-  report(opts, "host build done, packing and uploading blocks");
+  if (h->H.aca_pending) {
+    report(opts, "host build done, compressing far blocks on the device");
+    STCHK(device_aca(h->H, *opts, (hipStream_t)hip_stream));
+  }
+  report(opts, "packing and uploading blocks");
   STCHK(build_device(h, (hipStream_t)hip_stream));
   report(opts, "device build done");
   if (!(opts->flags & HM_BUILD_KEEP_HOST)) {
@@ -3374,6 +3503,21 @@ int build_host_phase(const hm_problem* prob, const hm_build_opts* opts, hm_matri
     std::unique_ptr<hm_matrix> h(new hm_matrix());
     const auto t0 = std::chrono::steady_clock::now();
     STCHK(build_host(copy_problem(prob), *opts, h->H));
+    if (h->H.aca_pending) {
+      // the far blocks are compressed here, so that the device bytes of the
+      // handle are known before its device part is built
+      std::string arch;
+      if (!check_arch(&arch)) {
+        set_error("no usable gfx950 device (found '" + arch + "')");
+        return HM_EHIP;
+      }
+      hipStream_t st = nullptr;
+      HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+      const int s = device_aca(h->H, *opts, st);
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+      STCHK(s);
+    }
     h->inst_off = {0, prob->n};
     hm_build_opts o = *opts;
     o.flags &= ~HM_BUILD_HOST_ONLY;
@@ -3451,6 +3595,8 @@ int64_t gmres_growth_bytes(hm_matrix_t h, int m, int nrhs) {
   return gmres_bytes(h->N, std::max(m, h->gm_m), std::max(nrhs, h->gm_nrhs)) -
          gmres_bytes(h->N, h->gm_m, h->gm_nrhs);
 }
+
+int gmres_rhs(hm_matrix_t h, int m) { return m <= h->gm_m ? h->gm_nrhs : 0; }
 
 int64_t resident_bytes(hm_matrix_t h) { return h->bytes + h->ws_bytes; }
 

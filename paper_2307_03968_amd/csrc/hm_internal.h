@@ -168,6 +168,13 @@ struct HostH {
   std::vector<EntryParams> inst;                 // kernel parameters per instance
   std::vector<int32_t> leaf_inst;                // instance of each leaf
   bool near_on_device = false;                   // near entries are left to the device build
+  // far blocks left to the device compression (one per lowrank entry):
+  // rows t_off .. t_off + m - 1, columns s_off .. s_off + n - 1, tree order
+  struct AcaBlock {
+    int32_t t_off, m, s_off, n, inst;
+  };
+  std::vector<AcaBlock> aca;
+  bool aca_pending = false;
   int32_t min_far_level = -1;
   int32_t max_leaf = 0;
 };
@@ -199,6 +206,7 @@ constexpr int kMmMinRhsDefault = 8;  // default right-hand sides from which MFMA
 // device bytes its workspace would add for m and nrhs (0 when it fits)
 int gmres_restart(const ps_opts& o);
 int64_t gmres_growth_bytes(hm_matrix_t h, int m, int nrhs);
+int gmres_rhs(hm_matrix_t h, int m);   // right-hand sides the GMRES basis holds at restart m
 int64_t matrix_n(hm_matrix_t h);
 
 // Export helper (binary named arrays).

@@ -99,8 +99,18 @@ int build_host(const Problem& p, const hm_build_opts& o, HostH& H) {
     return ta < tb || (ta == tb && tr.nodes[A.s].off < tr.nodes[B.s].off);
   });
   H.lowrank.assign(primary.size(), LowRank());
+  // with the near entries, the compression is left to the device build
+  H.aca_pending = H.near_on_device;
+  H.aca.clear();
+  if (H.aca_pending)
+    for (const int32_t q : primary) {
+      const Cluster& ct = tr.nodes[far[q].t];
+      const Cluster& cs = tr.nodes[far[q].s];
+      H.aca.push_back({ct.off, ct.size, cs.off, cs.size, 0});
+    }
+  const int64_t ncomp = H.aca_pending ? 0 : (int64_t)primary.size();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
-  for (int64_t q = 0; q < (int64_t)primary.size(); ++q) {
+  for (int64_t q = 0; q < ncomp; ++q) {
     const auto& bp = far[primary[q]];
     const Cluster& ct = tr.nodes[bp.t];
     const Cluster& cs = tr.nodes[bp.s];
@@ -151,7 +161,11 @@ void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst
   inst_off.assign(parts.size() + 1, 0);
   H.prob.kind = parts.empty() ? HM_SURFACE : parts[0].prob.kind;
   H.near_on_device = !parts.empty();
-  for (auto& P : parts) H.near_on_device = H.near_on_device && P.near_on_device;
+  H.aca_pending = !parts.empty();
+  for (auto& P : parts) {
+    H.near_on_device = H.near_on_device && P.near_on_device;
+    H.aca_pending = H.aca_pending && P.aca_pending;
+  }
   H.tree.depth = kTopLevel;
   H.min_far_level = -1;
   size_t near_total = 0;
@@ -185,6 +199,12 @@ void merge_hosts(std::vector<HostH>& parts, HostH& H, std::vector<int64_t>& inst
       H.min_far_level = (H.min_far_level < 0) ? g.level : std::min(H.min_far_level, g.level);
     }
     for (auto& lr : P.lowrank) H.lowrank.push_back(std::move(lr));
+    for (HostH::AcaBlock d : P.aca) {
+      d.t_off += (int32_t)n;
+      d.s_off += (int32_t)n;
+      d.inst += ibase;
+      H.aca.push_back(d);
+    }
     if (any_volume) {
       if (P.prob.kind == HM_VOLUME)
         H.chi_tree.insert(H.chi_tree.end(), P.chi_tree.begin(), P.chi_tree.end());

@@ -346,35 +346,53 @@ void hm_server::worker(int slot) {
     const int64_t n = g.n;
     st.batches++;
     st.batch_rhs += cols;
-    // a wider batch than before grows the geometry's workspace: room first
+    // a wider batch than before grows the geometry's workspace: room first.
+    // When no room can be made (the other resident geometries hold queued
+    // work and nothing runs that would release memory), the batch is solved
+    // in pieces of the width the geometry's workspace already holds.
     int s = HM_OK;
     std::string err;
     std::vector<hm_matrix_t> freed;
+    int chunk = cols;
     if (cols > hm::workspace_rhs(h)) {
       const int64_t extra = hm::workspace_bytes(h, cols, 0) - hm::workspace_bytes(h, hm::workspace_rhs(h), 0);
+      bool grown = true;
       while (!make_room(extra, key, freed)) {
         if (!running_elsewhere(key)) {
-          s = HM_ENOMEM;
-          err = "workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
+          grown = false;
+          if (hm::workspace_rhs(h) >= 1) {
+            chunk = hm::workspace_rhs(h);
+          } else {
+            s = HM_ENOMEM;
+            err = "workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
+          }
           break;
         }
         cv.wait(lk);
       }
-      if (s == HM_OK) g.bytes += extra;
+      if (grown) g.bytes += extra;
     }
     // GMRES keeps its basis on the handle: room for its growth too
     if (s == HM_OK && o.kind == PS_GMRES) {
-      const int64_t extra = hm::gmres_growth_bytes(h, hm::gmres_restart(o), cols);
+      const int m = hm::gmres_restart(o);
+      const int64_t extra = hm::gmres_growth_bytes(h, m, chunk);
+      bool grown = true;
       while (extra > 0 && !make_room(extra, key, freed)) {
         if (!running_elsewhere(key)) {
-          s = HM_ENOMEM;
-          err = "GMRES workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
+          grown = false;
+          if (hm::gmres_rhs(h, m) >= 1) {
+            chunk = std::min(chunk, hm::gmres_rhs(h, m));
+          } else {
+            s = HM_ENOMEM;
+            err = "GMRES workspace for " + std::to_string(cols) + " right-hand sides exceeds the budget";
+          }
           break;
         }
         cv.wait(lk);
       }
-      if (s == HM_OK) g.bytes += extra;
+      if (grown) g.bytes += extra;
     }
+    if (chunk < cols) st.split_batches++;
     lk.unlock();
     for (hm_matrix_t f : freed) hmat_free(f);
 
@@ -384,6 +402,7 @@ void hm_server::worker(int slot) {
       if (s != HM_OK) err = "worker staging allocation failed";
     }
     std::vector<ps_stats> stats(cols);
+    bool diverged = false;
     if (s == HM_OK) {
       int c0 = 0;
       for (Request* r : batch) {
@@ -392,10 +411,18 @@ void hm_server::worker(int slot) {
       }
       const size_t bytes = sizeof(cplx) * (size_t)n * cols;
       if (hipMemcpyAsync(db, hb, bytes, hipMemcpyHostToDevice, stream) != hipSuccess) s = HM_EHIP;
-      if (s == HM_OK) {
-        s = ps_solve(h, &o, db, n, dx, n, cols, stats.data(), stream);
-        if (s != HM_OK && s != HM_EDIVERGED) err = hm_last_error();
+      for (int q0 = 0; s == HM_OK && q0 < cols; q0 += chunk) {
+        const int qn = std::min(chunk, cols - q0);
+        const int sq = ps_solve(h, &o, static_cast<cplx*>(db) + (size_t)n * q0, n,
+                                static_cast<cplx*>(dx) + (size_t)n * q0, n, qn, stats.data() + q0, stream);
+        if (sq == HM_EDIVERGED) {
+          diverged = true;
+        } else if (sq != HM_OK) {
+          s = sq;
+          err = hm_last_error();
+        }
       }
+      if (s == HM_OK && diverged) s = HM_EDIVERGED;
       if ((s == HM_OK || s == HM_EDIVERGED) &&
           (hipMemcpyAsync(hx, dx, bytes, hipMemcpyDeviceToHost, stream) != hipSuccess ||
            hipStreamSynchronize(stream) != hipSuccess)) {

@@ -64,7 +64,7 @@ class ps_server_stats(C.Structure):
     _fields_ = [(k, C.c_int64) for k in (
         "budget_bytes", "resident_bytes", "resident_geometries", "builds", "evictions", "batches",
         "batch_rhs", "requests_submitted", "requests_done", "requests_failed", "rhs_done",
-        "queued")]
+        "queued", "split_batches")]
 
 
 class hm_tuning(C.Structure):

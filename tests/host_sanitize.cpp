@@ -133,6 +133,7 @@ int main(int argc, char** argv) {
     CHECK(build_host(c.p, o, Hd) == HM_OK);
     CHECK(Hd.near_on_device && Hd.near_data.empty() && Hd.near.size() == H.near.size());
     CHECK((int64_t)Hd.xyz_tree.size() == 3 * c.p.n && Hd.leaf_inst.size() == Hd.leaf_size.size());
+    CHECK(Hd.aca_pending && Hd.aca.size() == Hd.lowrank.size() && Hd.aca.size() == H.lowrank.size());
     std::printf("built n=%lld leaf=%d: %zu near, %zu far blocks\n", (long long)c.p.n, c.leaf,
                 H.near.size(), H.far.size());
     parts.push_back(std::move(H));

@@ -165,6 +165,30 @@ def test_server_rebuilds_under_load_stay_exact(oracles):
     srv.close()
 
 
+def test_server_splits_batch_without_room(oracles):
+    """A budget that holds geometry 3 with the workspace of a narrow request:
+    a 64-column request finds no room to widen the workspace (nothing else
+    is resident or running), so it is solved in pieces of the width the
+    workspace holds; every column equals the oracle."""
+    p = GEOMS[3][0]
+    probe = hmps.Server(slots=1)
+    seen = set()
+    probe.wait(_submit(probe, 3, W.plane_waves(p.xyz, W.Z_HAT), seen, K=2))
+    one = probe.info()["resident_bytes"]
+    probe.close()
+    srv = hmps.Server(budget_bytes=int(1.03 * one), slots=1)
+    seen = set()
+    srv.wait(_submit(srv, 3, W.plane_waves(p.xyz, W.Z_HAT), seen, K=2))
+    b = W.plane_waves(p.xyz, W.directions(64, 3, instance=77))
+    _say("server: 64 columns without room for their workspace")
+    x, st = srv.wait(_submit(srv, 3, b, seen, K=2))
+    assert_close(x, series.series(oracles[3], b, 2), 1e-10)
+    info = srv.info()
+    _say(f"server info {info}")
+    assert info["split_batches"] >= 1 and info["requests_failed"] == 0
+    srv.close()
+
+
 def test_server_rejects_geometry_over_budget():
     srv = hmps.Server(budget_bytes=1 << 20, slots=1)
     p, leaf, tol = GEOMS[1]
