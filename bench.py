@@ -253,8 +253,15 @@ def bench_single(a):
     prec = hmps.HM_F64 if pname == "f64" else hmps.HM_F32_APPLY
     log(f"library build {wl.name} n={wl.problem.n} leaf={wl.leaf_max} tol={wl.aca_tol}")
     t0 = time.perf_counter()
-    h = hmps.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol, progress=log)
+    marks = []
+
+    def progress(msg):
+        marks.append((time.perf_counter() - t0, msg))
+        log(msg)
+    h = hmps.HMatrix(wl.problem, wl.leaf_max, wl.eta, wl.aca_tol, progress=progress)
     build_s = time.perf_counter() - t0
+    # seconds of each build phase, ending at its progress message
+    build_phases = [[msg, round(t - (marks[i - 1][0] if i else 0.0), 4)] for i, (t, msg) in enumerate(marks)]
     info = h.info()
     L = info["leaf_level"]
     level = L if wl.level < 0 else wl.level
@@ -536,6 +543,7 @@ def bench_single(a):
                    else "complex64 blocks, complex128 vectors"},
         "rel_err_vs_oracle": rel, "latency_ms": lat, "roofline": roof,
         "per_solve_algorithmic_bytes": per_solve_bytes, "kernels": kernels, "build_s": build_s,
+        "build_phases_s": build_phases,
         "device_bytes": info["device_bytes"], "cpu_baseline": cpu, "extras": extras,
         "autotune": None if tune is None else {"choice": tune[0], "ms": tune[1]},
     }

@@ -187,6 +187,7 @@ struct hm_matrix {
   int term_wgs_auto = 1024;
   int num_cus = 256;            // compute units of the device
   int half_wgs_auto = 512;      // resident round of the half-storage kernel
+  int half_wgs_multi = 512;     // the same for its multi-term form
   int32_t* counters = nullptr;  // workspace
   // workspace
   int ws_nrhs = 0;
@@ -857,7 +858,10 @@ int scaled_terms(hm_matrix* h, int li, bool f32, int K, double2* xh, double2** l
     HalfArgs ha = half_args(h, li, f32, y_cur, ldin);
     ha.t.alpha = -1.0;
     const MultiArgs m{K, h->nl, {y_cur, y_nxt}, xh, h->hdone, h->herr};
-    TIMED(HM_K_TERM_SERIES, launch_half_multi(f32, h->max_m, ha, m, h->half[li].tl.nwg, st));
+    // a resident round of the multi-term kernel (pieces come from its queue,
+    // so the count need not match the list's)
+    const int nwg = h->half[li].tl.nwg == h->half_wgs_auto ? h->half_wgs_multi : h->half[li].tl.nwg;
+    TIMED(HM_K_TERM_SERIES, launch_half_multi(f32, h->max_m, ha, m, nwg, st));
     *last = (K & 1) ? y_nxt : y_cur;
     return HM_OK;
   }
@@ -2244,7 +2248,15 @@ int build_half(hm_matrix* h, const HalfSrc& hs, hipStream_t st) {
 }
 
 // ------------------------------------------------------------ device build
-int build_device(hm_matrix* h, hipStream_t st) {
+// Progress message of a build phase; with a progress callback attached the
+// stream is drained first, so that the message marks the phase's end.
+void build_mark(const hm_build_opts* o, hipStream_t st, const char* what) {
+  if (!o || !o->progress) return;
+  (void)hipStreamSynchronize(st);
+  o->progress(what, o->progress_user);
+}
+
+int build_device(hm_matrix* h, const hm_build_opts* opts, hipStream_t st) {
   const HostH& H = h->H;
   const int nl = h->nl;
   const int64_t N = h->N;
@@ -2565,6 +2577,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   STCHK(dalloc(h, (void**)&h->M64, sizeof(double2) * std::max<int64_t>(mtot, 1) + kPanelPad));
   HIPCHK(hipMemsetAsync(h->M64, 0, sizeof(double2) * std::max<int64_t>(mtot, 1) + kPanelPad, st));
 
+  build_mark(opts, st, "panels packed and uploaded");
   // ---- leaf LU with partial pivoting, then D^{-1} (eq. 12's near inverse)
   int* info = nullptr;
   STCHK(dalloc(h, (void**)&info, sizeof(int) * nl));
@@ -2580,6 +2593,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
       return HM_EINVAL;
     }
 
+  build_mark(opts, st, "leaf LU and D^{-1} done");
   // ---- series panels M_a = D_a^{-1} [near | in-row U | global U] columns
   std::vector<int32_t> tiles, ncm(nl);
   for (int a = 0; a < nl; ++a) {
@@ -2592,6 +2606,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
   HIPCHK(launch_premul(h->Dinv, h->Dinv_off, h->R64, h->R_off, h->leaf_m, d_ncm, h->M64, h->M_off,
                        d_tiles, (int)(tiles.size() / 2), h->max_m, st));
 
+  build_mark(opts, st, "premultiplied panels done");
   // ---- FP32 copies (same layout, pad rows stay zero)
   if (h->has_f32) {
     STCHK(dalloc(h, (void**)&h->R32, sizeof(float2) * std::max<int64_t>(rtot, 1) + kPanelPad));
@@ -2610,6 +2625,7 @@ int build_device(hm_matrix* h, hipStream_t st) {
     HIPCHK(launch_cast(h->Wmm64, h->Wmm32, wtot_mm, st));
   }
 
+  build_mark(opts, st, "FP32 copies done");
   // ---- stage-A items and entry counts per level
   h->sa.assign(h->nlev, GroupList());
   h->sa_mm.assign(h->nlev, GroupList());
@@ -2653,6 +2669,8 @@ int build_device(hm_matrix* h, hipStream_t st) {
     if (h->max_m <= kHalfMaxLeaf) {
       const int hocc = std::min(half_occupancy(false, h->max_m), half_occupancy(true, h->max_m));
       h->half_wgs_auto = std::max(1, prop.multiProcessorCount * hocc);
+      const int mocc = std::min(half_occupancy(false, h->max_m, true), half_occupancy(true, h->max_m, true));
+      h->half_wgs_multi = std::max(1, prop.multiProcessorCount * mocc);
     }
   }
   // ---- norm items: per instance (tree-order rows stay contiguous per
@@ -2675,7 +2693,9 @@ int build_device(hm_matrix* h, hipStream_t st) {
   {
     // half storage from the uploaded apply panels, stacks and groups
     const HalfSrc hs{&R_off, &ncols, &ir_off, &ir_ld, &ir_cols, &gs1.groups, &inrow};
+    build_mark(opts, st, "work lists prepared");
     STCHK(build_half(h, hs, st));
+    build_mark(opts, st, "half-storage data done");
   }
   STCHK(build_lists(h, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -2905,7 +2925,7 @@ static int device_part(hm_matrix* h, const hm_build_opts* opts, void* hip_stream
     STCHK(device_aca(h->H, *opts, (hipStream_t)hip_stream));
   }
   report(opts, "packing and uploading blocks");
-  STCHK(build_device(h, (hipStream_t)hip_stream));
+  STCHK(build_device(h, opts, (hipStream_t)hip_stream));
   report(opts, "device build done");
   if (!(opts->flags & HM_BUILD_KEEP_HOST)) {
     bigvec<cplx>().swap(h->H.near_data);
