@@ -582,6 +582,24 @@ def bench_batched(a):
     best, best_ms = h.autotune(nrhs, K=K, precision=F32)
     log(f"autotune: {best} {best_ms:.3f} ms")
     mm = nrhs >= best["mm_min_rhs"]
+    # the FP32 series with its K terms in one persistent launch and with one
+    # launch per stage A and term (eager, median of 5), then the choice again
+    modes = {}
+    if mm:
+        for mode, name in ((1, "multi_term_launch_ms"), (2, "per_term_launches_ms")):
+            h.tune(mm_multi=mode)
+            ts = []
+            for _ in range(7):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                h.solve(b, K=K, precision=F32)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            modes[name] = float(np.median(ts[2:]))
+        h.tune(mm_multi=best["mm_multi"])
+        log(f"FP32 series launch modes: {modes}")
 
     def graph_of(**kw):
         out = torch.empty((nrhs, n), dtype=torch.complex128, device="cuda")
@@ -698,6 +716,7 @@ def bench_batched(a):
         "refine_f32_graph": {"passes": passes, "ms_per_solve": 1e3 * wallr / rsteps,
                              "rel_err_vs_oracle_xstar_sample": rel["refine_f32_vs_xstar"]},
         "autotune": {"choice": best, "ms": best_ms},
+        "series_f32_launch_modes": modes,
         "oracle_sample_instances": sample,
     }
     out = {

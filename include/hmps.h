@@ -332,6 +332,13 @@ typedef struct {
                          With 1 or 3, hmat_apply of one right-hand side
                          on such a problem reads the half storage too,
                          as Z x = C (I + S) C^T x                          */
+  int32_t mm_multi;     /* 1 (default): the many-RHS series on the matrix
+                         cores runs its K terms (stage A included) as one
+                         persistent launch where the handle allows it
+                         (leaves of at most 64 rows, at most 32 right-hand
+                         sides, K <= 16): per-instance counters order the
+                         terms of each batched instance; 2: one launch per
+                         stage A and per term                              */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
@@ -340,7 +347,8 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);
  * right-hand sides (vectors the call allocates and frees) for every
  * candidate tuning -- term_wgs in {auto, auto/2, 2 auto, 4 auto} times
  * {streaming kernels with inrow_pct 100/150/200, MFMA kernels with RHS
- * tiles 16/32/64 up to nrhs}, and the half-storage kernel where it
+ * tiles 16/32/64 up to nrhs, each with the K terms in one launch and per
+ * term}, and the half-storage kernel where it
  * applies --
  * and keeps the fastest on the handle (median of five timed calls after
  * two warm-ups, HIP events on hip_stream).  When an MFMA candidate wins,

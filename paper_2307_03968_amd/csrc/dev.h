@@ -247,6 +247,57 @@ inline bool mm_wave_mode(int max_m) { return max_m <= kMmWaveLeaf; }
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,
                             int nitems, double2* xr, float2* xr32, int64_t ldr, int64_t N,
                             int zrow, int nrhs, int tile, hipStream_t st);
+// The K terms of the series on the matrix cores in one persistent launch
+// (wave mode: leaves of at most kMmWaveLeaf rows; one tile of at most 32
+// right-hand sides).  Work comes from a queue of wave items, term by term:
+// the stage-A tiles of every instance (16 rows of a group each), then the
+// term pieces of every instance.  Term k reads [y_{k-1} | t_k] from
+// rows r[(k - 1) & 1] and its leaf epilogues write y_k to rows r[k & 1] and
+// x += y_k (TermArgs epilogue, alpha = -1).  Per (instance, term) two
+// counters count the stage-A tiles done and the leaf epilogues done; a
+// stage-A tile of term k starts once its instance's epilogues of term k - 1
+// are all done, a term piece once its instance's stage-A tiles of term k are
+// (and the epilogues of term k - 1).  Every wait is on items earlier in the
+// queue, each taken by a running wave, so every wait ends; a wait that gives
+// up sets *err.  Rows, x and the counters move through device-coherent
+// loads and stores (the terms of one leaf run on any XCD).  The queue and
+// the counters are zero between launches (the last wave out clears them).
+struct MMItem {
+  int32_t kind;              // 0: stage-A tile of group a; 1: term piece of leaf a
+  int32_t inst;              // instance the item belongs to
+  int32_t a;
+  int32_t c0, c1;            // term piece: panel columns
+  int32_t prow;              // term piece: first partial row
+  int32_t row0, rows;        // stage-A tile: first row, active rows of the group
+};
+struct MMSeriesArgs {
+  int K;
+  int n_a, n_b;              // stage-A tiles and term pieces of one term
+  const MMItem* items;       // n_a + n_b, the same for every term
+  const Group* groups;       // stage-A groups and their W (FP64 or FP32)
+  const void* W;
+  double2* r64[2];
+  float2* r32[2];
+  int64_t N;                 // rows of y (t rows follow)
+  int32_t* cnt;              // per (instance, term): [tiles done, epilogues done]
+  int kmax;                  // terms the counters hold per instance
+  const int32_t* need_a;     // per instance: stage-A tiles of one term
+  const int32_t* need_b;     // per instance: leaf epilogues of one term
+  int ninst;
+  int32_t* queue;            // [next item, waves done]
+  int32_t* err;
+  // outputs of the last term only (the TermArgs yout / out are ignored)
+  double2* yout;
+  int64_t ldy;
+  double2* out;
+  int64_t ldo;
+  const int64_t* out_perm;
+};
+constexpr int kMmSeriesMaxTerms = 16;
+hipError_t launch_series_mm(bool f32, const TermArgs& a, const MMSeriesArgs& s, int nwg, int nrhs,
+                            hipStream_t st);
+// workgroups of the multi-term matrix-core kernel resident on one CU
+int series_mm_occupancy(bool f32, int nrhs);
 // column layout -> row layout: out[p ldr + c] = in[(perm ? perm[p] : p) + c ldi]
 // for p < n, c < nrhs, zero for nrhs <= c < ldr; FP64 (out) and/or FP32 (out32)
 hipError_t launch_rows(const double2* in, int64_t ldi, const int64_t* perm, int64_t n, int nrhs,

@@ -48,6 +48,47 @@ __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+// Device-coherent (agent-scope) loads and stores of the row-layout vectors
+// and x in the multi-term launch, where one term's values are read by
+// waves of any XCD in the next term.
+__device__ __forceinline__ float2 load_co(const float2* p) {
+  const uint64_t v =
+      __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  float2 r;
+  __builtin_memcpy(&r, &v, sizeof(r));
+  return r;
+}
+__device__ __forceinline__ double2 load_co(const double2* p) {
+  const double* d = reinterpret_cast<const double*>(p);
+  return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void store_co(float2* p, float2 v) {
+  uint64_t u;
+  __builtin_memcpy(&u, &v, sizeof(u));
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_co(double2* p, double2 v) {
+  double* d = reinterpret_cast<double*>(p);
+  __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-coherent load of a counter, the same value in every lane (a
+// wave-uniform value: the control flow that depends on it stays uniform).
+__device__ __forceinline__ int load_uniform(const int32_t* c) {
+  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Wave-uniform fetch-and-add of one: every lane issues the atomic (lane 0
+// adds one, the others zero), and every lane receives lane 0's result.
+// No lane-0-only branch feeds the wave's control flow, so the compiler has
+// no divergent region to split the wave's loop iterations over.
+__device__ __forceinline__ int fetch_add_uniform(int32_t* c, int lane) {
+  return __builtin_amdgcn_readfirstlane(
+      __hip_atomic_fetch_add(c, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
 template <bool F32>
 struct Prec;
 
@@ -132,8 +173,9 @@ struct MMAcc {
 // instructions; right-hand sides past the row length are read at the
 // clamped column ldr - 1 (their products land in result columns that are
 // never stored).  One loop iteration covers one block of 16 k-steps, so the
-// code inside the loop is the same in every iteration.
-template <bool F32, int RT, int NT, int RTL, typename SRCF>
+// code inside the loop is the same in every iteration.  CO: the inputs are
+// read with device-coherent loads (the multi-term launch).
+template <bool F32, int RT, int NT, int RTL, bool CO = false, typename SRCF>
 __device__ __forceinline__ void mm_wave(const void* __restrict__ P, uint32_t ld, int row0, int c0,
                                         int c1, const SRCF& srcf,
                                         const typename Prec<F32>::X* __restrict__ xr, int64_t ldr,
@@ -171,7 +213,10 @@ __device__ __forceinline__ void mm_wave(const void* __restrict__ P, uint32_t ld,
     const int srow = ring[((s >> 4) % 3) * 64 + 4 * (s & 15) + kq];
     const uint32_t rb = (uint32_t)srow * ldr32;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = xr[rb + cx[t]];
+    for (int t = 0; t < NT; ++t) {
+      if constexpr (CO) b[t] = load_co(xr + rb + cx[t]);
+      else b[t] = xr[rb + cx[t]];
+    }
   };
   ring[lane] = block(0);
   ring[64 + lane] = block(1);
@@ -206,9 +251,28 @@ __device__ __forceinline__ void mm_wave(const void* __restrict__ P, uint32_t ld,
 // Sum of the partial rows of one leaf's pieces for rows [row0, row0 + nrow)
 // and one tile of right-hand sides, then the term epilogue; one wave, the
 // right-hand sides of a row on consecutive lanes.
-template <int NRT>
+// Epilogue of one entry in the multi-term launch: y = alpha z to the next
+// term's rows and x += y, through device-coherent accesses (the leaf's
+// earlier terms may have run on another XCD); the last term also writes
+// the column-layout y and the output.
+__device__ __forceinline__ void finish_entry_co(const TermArgs& A, const MMSeriesArgs& S,
+                                                bool last, int64_t off, int i, int c, double2 z) {
+  const double2 y = make_double2(A.alpha * z.x, A.alpha * z.y);
+  if (A.yrow) store_co(A.yrow + (off + i) * A.ldr + c, y);
+  if (A.yrow32) store_co(A.yrow32 + (off + i) * A.ldr + c, make_float2((float)y.x, (float)y.y));
+  const int64_t q = off + i + (int64_t)c * A.ldxa;
+  const double2 o = load_co(A.xacc + q);
+  const double2 res = make_double2(y.x + o.x, y.y + o.y);
+  store_co(A.xacc + q, res);
+  if (last) {
+    if (S.yout) S.yout[off + i + (int64_t)c * S.ldy] = y;
+    if (S.out) S.out[S.out_perm[off + i] + (int64_t)c * S.ldo] = res;
+  }
+}
+
+template <int NRT, bool MT = false>
 __device__ void mm_epilogue(const TermArgs& A, int a, int row0, int nrow, int rhs0, int nrhs,
-                            int lane) {
+                            int lane, const MMSeriesArgs* S = nullptr, bool last = false) {
   const int64_t off = A.leaf_off[a];
   const int q0 = A.lptr[a], np = A.lptr[a + 1] - q0;
   for (int idx = lane; idx < nrow * NRT; idx += 64) {
@@ -236,17 +300,21 @@ __device__ void mm_epilogue(const TermArgs& A, int a, int row0, int nrow, int rh
         zi += vi[u];
       }
     }
-    finish_entry(A, off, i, c, make_double2(zr, zi));
+    if constexpr (MT) finish_entry_co(A, *S, last, off, i, c, make_double2(zr, zi));
+    else finish_entry(A, off, i, c, make_double2(zr, zi));
   }
 }
 
 // One piece on one wave: the products of its rows (RTL tiles), then either
 // the epilogue straight from the registers (the leaf's only piece) or the
 // partial sums published with agent-scope stores and the wave that brings
-// the (leaf, row block) counter to the piece count sums them.
-template <bool F32, int RT, int NT, int RTL>
-__device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it, int m, int rb,
-                                           int row0, int rhs0, int nrhs, int lane, int* ring) {
+// the (leaf, row block) counter to the piece count sums them.  Returns
+// whether this wave ran the epilogue.  MT: the multi-term launch (coherent
+// inputs and epilogue, S and last as in finish_entry_co).
+template <bool F32, int RT, int NT, int RTL, bool MT = false>
+__device__ __forceinline__ bool term_piece(const TermArgs& A, const TermItem& it, int m, int rb,
+                                           int row0, int rhs0, int nrhs, int lane, int* ring,
+                                           const MMSeriesArgs* S = nullptr, bool last = false) {
   using PR = Prec<F32>;
   using XV = typename PR::X;
   constexpr int NRT = 16 * NT;
@@ -263,8 +331,8 @@ __device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it
   MMAcc<F32, RT, NT> acc;
   acc.zero();
   auto srcf = [&](int c) -> int { return src[c]; };
-  mm_wave<F32, RT, NT, RTL>(P, ld, row0, it.c0, it.c1, srcf, xr, A.ldr, A.zrow, rhs0, acc, lane,
-                            ring);
+  mm_wave<F32, RT, NT, RTL, MT>(P, ld, row0, it.c0, it.c1, srcf, xr, A.ldr, A.zrow, rhs0, acc, lane,
+                                ring);
   const int l16 = lane & 15, kq = lane >> 4;
   const int np = __builtin_amdgcn_readfirstlane(A.lptr[a + 1] - A.lptr[a]);
   if (np == 1) {
@@ -277,9 +345,12 @@ __device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it
         for (int v = 0; v < 4; ++v) {
           const int i = row0 + 16 * r + PR::row(kq, v);
           const int c = rhs0 + 16 * t + l16;
-          if (i < m && c < nrhs) finish_entry(A, off, i, c, PR::result(acc.a[r][t], v));
+          if (i < m && c < nrhs) {
+            if constexpr (MT) finish_entry_co(A, *S, last, off, i, c, PR::result(acc.a[r][t], v));
+            else finish_entry(A, off, i, c, PR::result(acc.a[r][t], v));
+          }
         }
-    return;
+    return true;
   }
 #pragma unroll
   for (int r = 0; r < RTL; ++r)
@@ -300,13 +371,13 @@ __device__ __forceinline__ void term_piece(const TermArgs& A, const TermItem& it
   // counter moves, so the wave that finishes the count reads them all
   __builtin_amdgcn_s_waitcnt(0);
   int32_t* cnt = A.counters + ((int64_t)a * 4 + rb) * gridDim.y + blockIdx.y;
-  int old = 0;
-  if (lane == 0) old = __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  old = __shfl(old, 0);
+  const int old = fetch_add_uniform(cnt, lane);
   if (old == np - 1) {
-    mm_epilogue<NRT>(A, a, row0, min(16 * RTL, m - row0), rhs0, nrhs, lane);
+    mm_epilogue<NRT, MT>(A, a, row0, min(16 * RTL, m - row0), rhs0, nrhs, lane, S, last);
     if (lane == 0) __hip_atomic_store(cnt, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
   }
+  return false;
 }
 
 // Workgroups are dispatched to the eight XCDs in turn (workgroup b to XCD
@@ -393,6 +464,112 @@ __global__ __launch_bounds__(kThreads) void k_stageA_mm(const void* __restrict__
       const int c = rhs0 + 16 * t + l16;
       if (q < it.rows && c < nrhs) xr[(N + g.t0 + q) * ldr + c] = PR::from(PR::result(acc.a[0][t], v));
     }
+}
+
+// ---------------------------------------------------------------- multi-term
+constexpr int kSeriesSpinLimit = 1 << 21;
+
+// The wave waits (bounded) until *c reaches need; gives up setting *err.
+__device__ __forceinline__ void wait_count(const int32_t* c, int need, int32_t* err) {
+  if (need <= 0) return;
+  for (int spins = 0; load_uniform(c) < need; ++spins) {
+    if (spins >= kSeriesSpinLimit || load_uniform(err) != 0) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+// The K series terms of MMSeriesArgs in one launch; every wave takes items
+// from the queue on its own (no workgroup barrier anywhere).
+template <bool F32, int NT>
+__global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs S, int nrhs) {
+  using PR = Prec<F32>;
+  using XV = typename PR::X;
+  const int lane = threadIdx.x & 63;
+  const int w = wave_id();
+  const int l16 = lane & 15, kq = lane >> 4;
+  __shared__ int rings[4][3 * 64];
+  int* ring = rings[w];
+  const int per = S.n_a + S.n_b;
+  const int total = S.K * per;
+  for (;;) {
+    const int tk = fetch_add_uniform(S.queue, lane);
+    if (tk >= total) break;
+    const int k = tk / per + 1, j = tk - (k - 1) * per;
+    const int kind = __builtin_amdgcn_readfirstlane(S.items[j].kind);
+    const int inst = __builtin_amdgcn_readfirstlane(S.items[j].inst);
+    const int ia = __builtin_amdgcn_readfirstlane(S.items[j].a);
+    const int cur = (k - 1) & 1;
+    int32_t* cnt_k = S.cnt + ((int64_t)inst * S.kmax + (k - 1)) * 2;  // [tiles, epilogues] of term k
+    const int need_b = S.need_b[inst];
+    if (kind == 0) {
+      // stage-A tile: t_k rows of group ia from y_{k-1}
+      if (k > 1) wait_count(cnt_k - 2 + 1, need_b, S.err);
+      const int row0 = __builtin_amdgcn_readfirstlane(S.items[j].row0);
+      const int rows = __builtin_amdgcn_readfirstlane(S.items[j].rows);
+      const Group g = S.groups[ia];
+      XV* xr = F32 ? reinterpret_cast<XV*>(S.r32[cur]) : reinterpret_cast<XV*>(S.r64[cur]);
+      const void* Wg = F32 ? (const void*)(reinterpret_cast<const float2*>(S.W) + g.w_off)
+                           : (const void*)(reinterpret_cast<const double2*>(S.W) + g.w_off);
+      MMAcc<F32, 1, NT> acc;
+      acc.zero();
+      const int s_off = g.s_off;
+      auto srcf = [&](int c) -> int { return s_off + c; };
+      mm_wave<F32, 1, NT, 1, true>(Wg, (uint32_t)g.ld, row0, 0, g.n, srcf, xr, A.ldr, A.zrow, 0, acc,
+                                   lane, ring);
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = row0 + PR::row(kq, v);
+          const int c = 16 * t + l16;
+          if (q < rows && c < nrhs)
+            store_co(xr + (S.N + g.t0 + q) * A.ldr + c, PR::from(PR::result(acc.a[0][t], v)));
+        }
+      __builtin_amdgcn_s_waitcnt(0);  // the t rows are complete before the count moves
+      (void)fetch_add_uniform(cnt_k, lane);
+    } else {
+      // term piece of leaf ia: waits for its instance's t_k and y_{k-1}
+      wait_count(cnt_k, S.need_a[inst], S.err);
+      if (k > 1) wait_count(cnt_k - 2 + 1, need_b, S.err);
+      TermArgs T = A;
+      T.xr = S.r64[cur];
+      T.xr32 = S.r32[cur];
+      T.yrow = F32 ? nullptr : S.r64[cur ^ 1];
+      T.yrow32 = F32 ? S.r32[cur ^ 1] : nullptr;
+      TermItem it;
+      it.leaf = ia;
+      it.kind = 0;
+      it.c0 = __builtin_amdgcn_readfirstlane(S.items[j].c0);
+      it.c1 = __builtin_amdgcn_readfirstlane(S.items[j].c1);
+      it.r0 = it.r1 = 0;
+      it.prow = __builtin_amdgcn_readfirstlane(S.items[j].prow);
+      it.pad = 0;
+      const int m = __builtin_amdgcn_readfirstlane(A.ps.leaf_m[ia]);
+      const int rtl = min(4, (m + 15) >> 4);
+      const bool last = k == S.K;
+      bool epi;
+      if (rtl == 4) epi = term_piece<F32, 4, NT, 4, true>(T, it, m, 0, 0, 0, nrhs, lane, ring, &S, last);
+      else if (rtl == 3) epi = term_piece<F32, 4, NT, 3, true>(T, it, m, 0, 0, 0, nrhs, lane, ring, &S, last);
+      else if (rtl == 2) epi = term_piece<F32, 4, NT, 2, true>(T, it, m, 0, 0, 0, nrhs, lane, ring, &S, last);
+      else epi = term_piece<F32, 4, NT, 1, true>(T, it, m, 0, 0, 0, nrhs, lane, ring, &S, last);
+      if (epi) {
+        __builtin_amdgcn_s_waitcnt(0);  // y_k and x of the leaf are complete before the count
+        (void)fetch_add_uniform(cnt_k + 1, lane);
+      }
+    }
+  }
+  // the last wave out clears the queue and the counters for the next launch
+  if (fetch_add_uniform(S.queue + 1, lane) == (int)gridDim.x * 4 - 1) {
+    for (int i = lane; i < S.ninst * S.kmax * 2; i += 64)
+      __hip_atomic_store(S.cnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane == 0) {
+      __hip_atomic_store(S.queue, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(S.queue + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- layout
@@ -484,6 +661,34 @@ hipError_t launch_term_mm(bool f32, int max_m, const TermArgs& a, int nunits, in
                : term_mm_launch<false, 2, false>(a, nunits, nrhs, tile, st);
   return f32 ? term_mm_launch<true, 4, false>(a, nunits, nrhs, tile, st)
              : term_mm_launch<false, 4, false>(a, nunits, nrhs, tile, st);
+}
+
+hipError_t launch_series_mm(bool f32, const TermArgs& a, const MMSeriesArgs& s, int nwg, int nrhs,
+                            hipStream_t st) {
+  if (nwg <= 0 || s.K <= 0) return hipSuccess;
+  if (s.K > s.kmax || nrhs <= 0 || nrhs > 32 || a.ldr < row_ld(nrhs) || (f32 ? !a.xr32 : !a.xr) ||
+      (int64_t)s.K * (s.n_a + s.n_b) >= ((int64_t)1 << 31))
+    return hipErrorInvalidValue;
+  if (nrhs <= 16) {
+    if (f32) hipLaunchKernelGGL((k_series_mm<true, 1>), dim3(nwg), dim3(kThreads), 0, st, a, s, nrhs);
+    else hipLaunchKernelGGL((k_series_mm<false, 1>), dim3(nwg), dim3(kThreads), 0, st, a, s, nrhs);
+  } else {
+    if (f32) hipLaunchKernelGGL((k_series_mm<true, 2>), dim3(nwg), dim3(kThreads), 0, st, a, s, nrhs);
+    else hipLaunchKernelGGL((k_series_mm<false, 2>), dim3(nwg), dim3(kThreads), 0, st, a, s, nrhs);
+  }
+  return hipGetLastError();
+}
+
+int series_mm_occupancy(bool f32, int nrhs) {
+  int n = 0;
+  hipError_t e;
+  if (nrhs <= 16)
+    e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_series_mm<true, 1>, kThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_series_mm<false, 1>, kThreads, 0);
+  else
+    e = f32 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_series_mm<true, 2>, kThreads, 0)
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_series_mm<false, 2>, kThreads, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
 }
 
 hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const GroupItem* items,

@@ -52,6 +52,7 @@ struct TermList {
   int64_t rows = 0;            // partial rows
   int64_t vrow = 0;            // half lists: first partial row of the v slots
   int64_t frow = 0;            // half lists: first partial row of the far-pair slots
+  std::vector<TermItem> host;  // the pieces, in list order (before grouping)
 };
 
 struct GroupList {
@@ -173,6 +174,22 @@ struct hm_matrix {
   int32_t* herr = nullptr;        // multi-term launch: a dependency wait gave up
   int half_pct = 100;             // cost weight (%) of half-panel columns in the work split
   std::vector<hm::GroupList> sa_mm;
+  std::vector<std::vector<hm::GroupItem>> sa_mm_host;  // the same tiles on the host
+  std::vector<int32_t> group_mm_inst;                  // instance of each many-RHS group
+  // multi-term matrix-core series, per level (see MMSeriesArgs)
+  struct MMMulti {
+    hm::MMItem* items = nullptr;
+    int n_a = 0, n_b = 0;
+    int32_t* need_a = nullptr;
+    int32_t* need_b = nullptr;
+    bool ok = false;
+  };
+  std::vector<MMMulti> mm_multi;
+  int32_t* mm_cnt = nullptr;    // instances x kMmSeriesMaxTerms x 2, zero between launches
+  int32_t* mm_queue = nullptr;  // 2
+  int32_t* mm_err = nullptr;    // a wait of the multi-term launch gave up
+  int mm_multi_mode = 1;        // 1: one launch for the K terms where it applies; 2: per term
+  int mm_series_wgs[2][2] = {{0, 0}, {0, 0}};  // resident round by [f32][nrhs > 16]
   int mm_min_rhs = hm::kMmMinRhsDefault;  // right-hand sides from which the MFMA kernels run
   int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
   int inrow_pct = 100;          // cost weight (%) of in-row rows in the work split
@@ -558,6 +575,7 @@ int make_termlist(hm_matrix* h, const std::vector<std::vector<std::pair<int64_t,
   tl.nwg = G;
   tl.npieces = (int)items.size();
   tl.rows = rows;
+  tl.host = items;
   STCHK(upload(h, &tl.items, by_wg, st, true));
   STCHK(upload(h, &tl.wptr, wptr, st, true));
   STCHK(upload(h, &tl.lptr, lptr, st, true));
@@ -944,6 +962,12 @@ int scaled_refine_pass(hm_matrix* h, int li, bool f32, int K, bool check, hipStr
   return HM_OK;
 }
 
+// whether the many-RHS series at level li runs as one multi-term launch
+bool mm_multi_ok(const hm_matrix* h, int li, int K, int nrhs) {
+  return h->mm_multi_mode == 1 && h->mm_cnt && li < (int)h->mm_multi.size() && h->mm_multi[li].ok &&
+         K <= kMmSeriesMaxTerms && nrhs <= 32 && mm_wave_mode(h->max_m);
+}
+
 int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64_t ldr,
                 bool rhs_perm, double2* x_tree, double2* out, int64_t ldo, int nrhs,
                 bool want_norms, hipStream_t st, bool allow_half = true) {
@@ -1004,6 +1028,45 @@ int series_core(hm_matrix* h, int li, bool f32, int K, const double2* rhs, int64
       TIMED(HM_K_TERM_DINV, run_term(h, P, false, t, h->tl_dinv_mm, nrhs, st));
     }
     if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 0, st));
+    if (K >= 1 && mm_multi_ok(h, li, K, nrhs)) {
+      // the K terms in one launch (stage A included)
+      const hm_matrix::MMMulti& mmm = h->mm_multi[li];
+      TermArgs t = term_args(h, series_set(h, f32, P.src), tl, f32, nullptr, 0);
+      t.xr = r64[0];
+      t.xr32 = r32[0];
+      t.alpha = -1.0;
+      t.xacc = x_tree;
+      t.ldxa = N;
+      t.accumulate = 1;
+      MMSeriesArgs s{};
+      s.K = K;
+      s.n_a = mmm.n_a;
+      s.n_b = mmm.n_b;
+      s.items = mmm.items;
+      s.groups = P.groups;
+      s.W = P.W;
+      s.r64[0] = r64[0];
+      s.r64[1] = r64[1];
+      s.r32[0] = r32[0];
+      s.r32[1] = r32[1];
+      s.N = N;
+      s.cnt = h->mm_cnt;
+      s.kmax = kMmSeriesMaxTerms;
+      s.need_a = mmm.need_a;
+      s.need_b = mmm.need_b;
+      s.ninst = (int)h->inst_off.size() - 1;
+      s.queue = h->mm_queue;
+      s.err = h->mm_err;
+      s.yout = want_norms ? y_nxt : nullptr;
+      s.ldy = ldin;
+      s.out = out;
+      s.ldo = ldo;
+      s.out_perm = h->perm;
+      TIMED(HM_K_TERM_SERIES, launch_series_mm(f32, t, s, h->mm_series_wgs[f32][nrhs > 16], nrhs, st));
+      std::swap(y_cur, y_nxt);
+      if (want_norms) HIPCHK(norms_into(h, y_cur, ldin, nrhs, 1, st));
+      return HM_OK;
+    }
     int cur = 0;
     for (int k = 1; k <= K; ++k) {
       if (sa.n > 0)
@@ -1517,6 +1580,44 @@ bool mm_whole(const hm_matrix* h) {
 // persistent workgroups): one-RHS lists (dense column ranges + in-row stack
 // rows), many-RHS lists (dense column ranges only: in-row U columns read t
 // like the global ones), and the D^{-1} list.  Replaces earlier lists.
+// Queue items of the multi-term matrix-core series at level li (wave mode):
+// the stage-A tiles (16 rows of a group each), then the term pieces of the
+// level's many-RHS series list; per instance the tiles and the leaves
+// (one epilogue each per term).
+int build_mm_multi(hm_matrix* h, int li, hipStream_t st) {
+  const HostH& H = h->H;
+  const int ninst = (int)h->inst_off.size() - 1;
+  std::vector<MMItem> items;
+  std::vector<int32_t> need_a(ninst, 0), need_b(ninst, 0);
+  for (const GroupItem& gi : h->sa_mm_host[li])
+    for (int r0 = gi.row0; r0 < gi.rows && r0 < gi.row0 + kGroupTileMM; r0 += 16) {
+      const int inst = h->group_mm_inst[gi.group];
+      items.push_back({0, inst, gi.group, 0, 0, 0, r0, gi.rows});
+      need_a[inst]++;
+    }
+  const int n_a = (int)items.size();
+  std::vector<char> seen(h->nl, 0);
+  for (const TermItem& it : h->tl_series_mm[li].host) {
+    if (it.kind != 0) return HM_OK;  // not a list this launch runs
+    const int inst = H.leaf_inst[it.leaf];
+    items.push_back({1, inst, it.leaf, it.c0, it.c1, it.prow, 0, 0});
+    if (!seen[it.leaf]) {
+      seen[it.leaf] = 1;
+      need_b[inst]++;
+    }
+  }
+  for (int a = 0; a < h->nl; ++a)
+    if (!seen[a]) return HM_OK;  // a leaf without an epilogue: keep the per-term launches
+  hm_matrix::MMMulti& mm = h->mm_multi[li];
+  STCHK(upload(h, &mm.items, items, st, true));
+  STCHK(upload(h, &mm.need_a, need_a, st, true));
+  STCHK(upload(h, &mm.need_b, need_b, st, true));
+  mm.n_a = n_a;
+  mm.n_b = (int)items.size() - n_a;
+  mm.ok = true;
+  return HM_OK;
+}
+
 int build_lists(hm_matrix* h, hipStream_t st) {
   HIPCHK(hipStreamSynchronize(st));
   for (void* p : h->list_allocs) (void)hipFree(p);
@@ -1574,6 +1675,13 @@ int build_lists(hm_matrix* h, hipStream_t st) {
   STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv, st));
   STCHK(make_termlist(h, dense, zero, zero, h->ir_ncol_h, h->tl_dinv_mm, st, nullptr, mm_units(h),
                       true));
+  h->mm_multi.assign(h->nlev, hm_matrix::MMMulti());
+  if (h->mm_cnt) {
+    for (int li = 0; li < h->nlev; ++li) STCHK(build_mm_multi(h, li, st));
+    for (int f = 0; f < 2; ++f)
+      for (int big = 0; big < 2; ++big)
+        h->mm_series_wgs[f][big] = h->num_cus * series_mm_occupancy(f != 0, big ? 32 : 16);
+  }
   HIPCHK(hipStreamSynchronize(st));
   if (h->partial_rows > old_rows) h->ws_nrhs = 0;  // workspace is sized by partial_rows
   return HM_OK;
@@ -2629,6 +2737,10 @@ int build_device(hm_matrix* h, const hm_build_opts* opts, hipStream_t st) {
   // ---- stage-A items and entry counts per level
   h->sa.assign(h->nlev, GroupList());
   h->sa_mm.assign(h->nlev, GroupList());
+  h->sa_mm_host.assign(h->nlev, std::vector<GroupItem>());
+  h->group_mm_inst.assign(gsm.groups.size(), 0);
+  for (size_t g = 0; g < gsm.groups.size(); ++g)
+    h->group_mm_inst[g] = H.leaf_inst[H.tree.leaf_of[gsm.groups[g].s_off]];
   h->ent_R.assign(h->nlev, 0);
   h->ent_M.assign(h->nlev, 0);
   h->ent_W.assign(h->nlev, 0);
@@ -2654,10 +2766,19 @@ int build_device(hm_matrix* h, const hm_build_opts* opts, hipStream_t st) {
     }
     STCHK(upload_groups(h, items, h->sa[li], st));
     STCHK(upload_groups(h, items_mm, h->sa_mm[li], st));
+    h->sa_mm_host[li] = items_mm;
     h->ent_R[li] = eR;
     h->ent_M[li] = eM;
     h->ent_W[li] = eW;
     h->ncoef[li] = nc;
+  }
+  // counters and queue of the multi-term matrix-core launch (zero between launches)
+  if (mm_wave_mode(h->max_m)) {
+    const int64_t ncnt = (int64_t)(h->inst_off.size() - 1) * kMmSeriesMaxTerms * 2 + 3;
+    STCHK(dalloc(h, (void**)&h->mm_cnt, sizeof(int32_t) * ncnt));
+    HIPCHK(hipMemsetAsync(h->mm_cnt, 0, sizeof(int32_t) * ncnt, st));
+    h->mm_queue = h->mm_cnt + ncnt - 3;
+    h->mm_err = h->mm_cnt + ncnt - 1;
   }
   {
     hipDeviceProp_t prop;
@@ -3092,18 +3213,21 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
     HIPCHK(hipEventCreate(&ev1));
     HIPCHK(hipEventRecord(ev0, st));
   }
-  // a multi-term half-storage launch that gave up a dependency wait (a
-  // list inconsistent with its data; never expected) is reported by the
-  // calls that synchronise
+  // a multi-term launch (half storage or matrix cores) that gave up a
+  // dependency wait (a list inconsistent with its data; never expected) is
+  // reported by the calls that synchronise
   auto multi_ok = [&]() -> int {
-    if (!h->herr) return HM_OK;
-    int32_t e = 0;
-    HIPCHK(hipMemcpyAsync(&e, h->herr, sizeof(e), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (e == 0) return HM_OK;
-    HIPCHK(hipMemsetAsync(h->herr, 0, sizeof(e), st));
-    set_error("multi-term half-storage launch: a dependency wait gave up");
-    return HM_EHIP;
+    for (int32_t* flag : {h->herr, h->mm_err}) {
+      if (!flag) continue;
+      int32_t e = 0;
+      HIPCHK(hipMemcpyAsync(&e, flag, sizeof(e), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (e == 0) continue;
+      HIPCHK(hipMemsetAsync(flag, 0, sizeof(e), st));
+      set_error("multi-term launch: a dependency wait gave up");
+      return HM_EHIP;
+    }
+    return HM_OK;
   };
   if (o->kind == PS_NESTED) {
     STCHK(nested_solve(h, o->level, f32, o->K, (const double2*)b_dev, ldb, (double2*)x_dev, ldx,
@@ -3309,6 +3433,12 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
   }
   if (t->half_storage > 0) h->use_half = t->half_storage;
   if (t->half_storage == -1) h->use_half = 1;
+  if (t->mm_multi < -1 || t->mm_multi > 2) {
+    set_error("bad tuning values");
+    return HM_EINVAL;
+  }
+  if (t->mm_multi > 0) h->mm_multi_mode = t->mm_multi;
+  if (t->mm_multi == -1) h->mm_multi_mode = 1;
   if (t->inrow_pct < -1 || t->inrow_pct > 1000) {
     set_error("bad tuning values");
     return HM_EINVAL;
@@ -3339,6 +3469,7 @@ int hmat_get_tuning(hm_matrix_t h, hm_tuning* out) {
   out->rhs_tile = h->rhs_tile;
   out->inrow_pct = h->inrow_pct;
   out->half_storage = h->use_half;
+  out->mm_multi = h->mm_multi_mode;
   return HM_OK;
 }
 
@@ -3398,7 +3529,9 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
   // solves and keeps its value (it serves later one-RHS calls)
   std::vector<int> halves = {nrhs == 1 ? 2 : h->use_half};
   if (nrhs == 1 && h->half_ok) halves.push_back(1);
-  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct, halves[0]};
+  // the matrix-core candidates with the K terms in one launch and per term
+  const int multi0 = h->mm_multi_mode;
+  hm_tuning bt{h->mm_min_rhs, h->term_wgs, h->rhs_tile, h->inrow_pct, halves[0], multi0};
   double bms = INFINITY;
   for (int w : wgs) {
     for (int pct : pcts) {
@@ -3414,15 +3547,20 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
           if (nrhs == 1 && hs == 1 && c.mm_min == 1) continue;  // the half product is one-RHS only
           h->mm_min_rhs = c.mm_min;
           h->rhs_tile = c.tile;
-          double ms = 0;
-          STCHK(time_one(&ms));
-          if (ms < bms) {
-            bms = ms;
-            // the MFMA kernels were timed at nrhs only: they take over from
-            // min(nrhs, the default threshold) on, so one right-hand side
-            // (a GEMV, far below the MFMA ridge) keeps the streaming kernels
-            bt = hm_tuning{c.mm_min == 1 ? std::min(nrhs, kMmMinRhsDefault) : nrhs + 1, w, c.tile,
-                           pct, hs};
+          const std::vector<int> multis = c.mm_min == 1 && h->mm_cnt ? std::vector<int>{1, 2}
+                                                                      : std::vector<int>{multi0};
+          for (int mu : multis) {
+            h->mm_multi_mode = mu;
+            double ms = 0;
+            STCHK(time_one(&ms));
+            if (ms < bms) {
+              bms = ms;
+              // the MFMA kernels were timed at nrhs only: they take over from
+              // min(nrhs, the default threshold) on, so one right-hand side
+              // (a GEMV, far below the MFMA ridge) keeps the streaming kernels
+              bt = hm_tuning{c.mm_min == 1 ? std::min(nrhs, kMmMinRhsDefault) : nrhs + 1, w, c.tile,
+                             pct, hs, mu};
+            }
           }
         }
       }
@@ -3431,6 +3569,7 @@ int hmat_autotune(hm_matrix_t h, const ps_opts* opts, int32_t nrhs, void* hip_st
   h->use_half = bt.half_storage;
   h->mm_min_rhs = bt.mm_min_rhs;
   h->rhs_tile = bt.rhs_tile;
+  h->mm_multi_mode = bt.mm_multi;
   if (h->term_wgs != bt.term_wgs || h->inrow_pct != bt.inrow_pct) {
     h->term_wgs = bt.term_wgs;
     h->inrow_pct = bt.inrow_pct;

@@ -69,7 +69,7 @@ class ps_server_stats(C.Structure):
 
 class hm_tuning(C.Structure):
     _fields_ = [("mm_min_rhs", C.c_int32), ("term_wgs", C.c_int32), ("rhs_tile", C.c_int32),
-                ("inrow_pct", C.c_int32), ("half_storage", C.c_int32)]
+                ("inrow_pct", C.c_int32), ("half_storage", C.c_int32), ("mm_multi", C.c_int32)]
 
 
 class hm_info(C.Structure):
@@ -253,17 +253,17 @@ class HMatrix:
         return d
 
     def tune(self, mm_min_rhs: int = 0, term_wgs: int = 0, rhs_tile: int = 0, inrow_pct: int = 0,
-             half_storage: int = 0, stream=None) -> None:
+             half_storage: int = 0, mm_multi: int = 0, stream=None) -> None:
         """hmat_tune: 0 keeps a value, -1 restores its default."""
         t = hm_tuning(int(mm_min_rhs), int(term_wgs), int(rhs_tile), int(inrow_pct),
-                      int(half_storage))
+                      int(half_storage), int(mm_multi))
         _check(_lib().hmat_tune(self._h, C.byref(t), _stream(stream)), "hmat_tune")
 
     def tuning(self) -> dict:
         t = hm_tuning()
         _check(_lib().hmat_get_tuning(self._h, C.byref(t)), "hmat_get_tuning")
         return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
-                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage}
+                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage, "mm_multi": t.mm_multi}
 
     def autotune(self, nrhs: int, K: int, level: int = -1, precision: int = HM_F64,
                  stream=None):
@@ -274,7 +274,7 @@ class HMatrix:
         _check(_lib().hmat_autotune(self._h, C.byref(o), int(nrhs), _stream(stream), C.byref(t),
                                     C.byref(ms)), "hmat_autotune")
         return {"mm_min_rhs": t.mm_min_rhs, "term_wgs": t.term_wgs, "rhs_tile": t.rhs_tile,
-                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage}, ms.value
+                "inrow_pct": t.inrow_pct, "half_storage": t.half_storage, "mm_multi": t.mm_multi}, ms.value
 
     def export(self, path: str) -> None:
         _check(_lib().hmat_export(self._h, path.encode()), "hmat_export")
