@@ -291,7 +291,10 @@ __global__ __launch_bounds__(kT) void k_recompress(const AcaItem* __restrict__ i
   __syncthreads();
   // one-sided Jacobi: C Psi -> Phi Sigma.  Each sweep takes every pair of
   // columns once, in rounds of disjoint pairs (circle method; index k is a
-  // dummy when k is odd), one pair per wave at a time.
+  // dummy when k is odd), one pair per wave at a time; a pair is rotated
+  // while its columns' inner product exceeds 1e-15 of the product of their
+  // norms (a tighter test sits at the rounding level of the inner product
+  // and keeps rotating to the sweep limit).
   const int kk = k + (k & 1);
   for (int sweep = 0; sweep < 80; ++sweep) {
     if (tid == 0) s_rot = 0;
@@ -315,7 +318,7 @@ __global__ __launch_bounds__(kT) void k_recompress(const AcaItem* __restrict__ i
         g.x = wsum(g.x);
         g.y = wsum(g.y);
         const double ag = hypot(g.x, g.y);
-        if (ag == 0.0 || ag <= 1e-16 * sqrt(a2 * b2)) continue;
+        if (ag == 0.0 || ag <= 1e-15 * sqrt(a2 * b2)) continue;
         if (lane == 0) s_rot = 1;
         const double2 eph = make_double2(g.x / ag, -g.y / ag);  // e^{-i phi}
         const double zeta = (b2 - a2) / (2.0 * ag);

@@ -1833,7 +1833,7 @@ int fill_near_device(hm_matrix* h, const std::vector<std::vector<FillItem>>& fil
 // most kAcaChunkBytes of scratch, first with 32 columns per block, then with
 // kAcaMaxCols for the blocks that needed more; a block still short of
 // columns is compressed on the host by the same rules.
-constexpr int64_t kAcaChunkBytes = (int64_t)512 << 20;
+constexpr int64_t kAcaChunkBytes = (int64_t)1 << 30;
 
 int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
   if (!H.aca_pending) return HM_OK;
@@ -1851,6 +1851,35 @@ int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
   std::iota(todo.begin(), todo.end(), 0);
   for (int pass = 0; pass < 2 && !todo.empty(); ++pass) {
     const int cols = pass == 0 ? 32 : kAcaMaxCols;
+    // scratch of every block of the pass (elements), then the chunks
+    auto need_of = [&](const HostH::AcaBlock& d, int* r_max, int* rc) {
+      *r_max = o.max_rank <= 0 ? std::min(d.m, d.n) : std::min({o.max_rank, d.m, d.n});
+      *rc = std::min(cols, *r_max);
+      return 2 * ((int64_t)d.m + d.n) * *rc + 4 * (int64_t)*rc * *rc;
+    };
+    int64_t total = 0;
+    for (int q : todo) {
+      int r_max, rc;
+      total += need_of(H.aca[q], &r_max, &rc);
+    }
+    const int64_t cap = std::min<int64_t>(total, kAcaChunkBytes / (int64_t)sizeof(double2));
+    // buffers of the pass, reused by its chunks (grown when a chunk needs more)
+    DevTmp<double2> ws, packed;
+    DevTmp<AcaItem> ditems;
+    DevTmp<AcaOut> dout;
+    DevTmp<int64_t> dseg;
+    int64_t ws_cap = 0, packed_cap = 0, items_cap = 0, out_cap = 0, seg_cap = 0;
+    auto grow = [&](auto& buf, int64_t& have, int64_t want) -> int {
+      if (want <= have) return HM_OK;
+      if (buf.p) HIPCHK(hipFree(buf.p));
+      buf.p = nullptr;
+      have = 0;
+      STCHK(buf.alloc((size_t)want));
+      have = want;
+      return HM_OK;
+    };
+    std::unique_ptr<char[]> host;
+    int64_t host_cap = 0;
     std::vector<int> retry;
     size_t b0 = 0;
     while (b0 < todo.size()) {
@@ -1860,23 +1889,19 @@ int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
       size_t b1 = b0;
       for (; b1 < todo.size(); ++b1) {
         const HostH::AcaBlock& d = H.aca[todo[b1]];
-        const int r_max = o.max_rank <= 0 ? std::min(d.m, d.n) : std::min({o.max_rank, d.m, d.n});
-        const int rc = std::min(cols, r_max);
-        const int64_t mn = (int64_t)d.m + d.n, need = 2 * mn * rc + 4 * (int64_t)rc * rc;
-        if (!items.empty() && (off + need) * (int64_t)sizeof(double2) > kAcaChunkBytes) break;
+        int r_max, rc;
+        const int64_t need = need_of(d, &r_max, &rc);
+        if (!items.empty() && off + need > cap) break;
+        const int64_t mn = (int64_t)d.m + d.n;
         items.push_back({d.t_off, d.m, d.s_off, d.n, d.inst, r_max, rc, 0, off, off + (int64_t)d.m * rc,
                          off + mn * rc, off + mn * rc + 4 * (int64_t)rc * rc});
         off += need;
         max_m = std::max(max_m, d.m);
       }
       const int ni = (int)items.size();
-      DevTmp<double2> ws, packed;
-      DevTmp<AcaItem> ditems;
-      DevTmp<AcaOut> dout;
-      DevTmp<int64_t> dseg;
-      STCHK(ws.alloc(off));
-      STCHK(ditems.alloc(ni));
-      STCHK(dout.alloc(ni));
+      STCHK(grow(ws, ws_cap, off));
+      STCHK(grow(ditems, items_cap, ni));
+      STCHK(grow(dout, out_cap, ni));
       HIPCHK(hipMemcpyAsync(ditems.p, items.data(), sizeof(AcaItem) * ni, hipMemcpyHostToDevice, st));
       HIPCHK(launch_aca(ditems.p, ni, max_m, dxyz.p, dinst.p, o.aca_tol, ws.p, dout.p, st));
       HIPCHK(launch_recompress(ditems.p, ni, o.aca_tol, ws.p, dout.p, st));
@@ -1903,15 +1928,19 @@ int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
         seg.insert(seg.end(), {a.o_off + (int64_t)a.m * a.rcap, ptot + (int64_t)a.m * r, (int64_t)a.n * r});
         ptot += (int64_t)(a.m + a.n) * r;
       }
-      STCHK(packed.alloc(ptot));
-      STCHK(dseg.alloc(seg.size()));
-      std::vector<cplx> host((size_t)ptot);
       if (ptot > 0) {
+        STCHK(grow(packed, packed_cap, ptot));
+        STCHK(grow(dseg, seg_cap, (int64_t)seg.size()));
+        if (ptot > host_cap) {  // staging of the download, left uninitialised
+          host.reset(new char[(size_t)ptot * sizeof(double2)]);
+          host_cap = ptot;
+        }
         HIPCHK(hipMemcpyAsync(dseg.p, seg.data(), sizeof(int64_t) * seg.size(), hipMemcpyHostToDevice, st));
         HIPCHK(launch_seg_copy(ws.p, packed.p, dseg.p, (int)(seg.size() / 3), st));
-        HIPCHK(hipMemcpyAsync(host.data(), packed.p, sizeof(double2) * ptot, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(host.get(), packed.p, sizeof(double2) * ptot, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
       }
+      const cplx* hp = reinterpret_cast<const cplx*>(host.get());
       for (int q = 0; q < ni; ++q) {
         if (res[q].status != 0) continue;
         const AcaItem& a = items[q];
@@ -1925,7 +1954,7 @@ int device_aca(HostH& H, const hm_build_opts& o, hipStream_t st) {
           continue;
         }
         lr.r = res[q].rank;
-        const cplx* src = host.data() + pos[q];
+        const cplx* src = hp + pos[q];
         lr.U.assign(src, src + (size_t)a.m * lr.r);
         lr.V.assign(src + (size_t)a.m * lr.r, src + (size_t)(a.m + a.n) * lr.r);
       }
