@@ -332,13 +332,15 @@ typedef struct {
                          With 1 or 3, hmat_apply of one right-hand side
                          on such a problem reads the half storage too,
                          as Z x = C (I + S) C^T x                          */
-  int32_t mm_multi;     /* 1 (default): the many-RHS series on the matrix
-                         cores runs its K terms (stage A included) as one
-                         persistent launch where the handle allows it
-                         (leaves of at most 64 rows, at most 32 right-hand
-                         sides, K <= 16): per-instance counters order the
-                         terms of each batched instance; 2: one launch per
-                         stage A and per term                              */
+  int32_t mm_multi;     /* 2 (default): one launch per stage A and per term
+                         of the many-RHS series on the matrix cores; 1: the
+                         K terms (stage A included) as one persistent
+                         launch where the handle allows it (leaves of at
+                         most 64 rows, at most 32 right-hand sides,
+                         K <= 16), per-instance counters ordering the terms
+                         of each batched instance; its inputs are read with
+                         device-coherent loads, which makes it about 20x
+                         slower than the per-term launches on the batch     */
 } hm_tuning;
 int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream);
 int hmat_get_tuning(hm_matrix_t h, hm_tuning* out);

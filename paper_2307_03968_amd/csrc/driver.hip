@@ -188,7 +188,7 @@ struct hm_matrix {
   int32_t* mm_cnt = nullptr;    // instances x kMmSeriesMaxTerms x 2, zero between launches
   int32_t* mm_queue = nullptr;  // 2
   int32_t* mm_err = nullptr;    // a wait of the multi-term launch gave up
-  int mm_multi_mode = 1;        // 1: one launch for the K terms where it applies; 2: per term
+  int mm_multi_mode = 2;        // 1: one launch for the K terms where it applies; 2: per term
   int mm_series_wgs[2][2] = {{0, 0}, {0, 0}};  // resident round by [f32][nrhs > 16]
   int mm_min_rhs = hm::kMmMinRhsDefault;  // right-hand sides from which the MFMA kernels run
   int rhs_tile = 0;             // MFMA right-hand-side tile (0: by nrhs)
@@ -3467,7 +3467,7 @@ int hmat_tune(hm_matrix_t h, const hm_tuning* t, void* hip_stream) {
     return HM_EINVAL;
   }
   if (t->mm_multi > 0) h->mm_multi_mode = t->mm_multi;
-  if (t->mm_multi == -1) h->mm_multi_mode = 1;
+  if (t->mm_multi == -1) h->mm_multi_mode = 2;
   if (t->inrow_pct < -1 || t->inrow_pct > 1000) {
     set_error("bad tuning values");
     return HM_EINVAL;

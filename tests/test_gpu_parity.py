@@ -791,19 +791,19 @@ def test_batched_16_instances_mfma_graph_replay():
             assert np.array_equal(out.t().cpu().numpy(), ref), rep
             _host(h.solve(b, K=K))  # eager work between replays
 
-    assert h.tuning()["mm_multi"] == 1
+    assert h.tuning()["mm_multi"] == 2
     for prec, tol in ((hmps.HM_F64, TOL_F64), (hmps.HM_F32_APPLY, TOL_F32)):
         _say(f"batched c4 series precision={prec}")
         x = _host(h.solve(b, K=K, precision=prec))
         per_instance(x, refs, tol, f"series p{prec}")
         # the K terms (stage A included) in one launch, bit for bit the
         # result of one launch per stage A and per term
-        assert _term_launches(h, lambda: h.solve(b, K=K, precision=prec)) == 1
-        h.tune(mm_multi=2)
         assert _term_launches(h, lambda: h.solve(b, K=K, precision=prec)) == K
-        x2 = _host(h.solve(b, K=K, precision=prec))
         h.tune(mm_multi=1)
-        assert np.array_equal(x, x2), f"multi-term launch differs from per-term launches p{prec}"
+        assert _term_launches(h, lambda: h.solve(b, K=K, precision=prec)) == 1
+        x1 = _host(h.solve(b, K=K, precision=prec))
+        h.tune(mm_multi=2)
+        assert np.array_equal(x, x1), f"multi-term launch differs from per-term launches p{prec}"
         _say(f"batched c4 graph precision={prec}")
         g, out = graph_of(K=K, precision=prec)
         replay_equal(g, out, x)
