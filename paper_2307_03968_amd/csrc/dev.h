@@ -250,7 +250,7 @@ hipError_t launch_stageA_mm(bool f32, const void* W, const Group* groups, const 
 // The K terms of the series on the matrix cores in one persistent launch
 // (wave mode: leaves of at most kMmWaveLeaf rows; one tile of at most 32
 // right-hand sides).  Work comes from a queue of wave items, term by term:
-// the stage-A tiles of every instance (16 rows of a group each), then the
+// the stage-A tiles of every instance (64 rows of a group each), then the
 // term pieces of every instance.  Term k reads [y_{k-1} | t_k] from
 // rows r[(k - 1) & 1] and its leaf epilogues write y_k to rows r[k & 1] and
 // x += y_k (TermArgs epilogue, alpha = -1).  Per (instance, term) two

@@ -89,6 +89,14 @@ __device__ __forceinline__ int fetch_add_uniform(int32_t* c, int lane) {
       __hip_atomic_fetch_add(c, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
+// Count of one finished item: a non-returning atomic from lane 0 (no value
+// comes back into the wave's control flow, and the wave does not wait for
+// it: increments of one shared counter queue at the device's coherence
+// point instead of stalling every wave that makes them).
+__device__ __forceinline__ void count_done(int32_t* c, int lane) {
+  if (lane == 0) (void)__hip_atomic_fetch_add(c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <bool F32>
 struct Prec;
 
@@ -495,6 +503,8 @@ __global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs
   const int per = S.n_a + S.n_b;
   const int total = S.K * per;
   for (;;) {
+    // one ticket per fetch: items differ widely in size, and a wave holding
+    // several consecutive tickets leaves a long tail (measured)
     const int tk = fetch_add_uniform(S.queue, lane);
     if (tk >= total) break;
     const int k = tk / per + 1, j = tk - (k - 1) * per;
@@ -505,7 +515,8 @@ __global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs
     int32_t* cnt_k = S.cnt + ((int64_t)inst * S.kmax + (k - 1)) * 2;  // [tiles, epilogues] of term k
     const int need_b = S.need_b[inst];
     if (kind == 0) {
-      // stage-A tile: t_k rows of group ia from y_{k-1}
+      // stage-A tile: t_k rows [row0, row0 + kGroupTileMM) of group ia from
+      // y_{k-1}, 16 rows at a time
       if (k > 1) wait_count(cnt_k - 2 + 1, need_b, S.err);
       const int row0 = __builtin_amdgcn_readfirstlane(S.items[j].row0);
       const int rows = __builtin_amdgcn_readfirstlane(S.items[j].rows);
@@ -513,23 +524,25 @@ __global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs
       XV* xr = F32 ? reinterpret_cast<XV*>(S.r32[cur]) : reinterpret_cast<XV*>(S.r64[cur]);
       const void* Wg = F32 ? (const void*)(reinterpret_cast<const float2*>(S.W) + g.w_off)
                            : (const void*)(reinterpret_cast<const double2*>(S.W) + g.w_off);
-      MMAcc<F32, 1, NT> acc;
-      acc.zero();
       const int s_off = g.s_off;
       auto srcf = [&](int c) -> int { return s_off + c; };
-      mm_wave<F32, 1, NT, 1, true>(Wg, (uint32_t)g.ld, row0, 0, g.n, srcf, xr, A.ldr, A.zrow, 0, acc,
-                                   lane, ring);
+      for (int r0 = row0; r0 < rows && r0 < row0 + kGroupTileMM; r0 += 16) {
+        MMAcc<F32, 1, NT> acc;
+        acc.zero();
+        mm_wave<F32, 1, NT, 1, true>(Wg, (uint32_t)g.ld, r0, 0, g.n, srcf, xr, A.ldr, A.zrow, 0, acc,
+                                     lane, ring);
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int t = 0; t < NT; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int q = row0 + PR::row(kq, v);
-          const int c = 16 * t + l16;
-          if (q < rows && c < nrhs)
-            store_co(xr + (S.N + g.t0 + q) * A.ldr + c, PR::from(PR::result(acc.a[0][t], v)));
-        }
+          for (int v = 0; v < 4; ++v) {
+            const int q = r0 + PR::row(kq, v);
+            const int c = 16 * t + l16;
+            if (q < rows && c < nrhs)
+              store_co(xr + (S.N + g.t0 + q) * A.ldr + c, PR::from(PR::result(acc.a[0][t], v)));
+          }
+      }
       __builtin_amdgcn_s_waitcnt(0);  // the t rows are complete before the count moves
-      (void)fetch_add_uniform(cnt_k, lane);
+      count_done(cnt_k, lane);
     } else {
       // term piece of leaf ia: waits for its instance's t_k and y_{k-1}
       wait_count(cnt_k, S.need_a[inst], S.err);
@@ -557,7 +570,7 @@ __global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs
       else epi = term_piece<F32, 4, NT, 1, true>(T, it, m, 0, 0, 0, nrhs, lane, ring, &S, last);
       if (epi) {
         __builtin_amdgcn_s_waitcnt(0);  // y_k and x of the leaf are complete before the count
-        (void)fetch_add_uniform(cnt_k + 1, lane);
+        count_done(cnt_k + 1, lane);
       }
     }
   }

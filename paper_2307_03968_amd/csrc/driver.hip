@@ -1581,7 +1581,7 @@ bool mm_whole(const hm_matrix* h) {
 // rows), many-RHS lists (dense column ranges only: in-row U columns read t
 // like the global ones), and the D^{-1} list.  Replaces earlier lists.
 // Queue items of the multi-term matrix-core series at level li (wave mode):
-// the stage-A tiles (16 rows of a group each), then the term pieces of the
+// the stage-A tiles (64 rows of a group each), then the term pieces of the
 // level's many-RHS series list; per instance the tiles and the leaves
 // (one epilogue each per term).
 int build_mm_multi(hm_matrix* h, int li, hipStream_t st) {
@@ -1589,12 +1589,11 @@ int build_mm_multi(hm_matrix* h, int li, hipStream_t st) {
   const int ninst = (int)h->inst_off.size() - 1;
   std::vector<MMItem> items;
   std::vector<int32_t> need_a(ninst, 0), need_b(ninst, 0);
-  for (const GroupItem& gi : h->sa_mm_host[li])
-    for (int r0 = gi.row0; r0 < gi.rows && r0 < gi.row0 + kGroupTileMM; r0 += 16) {
-      const int inst = h->group_mm_inst[gi.group];
-      items.push_back({0, inst, gi.group, 0, 0, 0, r0, gi.rows});
-      need_a[inst]++;
-    }
+  for (const GroupItem& gi : h->sa_mm_host[li]) {  // one item per 64-row tile of a group
+    const int inst = h->group_mm_inst[gi.group];
+    items.push_back({0, inst, gi.group, 0, 0, 0, gi.row0, gi.rows});
+    need_a[inst]++;
+  }
   const int n_a = (int)items.size();
   std::vector<char> seen(h->nl, 0);
   for (const TermItem& it : h->tl_series_mm[li].host) {
