@@ -574,7 +574,11 @@ __global__ __launch_bounds__(kThreads) void k_series_mm(TermArgs A, MMSeriesArgs
       }
     }
   }
-  // the last wave out clears the queue and the counters for the next launch
+  // the last wave out clears the queue and the counters for the next launch.
+  // Every count of a wave has landed before the wave counts itself out: its
+  // later queue fetches return a value, and the wait for that value covers
+  // all of the wave's earlier vector memory operations (gfx950 counts them
+  // with one in-order counter), so no increment arrives after the clear.
   if (fetch_add_uniform(S.queue + 1, lane) == (int)gridDim.x * 4 - 1) {
     for (int i = lane; i < S.ninst * S.kmax * 2; i += 64)
       __hip_atomic_store(S.cnt + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
