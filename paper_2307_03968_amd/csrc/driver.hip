@@ -1607,6 +1607,12 @@ int build_mm_multi(hm_matrix* h, int li, hipStream_t st) {
   }
   for (int a = 0; a < h->nl; ++a)
     if (!seen[a]) return HM_OK;  // a leaf without an epilogue: keep the per-term launches
+  // each part of a term in instance order: the first instances finish their
+  // term first, and their next-term tiles, first in the next part, find
+  // their waits already met (every wait stays on an earlier part)
+  auto by_inst = [](const MMItem& x, const MMItem& y) { return x.inst < y.inst; };
+  std::stable_sort(items.begin(), items.begin() + n_a, by_inst);
+  std::stable_sort(items.begin() + n_a, items.end(), by_inst);
   hm_matrix::MMMulti& mm = h->mm_multi[li];
   STCHK(upload(h, &mm.items, items, st, true));
   STCHK(upload(h, &mm.need_a, need_a, st, true));
