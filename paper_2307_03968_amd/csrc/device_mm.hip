@@ -34,6 +34,9 @@ namespace {
 #ifndef HM_MM_D32
 #define HM_MM_D32 8  // k-steps of 4 columns in flight per wave, FP32 blocks
 #endif
+#ifndef HM_MM_D32_WIDE
+#define HM_MM_D32_WIDE 12  // the same, FP32 blocks with 64-RHS tiles
+#endif
 #ifndef HM_MM_D64
 #define HM_MM_D64 4  // the same, FP64 blocks
 #endif
@@ -192,7 +195,9 @@ __device__ __forceinline__ void mm_wave(const void* __restrict__ P, uint32_t ld,
   using PR = Prec<F32>;
   using AV = typename PR::A;
   using XV = typename PR::X;
-  constexpr int D = PR::D;
+  // a 64-RHS FP32 tile spends more matrix-core time per k-step, and a
+  // deeper pipeline keeps its loads ahead (measured on the 32^3 cube)
+  constexpr int D = (F32 && NT >= 4) ? HM_MM_D32_WIDE : PR::D;
   static_assert(D <= 16, "the loads of a k-step lie at most one block ahead");
   if (c1 <= c0) return;
   const int l16 = lane & 15, kq = lane >> 4;
