@@ -802,8 +802,14 @@ def test_batched_16_instances_mfma_graph_replay():
         h.tune(mm_multi=1)
         assert _term_launches(h, lambda: h.solve(b, K=K, precision=prec)) == 1
         x1 = _host(h.solve(b, K=K, precision=prec))
-        h.tune(mm_multi=2)
         assert np.array_equal(x, x1), f"multi-term launch differs from per-term launches p{prec}"
+        # replays of the one launch: each starts from the counters and queue
+        # the previous launch's last wave cleared
+        _say(f"batched c4 multi-term graph precision={prec}")
+        g, out = graph_of(K=K, precision=prec)
+        replay_equal(g, out, x)
+        del g
+        h.tune(mm_multi=2)
         _say(f"batched c4 graph precision={prec}")
         g, out = graph_of(K=K, precision=prec)
         replay_equal(g, out, x)
