@@ -84,9 +84,12 @@ enum { HM_F64 = 0, HM_F32_APPLY = 1 };
  * per step (the stopping test), so it cannot be captured into a graph.
  * Statistics: passes = Arnoldi steps the column was active, resid_rel = the
  * true final relative residual, growth = 0, diverged = resid_rel above
- * refine_tol; HM_EDIVERGED is returned then.  Single-instance handles only
- * (HM_EINVAL for a batched handle).  The request server takes it (the
- * workspace counts against its budget).
+ * refine_tol; HM_EDIVERGED is returned then.  On a batched handle a column
+ * is one Krylov space over every instance, and ||b|| above (and in
+ * resid_rel) is the smallest nonzero ||b_i|| of the column's instances, so
+ * that each instance's residual, which is at most the column's, meets
+ * refine_tol relative to its own right-hand side.  The request server takes
+ * it (the workspace counts against its budget).
  * Workspace: (2 restart + 1) vectors of N x nrhs complex128, kept on the
  * handle. */
 /* PS_NESTED: the nested multi-level form of eq. 14-22,

@@ -1244,9 +1244,12 @@ int ensure_gmres(hm_matrix* h, int m, int nrhs) {
 // until its residual estimate is below tol and the true residual of the
 // cycle's end confirms it, or the iteration budget is spent.  iters[c] =
 // Arnoldi steps in which column c was active; rel[c] = true final
-// ||b - Z_l x|| / ||b||.
+// ||b - Z_l x|| / ||b||.  On a batched handle each column is one Krylov
+// space over every instance and ||b|| is the smallest nonzero ||b_i|| of
+// the column (every instance then meets the tolerance on its own b).
 //
-// One right-hand side of a symmetric problem iterates in the scaled basis
+// One right-hand side of a symmetric single-instance problem iterates in the
+// scaled basis
 // of the half-storage series instead: (I + S) xhat = bhat with
 // bhat = C^{-1} b and x = C^{-T} xhat, preconditioned by sum_k (-S)^k (the
 // same series, K terms), so every product is one half-storage launch and
@@ -1265,7 +1268,7 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
   double2* Zb = h->gm_Z;
   double* hres = h->gm_host;               // nrhs residuals
   double* hact = h->gm_host + nrhs;         // nrhs flags (as doubles)
-  const bool scaled = use_half(h, li, nrhs);
+  const bool scaled = use_half(h, li, nrhs) && h->nseg == 1;
   const GroupList& sa1 = h->sa[li];
   auto dots = [&](const double2* Vb, int nvec, const double2* w, double2* out, int ldo) {
     return launch_kdots(Vb, vs, N, w, N, nvec, nrhs, h->gm_part, out, ldo, st);
@@ -1341,6 +1344,29 @@ int gmres_solve(hm_matrix* h, int li, bool f32, int K, int m, int max_iter, doub
     HIPCHK(launch_permute_in(b_dev, ldb, h->perm, h->bt, N, N, nrhs, st));
     HIPCHK(dots(h->bt, 1, h->bt, h->gm_bn, 1));
     HIPCHK(launch_axpy(1.0, h->bt, N, V, N, N, nrhs, 0, st));
+    if (h->nseg > 1) {
+      // batched instances: one Krylov space per column over all of them,
+      // measured against the smallest nonzero ||b_i|| of the column, so that
+      // every instance's residual (at most the column's) meets the tolerance
+      // relative to its own right-hand side.  A NaN norm stays NaN.
+      HIPCHK(norms_into(h, h->bt, N, nrhs, 0, st));
+      HIPCHK(hipMemcpyAsync(h->norms_host, h->norms, sizeof(double) * h->nseg * nrhs,
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      std::vector<double2> bmin(nrhs);
+      for (int c = 0; c < nrhs; ++c) {
+        double mn = INFINITY;
+        for (int g = 0; g < h->nseg; ++g) {
+          const double v = h->norms_host[(int64_t)c * h->nseg + g];
+          if (std::isnan(v) || std::isnan(mn)) mn = NAN;
+          else if (v > 0.0 && v < mn) mn = v;
+        }
+        bmin[c] = make_double2(std::isinf(mn) ? 0.0 : mn, 0.0);  // all zero: b = 0
+      }
+      HIPCHK(hipMemcpyAsync(h->gm_bn, bmin.data(), sizeof(double2) * nrhs, hipMemcpyHostToDevice,
+                            st));
+      HIPCHK(hipStreamSynchronize(st));  // bmin is pageable host memory
+    }
   }
   HIPCHK(hipMemsetAsync(h->xt, 0, sizeof(double2) * vs, st));
   double tol_s = scaled ? 0.25 * tol : tol;
@@ -3215,10 +3241,6 @@ static int ps_solve_impl(hm_matrix_t h, const ps_opts* o, const void* b_dev, int
   if (o->kind == PS_GMRES) {
     if (o->max_passes < 1 || !(o->refine_tol > 0) || o->restart < 0 || o->restart > kMaxKrylov) {
       set_error("GMRES needs max_passes >= 1, refine_tol > 0 and restart in [0, 64]");
-      return HM_EINVAL;
-    }
-    if (h->nseg != 1) {
-      set_error("GMRES solves single-instance handles only");
       return HM_EINVAL;
     }
   }

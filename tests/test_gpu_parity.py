@@ -821,6 +821,14 @@ def test_batched_16_instances_mfma_graph_replay():
     passes = max(s_["passes"] for s_ in st)
     assert all(s_["diverged"] == 0 for s_ in st) and passes < 400
     per_instance(x, xss, TOL_REFINE, "refine")
+    # GMRES over all instances at once, preconditioned by the FP32 series:
+    # stopped against the smallest instance's ||b_i||, so every instance
+    # reaches its own x*
+    _say("batched c4 gmres series f32")
+    xg, stg = h.solve(b, K=K, precision=hmps.HM_F32_APPLY, kind=hmps.PS_GMRES, max_passes=1000,
+                      refine_tol=1e-10, stats=True)
+    assert all(s_["diverged"] == 0 and s_["resid_rel"] <= 1e-10 for s_ in stg), stg
+    per_instance(_host(xg), xss, TOL_REFINE, "gmres")
     _say(f"batched c4 fixed refinement graph passes={passes}")
     g, out = graph_of(K=K, precision=hmps.HM_F32_APPLY, kind=hmps.PS_REFINE_FIXED,
                       max_passes=passes, refine_tol=1e-10)
