@@ -335,6 +335,22 @@ def test_batched_instances_match_per_instance_oracle():
     x1 = _host(h.solve(_dev(b), K=K))
     x0 = _host(h.solve(_dev(b), K=K, level=-1))
     assert np.array_equal(x0, x1)
+    # GMRES with D^{-1} over all three instances at once reaches each one's
+    # own x*; column 1 of the last instance is zero (its x stays near zero,
+    # and the stopping norm is the smallest nonzero ||b_i||)
+    _say("batched gmres jacobi f64")
+    bs[2][:, 1] = 0
+    b = np.vstack(bs)
+    xg, stg = h.solve(_dev(b), K=0, precision=hmps.HM_F64, kind=hmps.PS_GMRES, max_passes=500,
+                      refine_tol=1e-11, stats=True)
+    assert all(s_["diverged"] == 0 for s_ in stg), stg
+    xg = _host(xg)
+    for i, H in enumerate(Hs):
+        o0, o1 = h.offsets[i], h.offsets[i + 1]
+        cols = [c for c in range(nrhs) if np.any(bs[i][:, c])]
+        assert_close(xg[o0:o1, cols], series.solve_exact(H, bs[i][:, cols]), 1e-8, ("gmres", i))
+    o0, o1 = h.offsets[2], h.offsets[3]
+    assert np.linalg.norm(xg[o0:o1, 1]) <= 1e-8 * np.linalg.norm(xg[o0:o1, 0])
     h.close()
 
 
